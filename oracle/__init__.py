@@ -1,0 +1,288 @@
+"""FP64 CPU oracle for the entropic (KBC) lattice Boltzmann step with moving walls.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library (``paper_1608_04658_amd``) never imports, links or calls it, and it
+shares no code with the GPU path: its C source (``elbm_oracle.c``) carries its
+own lattice tables and follows the paper's equations with one scalar loop per
+node in FP64.
+
+This module is a ctypes wrapper (argument marshalling plus the time loop).
+Population arrays are float64 numpy arrays of shape (27, nz, ny, nx); the
+velocity order is i = 9 (cz+1) + 3 (cy+1) + (cx+1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "elbm_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libelbm_oracle.so")
+_lib = None
+
+NQ = 27
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("channel", ctypes.c_int32), ("beta", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("u_in", ctypes.c_double * 3), ("stream_only", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class Body(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad", ctypes.c_int32), ("p0", ctypes.c_double * 3),
+                ("radius", ctypes.c_double), ("normal", ctypes.c_double * 3), ("amp", ctypes.c_double),
+                ("period", ctypes.c_double), ("dir", ctypes.c_double * 3), ("vel", ctypes.c_double * 3),
+                ("omega", ctypes.c_double * 3)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("boundary_nodes", ctypes.c_int64), ("links", ctypes.c_int64),
+                ("refill_nodes", ctypes.c_int64), ("gamma_guard", ctypes.c_int64),
+                ("gamma_min", ctypes.c_double), ("gamma_max", ctypes.c_double)]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.or_feq.argtypes = [ctypes.c_double, _D, _D]
+        L.or_collide_ex.argtypes = [_D, ctypes.c_double, _D, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+        L.or_collide_ex.restype = ctypes.c_double
+        L.or_gamma_exact.argtypes = [_D, ctypes.c_double]
+        L.or_gamma_exact.restype = ctypes.c_double
+        L.or_H.argtypes = [_D]
+        L.or_H.restype = ctypes.c_double
+        L.or_shear_part.argtypes = [_D, _D]
+        L.or_grad_dist.argtypes = [ctypes.c_double, _D, _D, _D]
+        L.or_pressure.argtypes = [ctypes.c_double, _D, _D, ctypes.c_double, _D]
+        L.or_beta_from_nu.argtypes = [ctypes.c_double]
+        L.or_beta_from_nu.restype = ctypes.c_double
+        L.or_kinematics.argtypes = [ctypes.POINTER(Body), ctypes.c_double, _D, _D]
+        L.or_q.argtypes = [ctypes.POINTER(Body), _D, _D, ctypes.c_int]
+        L.or_q.restype = ctypes.c_double
+        L.or_solid_mask.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Body), ctypes.c_int, ctypes.c_double, _U8]
+        L.or_grad_u.argtypes = [ctypes.POINTER(Grid), _D, _U8, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]
+        L.or_macro.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Body), ctypes.c_int, ctypes.c_double, _D, _U8,
+                               _D, _D, _D]
+        L.or_step.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Body), ctypes.c_int, ctypes.c_double, _D, _U8,
+                              _U8, _D, _D, _D, ctypes.POINTER(Stats)]
+        L.or_step.restype = ctypes.c_int
+        L.or_init_equilibrium.argtypes = [ctypes.c_long, _D, _D, _D]
+        L.or_moments.argtypes = [ctypes.c_long, _D, _D, _D]
+        L.or_lattice.argtypes = [ctypes.POINTER(ctypes.c_int32), _D]
+        L.or_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _u8(a: np.ndarray):
+    assert a.dtype == np.uint8 and a.flags.c_contiguous
+    return a.ctypes.data_as(_U8)
+
+
+# ----------------------------------------------------------------------------- single-node routines
+def lattice():
+    c = (ctypes.c_int32 * 81)()
+    w = (ctypes.c_double * 27)()
+    lib().or_lattice(c, w)
+    return np.array(c[:], dtype=np.int64).reshape(27, 3), np.array(w[:])
+
+
+def beta_from_nu(nu: float) -> float:
+    return lib().or_beta_from_nu(nu)
+
+
+def feq(rho: float, u) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(27)
+    lib().or_feq(rho, _dp(u), _dp(out))
+    return out
+
+
+def collide(f, beta: float, F=None, gamma_fixed: float = 0.0):
+    """KBC collision of one node. Returns (f_post, gamma, guard_used)."""
+    f = np.array(f, dtype=np.float64).copy()
+    g = ctypes.c_int(0)
+    Fp = _dp(np.ascontiguousarray(F, dtype=np.float64)) if F is not None else None
+    gam = lib().or_collide_ex(_dp(f), beta, Fp, gamma_fixed, ctypes.byref(g))
+    return f, gam, bool(g.value)
+
+
+def gamma_exact(f, beta: float) -> float:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().or_gamma_exact(_dp(f), beta)
+
+
+def H(f) -> float:
+    return lib().or_H(_dp(np.ascontiguousarray(f, dtype=np.float64)))
+
+
+def shear_part(f) -> np.ndarray:
+    out = np.zeros(27)
+    lib().or_shear_part(_dp(np.ascontiguousarray(f, dtype=np.float64)), _dp(out))
+    return out
+
+
+def grad_dist(rho: float, u, Pi) -> np.ndarray:
+    out = np.zeros(27)
+    lib().or_grad_dist(rho, _dp(np.ascontiguousarray(u, dtype=np.float64)),
+                       _dp(np.ascontiguousarray(np.asarray(Pi, dtype=np.float64).reshape(9))), _dp(out))
+    return out
+
+
+def pressure(rho: float, u, G, beta: float) -> np.ndarray:
+    out = np.zeros(9)
+    lib().or_pressure(rho, _dp(np.ascontiguousarray(u, dtype=np.float64)),
+                      _dp(np.ascontiguousarray(np.asarray(G, dtype=np.float64).reshape(9))), beta, _dp(out))
+    return out.reshape(3, 3)
+
+
+# ----------------------------------------------------------------------------- bodies
+def make_body(kind="sphere", center=(0, 0, 0), radius=0.0, normal=(0, 0, 0), amp=0.0, period=0.0,
+              direction=(0, 0, 0), vel=(0, 0, 0), omega=(0, 0, 0)) -> Body:
+    b = Body()
+    b.kind = 0 if kind == "sphere" else 1
+    b.p0[:] = list(map(float, center))
+    b.radius = float(radius)
+    b.normal[:] = list(map(float, normal))
+    b.amp = float(amp)
+    b.period = float(period)
+    b.dir[:] = list(map(float, direction))
+    b.vel[:] = list(map(float, vel))
+    b.omega[:] = list(map(float, omega))
+    return b
+
+
+def body_from_spec(spec: dict) -> Body:
+    return make_body(**spec)
+
+
+def kinematics(body: Body, t: float):
+    c = np.zeros(3)
+    U = np.zeros(3)
+    lib().or_kinematics(ctypes.byref(body), t, _dp(c), _dp(U))
+    return c, U
+
+
+def q_link(body: Body, t: float, xb, i: int) -> float:
+    c, _ = kinematics(body, t)
+    return lib().or_q(ctypes.byref(body), _dp(c), _dp(np.asarray(xb, dtype=np.float64)), i)
+
+
+# ----------------------------------------------------------------------------- simulation
+class Simulation:
+    """Time loop around ``or_step``.  ``A`` holds the post-collision populations."""
+
+    def __init__(self, shape, nu: float, rho=None, u=None, bodies=(), channel: bool = False,
+                 u_in=(0.0, 0.0, 0.0), rho0: float = 1.0, F=None, beta: float | None = None,
+                 stream_only: bool = False, A0=None):
+        nx, ny, nz = shape
+        self.shape = (nx, ny, nz)
+        self.N = nx * ny * nz
+        self.grid = Grid()
+        self.grid.nx, self.grid.ny, self.grid.nz = nx, ny, nz
+        self.grid.channel = 1 if channel else 0
+        self.grid.beta = beta_from_nu(nu) if beta is None else beta
+        self.grid.rho0 = rho0
+        self.grid.u_in[:] = list(map(float, u_in))
+        self.grid.stream_only = 1 if stream_only else 0
+        self.bodies = (Body * max(1, len(bodies)))(*[body_from_spec(b) if isinstance(b, dict) else b
+                                                      for b in bodies])
+        self.nb = len(bodies)
+        self.t = 0
+        self.F = None if F is None else np.ascontiguousarray(F, dtype=np.float64).reshape(3, nz, ny, nx)
+        self.A = np.zeros((27, nz, ny, nx))
+        if u is None:
+            u = np.zeros((3, nz, ny, nx))
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, nz, ny, nx)
+        rp = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64).reshape(nz, ny, nx)
+        if A0 is not None:
+            self.A = np.ascontiguousarray(A0, dtype=np.float64).reshape(27, nz, ny, nx).copy()
+        else:
+            lib().or_init_equilibrium(self.N, _dp(rp) if rp is not None else None, _dp(u), _dp(self.A))
+        self.B = np.zeros_like(self.A)
+        self.solid = self.mask(0)
+        self.forces = []      # per step: array (nb, 6) for the step producing A^{t+1}
+        self.stats = []
+        self.frozen_masks = None   # optional list of masks indexed by time level
+
+    def mask(self, t: float) -> np.ndarray:
+        nx, ny, nz = self.shape
+        out = np.zeros((nz, ny, nx), dtype=np.uint8)
+        if self.nb:
+            lib().or_solid_mask(ctypes.byref(self.grid), self.bodies, self.nb, float(t), _u8(out))
+        return out
+
+    def step(self, n: int = 1, record_masks: list | None = None):
+        for _ in range(n):
+            if self.frozen_masks is not None:
+                s1 = self.frozen_masks[self.t + 1]
+            else:
+                s1 = self.mask(self.t + 1)
+            if record_masks is not None:
+                if not record_masks:
+                    record_masks.append(self.solid.copy())
+                record_masks.append(s1.copy())
+            forces = np.zeros(max(1, self.nb) * 6)
+            st = Stats()
+            Fp = _dp(self.F) if self.F is not None else None
+            rc = lib().or_step(ctypes.byref(self.grid), self.bodies, self.nb, float(self.t), _dp(self.A),
+                               _u8(self.solid), _u8(s1), Fp, _dp(self.B), _dp(forces), ctypes.byref(st))
+            if rc != 0:
+                raise RuntimeError(f"or_step failed: {rc}")
+            self.A, self.B = self.B, self.A
+            self.solid = s1
+            self.t += 1
+            self.forces.append(forces[: 6 * self.nb].reshape(self.nb, 6).copy() if self.nb else np.zeros((0, 6)))
+            self.stats.append({k: getattr(st, k) for k, _ in Stats._fields_})
+        return self
+
+    def moments(self):
+        rho = np.zeros(self.N)
+        j = np.zeros(3 * self.N)
+        lib().or_moments(self.N, _dp(self.A), _dp(rho), _dp(j))
+        nx, ny, nz = self.shape
+        return rho.reshape(nz, ny, nx), j.reshape(3, nz, ny, nx)
+
+    def velocity(self):
+        """Physical velocity U = (j - F/2)/rho of the stored state (previous-step macroscopic field)."""
+        rho, j = self.moments()
+        if self.F is not None:
+            j = j - 0.5 * self.F
+        return rho, j / rho
+
+    def grad_u(self, U: np.ndarray, solid_t1: np.ndarray, x: int, y: int, z: int) -> np.ndarray:
+        G = np.zeros(9)
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        lib().or_grad_u(ctypes.byref(self.grid), _dp(U), _u8(np.ascontiguousarray(solid_t1)), x, y, z, _dp(G))
+        return G.reshape(3, 3)
+
+
+def max_threads() -> int:
+    return lib().or_max_threads()

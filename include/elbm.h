@@ -1,0 +1,196 @@
+/*
+ * elbm.h -- C ABI of the MI355X (gfx950) entropic lattice Boltzmann library.
+ *
+ * The library advances the D3Q27 entropic multi-relaxation-time (KBC) lattice
+ * Boltzmann method with moving-wall Grad boundary conditions of Dorschner,
+ * Chikatamarla and Karlin (arXiv:1608.04658): pull streaming, moments,
+ * entropic equilibrium, KBC collision with a per-node stabiliser gamma (Sec. II,
+ * eqs. kineticEq, kbc_relax, feq_min), reconstruction of the missing populations
+ * at moving walls with Grad's distribution and refill of uncovered nodes
+ * (Sec. III, eqs. grad, pressure, pressure2), and the momentum-exchange force on
+ * each body (Sec. IV.A).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: ELBM_OK (0) or a negative ELBM_E* code.  No exception crosses
+ *    the ABI.  elbm_last_error() describes the last failure of a context.
+ *  - Memory: the caller owns all device memory.  elbm_workspace_bytes() sizes
+ *    one device buffer that the caller allocates (256-byte aligned) and hands
+ *    to elbm_create(); the library carves its fields out of it and never calls
+ *    hipMalloc or hipFree.  Host memory passed in is only read or written during
+ *    the call.  "dev" pointers are device pointers, "host" pointers host ones.
+ *  - Streams: every kernel is enqueued on the stream given to elbm_create()
+ *    (or elbm_set_stream()).  Calls return without waiting for the GPU unless
+ *    stated ("synchronises").
+ *  - Layout: N = nx*ny*nz nodes, node n = (z*ny + y)*nx + x (x fastest).
+ *    Population arrays are structure-of-arrays [27][N]; velocity i has
+ *    c_i = (i%3 - 1, (i/3)%3 - 1, i/9 - 1), so the opposite of i is 26 - i.
+ *    Vector fields are [3][N].
+ *  - One context per host thread at a time; contexts are independent.
+ */
+#ifndef ELBM_H
+#define ELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ELBM_OK 0
+#define ELBM_EINVAL (-1)     /* bad argument */
+#define ELBM_ENOSPACE (-2)   /* workspace too small, or a device list overflowed */
+#define ELBM_EDEVICE (-3)    /* a HIP call failed */
+#define ELBM_ESTATE (-4)     /* call not valid in the context's current state */
+#define ELBM_ENONFINITE (-5) /* non-finite or non-positive population found */
+
+/* storage of the populations in HBM */
+#define ELBM_STORAGE_F32 0   /* f_i as binary32 */
+#define ELBM_STORAGE_F16 1   /* d_i = f_i - W_i as binary16 (round to nearest even) */
+#define ELBM_STORAGE_BF16 2  /* d_i = f_i - W_i as bfloat16 (round to nearest even) */
+
+/* x-direction boundary (y and z are always periodic) */
+#define ELBM_BC_PERIODIC 0
+#define ELBM_BC_CHANNEL 1    /* inlet at x = 0 (moving wall at x = -1/2 with velocity u_inlet,
+                                link fraction 1/2, not counted as a body); outlet at x = nx-1
+                                (a population entering from x = nx takes the value streamed into
+                                x = nx-2 in the same direction) */
+
+#define ELBM_BODY_SPHERE 0
+#define ELBM_BODY_PLANE 1    /* solid half-space n.(x - c) < 0, normal pointing into the fluid */
+
+#define ELBM_MAX_BODIES 8
+
+/* elbm_params.flags */
+#define ELBM_FLAG_BODY_FORCE 1u   /* a per-node body-force field will be bound */
+#define ELBM_FLAG_STREAM_ONLY 2u  /* no collision: the step is the streaming permutation alone */
+#define ELBM_FLAG_NO_FP64 4u      /* disable the FP64 recomputation of near-equilibrium nodes */
+
+typedef struct elbm_params {
+  int32_t nx, ny, nz;   /* lattice size, each >= 1 (channel mode: nx >= 4) */
+  int32_t storage;      /* ELBM_STORAGE_* */
+  int32_t bc_x;         /* ELBM_BC_* */
+  int32_t max_bodies;   /* 0 .. ELBM_MAX_BODIES; 0 = no geometry at all */
+  uint32_t flags;       /* ELBM_FLAG_* */
+  int32_t force_ring;   /* per-step force records kept on the device (>= 1 if max_bodies > 0) */
+  int64_t max_boundary; /* capacity of the boundary-node list; 0 = library default */
+  double nu;            /* kinematic viscosity; beta = 1/(6 nu + 1) (Sec. II, Chapman-Enskog) */
+  double rho0;          /* reference density of the displacement term of Sec. III (1.0) */
+  double u_inlet[3];    /* ELBM_BC_CHANNEL inlet velocity */
+  double fp64_threshold;/* <dh|dh> below this (times rho) is recomputed in FP64; 0 = 1e-10 */
+} elbm_params;
+
+/* A rigid body with prescribed motion (Sec. III).  Every quantity is evaluated
+ * in FP64 in the order written:
+ *   centre   c(t) = center + (amp * sin(((2*pi)*t)/period)) * dir + vel * t
+ *   velocity U(t) = (amp * ((2*pi)/period) * cos(((2*pi)*t)/period)) * dir + vel
+ *   wall velocity at a point x: U(t) + omega x (x - c(t))
+ * (period = 0 means no oscillation).  A node x is solid at t iff it lies strictly
+ * inside: |x - c|^2 < radius^2 (sphere, squares and sums left to right, no fused
+ * multiply-add) or n.(x - c) < 0 (plane).  The first body in the array that
+ * contains a node owns it. */
+typedef struct elbm_body {
+  int32_t kind;         /* ELBM_BODY_* */
+  int32_t reserved;
+  double center[3];
+  double radius;
+  double normal[3];     /* plane only: unit normal into the fluid */
+  double amp;
+  double period;
+  double dir[3];
+  double vel[3];
+  double omega[3];
+} elbm_body;
+
+typedef struct elbm_info {
+  int64_t t;              /* time level of the current populations */
+  int64_t nodes;          /* N */
+  double beta;
+  size_t pop_bytes;       /* bytes of one population array */
+  size_t pop_offset;      /* byte offset of the current populations A^t in the workspace */
+  size_t flags_offset;    /* byte offset of the uint8 node flags (0 if no geometry) */
+  int32_t storage;
+  int32_t nbodies;
+  int64_t boundary_nodes; /* boundary + refill nodes of the last step (synchronises) */
+  int64_t fp64_nodes;     /* nodes recomputed in FP64 during the last step (synchronises) */
+} elbm_info;
+
+/* Bytes of device workspace a context with these parameters needs. */
+int elbm_workspace_bytes(const elbm_params* p, size_t* bytes);
+
+/* Create a context.  stream: a hipStream_t (NULL = default stream).  workspace:
+ * dev, >= elbm_workspace_bytes(p), 256-byte aligned, owned by the caller and
+ * kept alive until elbm_destroy().  The populations are undefined until
+ * elbm_init_equilibrium() or elbm_write_populations(). */
+int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_bytes, struct elbm_ctx** out);
+
+/* Free the context's host-side state (the workspace stays the caller's). */
+int elbm_destroy(struct elbm_ctx* ctx);
+
+int elbm_set_stream(struct elbm_ctx* ctx, void* stream);
+
+/* A^0 = feq(rho, u) at every node (the entropic equilibrium of eq. feq_min),
+ * computed in FP64 and rounded to the storage format; sets t = 0.
+ * rho_dev: dev [N] FP64, or NULL for rho = 1; u_dev: dev [3][N] FP64. */
+int elbm_init_equilibrium(struct elbm_ctx* ctx, const double* rho_dev, const double* u_dev);
+
+/* Replace the populations with pop_dev (dev [27][N] FP64, rounded to the storage
+ * format) and set the time level to t. */
+int elbm_write_populations(struct elbm_ctx* ctx, const double* pop_dev, int64_t t);
+
+/* Copy the current populations to pop_dev (dev [27][N] FP64, widened exactly). */
+int elbm_read_populations(struct elbm_ctx* ctx, double* pop_dev);
+
+/* Set the bodies (host array of nb <= max_bodies records; nb = 0 removes them)
+ * and compute the solid mask at the current time level.  In channel mode a body
+ * must stay at least 6 nodes away from the inlet and outlet faces. */
+int elbm_set_geometry(struct elbm_ctx* ctx, const elbm_body* bodies, int32_t nb);
+
+/* Bind a body-force field F_dev (dev [3][N] FP32, borrowed until replaced) or
+ * NULL for none.  Needs ELBM_FLAG_BODY_FORCE.  The collision adds
+ * feq(rho, u + F/rho) - feq(rho, u); the reported velocity is (j + F/2)/rho. */
+int elbm_set_body_force(struct elbm_ctx* ctx, const float* F_dev);
+
+/* Advance nsteps >= 0 time steps (Secs. II-III): per step the geometry at t+1,
+ * pull streaming, reconstruction of missing populations at walls, refill of
+ * uncovered nodes, KBC collision, store, and the force on each body. */
+int elbm_step(struct elbm_ctx* ctx, int32_t nsteps);
+
+/* Force and torque on body `body` from the step that produced time level
+ * `step` (1 <= step <= t, within the last force_ring steps): momentum exchange
+ * of Sec. IV.A, torque about the body centre.  F, M: host double[3].
+ * Synchronises. */
+int elbm_force(struct elbm_ctx* ctx, int32_t body, int64_t step, double F[3], double M[3]);
+
+/* Forces of `count` consecutive steps starting at time level `first`:
+ * out_host [count][6] = (Fx, Fy, Fz, Mx, My, Mz).  Synchronises. */
+int elbm_force_history(struct elbm_ctx* ctx, int32_t body, int64_t first, int32_t count, double* out_host);
+
+/* Node flags at the current time level: out_dev (dev [N] uint8), bit 0 = solid. */
+int elbm_read_flags(struct elbm_ctx* ctx, uint8_t* out_dev);
+
+/* Context information (synchronises for the per-step counters). */
+int elbm_get_info(struct elbm_ctx* ctx, elbm_info* out);
+
+/* Per-step timing of the bulk sweep kernel with HIP events recorded on the context's stream
+ * around each launch.  enable = 1 starts (and clears) the record, 0 stops it. */
+int elbm_set_timing(struct elbm_ctx* ctx, int32_t enable);
+
+/* Sum of the recorded sweep-kernel durations in ms and the number of launches (synchronises). */
+int elbm_get_timing(struct elbm_ctx* ctx, double* sweep_ms, int64_t* launches);
+
+/* Text of the last error of ctx (or of the last failed elbm_create if ctx is NULL). */
+const char* elbm_last_error(const struct elbm_ctx* ctx);
+
+/* Context-free KBC collision of n independent nodes (Sec. II): f_in_dev, f_out_dev
+ * dev [27][n] FP32, gamma_dev dev [n] FP32 (or NULL), F_dev dev [3][n] FP32 or
+ * NULL.  Uses the same device code as elbm_step, FP64 recomputation included
+ * unless fp64_threshold < 0.  stream: hipStream_t. */
+int elbm_collide_nodes(const float* f_in_dev, float* f_out_dev, float* gamma_dev, const float* F_dev,
+                       int64_t n, double nu, double fp64_threshold, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELBM_H */

@@ -1,0 +1,397 @@
+// capi.hip -- the C ABI of include/elbm.h: context set-up over a caller-owned device workspace,
+// the per-step launch sequence, and force/state readback.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "elbm_internal.hpp"
+
+using namespace elbm;
+
+static char g_create_err[256] = "";
+
+static int fail(elbm_ctx* c, int code, const char* fmt, ...) {
+  char* buf = c ? c->err : g_create_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, 256, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_OK(c, expr)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail((c), ELBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  size_t pop[2], cnt, fix_list, flags, macro, blist, brec, ring, scratch, total;
+  int64_t cap;
+  bool geometry;
+};
+
+bool has_geometry(const elbm_params* p) { return p->max_bodies > 0 || p->bc_x == ELBM_BC_CHANNEL; }
+
+int64_t default_cap(const elbm_params* p) {
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  const int64_t surf = 2 * ((int64_t)p->nx * p->ny + (int64_t)p->ny * p->nz + (int64_t)p->nx * p->nz) + 65536;
+  return surf < N ? surf : N;
+}
+
+int validate(const elbm_params* p, char* err) {
+  if (!p) return snprintf(err, 256, "params is NULL"), ELBM_EINVAL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return snprintf(err, 256, "lattice size must be >= 1"), ELBM_EINVAL;
+  const double N = (double)p->nx * p->ny * p->nz;
+  if (N >= 4294967295.0) return snprintf(err, 256, "more than 2^32-1 nodes"), ELBM_EINVAL;
+  if (p->storage < 0 || p->storage > 2) return snprintf(err, 256, "bad storage %d", p->storage), ELBM_EINVAL;
+  if (p->bc_x != ELBM_BC_PERIODIC && p->bc_x != ELBM_BC_CHANNEL) return snprintf(err, 256, "bad bc_x"), ELBM_EINVAL;
+  if (p->bc_x == ELBM_BC_CHANNEL && p->nx < 4) return snprintf(err, 256, "channel needs nx >= 4"), ELBM_EINVAL;
+  if (p->max_bodies < 0 || p->max_bodies > ELBM_MAX_BODIES) return snprintf(err, 256, "bad max_bodies"), ELBM_EINVAL;
+  if (p->max_bodies > 0 && p->force_ring < 1) return snprintf(err, 256, "force_ring must be >= 1"), ELBM_EINVAL;
+  if (!(p->nu > 0.0) || !isfinite(p->nu)) return snprintf(err, 256, "nu must be positive"), ELBM_EINVAL;
+  if (p->max_boundary < 0) return snprintf(err, 256, "bad max_boundary"), ELBM_EINVAL;
+  return ELBM_OK;
+}
+
+Layout layout(const elbm_params* p) {
+  Layout L{};
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  const size_t es = storage_bytes(p->storage);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  L.pop[0] = take(27 * N * es);
+  L.pop[1] = take(27 * N * es);
+  L.cnt = take(sizeof(DevCounters));
+  L.scratch = take(64 * sizeof(double));
+  L.fix_list = take(4 * N);
+  L.geometry = has_geometry(p);
+  L.cap = 0;
+  if (L.geometry) {
+    L.cap = p->max_boundary > 0 ? p->max_boundary : default_cap(p);
+    const int nbm = p->max_bodies > 0 ? p->max_bodies : 1;
+    const int ring = p->force_ring > 0 ? p->force_ring : 1;
+    L.flags = take(N);
+    L.macro = take(16 * N);
+    L.blist = take(4 * (size_t)L.cap);
+    L.brec = take(sizeof(double) * 6 * nbm * (size_t)L.cap);
+    L.ring = take(sizeof(double) * 6 * ELBM_MAX_BODIES * ring);
+  }
+  L.total = off;
+  return L;
+}
+
+bool body_moves(const elbm_body& b) {
+  if (b.kind == ELBM_BODY_SPHERE)
+    return (b.amp != 0.0 && b.period != 0.0) || b.vel[0] != 0.0 || b.vel[1] != 0.0 || b.vel[2] != 0.0;
+  const double dn = b.dir[0] * b.normal[0] + b.dir[1] * b.normal[1] + b.dir[2] * b.normal[2];
+  const double vn = b.vel[0] * b.normal[0] + b.vel[1] * b.normal[1] + b.vel[2] * b.normal[2];
+  return (b.amp != 0.0 && b.period != 0.0 && dn != 0.0) || vn != 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int elbm_workspace_bytes(const elbm_params* p, size_t* bytes) {
+  const int rc = validate(p, g_create_err);
+  if (rc) return rc;
+  if (!bytes) return fail(nullptr, ELBM_EINVAL, "bytes is NULL");
+  *bytes = layout(p).total;
+  return ELBM_OK;
+}
+
+int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_bytes, elbm_ctx** out) {
+  const int rc = validate(p, g_create_err);
+  if (rc) return rc;
+  if (!out) return fail(nullptr, ELBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  const Layout L = layout(p);
+  if (!workspace) return fail(nullptr, ELBM_EINVAL, "workspace is NULL");
+  if (((uintptr_t)workspace) % ALIGN) return fail(nullptr, ELBM_EINVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(nullptr, ELBM_ENOSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  elbm_ctx* c = new (std::nothrow) elbm_ctx();
+  if (!c) return fail(nullptr, ELBM_EINVAL, "out of host memory");
+  c->p = *p;
+  if (c->p.rho0 == 0.0) c->p.rho0 = 1.0;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)workspace;
+  c->ws_bytes = ws_bytes;
+  c->N = (int64_t)p->nx * p->ny * p->nz;
+  c->beta = 1.0 / (6.0 * p->nu + 1.0);
+  c->fp64_thr = p->fp64_threshold > 0.0 ? p->fp64_threshold : 1e-10;
+  c->pop[0] = c->ws + L.pop[0];
+  c->pop[1] = c->ws + L.pop[1];
+  c->cur = 0;
+  c->cnt = (DevCounters*)(c->ws + L.cnt);
+  c->scratch64 = (double*)(c->ws + L.scratch);
+  c->fix_list = (int32_t*)(c->ws + L.fix_list);
+  c->flags = L.geometry ? (uint8_t*)(c->ws + L.flags) : nullptr;
+  c->macro = L.geometry ? (float*)(c->ws + L.macro) : nullptr;
+  c->blist = L.geometry ? (int32_t*)(c->ws + L.blist) : nullptr;
+  c->brec = L.geometry ? (double*)(c->ws + L.brec) : nullptr;
+  c->ring = L.geometry ? (double*)(c->ws + L.ring) : nullptr;
+  c->blist_cap = L.cap;
+  c->n_static = 0;
+  c->bodyforce = nullptr;
+  c->nb = 0;
+  c->moving = false;
+  c->t = 0;
+  c->err[0] = 0;
+  c->timing = false;
+  c->ev = nullptr;
+  c->ev_cap = c->ev_used = 0;
+  hipError_t e = hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), c->stream);
+  if (e == hipSuccess && L.geometry) e = hipMemsetAsync(c->flags, 0, (size_t)c->N, c->stream);
+  if (e == hipSuccess && L.geometry)
+    e = hipMemsetAsync(c->ring, 0, sizeof(double) * 6 * ELBM_MAX_BODIES * c->p.force_ring, c->stream);
+  if (e == hipSuccess && L.geometry) e = hipMemsetAsync(c->macro, 0, 16 * (size_t)c->N, c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, ELBM_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
+  }
+  if (L.geometry) {
+    // channel without bodies: the inlet face is the static boundary list
+    const int g = geometry_init(c);
+    if (g != hipSuccess) {
+      delete c;
+      return fail(nullptr, ELBM_EDEVICE, "geometry set-up failed");
+    }
+  }
+  *out = c;
+  return ELBM_OK;
+}
+
+static void free_events(elbm_ctx* c) {
+  if (c->ev) {
+    for (int64_t k = 0; k < 2 * c->ev_cap; ++k)
+      if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    free(c->ev);
+  }
+  c->ev = nullptr;
+  c->ev_cap = c->ev_used = 0;
+}
+
+int elbm_destroy(elbm_ctx* c) {
+  if (!c) return ELBM_EINVAL;
+  free_events(c);
+  delete c;
+  return ELBM_OK;
+}
+
+int elbm_set_stream(elbm_ctx* c, void* stream) {
+  if (!c) return ELBM_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return ELBM_OK;
+}
+
+int elbm_init_equilibrium(elbm_ctx* c, const double* rho_dev, const double* u_dev) {
+  if (!c) return ELBM_EINVAL;
+  if (!u_dev) return fail(c, ELBM_EINVAL, "u_dev is NULL");
+  c->cur = 0;
+  c->t = 0;
+  HIP_OK(c, launch_init_eq(c, rho_dev, u_dev));
+  if (c->flags) HIP_OK(c, geometry_init(c));
+  return ELBM_OK;
+}
+
+int elbm_write_populations(elbm_ctx* c, const double* pop_dev, int64_t t) {
+  if (!c) return ELBM_EINVAL;
+  if (!pop_dev || t < 0) return fail(c, ELBM_EINVAL, "bad arguments");
+  c->t = t;
+  HIP_OK(c, launch_write_pop(c, pop_dev));
+  if (c->flags) HIP_OK(c, geometry_init(c));
+  return ELBM_OK;
+}
+
+int elbm_read_populations(elbm_ctx* c, double* pop_dev) {
+  if (!c) return ELBM_EINVAL;
+  if (!pop_dev) return fail(c, ELBM_EINVAL, "pop_dev is NULL");
+  HIP_OK(c, launch_read_pop(c, pop_dev));
+  return ELBM_OK;
+}
+
+int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
+  if (!c) return ELBM_EINVAL;
+  if (nb < 0 || nb > c->p.max_bodies) return fail(c, ELBM_EINVAL, "nb = %d exceeds max_bodies = %d", nb, c->p.max_bodies);
+  if (nb > 0 && !bodies) return fail(c, ELBM_EINVAL, "bodies is NULL");
+  bool moving = false;
+  for (int k = 0; k < nb; ++k) {
+    const elbm_body& b = bodies[k];
+    if (b.kind != ELBM_BODY_SPHERE && b.kind != ELBM_BODY_PLANE) return fail(c, ELBM_EINVAL, "body %d: bad kind", k);
+    if (b.kind == ELBM_BODY_SPHERE && !(b.radius > 0.0)) return fail(c, ELBM_EINVAL, "body %d: radius <= 0", k);
+    if (b.kind == ELBM_BODY_PLANE) {
+      const double nn = b.normal[0] * b.normal[0] + b.normal[1] * b.normal[1] + b.normal[2] * b.normal[2];
+      if (fabs(nn - 1.0) > 1e-12) return fail(c, ELBM_EINVAL, "body %d: plane normal not unit", k);
+    }
+    if (b.kind == ELBM_BODY_SPHERE && c->p.bc_x == ELBM_BC_CHANNEL) {
+      const double ex = b.radius + fabs(b.amp * b.dir[0]);
+      if (b.vel[0] != 0.0 || b.center[0] - ex < 6.0 || b.center[0] + ex > c->p.nx - 7.0)
+        return fail(c, ELBM_EINVAL, "body %d: sphere must stay 6 nodes from inlet and outlet", k);
+    }
+    moving = moving || body_moves(b);
+  }
+  c->nb = nb;
+  for (int k = 0; k < nb; ++k) c->bodies[k] = bodies[k];
+  c->moving = moving;
+  if (!c->flags) {
+    if (nb > 0) return fail(c, ELBM_ESTATE, "context created with max_bodies = 0");
+    return ELBM_OK;
+  }
+  HIP_OK(c, geometry_init(c));
+  return ELBM_OK;
+}
+
+int elbm_set_body_force(elbm_ctx* c, const float* F_dev) {
+  if (!c) return ELBM_EINVAL;
+  if (F_dev && !(c->p.flags & ELBM_FLAG_BODY_FORCE)) return fail(c, ELBM_ESTATE, "ELBM_FLAG_BODY_FORCE not set");
+  c->bodyforce = F_dev;
+  return ELBM_OK;
+}
+
+int elbm_step(elbm_ctx* c, int32_t nsteps) {
+  if (!c) return ELBM_EINVAL;
+  if (nsteps < 0) return fail(c, ELBM_EINVAL, "nsteps < 0");
+  const bool geo = c->flags != nullptr;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    Bodies bd;
+    if (geo) {
+      bd = make_bodies(c, (double)c->t);
+      HIP_OK(c, geometry_pre_step(c, bd));
+    }
+    const bool rec = c->timing && c->ev_used < c->ev_cap;
+    if (rec) HIP_OK(c, hipEventRecord(c->ev[2 * c->ev_used], c->stream));
+    HIP_OK(c, launch_sweep(c));
+    if (rec) {
+      HIP_OK(c, hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream));
+      c->ev_used += 1;
+    }
+    HIP_OK(c, launch_fixup(c));
+    if (geo) {
+      HIP_OK(c, launch_boundary(c, bd));
+      HIP_OK(c, launch_force_reduce(c));
+    }
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return ELBM_OK;
+}
+
+int elbm_force_history(elbm_ctx* c, int32_t body, int64_t first, int32_t count, double* out_host) {
+  if (!c) return ELBM_EINVAL;
+  if (body < 0 || body >= c->nb) return fail(c, ELBM_EINVAL, "no body %d", body);
+  if (count < 0 || !out_host) return fail(c, ELBM_EINVAL, "bad arguments");
+  const int64_t ring = c->p.force_ring;
+  if (first < 1 || first + count - 1 > c->t || first <= c->t - ring)
+    return fail(c, ELBM_EINVAL, "steps %lld..%lld not in the force ring (t = %lld, ring = %lld)", (long long)first,
+                (long long)(first + count - 1), (long long)c->t, (long long)ring);
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  uint32_t ov = 0;
+  HIP_OK(c, hipMemcpy(&ov, &c->cnt->overflow, sizeof ov, hipMemcpyDeviceToHost));
+  if (ov) return fail(c, ELBM_ENOSPACE, "boundary list overflowed its capacity (%lld)", (long long)c->blist_cap);
+  for (int32_t k = 0; k < count; ++k) {
+    const int64_t step = first + k;
+    const int slot = (int)(step % ring);
+    HIP_OK(c, hipMemcpy(out_host + 6 * k, c->ring + ((size_t)slot * ELBM_MAX_BODIES + body) * 6, 6 * sizeof(double),
+                        hipMemcpyDeviceToHost));
+  }
+  return ELBM_OK;
+}
+
+int elbm_force(elbm_ctx* c, int32_t body, int64_t step, double F[3], double M[3]) {
+  double rec[6];
+  const int rc = elbm_force_history(c, body, step, 1, rec);
+  if (rc) return rc;
+  for (int a = 0; a < 3; ++a) {
+    if (F) F[a] = rec[a];
+    if (M) M[a] = rec[3 + a];
+  }
+  return ELBM_OK;
+}
+
+int elbm_read_flags(elbm_ctx* c, uint8_t* out_dev) {
+  if (!c) return ELBM_EINVAL;
+  if (!out_dev) return fail(c, ELBM_EINVAL, "out_dev is NULL");
+  if (!c->flags) {
+    HIP_OK(c, hipMemsetAsync(out_dev, 0, (size_t)c->N, c->stream));
+    return ELBM_OK;
+  }
+  HIP_OK(c, hipMemcpyAsync(out_dev, c->flags, (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+  return ELBM_OK;
+}
+
+int elbm_get_info(elbm_ctx* c, elbm_info* out) {
+  if (!c || !out) return ELBM_EINVAL;
+  memset(out, 0, sizeof *out);
+  out->t = c->t;
+  out->nodes = c->N;
+  out->beta = c->beta;
+  out->pop_bytes = 27 * (size_t)c->N * storage_bytes(c->p.storage);
+  out->pop_offset = (size_t)((char*)c->pop[c->cur] - c->ws);
+  out->flags_offset = c->flags ? (size_t)((char*)c->flags - c->ws) : 0;
+  out->storage = c->p.storage;
+  out->nbodies = c->nb;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  DevCounters h;
+  HIP_OK(c, hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+  out->boundary_nodes = c->flags ? c->n_static + (c->moving ? (int64_t)h.dyn_count : 0) : 0;
+  out->fp64_nodes = h.fix_total;
+  return ELBM_OK;
+}
+
+int elbm_set_timing(elbm_ctx* c, int32_t enable) {
+  if (!c) return ELBM_EINVAL;
+  c->ev_used = 0;
+  c->timing = enable != 0;
+  if (c->timing && !c->ev) {
+    const int64_t cap = 8192;
+    c->ev = (hipEvent_t*)calloc(2 * cap, sizeof(hipEvent_t));
+    if (!c->ev) return fail(c, ELBM_EINVAL, "out of host memory");
+    c->ev_cap = cap;
+    for (int64_t k = 0; k < 2 * cap; ++k) HIP_OK(c, hipEventCreate(&c->ev[k]));
+  }
+  return ELBM_OK;
+}
+
+int elbm_get_timing(elbm_ctx* c, double* sweep_ms, int64_t* launches) {
+  if (!c || !sweep_ms || !launches) return ELBM_EINVAL;
+  double total = 0.0;
+  if (c->ev_used) HIP_OK(c, hipEventSynchronize(c->ev[2 * c->ev_used - 1]));
+  for (int64_t k = 0; k < c->ev_used; ++k) {
+    float ms = 0.f;
+    HIP_OK(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+    total += ms;
+  }
+  *sweep_ms = total;
+  *launches = c->ev_used;
+  return ELBM_OK;
+}
+
+const char* elbm_last_error(const elbm_ctx* c) { return c ? c->err : g_create_err; }
+
+int elbm_collide_nodes(const float* f_in_dev, float* f_out_dev, float* gamma_dev, const float* F_dev, int64_t n,
+                       double nu, double fp64_threshold, void* stream) {
+  if (!f_in_dev || !f_out_dev || n < 0 || !(nu > 0.0)) return fail(nullptr, ELBM_EINVAL, "bad arguments");
+  if (n == 0) return ELBM_OK;
+  const double beta = 1.0 / (6.0 * nu + 1.0);
+  const double thr = fp64_threshold < 0.0 ? -1.0 : (fp64_threshold == 0.0 ? 1e-10 : fp64_threshold);
+  hipError_t e = launch_collide_nodes(f_in_dev, f_out_dev, gamma_dev, F_dev, n, beta, thr, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(nullptr, ELBM_EDEVICE, "collide: %s", hipGetErrorString(e));
+  return ELBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,363 @@
+// elbm_internal.hpp -- shared declarations of the gfx950 entropic lattice Boltzmann library.
+//
+// Device helpers for the D3Q27 KBC step (Dorschner, Chikatamarla, Karlin, arXiv:1608.04658):
+// lattice tables, the KBC collision (Sec. II), Grad's distribution and pressure tensor
+// (Sec. III, eqs. grad, pressure, pressure2), population storage codecs, and the host-side
+// context that the C ABI in include/elbm.h manipulates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "elbm.h"
+
+namespace elbm {
+
+// ---------------------------------------------------------------------------------------------
+// D3Q27 lattice.  i = 9 (cz+1) + 3 (cy+1) + (cx+1); opposite direction 26 - i; rest i = 13.
+// Weights are the tensor products of w(0) = 2/3, w(+-1) = 1/6 (c_s^2 = 1/3).
+__host__ __device__ constexpr int cx(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int cy(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int cz(int i) { return i / 9 - 1; }
+__host__ __device__ constexpr int opp(int i) { return 26 - i; }
+__host__ __device__ constexpr double w1d(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+__host__ __device__ constexpr double wd(int i) { return w1d(cx(i)) * w1d(cy(i)) * w1d(cz(i)); }
+__host__ __device__ constexpr float wf(int i) { return (float)wd(i); }
+__host__ __device__ constexpr int nnz(int i) { return (cx(i) != 0) + (cy(i) != 0) + (cz(i) != 0); }
+
+// node flag bits
+constexpr uint8_t FL_SOLID = 1;       // solid at the time level being produced (t+1)
+constexpr uint8_t FL_SOLID_PREV = 2;  // solid at the previous time level (t)
+constexpr uint8_t FL_SPECIAL = 4;     // handled by the boundary kernel (missing populations or refill)
+
+// ---------------------------------------------------------------------------------------------
+// Population storage.  F32 stores f; F16/BF16 store the deviation d = f - W_i, rounded to
+// nearest even; all arithmetic is FP32.
+template <int S> struct Codec;
+template <> struct Codec<ELBM_STORAGE_F32> {
+  using E = float;
+  static __device__ __forceinline__ float load(const E* p, float) { return *p; }
+  static __device__ __forceinline__ void store(E* p, float v, float) { *p = v; }
+};
+template <> struct Codec<ELBM_STORAGE_F16> {
+  using E = _Float16;
+  static __device__ __forceinline__ float load(const E* p, float w) { return (float)(*p) + w; }
+  static __device__ __forceinline__ void store(E* p, float v, float w) { *p = (_Float16)(v - w); }
+};
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+template <> struct Codec<ELBM_STORAGE_BF16> {
+  using E = uint16_t;
+  static __device__ __forceinline__ float load(const E* p, float w) { return __uint_as_float(((uint32_t)*p) << 16) + w; }
+  static __device__ __forceinline__ void store(E* p, float v, float w) { *p = f32_to_bf16_rne(v - w); }
+};
+
+inline size_t storage_bytes(int s) { return s == ELBM_STORAGE_F32 ? 4 : 2; }
+
+// ---------------------------------------------------------------------------------------------
+// Arithmetic helpers (FP32: hardware reciprocal and square root; FP64: IEEE division).
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+
+// Per-axis factors of the factorised entropic equilibrium (eq. feq_min):
+//   phi(c) = w(c) (2 - s) X^c,  X = (2u + s)/(1 - u),  1/X = (s - 2u)/(1 + u),  s = sqrt(1 + 3u^2),
+// and of its reciprocal psi(c) = 1/phi(c) (used by the entropic scalar product).
+template <typename T>
+__device__ __forceinline__ void axis_factors(T u, T (&ph)[3], T (&ps)[3], T& s) {
+  s = sqrt_(T(3) * u * u + T(1));
+  const T g = T(2) - s;
+  const T X = (T(2) * u + s) * rcp_(T(1) - u);
+  const T Xi = (s - T(2) * u) * rcp_(T(1) + u);
+  const T gr = rcp_(g);
+  ph[0] = g * Xi * T(1.0 / 6.0);
+  ph[1] = g * T(2.0 / 3.0);
+  ph[2] = g * X * T(1.0 / 6.0);
+  ps[0] = T(6) * X * gr;
+  ps[1] = T(1.5) * gr;
+  ps[2] = T(6) * Xi * gr;
+}
+
+template <typename T>
+__device__ __forceinline__ void axis_phi(T u, T (&ph)[3]) {
+  const T s = sqrt_(T(3) * u * u + T(1));
+  const T g = T(2) - s;
+  ph[0] = g * ((s - T(2) * u) / (T(1) + u)) * T(1.0 / 6.0);
+  ph[1] = g * T(2.0 / 3.0);
+  ph[2] = g * ((T(2) * u + s) / (T(1) - u)) * T(1.0 / 6.0);
+}
+
+// Entropic equilibrium of all 27 directions (double precision, used for initial states and the
+// body-force increment).
+__device__ __forceinline__ void feq_all(double rho, double ux, double uy, double uz, double (&fe)[27]) {
+  double px[3], py[3], pz[3];
+  axis_phi(ux, px);
+  axis_phi(uy, py);
+  axis_phi(uz, pz);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) fe[i] = rho * px[cx(i) + 1] * py[cy(i) + 1] * pz[cz(i) + 1];
+}
+
+template <typename T> struct KbcOut {
+  T gamma;
+  T b;    // <dh|dh>
+  T rho;
+};
+
+// KBC collision of one node, in place (Sec. II, eqs. kineticEq and kbc_relax).  The mirror-state
+// update is applied in its equivalent increment form  f' = f - beta (2 ds + gamma dh),
+// with ds, dh the deviations of the shear part s and the higher-order part h from equilibrium:
+//   - raw moments M_pqr of f by a separable 1-D transform along x, y, z;
+//   - feq from the factorised closed form, 1/feq from the reciprocal factors;
+//   - ds from the deviatoric second moments of df = f - feq through the dual basis
+//     phi_0 = 1 - c^2, phi_1 = c/2, phi_2 = 3c^2/2 - 1 (faces: D_aa/2, edges: c_a c_b P_ab/4,
+//     rest and corners: 0); the equilibrium second moments are rho (2 s_a - 1)/3 and rho u_a u_b;
+//   - dh = df - ds;  gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh>, <X|Y> = sum X Y / feq;
+//     gamma = 2 when <dh|dh> <= 1e-30 (then dh is zero to round-off and f' does not depend on it).
+// FORCE adds the exact-difference body-force increment feq(rho, u + F/rho) - feq(rho, u),
+// evaluated in FP64 to avoid cancellation.
+template <typename T, bool FORCE>
+__device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const T inv_beta, const T Fx, const T Fy,
+                                                 const T Fz) {
+  // separable raw-moment transform: (a, b, c) at c = -1, 0, +1  ->  (a+b+c, c-a, a+c)
+  T m0[9], m1[9], m2[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    const T a = f[3 * r], b = f[3 * r + 1], c = f[3 * r + 2];
+    const T ac = a + c;
+    m0[r] = ac + b;
+    m1[r] = c - a;
+    m2[r] = ac;
+  }
+  T m00[3], m01[3], m02[3], m10[3], m11[3], m20[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    {
+      const T a = m0[3 * k], b = m0[3 * k + 1], c = m0[3 * k + 2];
+      const T ac = a + c;
+      m00[k] = ac + b;
+      m01[k] = c - a;
+      m02[k] = ac;
+    }
+    {
+      const T a = m1[3 * k], b = m1[3 * k + 1], c = m1[3 * k + 2];
+      m10[k] = (a + c) + b;
+      m11[k] = c - a;
+    }
+    m20[k] = (m2[3 * k] + m2[3 * k + 2]) + m2[3 * k + 1];
+  }
+  const T rho = (m00[0] + m00[2]) + m00[1];
+  const T jz = m00[2] - m00[0];
+  const T M002 = m00[0] + m00[2];
+  const T jy = (m01[0] + m01[2]) + m01[1];
+  const T M011 = m01[2] - m01[0];
+  const T M020 = (m02[0] + m02[2]) + m02[1];
+  const T jx = (m10[0] + m10[2]) + m10[1];
+  const T M101 = m10[2] - m10[0];
+  const T M110 = (m11[0] + m11[2]) + m11[1];
+  const T M200 = (m20[0] + m20[2]) + m20[1];
+
+  const T rinv = rcp_(rho);
+  const T ux = jx * rinv, uy = jy * rinv, uz = jz * rinv;
+  T phx[3], phy[3], phz[3], psx[3], psy[3], psz[3], sx, sy, sz;
+  axis_factors(ux, phx, psx, sx);
+  axis_factors(uy, phy, psy, sy);
+  axis_factors(uz, phz, psz, sz);
+
+  // deviatoric moments of df (exact equilibrium moments subtracted in closed form)
+  const T third = T(1.0 / 3.0);
+  const T dM200 = M200 - rho * (T(2) * sx - T(1)) * third;
+  const T dM020 = M020 - rho * (T(2) * sy - T(1)) * third;
+  const T dM002 = M002 - rho * (T(2) * sz - T(1)) * third;
+  const T tr3 = (dM200 + dM020 + dM002) * third;
+  const T sfx = T(0.5) * (dM200 - tr3), sfy = T(0.5) * (dM020 - tr3), sfz = T(0.5) * (dM002 - tr3);
+  const T sxy = T(0.25) * (M110 - jx * uy), sxz = T(0.25) * (M101 - jx * uz), syz = T(0.25) * (M011 - jy * uz);
+
+  T dh[27];
+  T a = T(0), b = T(0);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const T pyz = phy[cy(i) + 1] * phz[cz(i) + 1];
+    const T qyz = psy[cy(i) + 1] * psz[cz(i) + 1];
+    const T fe = (rho * pyz) * phx[cx(i) + 1];
+    const T ife = (rinv * qyz) * psx[cx(i) + 1];
+    T ds = T(0);
+    if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
+    if (nnz(i) == 2) {
+      if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
+      else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
+      else ds = T(cy(i) * cz(i)) * syz;
+    }
+    const T h = (f[i] - fe) - ds;
+    const T th = h * ife;
+    b += th * h;
+    if (nnz(i) == 1 || nnz(i) == 2) a += th * ds;
+    dh[i] = h;
+  }
+  const T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * a / b : T(2);
+  const T bg = beta * gamma, b2 = T(2) * beta;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    T ds = T(0);
+    if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
+    if (nnz(i) == 2) {
+      if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
+      else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
+      else ds = T(cy(i) * cz(i)) * syz;
+    }
+    f[i] = f[i] - b2 * ds - bg * dh[i];
+  }
+  if (FORCE) {
+    const double r = (double)rho;
+    double e0[27], e1[27];
+    feq_all(r, (double)ux, (double)uy, (double)uz, e0);
+    feq_all(r, (double)ux + (double)Fx / r, (double)uy + (double)Fy / r, (double)uz + (double)Fz / r, e1);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f[i] = (T)((double)f[i] + (e1[i] - e0[i]));
+  }
+  return KbcOut<T>{gamma, b, rho};
+}
+
+// Grad's distribution (eq. grad) with c_s^2 = 1/3:
+//   f*_i = W_i [rho + 3 rho c.u + (9/2) (Pi - rho/3 I) : (c c - I/3)].
+template <typename T>
+__device__ __forceinline__ T grad_pop(int i, T rho, const T (&u)[3], const T (&Pi)[6]) {
+  // Pi packed as xx, yy, zz, xy, xz, yz
+  const T c[3] = {T(cx(i)), T(cy(i)), T(cz(i))};
+  const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+  const T r3 = rho * T(1.0 / 3.0);
+  const T Axx = Pi[0] - r3, Ayy = Pi[1] - r3, Azz = Pi[2] - r3;
+  const T t = T(1.0 / 3.0);
+  const T PQ = Axx * (c[0] * c[0] - t) + Ayy * (c[1] * c[1] - t) + Azz * (c[2] * c[2] - t) +
+               T(2) * (Pi[3] * c[0] * c[1] + Pi[4] * c[0] * c[2] + Pi[5] * c[1] * c[2]);
+  return T(wd(i)) * (rho + T(3) * rho * cu + T(4.5) * PQ);
+}
+
+// Pressure tensor (eqs. pressure, pressure2): Pi = rho/3 I + rho u u - (rho/3)/(2 beta) (G + G^T),
+// G[a][b] = d u_a / d x_b.
+template <typename T>
+__device__ __forceinline__ void pressure_tensor(T rho, const T (&u)[3], const T (&G)[9], T beta, T (&Pi)[6]) {
+  const T k = rho * T(1.0 / 3.0) / (T(2) * beta);
+  const T r3 = rho * T(1.0 / 3.0);
+  Pi[0] = r3 + rho * u[0] * u[0] - k * T(2) * G[0];
+  Pi[1] = r3 + rho * u[1] * u[1] - k * T(2) * G[4];
+  Pi[2] = r3 + rho * u[2] * u[2] - k * T(2) * G[8];
+  Pi[3] = rho * u[0] * u[1] - k * (G[1] + G[3]);
+  Pi[4] = rho * u[0] * u[2] - k * (G[2] + G[6]);
+  Pi[5] = rho * u[1] * u[2] - k * (G[5] + G[7]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Bodies as seen by kernels: kinematics evaluated on the host (FP64) at t and t+1.
+struct BodyDev {
+  int32_t kind;
+  int32_t pad;
+  double c0[3];      // centre at t
+  double c1[3];      // centre at t+1
+  double U0[3];      // velocity at t
+  double U1[3];      // velocity at t+1
+  double r2;         // radius^2
+  double radius;
+  double n[3];       // plane normal
+  double omega[3];
+};
+
+struct Bodies {
+  int32_t nb;
+  int32_t pad;
+  BodyDev b[ELBM_MAX_BODIES];
+};
+
+// Strictly-inside test (FP64, operations in the written order, no contraction).
+__host__ __device__ inline bool inside_body(const BodyDev& b, const double* c, double x, double y, double z) {
+#pragma clang fp contract(off)
+  if (b.kind == ELBM_BODY_SPHERE) {
+    const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+    double d2 = dx * dx;
+    d2 = d2 + dy * dy;
+    d2 = d2 + dz * dz;
+    return d2 < b.r2;
+  }
+  double s = b.n[0] * (x - c[0]);
+  s = s + b.n[1] * (y - c[1]);
+  s = s + b.n[2] * (z - c[2]);
+  return s < 0.0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Device-resident counters.
+struct DevCounters {
+  uint32_t fix_count;     // nodes queued for FP64 recomputation this step
+  uint32_t fix_ticket;    // last-block ticket of the fix-up kernel
+  uint32_t fix_total;     // nodes recomputed during the last step (copied at the end)
+  uint32_t dyn_count;     // dynamic boundary nodes this step
+  uint32_t overflow;      // boundary list overflowed (sticky)
+  uint32_t pad[3];
+};
+
+struct Box {
+  int lo[3];
+  int n[3];
+  __host__ __device__ long count() const { return (long)n[0] * n[1] * n[2]; }
+};
+
+}  // namespace elbm
+
+// ---------------------------------------------------------------------------------------------
+// The context behind the C ABI.
+struct elbm_ctx {
+  elbm_params p;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  int64_t N;
+  double beta;
+  double fp64_thr;
+  // carved fields (device)
+  void* pop[2];
+  int cur;                 // pop[cur] holds A^t
+  uint8_t* flags;          // N (geometry only)
+  float* macro;            // 4 N: U (3 N) then R (N) (geometry only)
+  int32_t* blist;          // boundary list (geometry only)
+  int64_t blist_cap;
+  int64_t n_static;        // static part (channel inlet face, or all entries for static geometry)
+  double* brec;            // per-list-entry force records [cap][nb][6]
+  double* ring;            // [force_ring][MAX_BODIES][6]
+  int32_t* fix_list;       // N
+  elbm::DevCounters* cnt;
+  double* scratch64;       // small FP64 scratch (force sums)
+  const float* bodyforce;
+  // geometry state
+  int32_t nb;
+  elbm_body bodies[ELBM_MAX_BODIES];
+  bool moving;
+  int64_t t;
+  char err[256];
+  // sweep timing (HIP events around each bulk-sweep launch)
+  bool timing;
+  hipEvent_t* ev;
+  int64_t ev_cap, ev_used;
+};
+
+namespace elbm {
+// kernel launchers (defined in sweep.hip / geometry.hip)
+hipError_t launch_sweep(elbm_ctx* c);
+hipError_t launch_fixup(elbm_ctx* c);
+hipError_t launch_init_eq(elbm_ctx* c, const double* rho, const double* u);
+hipError_t launch_write_pop(elbm_ctx* c, const double* src);
+hipError_t launch_read_pop(elbm_ctx* c, double* dst);
+hipError_t launch_collide_nodes(const float* fin, float* fout, float* gam, const float* F, int64_t n, double beta,
+                                double thr, hipStream_t s);
+hipError_t geometry_init(elbm_ctx* c);
+hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd);
+hipError_t launch_boundary(elbm_ctx* c, const Bodies& bd);
+hipError_t launch_force_reduce(elbm_ctx* c);
+void host_kinematics(const elbm_body& b, double t, double c[3], double U[3]);
+Bodies make_bodies(const elbm_ctx* c, double t);
+}  // namespace elbm

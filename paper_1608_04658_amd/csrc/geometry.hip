@@ -1,0 +1,702 @@
+// geometry.hip -- moving-wall boundary treatment of the KBC step on gfx950 (Sec. III):
+// solid masks, the compacted list of boundary and refill nodes, the previous-step macroscopic
+// field, reconstruction of the missing populations with Grad's distribution at target values
+// (eqs. grad, pressure, pressure2), refill of uncovered nodes, and the momentum-exchange force
+// (Sec. IV.A).
+//
+// The boundary work touches a few thousand nodes per step.  It runs in its own kernels over a
+// compacted node list so that the bulk sweep keeps its register budget and its wavefronts stay
+// convergent; the bulk sweep skips every flagged node.  Force sums are deterministic: each list
+// entry writes its own FP64 record and a separate kernel reduces the records in list order.
+#include <math.h>
+#include <stdio.h>
+
+#include "elbm_internal.hpp"
+
+namespace elbm {
+
+constexpr int BOX_MARGIN = 5;
+
+// ---------------------------------------------------------------------------------------------
+// Host kinematics, FP64, in the order written in elbm.h.
+void host_kinematics(const elbm_body& b, double t, double c[3], double U[3]) {
+#pragma clang fp contract(off)
+  double sn = 0.0, cs = 0.0, om = 0.0;
+  if (b.period != 0.0) {
+    const double ph = ((2.0 * M_PI) * t) / b.period;
+    sn = sin(ph);
+    cs = cos(ph);
+    om = (2.0 * M_PI) / b.period;
+  }
+  for (int a = 0; a < 3; ++a) {
+    c[a] = b.center[a] + (b.amp * sn) * b.dir[a] + b.vel[a] * t;
+    U[a] = (b.amp * om * cs) * b.dir[a] + b.vel[a];
+  }
+}
+
+Bodies make_bodies(const elbm_ctx* c, double t) {
+  Bodies bd;
+  bd.nb = c->nb;
+  bd.pad = 0;
+  for (int k = 0; k < c->nb; ++k) {
+    const elbm_body& b = c->bodies[k];
+    BodyDev& d = bd.b[k];
+    d.kind = b.kind;
+    d.pad = 0;
+    host_kinematics(b, t, d.c0, d.U0);
+    host_kinematics(b, t + 1.0, d.c1, d.U1);
+    d.radius = b.radius;
+    d.r2 = b.radius * b.radius;
+    for (int a = 0; a < 3; ++a) {
+      d.n[a] = b.normal[a];
+      d.omega[a] = b.omega[a];
+    }
+  }
+  for (int k = c->nb; k < ELBM_MAX_BODIES; ++k) bd.b[k] = BodyDev{};
+  return bd;
+}
+
+// Axis-aligned box covering every body at t and t+1 plus a margin (the whole axis when the box
+// would cross a periodic face, or for planes not normal to an axis).
+static Box union_box(const elbm_ctx* c, const Bodies& bd) {
+  const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  bool full[3] = {false, false, false};
+  for (int k = 0; k < bd.nb; ++k) {
+    const BodyDev& b = bd.b[k];
+    if (b.kind == ELBM_BODY_SPHERE) {
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fmin(lo[a], fmin(b.c0[a], b.c1[a]) - b.radius - BOX_MARGIN);
+        hi[a] = fmax(hi[a], fmax(b.c0[a], b.c1[a]) + b.radius + BOX_MARGIN);
+      }
+    } else {
+      int axis = -1;
+      for (int a = 0; a < 3; ++a)
+        if (fabs(b.n[a]) == 1.0) axis = a;
+      for (int a = 0; a < 3; ++a) {
+        if (a == axis) {
+          lo[a] = fmin(lo[a], fmin(b.c0[a], b.c1[a]) - BOX_MARGIN);
+          hi[a] = fmax(hi[a], fmax(b.c0[a], b.c1[a]) + BOX_MARGIN);
+        } else {
+          full[a] = true;
+        }
+      }
+    }
+  }
+  Box box;
+  for (int a = 0; a < 3; ++a) {
+    int l = (int)floor(lo[a]), h = (int)ceil(hi[a]);
+    const bool periodic = !(a == 0 && c->p.bc_x == ELBM_BC_CHANNEL);
+    if (full[a] || bd.nb == 0) {
+      l = 0;
+      h = dims[a] - 1;
+    } else if (l < 0 || h > dims[a] - 1) {
+      if (periodic) {
+        l = 0;
+        h = dims[a] - 1;
+      } else {
+        l = l < 0 ? 0 : l;
+        h = h > dims[a] - 1 ? dims[a] - 1 : h;
+      }
+    }
+    box.lo[a] = l;
+    box.n[a] = h - l + 1;
+    if (box.n[a] < 1) box.n[a] = 1;
+  }
+  return box;
+}
+
+static Box full_box(const elbm_ctx* c) {
+  Box b;
+  b.lo[0] = b.lo[1] = b.lo[2] = 0;
+  b.n[0] = c->p.nx;
+  b.n[1] = c->p.ny;
+  b.n[2] = c->p.nz;
+  return b;
+}
+
+struct GeoArgs {
+  uint8_t* flags;
+  int32_t nx, ny, nz;
+  int32_t channel;
+  Box box;
+};
+
+__device__ __forceinline__ void box_node(const Box& b, long idx, int& x, int& y, int& z) {
+  x = b.lo[0] + (int)(idx % b.n[0]);
+  y = b.lo[1] + (int)((idx / b.n[0]) % b.n[1]);
+  z = b.lo[2] + (int)(idx / ((long)b.n[0] * b.n[1]));
+}
+
+__device__ __forceinline__ int first_body(const Bodies& bd, bool at_t1, double x, double y, double z) {
+  for (int k = 0; k < bd.nb; ++k)
+    if (inside_body(bd.b[k], at_t1 ? bd.b[k].c1 : bd.b[k].c0, x, y, z)) return k;
+  return -1;
+}
+
+// Masks at a single time level (set-up): solid at t and "t+1" alike.
+__global__ void k_flags_init(GeoArgs g, Bodies bd) {
+  const long total = g.box.count();
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    box_node(g.box, idx, x, y, z);
+    const long n = ((long)z * g.ny + y) * g.nx + x;
+    const bool s = first_body(bd, false, x, y, z) >= 0;
+    g.flags[n] = s ? (FL_SOLID | FL_SOLID_PREV) : 0;
+  }
+}
+
+// Advance masks t -> t+1 inside the box: previous <- current, current <- inside at t+1.
+__global__ void k_flags_update(GeoArgs g, Bodies bd) {
+  const long total = g.box.count();
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    box_node(g.box, idx, x, y, z);
+    const long n = ((long)z * g.ny + y) * g.nx + x;
+    const uint8_t old = g.flags[n];
+    const bool s1 = first_body(bd, true, x, y, z) >= 0;
+    uint8_t nf = old & (uint8_t)~(FL_SOLID | FL_SOLID_PREV);
+    if (old & FL_SOLID) nf |= FL_SOLID_PREV;
+    if (s1) nf |= FL_SOLID;
+    g.flags[n] = nf;
+  }
+}
+
+// Periodic index for any offset (stencils reach +-2, lattices may be 1 or 2 nodes thick).
+__device__ __forceinline__ int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+// Missing set Dbar is non-empty (a source x - c_i is solid at t+1, or lies through the inlet) or
+// the node was solid at t (refill).
+__device__ __forceinline__ bool is_boundary(const GeoArgs& g, int x, int y, int z, uint8_t fl) {
+  if (fl & FL_SOLID) return false;
+  if (fl & FL_SOLID_PREV) return true;
+  for (int i = 0; i < 27; ++i) {
+    if (i == 13) continue;
+    int sx = x - cx(i);
+    if (g.channel) {
+      if (sx < 0) return true;
+      if (sx >= g.nx) sx = g.nx - 1;
+    } else {
+      sx = wrap(sx, g.nx);
+    }
+    const int sy = wrap(y - cy(i), g.ny), sz = wrap(z - cz(i), g.nz);
+    if (g.flags[((long)sz * g.ny + sy) * g.nx + sx] & FL_SOLID) return true;
+  }
+  return false;
+}
+
+// Single-workgroup ordered compaction of the boundary nodes of a box (deterministic order: the
+// box's linear order).  Sets FL_SPECIAL on listed nodes and clears it on the others; with
+// skip_inlet the x = 0 face keeps its flags and is not listed (it sits in the static part).
+constexpr int SCAN_THREADS = 1024;
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan(GeoArgs g, int32_t* list, int64_t base, int64_t cap,
+                                                       uint32_t* count_out, uint32_t* overflow, int skip_inlet) {
+  __shared__ uint32_t sh[SCAN_THREADS];
+  const long total = g.box.count();
+  uint32_t running = 0;
+  for (long start = 0; start < total; start += SCAN_THREADS) {
+    const long idx = start + threadIdx.x;
+    uint32_t isb = 0;
+    long n = 0;
+    if (idx < total) {
+      int x, y, z;
+      box_node(g.box, idx, x, y, z);
+      n = ((long)z * g.ny + y) * g.nx + x;
+      if (!(skip_inlet && g.channel && x == 0)) {
+        const uint8_t fl = g.flags[n];
+        isb = is_boundary(g, x, y, z, fl) ? 1u : 0u;
+        g.flags[n] = isb ? (uint8_t)(fl | FL_SPECIAL) : (uint8_t)(fl & ~FL_SPECIAL);
+      }
+    }
+    sh[threadIdx.x] = isb;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+      const uint32_t v = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0u;
+      __syncthreads();
+      sh[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const uint32_t incl = sh[threadIdx.x];
+    const uint32_t tot = sh[SCAN_THREADS - 1];
+    if (isb) {
+      const int64_t pos = base + running + incl - 1;
+      if (pos < cap) list[pos] = (int32_t)n;
+    }
+    running += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *count_out = running;
+    if (base + (int64_t)running > cap) *overflow = 1u;
+  }
+}
+
+// Previous-step macroscopic field U^t, R^t on a box: moments of A^t with U = (j - F/2)/rho at
+// nodes fluid at t; rigid-body velocity (R = rho0) at nodes solid at t.
+template <int S>
+__global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, float* macro, const float* F, Box box,
+                        int32_t nx, int32_t ny, int64_t N, double rho0, Bodies bd) {
+  using C = Codec<S>;
+  const long total = box.count();
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    box_node(box, idx, x, y, z);
+    const long n = ((long)z * ny + y) * nx + x;
+    float U[3], R;
+    if (flags[n] & FL_SOLID_PREV) {
+      int k = first_body(bd, false, x, y, z);
+      if (k < 0) k = 0;
+      const BodyDev& b = bd.b[k];
+      const double r[3] = {x - b.c0[0], y - b.c0[1], z - b.c0[2]};
+      U[0] = (float)(b.U0[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
+      U[1] = (float)(b.U0[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
+      U[2] = (float)(b.U0[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+      R = (float)rho0;
+    } else {
+      float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        const float v = C::load(A + i * N + n, wf(i));
+        rho += v;
+        jx += cx(i) * v;
+        jy += cy(i) * v;
+        jz += cz(i) * v;
+      }
+      if (F) {
+        jx -= 0.5f * F[n];
+        jy -= 0.5f * F[N + n];
+        jz -= 0.5f * F[2 * N + n];
+      }
+      U[0] = jx / rho;
+      U[1] = jy / rho;
+      U[2] = jz / rho;
+      R = rho;
+    }
+    macro[n] = U[0];
+    macro[N + n] = U[1];
+    macro[2 * N + n] = U[2];
+    macro[3 * N + n] = R;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+struct BArgs {
+  const void* A;
+  void* B;
+  const uint8_t* flags;
+  const float* macro;
+  const float* F;
+  const int32_t* list;
+  const uint32_t* dyn_count;
+  double* brec;
+  int64_t n_static;
+  int64_t cap;
+  int32_t moving;
+  int32_t nx, ny, nz;
+  int64_t N;
+  int32_t channel;
+  int32_t fp64;
+  int32_t stream_only;
+  float beta, inv_beta, thr;
+  double rho0;
+  double u_in[3];
+};
+
+__device__ __forceinline__ long node_at(const BArgs& a, int x, int y, int z) {
+  return ((long)z * a.ny + y) * a.nx + x;
+}
+
+// Node x + d, or -1 when it does not exist (outside [0, nx) in channel mode).
+__device__ __forceinline__ long neighbour(const BArgs& a, int x, int y, int z, int dx, int dy, int dz) {
+  int X = x + dx;
+  if (a.channel) {
+    if (X < 0 || X >= a.nx) return -1;
+  } else {
+    X = wrap(X, a.nx);
+  }
+  return node_at(a, X, wrap(y + dy, a.ny), wrap(z + dz, a.nz));
+}
+
+// Velocity gradient by finite differences on U^t (Sec. III), G[3a+b] = d u_a / d x_b.  Per axis:
+// central if both neighbours are usable (exist and fluid at t+1), else second-order one-sided
+// (forward side first), else first-order one-sided, else 0.
+__device__ void grad_u(const BArgs& a, int x, int y, int z, long n0, float (&G)[9]) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int e0 = b == 0, e1 = b == 1, e2 = b == 2;
+    const long p1 = neighbour(a, x, y, z, e0, e1, e2), p2 = neighbour(a, x, y, z, 2 * e0, 2 * e1, 2 * e2);
+    const long m1 = neighbour(a, x, y, z, -e0, -e1, -e2), m2 = neighbour(a, x, y, z, -2 * e0, -2 * e1, -2 * e2);
+    const bool op1 = p1 >= 0 && !(a.flags[p1] & FL_SOLID), op2 = p2 >= 0 && !(a.flags[p2] & FL_SOLID);
+    const bool om1 = m1 >= 0 && !(a.flags[m1] & FL_SOLID), om2 = m2 >= 0 && !(a.flags[m2] & FL_SOLID);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float* U = a.macro + c * a.N;
+      float d;
+      if (op1 && om1) d = 0.5f * (U[p1] - U[m1]);
+      else if (op1 && op2) d = 0.5f * (-3.f * U[n0] + 4.f * U[p1] - U[p2]);
+      else if (om1 && om2) d = 0.5f * (3.f * U[n0] - 4.f * U[m1] + U[m2]);
+      else if (op1) d = U[p1] - U[n0];
+      else if (om1) d = U[n0] - U[m1];
+      else d = 0.f;
+      G[3 * c + b] = d;
+    }
+  }
+}
+
+// Geometry of boundary link i (i in Dbar) at node (x,y,z): link fraction q, wall velocity u_w and
+// owning body (-1 for the inlet wall at x = -1/2).  q is the ray parameter where x - s c_i meets
+// the surface (FP64): sphere (|d|^2 - R^2)/(d.c_i + sqrt((d.c_i)^2 - |c_i|^2 (|d|^2 - R^2))),
+// plane n.d / n.c_i, d = x - centre(t+1).
+__device__ void link_geometry(const BArgs& a, const Bodies& bd, int i, int x, int y, int z, double& q, double (&uw)[3],
+                              int& kb) {
+  int sx = x - cx(i);
+  if (a.channel && sx < 0) {
+    kb = -1;
+    q = ((double)x + 0.5) / (double)cx(i);
+    uw[0] = a.u_in[0];
+    uw[1] = a.u_in[1];
+    uw[2] = a.u_in[2];
+    return;
+  }
+  if (a.channel) sx = sx >= a.nx ? a.nx - 1 : sx;
+  else sx = wrap(sx, a.nx);
+  const int sy = wrap(y - cy(i), a.ny), sz = wrap(z - cz(i), a.nz);
+  kb = first_body(bd, true, sx, sy, sz);
+  if (kb < 0) kb = 0;
+  const BodyDev& b = bd.b[kb];
+  const double v[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+  const double d[3] = {x - b.c1[0], y - b.c1[1], z - b.c1[2]};
+  if (b.kind == ELBM_BODY_SPHERE) {
+    const double dv = d[0] * v[0] + d[1] * v[1] + d[2] * v[2];
+    const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] - b.r2;
+    double disc = dv * dv - vv * dd;
+    disc = disc < 0.0 ? 0.0 : disc;
+    q = dd / (dv + sqrt(disc));
+  } else {
+    const double nd = b.n[0] * d[0] + b.n[1] * d[1] + b.n[2] * d[2];
+    const double nv = b.n[0] * v[0] + b.n[1] * v[1] + b.n[2] * v[2];
+    q = nd / nv;
+  }
+  const double r[3] = {d[0] - q * v[0], d[1] - q * v[1], d[2] - q * v[2]};  // x_w - centre
+  uw[0] = b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]);
+  uw[1] = b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]);
+  uw[2] = b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]);
+}
+
+template <int S, bool FORCE>
+__global__ __launch_bounds__(128) void k_boundary(const BArgs a, const Bodies bd) {
+  using C = Codec<S>;
+  using E = typename C::E;
+  const E* __restrict__ A = (const E*)a.A;
+  E* __restrict__ B = (E*)a.B;
+  int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
+  if (count > a.cap) count = a.cap;
+  const int nb = bd.nb;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
+    const long n = a.list[k];
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    double* rec = a.brec + k * nb * 6;
+    for (int j = 0; j < nb * 6; ++j) rec[j] = 0.0;
+    const uint8_t fl = a.flags[n];
+    float f[27];
+    if (fl & FL_SOLID_PREV) {
+      // refill of an uncovered node (Sec. III)
+      int kb = first_body(bd, false, x, y, z);
+      if (kb < 0) kb = 0;
+      const BodyDev& b = bd.b[kb];
+      const double r[3] = {x - b.c1[0], y - b.c1[1], z - b.c1[2]};
+      float uw[3];
+      uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
+      uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
+      uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+      float rs = 0.f;
+      int m = 0;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        if (i == 13) continue;
+        const long nn = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
+        if (nn < 0 || (a.flags[nn] & (FL_SOLID | FL_SOLID_PREV))) continue;
+        rs += a.macro[3 * a.N + nn];
+        ++m;
+      }
+      const float ravg = m ? rs / (float)m : (float)a.rho0;
+      float G[9], Pi[6];
+      grad_u(a, x, y, z, n, G);
+      pressure_tensor(ravg, uw, G, a.beta, Pi);
+#pragma unroll
+      for (int i = 0; i < 27; ++i) f[i] = grad_pop(i, ravg, uw, Pi);
+    } else {
+      // missing populations at a wall (Sec. III)
+      uint32_t dmask = 0;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        int sx = x - cx(i);
+        if (a.channel && sx < 0) {
+          dmask |= 1u << i;
+          f[i] = 0.f;
+          continue;
+        }
+        if (a.channel) sx = sx >= a.nx ? a.nx - 1 : sx;
+        else sx = wrap(sx, a.nx);
+        const long ns = node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
+        if (a.flags[ns] & FL_SOLID) {
+          dmask |= 1u << i;
+          f[i] = 0.f;
+          continue;
+        }
+        f[i] = C::load(A + i * a.N + ns, wf(i));
+      }
+      if (dmask) {
+        float ut[3] = {0.f, 0.f, 0.f};
+        float rstat = 0.f, rdyn = 0.f;
+        int nD = 0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+          if (!((dmask >> i) & 1u)) {
+            rstat += f[i];
+            continue;
+          }
+          ++nD;
+          rstat += C::load(A + opp(i) * a.N + n, wf(opp(i)));
+          double q, uw[3];
+          int kb;
+          link_geometry(a, bd, i, x, y, z, q, uw, kb);
+          const long nf = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
+          float uf[3];
+          if (nf >= 0 && !(a.flags[nf] & FL_SOLID)) {
+            uf[0] = a.macro[nf];
+            uf[1] = a.macro[a.N + nf];
+            uf[2] = a.macro[2 * a.N + nf];
+          } else {
+            uf[0] = (float)uw[0];
+            uf[1] = (float)uw[1];
+            uf[2] = (float)uw[2];
+          }
+          const float qf = (float)q, inv = 1.f / (1.f + qf);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) ut[c] += (qf * uf[c] + (float)uw[c]) * inv;
+          rdyn += (float)(6.0 * wd(i) * a.rho0 * (cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]));
+        }
+        const float invn = 1.f / (float)nD;
+        ut[0] *= invn;
+        ut[1] *= invn;
+        ut[2] *= invn;
+        const float rt = rstat + rdyn;
+        float G[9], Pi[6];
+        grad_u(a, x, y, z, n, G);
+        pressure_tensor(rt, ut, G, a.beta, Pi);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+          if (!((dmask >> i) & 1u)) continue;
+          const float fs = grad_pop(i, rt, ut, Pi);
+          f[i] = fs;
+          double q, uw[3];
+          int kb;
+          link_geometry(a, bd, i, x, y, z, q, uw, kb);
+          if (kb < 0) continue;
+          // Galilean-invariant momentum exchange of the link
+          const double fo = (double)C::load(A + opp(i) * a.N + n, wf(opp(i)));
+          const double c[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+          double dF[3];
+#pragma unroll
+          for (int e = 0; e < 3; ++e) dF[e] = fo * (-c[e] - uw[e]) - (double)fs * (c[e] - uw[e]);
+          const BodyDev& b = bd.b[kb];
+          const double r[3] = {x - q * c[0] - b.c1[0], y - q * c[1] - b.c1[1], z - q * c[2] - b.c1[2]};
+          double* rb = rec + kb * 6;
+          rb[0] += dF[0];
+          rb[1] += dF[1];
+          rb[2] += dF[2];
+          rb[3] += r[1] * dF[2] - r[2] * dF[1];
+          rb[4] += r[2] * dF[0] - r[0] * dF[2];
+          rb[5] += r[0] * dF[1] - r[1] * dF[0];
+        }
+      }
+    }
+    if (a.stream_only) {
+#pragma unroll
+      for (int i = 0; i < 27; ++i) C::store(B + i * a.N + n, f[i], wf(i));
+      continue;
+    }
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    if (FORCE) {
+      Fx = a.F[n];
+      Fy = a.F[a.N + n];
+      Fz = a.F[2 * a.N + n];
+    }
+    double d[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) d[i] = (double)f[i];
+    const KbcOut<float> r = kbc_collide<float, FORCE>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
+    if (a.fp64 && !(r.b >= a.thr * r.rho)) {
+      kbc_collide<double, FORCE>(d, (double)a.beta, 1.0 / (double)a.beta, Fx, Fy, Fz);
+#pragma unroll
+      for (int i = 0; i < 27; ++i) f[i] = (float)d[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) C::store(B + i * a.N + n, f[i], wf(i));
+  }
+}
+
+// Deterministic per-body force sum: one workgroup per (body, component), strided partial sums in
+// a fixed order followed by a fixed tree.
+__global__ __launch_bounds__(256) void k_force_reduce(const double* brec, const uint32_t* dyn_count, int64_t n_static,
+                                                      int64_t cap, int32_t moving, int32_t nb, double* out) {
+  __shared__ double sh[256];
+  const int kb = blockIdx.x / 6, comp = blockIdx.x % 6;
+  int64_t count = n_static + (moving ? (int64_t)*dyn_count : 0);
+  if (count > cap) count = cap;
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < count; k += 256) s += brec[k * nb * 6 + kb * 6 + comp];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[kb * 6 + comp] = sh[0];
+}
+
+// ---------------------------------------------------------------------------------------------
+static dim3 grid_for(long n) {
+  long b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+static GeoArgs geo_args(elbm_ctx* c, const Box& box) {
+  GeoArgs g;
+  g.flags = c->flags;
+  g.nx = c->p.nx;
+  g.ny = c->p.ny;
+  g.nz = c->p.nz;
+  g.channel = c->p.bc_x == ELBM_BC_CHANNEL;
+  g.box = box;
+  return g;
+}
+
+template <int S>
+static void macro_launch(elbm_ctx* c, const Box& box, const Bodies& bd) {
+  hipLaunchKernelGGL(k_macro<S>, grid_for(box.count()), dim3(256), 0, c->stream,
+                     (const typename Codec<S>::E*)c->pop[c->cur], (const uint8_t*)c->flags, c->macro, c->bodyforce, box,
+                     c->p.nx, c->p.ny, (int64_t)c->N, c->p.rho0, bd);
+}
+
+static void macro_box(elbm_ctx* c, const Box& box, const Bodies& bd) {
+  switch (c->p.storage) {
+    case ELBM_STORAGE_F32: macro_launch<ELBM_STORAGE_F32>(c, box, bd); break;
+    case ELBM_STORAGE_F16: macro_launch<ELBM_STORAGE_F16>(c, box, bd); break;
+    default: macro_launch<ELBM_STORAGE_BF16>(c, box, bd);
+  }
+}
+
+// Set-up at the current time level: masks everywhere, then the static part of the boundary list
+// (all boundary nodes for fixed geometry; only the inlet face when bodies move).
+hipError_t geometry_init(elbm_ctx* c) {
+  const Bodies bd = make_bodies(c, (double)c->t);
+  const Box fb = full_box(c);
+  GeoArgs g = geo_args(c, fb);
+  hipLaunchKernelGGL(k_flags_init, grid_for(fb.count()), dim3(256), 0, c->stream, g, bd);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  Box sb = fb;
+  const bool channel = c->p.bc_x == ELBM_BC_CHANNEL;
+  if (c->moving) {
+    if (channel) {
+      sb.n[0] = 1;  // inlet face only
+    } else {
+      c->n_static = 0;
+      return hipSuccess;
+    }
+  } else if (c->nb == 0 && !channel) {
+    c->n_static = 0;
+    return hipSuccess;
+  }
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, geo_args(c, sb), c->blist, (int64_t)0,
+                     c->blist_cap, &c->cnt->dyn_count, &c->cnt->overflow, 0);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  uint32_t n = 0;
+  e = hipMemcpyAsync(&n, &c->cnt->dyn_count, sizeof n, hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  c->n_static = (int64_t)n;
+  return hipSuccess;
+}
+
+// Per step, before the sweep: masks at t+1 and the dynamic list (moving bodies), then U^t, R^t
+// around the bodies and on the inlet slab.
+hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd) {
+  const bool channel = c->p.bc_x == ELBM_BC_CHANNEL;
+  if (c->nb == 0 && !channel) return hipSuccess;
+  Box ub = union_box(c, bd);
+  if (c->moving) {
+    GeoArgs g = geo_args(c, ub);
+    hipLaunchKernelGGL(k_flags_update, grid_for(ub.count()), dim3(256), 0, c->stream, g, bd);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, g, c->blist, c->n_static, c->blist_cap,
+                       &c->cnt->dyn_count, &c->cnt->overflow, 1);
+  }
+  if (c->nb > 0) macro_box(c, ub, bd);
+  if (channel) {
+    Box slab = full_box(c);
+    slab.n[0] = c->p.nx < 3 ? c->p.nx : 3;
+    macro_box(c, slab, bd);
+  }
+  return hipGetLastError();
+}
+
+template <int S>
+static void boundary_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd) {
+  const dim3 g(512), b(128);
+  if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true>), g, b, 0, c->stream, a, bd);
+  else hipLaunchKernelGGL((k_boundary<S, false>), g, b, 0, c->stream, a, bd);
+}
+
+hipError_t launch_boundary(elbm_ctx* c, const Bodies& bd) {
+  const bool channel = c->p.bc_x == ELBM_BC_CHANNEL;
+  if (c->nb == 0 && !channel) return hipSuccess;
+  BArgs a;
+  a.A = c->pop[c->cur];
+  a.B = c->pop[c->cur ^ 1];
+  a.flags = c->flags;
+  a.macro = c->macro;
+  a.F = c->bodyforce;
+  a.list = c->blist;
+  a.dyn_count = &c->cnt->dyn_count;
+  a.brec = c->brec;
+  a.n_static = c->n_static;
+  a.cap = c->blist_cap;
+  a.moving = c->moving ? 1 : 0;
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.nz = c->p.nz;
+  a.N = c->N;
+  a.channel = channel ? 1 : 0;
+  a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64);
+  a.stream_only = (c->p.flags & ELBM_FLAG_STREAM_ONLY) != 0;
+  a.beta = (float)c->beta;
+  a.inv_beta = (float)(1.0 / c->beta);
+  a.thr = (float)c->fp64_thr;
+  a.rho0 = c->p.rho0;
+  for (int e = 0; e < 3; ++e) a.u_in[e] = c->p.u_inlet[e];
+  switch (c->p.storage) {
+    case ELBM_STORAGE_F32: boundary_launch<ELBM_STORAGE_F32>(c, a, bd); break;
+    case ELBM_STORAGE_F16: boundary_launch<ELBM_STORAGE_F16>(c, a, bd); break;
+    default: boundary_launch<ELBM_STORAGE_BF16>(c, a, bd);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_force_reduce(elbm_ctx* c) {
+  if (c->nb == 0) return hipSuccess;
+  const int slot = (int)((c->t + 1) % c->p.force_ring);
+  double* out = c->ring + (size_t)slot * ELBM_MAX_BODIES * 6;
+  hipLaunchKernelGGL(k_force_reduce, dim3(c->nb * 6), dim3(256), 0, c->stream, (const double*)c->brec,
+                     (const uint32_t*)&c->cnt->dyn_count, c->n_static, c->blist_cap, (int32_t)(c->moving ? 1 : 0),
+                     (int32_t)c->nb, out);
+  return hipGetLastError();
+}
+
+}  // namespace elbm

@@ -1,0 +1,339 @@
+// sweep.hip -- the fused bulk sweep of the D3Q27 KBC step on gfx950: pull streaming, moments,
+// entropic equilibrium, KBC collision with the per-node stabiliser, store (Sec. II,
+// eqs. kineticEq, kbc_relax, feq_min), plus the FP64 recomputation of near-equilibrium nodes.
+//
+// One thread per node, x fastest inside a wavefront: every load and store of a population
+// array is a contiguous 64-lane access (the +-x shifted loads straddle one extra cache line,
+// which the neighbouring lanes of the same workgroup bring into L2).  Population arrays are
+// structure-of-arrays, so each direction streams through HBM exactly once per step.
+#include "elbm_internal.hpp"
+
+namespace elbm {
+
+struct SweepArgs {
+  const void* A;
+  void* B;
+  const uint8_t* flags;
+  const float* F;
+  uint32_t* fix_list;
+  DevCounters* cnt;
+  int32_t nx, ny, nz;
+  uint32_t N;
+  float beta, inv_beta, thr;
+  int32_t channel;
+  int32_t fp64;
+  int32_t stream_only;
+};
+
+// Source coordinates of the pull for each velocity component: xs[cx+1] = x - cx and the 9 row
+// offsets rs[3 (cz+1) + (cy+1)] = ((z - cz) ny + (y - cy)) nx, periodic in y and z; periodic in x
+// or, in channel mode, clamped (the outlet copy; x = 0 is never gathered by the bulk path).
+__device__ __forceinline__ void gather_offsets(int x, int y, int z, const SweepArgs& a, uint32_t (&xs)[3],
+                                               uint32_t (&rs)[9]) {
+  if (a.channel) {
+    xs[0] = (uint32_t)min(x + 1, a.nx - 1);
+    xs[2] = (uint32_t)max(x - 1, 0);
+  } else {
+    xs[0] = (uint32_t)(x + 1 == a.nx ? 0 : x + 1);
+    xs[2] = (uint32_t)(x == 0 ? a.nx - 1 : x - 1);
+  }
+  xs[1] = (uint32_t)x;
+  const int ym = (y + 1 == a.ny) ? 0 : y + 1, yp = (y == 0) ? a.ny - 1 : y - 1;
+  const int zm = (z + 1 == a.nz) ? 0 : z + 1, zp = (z == 0) ? a.nz - 1 : z - 1;
+  const int ys[3] = {ym, y, yp};  // source y for cy = -1, 0, +1
+  const int zs[3] = {zm, z, zp};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) rs[3 * k + j] = (uint32_t)((zs[k] * a.ny + ys[j]) * a.nx);
+}
+
+template <int S, bool FLAGS, bool FORCE>
+__global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
+  using C = Codec<S>;
+  using E = typename C::E;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  const uint32_t n = (uint32_t)((z * a.ny + y) * a.nx + x);
+  if (FLAGS) {
+    if (a.flags[n] & (FL_SOLID | FL_SPECIAL)) return;
+  }
+  uint32_t xs[3], rs[9];
+  gather_offsets(x, y, z, a, xs, rs);
+  const E* __restrict__ A = (const E*)a.A;
+  float f[27];
+#pragma unroll
+  for (int i = 0; i < 27; ++i) f[i] = C::load(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]), wf(i));
+  if (!a.stream_only) {
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    if (FORCE) {
+      Fx = a.F[n];
+      Fy = a.F[a.N + n];
+      Fz = a.F[2 * (size_t)a.N + n];
+    }
+    const KbcOut<float> r = kbc_collide<float, FORCE>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
+    if (a.fp64 && !(r.b >= a.thr * r.rho)) {
+      const uint32_t k = atomicAdd(&a.cnt->fix_count, 1u);
+      a.fix_list[k] = n;
+    }
+  }
+  E* __restrict__ B = (E*)a.B;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) C::store(B + (size_t)i * a.N + n, f[i], wf(i));
+}
+
+// FP64 recomputation of the nodes whose <dh|dh> fell below the FP32 threshold: the same gather
+// and the same collision in double precision, rounded once on store.  The last block to finish
+// resets the queue, so the kernel can be launched every step without a host round trip.
+template <int S, bool FORCE>
+__global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
+  using C = Codec<S>;
+  using E = typename C::E;
+  const uint32_t count = __atomic_load_n(&a.cnt->fix_count, __ATOMIC_RELAXED);
+  const E* __restrict__ A = (const E*)a.A;
+  E* __restrict__ B = (E*)a.B;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
+    const uint32_t n = a.fix_list[k];
+    const int x = (int)(n % (uint32_t)a.nx);
+    const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
+    const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
+    uint32_t xs[3], rs[9];
+    gather_offsets(x, y, z, a, xs, rs);
+    double f[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i)
+      f[i] = (double)C::load(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]), wf(i));
+    double Fx = 0, Fy = 0, Fz = 0;
+    if (FORCE) {
+      Fx = a.F[n];
+      Fy = a.F[a.N + n];
+      Fz = a.F[2 * (size_t)a.N + n];
+    }
+    const double beta = (double)a.beta;
+    kbc_collide<double, FORCE>(f, beta, 1.0 / beta, Fx, Fy, Fz);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) C::store(B + (size_t)i * a.N + n, (float)f[i], wf(i));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t t = atomicAdd(&a.cnt->fix_ticket, 1u);
+    if (t == gridDim.x - 1) {
+      a.cnt->fix_total = count;
+      a.cnt->fix_count = 0;
+      a.cnt->fix_ticket = 0;
+      __threadfence();
+    }
+  }
+}
+
+static SweepArgs sweep_args(elbm_ctx* c) {
+  SweepArgs a;
+  a.A = c->pop[c->cur];
+  a.B = c->pop[c->cur ^ 1];
+  a.flags = c->flags;
+  a.F = c->bodyforce;
+  a.fix_list = (uint32_t*)c->fix_list;
+  a.cnt = c->cnt;
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.nz = c->p.nz;
+  a.N = (uint32_t)c->N;
+  a.beta = (float)c->beta;
+  a.inv_beta = (float)(1.0 / c->beta);
+  a.thr = (float)c->fp64_thr;
+  a.channel = c->p.bc_x == ELBM_BC_CHANNEL;
+  a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64) && !(c->p.flags & ELBM_FLAG_STREAM_ONLY);
+  a.stream_only = (c->p.flags & ELBM_FLAG_STREAM_ONLY) != 0;
+  return a;
+}
+
+// Block shape: the widest power of two <= 256 along x that divides nx (at least 32), the rest of
+// the 256 threads along y.
+static void sweep_shape(int nx, int ny, int nz, dim3& grid, dim3& block) {
+  int bx = 256;
+  while (bx > 32 && (nx % bx) != 0) bx >>= 1;
+  if (nx < bx) bx = 32;
+  const int by = 256 / bx;
+  block = dim3(bx, by, 1);
+  grid = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nz);
+}
+
+template <int S>
+static hipError_t sweep_s(elbm_ctx* c, const SweepArgs& a, dim3 g, dim3 b) {
+  const bool flags = c->flags != nullptr;
+  const bool force = c->bodyforce != nullptr;
+  if (flags && force) hipLaunchKernelGGL((k_sweep<S, true, true>), g, b, 0, c->stream, a);
+  else if (flags) hipLaunchKernelGGL((k_sweep<S, true, false>), g, b, 0, c->stream, a);
+  else if (force) hipLaunchKernelGGL((k_sweep<S, false, true>), g, b, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_sweep<S, false, false>), g, b, 0, c->stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(elbm_ctx* c) {
+  const SweepArgs a = sweep_args(c);
+  dim3 g, b;
+  sweep_shape(c->p.nx, c->p.ny, c->p.nz, g, b);
+  switch (c->p.storage) {
+    case ELBM_STORAGE_F32: return sweep_s<ELBM_STORAGE_F32>(c, a, g, b);
+    case ELBM_STORAGE_F16: return sweep_s<ELBM_STORAGE_F16>(c, a, g, b);
+    default: return sweep_s<ELBM_STORAGE_BF16>(c, a, g, b);
+  }
+}
+
+template <int S>
+static hipError_t fixup_s(elbm_ctx* c, const SweepArgs& a) {
+  const dim3 g(256), b(256);
+  if (c->bodyforce) hipLaunchKernelGGL((k_fixup<S, true>), g, b, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_fixup<S, false>), g, b, 0, c->stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fixup(elbm_ctx* c) {
+  const SweepArgs a = sweep_args(c);
+  if (!a.fp64) return hipSuccess;
+  switch (c->p.storage) {
+    case ELBM_STORAGE_F32: return fixup_s<ELBM_STORAGE_F32>(c, a);
+    case ELBM_STORAGE_F16: return fixup_s<ELBM_STORAGE_F16>(c, a);
+    default: return fixup_s<ELBM_STORAGE_BF16>(c, a);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Conversions between FP64 population arrays and the storage format.
+template <int S> __device__ __forceinline__ void store_d(typename Codec<S>::E* p, double v, int i);
+template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_F32>(float* p, double v, int) { *p = (float)v; }
+template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_F16>(_Float16* p, double v, int i) {
+  *p = (_Float16)(float)(v - wd(i));
+}
+template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_BF16>(uint16_t* p, double v, int i) {
+  *p = f32_to_bf16_rne((float)(v - wd(i)));
+}
+template <int S> __device__ __forceinline__ double load_d(const typename Codec<S>::E* p, int i);
+template <> __device__ __forceinline__ double load_d<ELBM_STORAGE_F32>(const float* p, int) { return (double)*p; }
+template <> __device__ __forceinline__ double load_d<ELBM_STORAGE_F16>(const _Float16* p, int i) {
+  return (double)(float)*p + wd(i);
+}
+template <> __device__ __forceinline__ double load_d<ELBM_STORAGE_BF16>(const uint16_t* p, int i) {
+  return (double)__uint_as_float(((uint32_t)*p) << 16) + wd(i);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_init_eq(typename Codec<S>::E* A, const double* rho, const double* u, int64_t N) {
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+    double fe[27];
+    feq_all(rho ? rho[n] : 1.0, u[n], u[N + n], u[2 * N + n], fe);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) store_d<S>(A + i * N + n, fe[i], i);
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_write_pop(typename Codec<S>::E* A, const double* src, int64_t N) {
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < 27; ++i) store_d<S>(A + i * N + n, src[i * N + n], i);
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_read_pop(const typename Codec<S>::E* A, double* dst, int64_t N) {
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < 27; ++i) dst[i * N + n] = load_d<S>(A + i * N + n, i);
+  }
+}
+
+static dim3 grid_for(int64_t N) {
+  int64_t b = (N + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+hipError_t launch_init_eq(elbm_ctx* c, const double* rho, const double* u) {
+  void* A = c->pop[c->cur];
+  switch (c->p.storage) {
+    case ELBM_STORAGE_F32:
+      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F32>, grid_for(c->N), dim3(256), 0, c->stream, (float*)A, rho, u, c->N);
+      break;
+    case ELBM_STORAGE_F16:
+      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F16>, grid_for(c->N), dim3(256), 0, c->stream, (_Float16*)A, rho, u, c->N);
+      break;
+    default:
+      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_BF16>, grid_for(c->N), dim3(256), 0, c->stream, (uint16_t*)A, rho, u, c->N);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_write_pop(elbm_ctx* c, const double* src) {
+  void* A = c->pop[c->cur];
+  switch (c->p.storage) {
+    case ELBM_STORAGE_F32:
+      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F32>, grid_for(c->N), dim3(256), 0, c->stream, (float*)A, src, c->N);
+      break;
+    case ELBM_STORAGE_F16:
+      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F16>, grid_for(c->N), dim3(256), 0, c->stream, (_Float16*)A, src, c->N);
+      break;
+    default:
+      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_BF16>, grid_for(c->N), dim3(256), 0, c->stream, (uint16_t*)A, src, c->N);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_read_pop(elbm_ctx* c, double* dst) {
+  const void* A = c->pop[c->cur];
+  switch (c->p.storage) {
+    case ELBM_STORAGE_F32:
+      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F32>, grid_for(c->N), dim3(256), 0, c->stream, (const float*)A, dst, c->N);
+      break;
+    case ELBM_STORAGE_F16:
+      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F16>, grid_for(c->N), dim3(256), 0, c->stream, (const _Float16*)A, dst,
+                         c->N);
+      break;
+    default:
+      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_BF16>, grid_for(c->N), dim3(256), 0, c->stream, (const uint16_t*)A, dst,
+                         c->N);
+  }
+  return hipGetLastError();
+}
+
+// Context-free collision of independent nodes (unit tests of the collision alone).
+__global__ __launch_bounds__(256) void k_collide_nodes(const float* fin, float* fout, float* gam, const float* F,
+                                                       int64_t n, float beta, float inv_beta, float thr) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    float f[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f[i] = fin[i * n + k];
+    const float Fx = F ? F[k] : 0.f, Fy = F ? F[n + k] : 0.f, Fz = F ? F[2 * n + k] : 0.f;
+    KbcOut<float> r;
+    if (F) r = kbc_collide<float, true>(f, beta, inv_beta, Fx, Fy, Fz);
+    else r = kbc_collide<float, false>(f, beta, inv_beta, Fx, Fy, Fz);
+    float g = r.gamma;
+    if (thr >= 0.f && !(r.b >= thr * r.rho)) {
+      double d[27];
+#pragma unroll
+      for (int i = 0; i < 27; ++i) d[i] = (double)fin[i * n + k];
+      KbcOut<double> r2;
+      if (F) r2 = kbc_collide<double, true>(d, (double)beta, 1.0 / (double)beta, Fx, Fy, Fz);
+      else r2 = kbc_collide<double, false>(d, (double)beta, 1.0 / (double)beta, 0.0, 0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < 27; ++i) f[i] = (float)d[i];
+      g = (float)r2.gamma;
+    }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) fout[i * n + k] = f[i];
+    if (gam) gam[k] = g;
+  }
+}
+
+hipError_t launch_collide_nodes(const float* fin, float* fout, float* gam, const float* F, int64_t n, double beta,
+                                double thr, hipStream_t s) {
+  hipLaunchKernelGGL(k_collide_nodes, grid_for(n), dim3(256), 0, s, fin, fout, gam, F, n, (float)beta,
+                     (float)(1.0 / beta), (float)thr);
+  return hipGetLastError();
+}
+
+}  // namespace elbm

@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import math
 import numpy as np
+import scipy.fft
 
 
 def node_coords(shape):
@@ -104,11 +105,48 @@ def turbulence(n: int, k0: float, urms: float, seed: int):
     del e, wgt, shell, kmag, k2, k2s
     u = np.empty((3, n, n, n))
     for c in range(3):
-        u[c] = np.fft.irfftn(a[c] * fac, s=(n, n, n), axes=(0, 1, 2))
+        u[c] = scipy.fft.irfftn(a[c] * fac, s=(n, n, n), axes=(0, 1, 2), workers=-1)
     a = None
     rms = math.sqrt(float(np.mean(u * u)) )
     u *= urms / rms
     return np.ones((n, n, n)), u
+
+
+def turbulence_device(n: int, k0: float, urms: float, seed: int, device="cuda"):
+    """Same recipe as ``turbulence`` drawn on a torch device (torch.Generator seeded with ``seed``;
+    a different random stream from numpy's).  Used for the largest boxes, where the host FFT is slow.
+    Returns float64 torch tensors (rho, u) on ``device``."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    kf = torch.fft.fftfreq(n, d=1.0 / n, device=device, dtype=torch.float64)
+    kr = torch.fft.rfftfreq(n, d=1.0 / n, device=device, dtype=torch.float64)
+    KZ, KY, KX = torch.meshgrid(kf, kf, kr, indexing="ij")
+    shp = KX.shape
+    a = [torch.complex(torch.randn(shp, generator=g, device=device, dtype=torch.float64),
+                       torch.randn(shp, generator=g, device=device, dtype=torch.float64)) for _ in range(3)]
+    k2 = KX * KX + KY * KY + KZ * KZ
+    k2s = torch.where(k2 == 0, torch.ones_like(k2), k2)
+    kdota = (KX * a[0] + KY * a[1] + KZ * a[2]) / k2s
+    a = [a[0] - KX * kdota, a[1] - KY * kdota, a[2] - KZ * kdota]
+    del kdota
+    shell = torch.round(torch.sqrt(k2)).to(torch.int64)
+    nsh = int(shell.max().item()) + 1
+    wgt = torch.where(KX > 0, 2.0, 1.0)
+    e = (a[0].abs() ** 2 + a[1].abs() ** 2 + a[2].abs() ** 2) * wgt
+    e_shell = torch.bincount(shell.reshape(-1), weights=e.reshape(-1), minlength=nsh)
+    ks = torch.arange(nsh, device=device, dtype=torch.float64)
+    target = ks ** 4 * torch.exp(-2.0 * (ks / k0) ** 2)
+    target[0] = 0.0
+    scale = torch.where(e_shell > 0, torch.sqrt(target / torch.where(e_shell > 0, e_shell, 1.0)), 0.0)
+    fac = scale[shell]
+    del e, wgt, k2, k2s, KX, KY, KZ
+    u = torch.empty((3, n, n, n), device=device, dtype=torch.float64)
+    for c in range(3):
+        u[c] = torch.fft.irfftn(a[c] * fac, s=(n, n, n), dim=(0, 1, 2))
+    del a, fac, shell
+    u *= urms / torch.sqrt(torch.mean(u * u))
+    return torch.ones((n, n, n), device=device, dtype=torch.float64), u
 
 
 def body_force(shape, seed: int, amp: float):

@@ -145,6 +145,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--form-steps", type=int, default=100)
+    ap.add_argument("--probe-copy-mib", type=int, default=0,
+                    help="after the headline run, copy a buffer of this many MiB 5 times (a plain copy kernel "
+                         "of known size, used to scale the HBM byte counters of a rocprofv3 --pmc run)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -189,6 +192,16 @@ def main():
             "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic_from_profile(n_nodes),
             "kernel": "k_sweep<f32> (bulk stream-collide)", "bytes_per_launch": BYTES_PER_NODE["f32"] * n_nodes,
             "avg_launch_ms": round(sweep_ms, 4)}
+
+    if args.probe_copy_mib:
+        nb = args.probe_copy_mib << 20
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: 5 copies of {args.probe_copy_mib} MiB (read {nb} B + write {nb} B each)")
+        del a, b
 
     forms = {}
     if not args.no_forms:

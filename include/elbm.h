@@ -65,6 +65,7 @@ extern "C" {
 #define ELBM_FLAG_BODY_FORCE 1u   /* a per-node body-force field will be bound */
 #define ELBM_FLAG_STREAM_ONLY 2u  /* no collision: the step is the streaming permutation alone */
 #define ELBM_FLAG_NO_FP64 4u      /* disable the FP64 recomputation of near-equilibrium nodes */
+#define ELBM_FLAG_ADJOINT 8u      /* reserve workspace for elbm_adjoint_step */
 
 typedef struct elbm_params {
   int32_t nx, ny, nz;   /* lattice size, each >= 1 (channel mode: nx >= 4) */
@@ -171,6 +172,34 @@ int elbm_read_flags(struct elbm_ctx* ctx, uint8_t* out_dev);
 
 /* Context information (synchronises for the per-step counters). */
 int elbm_get_info(struct elbm_ctx* ctx, elbm_info* out);
+
+/* Copy the current populations, in the context's storage format ([27][N] elements of 4 or 2
+ * bytes), to pop_dev (dev).  Used for checkpoints. */
+int elbm_save_state(struct elbm_ctx* ctx, void* pop_dev);
+
+/* Replace the current populations by pop_dev (dev, storage format, as written by
+ * elbm_save_state) and set the time level to t; the geometry is recomputed for t. */
+int elbm_load_state(struct elbm_ctx* ctx, const void* pop_dev, int64_t t);
+
+/* One reverse step of the adjoint of elbm_step for the step t -> t+1 (an addition of this
+ * library; the forward step it differentiates is the one of Secs. II-III and IV.A):
+ *   lam_out = (dA^{t+1}/dA^t)^T lam_in + dL_t/dA^t,
+ * where L_t = sum_b w_force[3b..3b+2] . F_b(t+1) is the loss term on the momentum-exchange force
+ * of that step (w_force: host double[nbodies][3], NULL for none).  Also accumulates
+ *   gF_dev += dL/dF (dev [3][N] FP32, body-force field; NULL to skip)
+ * and, inside the context, dL/d(amp) of every body (elbm_adjoint_param_grad).
+ * pop_t_dev: dev, the populations A^t in the storage format (e.g. recomputed from a checkpoint); the
+ * entries of nodes uncovered by the step are overwritten with their refill values, as the forward
+ * step does with its own buffer;
+ * lam_in_dev, lam_out_dev: dev [27][N] FP32, distinct.  The solid masks of the step are those of
+ * the forward run (their derivative is zero).  Needs ELBM_FLAG_ADJOINT and bodies without
+ * rotation.  Overwrites the context's geometry state: call elbm_load_state before stepping on. */
+int elbm_adjoint_step(struct elbm_ctx* ctx, int64_t t, void* pop_t_dev, const float* lam_in_dev,
+                      float* lam_out_dev, const double* w_force, float* gF_dev);
+
+/* dL/d(amp) of each body accumulated by elbm_adjoint_step (g_amp: host double[nbodies]);
+ * reset = 1 clears the accumulators afterwards.  Synchronises. */
+int elbm_adjoint_param_grad(struct elbm_ctx* ctx, double* g_amp, int32_t reset);
 
 /* Per-step timing of the bulk sweep kernel with HIP events recorded on the context's stream
  * around each launch.  enable = 1 starts (and clears) the record, 0 stops it. */

@@ -88,6 +88,8 @@ def lib():
         L.or_step.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Body), ctypes.c_int, ctypes.c_double, _D, _U8,
                               _U8, _D, _D, _D, ctypes.POINTER(Stats)]
         L.or_step.restype = ctypes.c_int
+        L.or_refill_state.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Body), ctypes.c_int, ctypes.c_double, _D,
+                                      _U8, _U8, _D, _D, _D, ctypes.POINTER(ctypes.c_int64)]
         L.or_init_equilibrium.argtypes = [ctypes.c_long, _D, _D, _D]
         L.or_moments.argtypes = [ctypes.c_long, _D, _D, _D]
         L.or_lattice.argtypes = [ctypes.POINTER(ctypes.c_int32), _D]
@@ -276,6 +278,26 @@ class Simulation:
         if self.F is not None:
             j = j - 0.5 * self.F
         return rho, j / rho
+
+    def macro(self):
+        """Previous-step fields (U^t, R^t) of the current state, as the step uses them."""
+        nx, ny, nz = self.shape
+        U = np.zeros((3, nz, ny, nx))
+        R = np.zeros((nz, ny, nx))
+        Fp = _dp(self.F) if self.F is not None else None
+        lib().or_macro(ctypes.byref(self.grid), self.bodies, self.nb, float(self.t), _dp(self.A), _u8(self.solid), Fp,
+                       _dp(U), _dp(R))
+        return U, R
+
+    def refill_state(self, solid_t1: np.ndarray):
+        """The current state with the nodes uncovered at t+1 refilled (first phase of a step)."""
+        U, R = self.macro()
+        Aw = np.zeros_like(self.A)
+        cnt = ctypes.c_int64(0)
+        lib().or_refill_state(ctypes.byref(self.grid), self.bodies, self.nb, float(self.t), _dp(self.A),
+                              _u8(self.solid), _u8(np.ascontiguousarray(solid_t1)), _dp(U), _dp(R), _dp(Aw),
+                              ctypes.byref(cnt))
+        return Aw, cnt.value, U, R
 
     def grad_u(self, U: np.ndarray, solid_t1: np.ndarray, x: int, y: int, z: int) -> np.ndarray:
         G = np.zeros(9)

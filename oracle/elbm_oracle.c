@@ -468,6 +468,52 @@ void or_macro(const or_grid *g, const or_body *bodies, int nb, double t, const d
 }
 
 /* ------------------------------------------------------------------------ */
+/* Refill of uncovered nodes (Sec. III): a node solid at t and fluid at t+1 has no
+ * populations of its own.  It receives Grad's distribution with the wall velocity at the node, a
+ * local density average and the pressure tensor of eqs. pressure/pressure2.
+ * Readings: the refill takes place before streaming, so the refilled populations are the node's
+ * state at t -- its neighbours pull them and the node itself then streams, meets the wall and
+ * collides like any other fluid node; the density average is over the 26 neighbours fluid at both
+ * t and t+1 (rho0 if none); the body is the one that held the node at t, its velocity taken at t+1;
+ * the gradient is the finite difference of U^t at the node.
+ * Writes A_w = A_t with the refill nodes replaced; U, R are U^t, R^t of or_macro. */
+void or_refill_state(const or_grid *g, const or_body *bodies, int nb, double t, const double *A_t,
+                     const uint8_t *solid_t, const uint8_t *solid_t1, const double *U, const double *R,
+                     double *A_w, int64_t *count) {
+  const long N = (long)g->nx * g->ny * g->nz;
+  double c1[MAXB][3], U1[MAXB][3];
+  for (int k = 0; k < nb; ++k) or_kinematics(&bodies[k], t + 1.0, c1[k], U1[k]);
+  memcpy(A_w, A_t, sizeof(double) * NQ * N);
+  int64_t cnt = 0;
+#pragma omp parallel for schedule(static) reduction(+ : cnt)
+  for (long n = 0; n < N; ++n) {
+    if (!(solid_t[n] && !solid_t1[n])) continue;
+    const int x = (int)(n % g->nx), y = (int)((n / g->nx) % g->ny), z = (int)(n / ((long)g->nx * g->ny));
+    const double xb[3] = {x, y, z};
+    const int k = solid_t[n] - 1;
+    double uw[3];
+    rigid_velocity(&bodies[k], c1[k], U1[k], xb, uw);
+    double rs = 0.0;
+    int m = 0;
+    for (int i = 0; i < NQ; ++i) {
+      if (i == 13) continue;
+      long nn = nbr(g, x, y, z, cxi(i), cyi(i), czi(i));
+      if (nn < 0 || solid_t[nn] || solid_t1[nn]) continue;
+      rs += R[nn];
+      ++m;
+    }
+    double rho_avg = m ? rs / m : g->rho0;
+    double G[9], Pi[9], f[NQ];
+    or_grad_u(g, U, solid_t1, x, y, z, G);
+    or_pressure(rho_avg, uw, G, g->beta, Pi);
+    or_grad_dist(rho_avg, uw, Pi, f);
+    for (int i = 0; i < NQ; ++i) A_w[i * N + n] = f[i];
+    ++cnt;
+  }
+  if (count) *count = cnt;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One time step t -> t+1 (Secs. II and III).
  *   A_t     : post-collision populations at t (27 N)
  *   solid_t : solid mask at t, solid_t1 : solid mask at t+1 (or_solid_mask)
@@ -475,13 +521,9 @@ void or_macro(const or_grid *g, const or_body *bodies, int nb, double t, const d
  *   A_t1    : output populations at t+1 (27 N).  Solid nodes keep A_t.
  *   forces  : output, per body 6 doubles (force[3], torque[3]) of the links
  *             used while producing A_t1
- * For each node fluid at t+1:
- *  - solid at t ("uncovered", Sec. III refill): all 27 populations are set to
- *    Grad's distribution with the wall velocity at the node, a local density
- *    average and the pressure tensor of eqs. pressure/pressure2.
- *    Reading: the average is over the 26 neighbours that are fluid at both t
- *    and t+1 (rho0 if none); the body is the one that held the node at t.
- *  - otherwise: pull streaming f_i = A_t,i(x - c_i) for the populations whose
+ * First the nodes uncovered by the bodies are refilled (or_refill_state), then for
+ * each node fluid at t+1:
+ *  - pull streaming f_i = A_t,i(x - c_i) for the populations whose
  *    source exists and is fluid at t+1.  The others form the missing set Dbar
  *    (reading: streamed from a node solid at t+1, or through the inlet face)
  *    and are rebuilt with Grad's distribution at target values (Sec. III):
@@ -513,6 +555,10 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
   double *gmin = (double *)malloc(sizeof(double) * g->nz), *gmax = (double *)malloc(sizeof(double) * g->nz);
   if (!U || !R || !fz || !cnt || !gmin || !gmax) return -2;
   or_macro(g, bodies, nb, t, A_t, solid_t, F, U, R);
+  double *Aw = (double *)malloc(sizeof(double) * NQ * N);
+  if (!Aw) return -2;
+  int64_t nrefill = 0;
+  or_refill_state(g, bodies, nb, t, A_t, solid_t, solid_t1, U, R, Aw, &nrefill);
   double c1[MAXB][3], U1[MAXB][3];
   for (int k = 0; k < nb; ++k) or_kinematics(&bodies[k], t + 1.0, c1[k], U1[k]);
 
@@ -528,27 +574,7 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
         }
         double xb[3] = {x, y, z};
         double f[NQ];
-        if (solid_t[n]) {
-          /* refill of an uncovered node */
-          int k = solid_t[n] - 1;
-          double uw[3];
-          rigid_velocity(&bodies[k], c1[k], U1[k], xb, uw);
-          double rs = 0.0;
-          int m = 0;
-          for (int i = 0; i < NQ; ++i) {
-            if (i == 13) continue;
-            long nn = nbr(g, x, y, z, cxi(i), cyi(i), czi(i));
-            if (nn < 0 || solid_t[nn] || solid_t1[nn]) continue;
-            rs += R[nn];
-            ++m;
-          }
-          double rho_avg = m ? rs / m : g->rho0;
-          double G[9], Pi[9];
-          or_grad_u(g, U, solid_t1, x, y, z, G);
-          or_pressure(rho_avg, uw, G, beta, Pi);
-          or_grad_dist(rho_avg, uw, Pi, f);
-          cnt[4 * z + 2]++;
-        } else {
+        {
           int inD[NQ], bodyof[NQ];
           double q[NQ];
           int nD = 0;
@@ -573,13 +599,13 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
               ++nD;
               continue;
             }
-            f[i] = A_t[i * N + src];
+            f[i] = Aw[i * N + src];
           }
           if (nD) {
             double uw[NQ][3], ut[3] = {0, 0, 0}, rstat = 0, rdyn = 0;
             for (int i = 0; i < NQ; ++i) {
               if (!inD[i]) { rstat += f[i]; continue; }
-              rstat += A_t[opp(i) * N + n];
+              rstat += Aw[opp(i) * N + n];
               if (bodyof[i] < 0) {
                 for (int a = 0; a < 3; ++a) uw[i][a] = g->u_in[a];
               } else {
@@ -608,7 +634,7 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
               int k = bodyof[i];
               cnt[4 * z + 1]++;
               if (k < 0) continue;
-              double fo = A_t[opp(i) * N + n];
+              double fo = Aw[opp(i) * N + n];
               double dF[3], xw[3];
               for (int a = 0; a < 3; ++a) {
                 dF[a] = fo * (-ci(i, a) - uw[i][a]) - fs[i] * (ci(i, a) - uw[i][a]);
@@ -645,12 +671,13 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
     st->gamma_min = 1e300; st->gamma_max = -1e300;
     for (int z = 0; z < g->nz; ++z) {
       st->boundary_nodes += cnt[4 * z]; st->links += cnt[4 * z + 1];
-      st->refill_nodes += cnt[4 * z + 2]; st->gamma_guard += cnt[4 * z + 3];
+      st->gamma_guard += cnt[4 * z + 3];
       if (gmin[z] < st->gamma_min) st->gamma_min = gmin[z];
       if (gmax[z] > st->gamma_max) st->gamma_max = gmax[z];
     }
+    st->refill_nodes = nrefill;
   }
-  free(U); free(R); free(fz); free(cnt); free(gmin); free(gmax);
+  free(Aw); free(U); free(R); free(fz); free(cnt); free(gmin); free(gmax);
   return 0;
 }
 

@@ -1,0 +1,743 @@
+// adjoint.hip -- hand-written reverse mode of one step of the forward path (an addition of this
+// library, not part of the paper): given dL/dA^{t+1} it produces dL/dA^t and accumulates dL/dF for
+// the body-force field and dL/d(amp) for each body's oscillation amplitude.  The forward step it
+// differentiates is exactly the one of sweep.hip and geometry.hip: pull streaming, the KBC
+// collision of Sec. II (stabiliser included), the moving-wall Grad reconstruction and the
+// momentum-exchange force of Sec. III / IV.A.  The solid masks are piecewise constant in the
+// parameters, so their derivative is zero (the topology of each step is that of the forward run).
+//
+// Data flow of a reverse step (all on the context's stream):
+//   k_adj_bulk      per fluid node: collision VJP, then the transpose of the pull -- every
+//                   (source, direction) entry of dL/dA^t is written exactly once by the node that
+//                   pulled it, so the scatter needs no atomics;  solid nodes write zeros.
+//   k_adj_boundary  per boundary/refill node: the adjoint of the reconstruction (Grad populations,
+//                   targets, finite-difference gradient, force term of the loss); contributions to
+//                   U^t and R^t of other nodes go to FP64 accumulators.
+//   k_adj_faces_zero / k_adj_outlet
+//                   channel mode: entries no node pulls start at zero (before the wall adjoint, which
+//                   adds the inlet bounce-back terms); the outlet copy is added afterwards.
+//   k_adj_refill    the completed dL/dA^t of refilled nodes sent through Grad's distribution.
+//   k_adj_macro     the accumulated dL/dU^t, dL/dR^t turned into dL/dA^t (nodes fluid at t) or
+//                   into dL/d(amp) (nodes solid at t, whose U^t is the rigid-body velocity).
+#include "elbm_internal.hpp"
+#include "boundary_dev.hpp"
+
+namespace elbm {
+
+// d ln phi(c, u) / du of the factorised equilibrium factor phi(c,u) = w(c)(2 - s) X^c.
+template <typename T>
+__device__ inline T dlnphi(int c, T u) {
+  const T s = sqrt_(T(3) * u * u + T(1));
+  const T d0 = -T(3) * u / (s * (T(2) - s));
+  if (c == 0) return d0;
+  const T dX = (T(2) + T(3) * u / s) / (T(2) * u + s) + T(1) / (T(1) - u);
+  return d0 + T(c) * dX;
+}
+
+template <typename T> struct VjpOut {
+  T b;
+  T rho;
+};
+
+// Vector-Jacobian product of kbc_collide: g = (d f'/d f)^T gp and gF = (d f'/d F)^T gp.
+template <typename T, bool FORCE>
+__device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T beta, const T Fx, const T Fy,
+                                    const T Fz, T (&g)[27], T (&gF)[3]) {
+  T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    rho += f[i];
+    jx += T(cx(i)) * f[i];
+    jy += T(cy(i)) * f[i];
+    jz += T(cz(i)) * f[i];
+  }
+  const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
+  T px[3], py[3], pz[3];
+  axis_phi(ux, px);
+  axis_phi(uy, py);
+  axis_phi(uz, pz);
+  T feq[27], dh[27];
+  T M200 = 0, M020 = 0, M002 = 0, M110 = 0, M101 = 0, M011 = 0;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    feq[i] = rho * px[cx(i) + 1] * py[cy(i) + 1] * pz[cz(i) + 1];
+    const T d = f[i] - feq[i];
+    dh[i] = d;
+    M200 += T(cx(i) * cx(i)) * d;
+    M020 += T(cy(i) * cy(i)) * d;
+    M002 += T(cz(i) * cz(i)) * d;
+    M110 += T(cx(i) * cy(i)) * d;
+    M101 += T(cx(i) * cz(i)) * d;
+    M011 += T(cy(i) * cz(i)) * d;
+  }
+  const T tr3 = (M200 + M020 + M002) * T(1.0 / 3.0);
+  const T sfx = T(0.5) * (M200 - tr3), sfy = T(0.5) * (M020 - tr3), sfz = T(0.5) * (M002 - tr3);
+  const T sxy = T(0.25) * M110, sxz = T(0.25) * M101, syz = T(0.25) * M011;
+  auto DS = [&](int i) -> T {
+    if (nnz(i) == 1) return cx(i) ? sfx : (cy(i) ? sfy : sfz);
+    if (nnz(i) == 2) {
+      if (cz(i) == 0) return T(cx(i) * cy(i)) * sxy;
+      if (cy(i) == 0) return T(cx(i) * cz(i)) * sxz;
+      return T(cy(i) * cz(i)) * syz;
+    }
+    return T(0);
+  };
+  T a = T(0), b = T(0);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    dh[i] -= DS(i);
+    const T th = dh[i] / feq[i];
+    b += th * dh[i];
+    a += th * DS(i);
+  }
+  const bool guard = !(b > T(1e-30));
+  const T ib = T(1) / beta;
+  const T gam = guard ? T(2) : ib - (T(2) - ib) * a / b;
+  // reverse
+  T g_gam = T(0);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) g_gam += gp[i] * dh[i];
+  g_gam *= -beta;
+  const T g_a = guard ? T(0) : -(T(2) - ib) / b * g_gam;
+  const T g_b = guard ? T(0) : (T(2) - ib) * a / (b * b) * g_gam;
+  T gDx = 0, gDy = 0, gDz = 0, gPxy = 0, gPxz = 0, gPyz = 0;
+  T g_feq[27];
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const T ds = DS(i), fe = feq[i], h = dh[i];
+    const T g_dh = -beta * gam * gp[i] + (g_a * ds + T(2) * g_b * h) / fe;
+    const T g_ds = -T(2) * beta * gp[i] + g_a * h / fe - g_dh;
+    g_feq[i] = -(g_a * ds * h + g_b * h * h) / (fe * fe) - g_dh;
+    g[i] = gp[i] + g_dh;
+    if (nnz(i) == 1) {
+      if (cx(i)) gDx += T(0.5) * g_ds;
+      else if (cy(i)) gDy += T(0.5) * g_ds;
+      else gDz += T(0.5) * g_ds;
+    } else if (nnz(i) == 2) {
+      if (cz(i) == 0) gPxy += T(0.25) * T(cx(i) * cy(i)) * g_ds;
+      else if (cy(i) == 0) gPxz += T(0.25) * T(cx(i) * cz(i)) * g_ds;
+      else gPyz += T(0.25) * T(cy(i) * cz(i)) * g_ds;
+    }
+  }
+  const T gm = (gDx + gDy + gDz) * T(1.0 / 3.0);
+  const T gM200 = gDx - gm, gM020 = gDy - gm, gM002 = gDz - gm;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const T e = gM200 * T(cx(i) * cx(i)) + gM020 * T(cy(i) * cy(i)) + gM002 * T(cz(i) * cz(i)) +
+                gPxy * T(cx(i) * cy(i)) + gPxz * T(cx(i) * cz(i)) + gPyz * T(cy(i) * cz(i));
+    g[i] += e;
+    g_feq[i] -= e;
+  }
+  T g_rho = T(0), gux = T(0), guy = T(0), guz = T(0);
+  gF[0] = gF[1] = gF[2] = T(0);
+  if (FORCE) {
+    // f' += feq(rho, u + F/rho) - feq(rho, u)
+    const T u1x = ux + Fx / rho, u1y = uy + Fy / rho, u1z = uz + Fz / rho;
+    T qx[3], qy[3], qz[3];
+    axis_phi(u1x, qx);
+    axis_phi(u1y, qy);
+    axis_phi(u1z, qz);
+    const T D1x[3] = {dlnphi(-1, u1x), dlnphi(0, u1x), dlnphi(1, u1x)};
+    const T D1y[3] = {dlnphi(-1, u1y), dlnphi(0, u1y), dlnphi(1, u1y)};
+    const T D1z[3] = {dlnphi(-1, u1z), dlnphi(0, u1z), dlnphi(1, u1z)};
+    T g1x = 0, g1y = 0, g1z = 0, gr1 = 0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const T e1 = rho * qx[cx(i) + 1] * qy[cy(i) + 1] * qz[cz(i) + 1];
+      const T ge = gp[i] * e1;
+      gr1 += ge;
+      g1x += ge * D1x[cx(i) + 1];
+      g1y += ge * D1y[cy(i) + 1];
+      g1z += ge * D1z[cz(i) + 1];
+      g_feq[i] -= gp[i];
+    }
+    g_rho += gr1 / rho - (g1x * Fx + g1y * Fy + g1z * Fz) / (rho * rho);
+    gux += g1x;
+    guy += g1y;
+    guz += g1z;
+    gF[0] = g1x / rho;
+    gF[1] = g1y / rho;
+    gF[2] = g1z / rho;
+  }
+  const T Dx[3] = {dlnphi(-1, ux), dlnphi(0, ux), dlnphi(1, ux)};
+  const T Dy[3] = {dlnphi(-1, uy), dlnphi(0, uy), dlnphi(1, uy)};
+  const T Dz[3] = {dlnphi(-1, uz), dlnphi(0, uz), dlnphi(1, uz)};
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const T ge = g_feq[i] * feq[i];
+    g_rho += ge / rho;
+    gux += ge * Dx[cx(i) + 1];
+    guy += ge * Dy[cy(i) + 1];
+    guz += ge * Dz[cz(i) + 1];
+  }
+  const T gjx = gux / rho, gjy = guy / rho, gjz = guz / rho;
+  g_rho -= (gux * ux + guy * uy + guz * uz) / rho;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) g[i] += g_rho + T(cx(i)) * gjx + T(cy(i)) * gjy + T(cz(i)) * gjz;
+  return VjpOut<T>{b, rho};
+}
+
+// Collision VJP in FP32 with the same FP64 recomputation rule as the forward collision.
+template <bool FORCE>
+__device__ inline void collide_vjp(const float (&f)[27], const float (&gp)[27], float beta, float Fx, float Fy, float Fz,
+                                   float thr, int fp64, float (&g)[27], float (&gF)[3]) {
+  const VjpOut<float> r = kbc_vjp<float, FORCE>(f, gp, beta, Fx, Fy, Fz, g, gF);
+  if (fp64 && !(r.b >= thr * r.rho)) {
+    double fd[27], gd[27], outd[27], gFd[3];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      fd[i] = f[i];
+      gd[i] = gp[i];
+    }
+    kbc_vjp<double, FORCE>(fd, gd, (double)beta, Fx, Fy, Fz, outd, gFd);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) g[i] = (float)outd[i];
+    gF[0] = (float)gFd[0];
+    gF[1] = (float)gFd[1];
+    gF[2] = (float)gFd[2];
+  }
+}
+
+struct AdjArgs {
+  const float* lam_in;
+  float* lam_out;
+  float* side;
+  float* gF;
+  double* gUR;
+};
+
+struct AdjBodyArgs {
+  double dc1[ELBM_MAX_BODIES][3];  // d c(t+1) / d amp
+  double dU1[ELBM_MAX_BODIES][3];  // d U(t+1) / d amp
+  double dU0[ELBM_MAX_BODIES][3];  // d U(t) / d amp
+  double w[ELBM_MAX_BODIES][3];    // dL / dF_body(t+1)
+  double* gamp;                    // [MAX_BODIES] accumulators
+  int32_t loss;
+  int32_t pad;
+};
+
+// Transpose of the pull: entry (x - c_i, i) of dL/dA^t receives v.  Channel mode: nothing for a
+// source through the inlet; the outlet copy goes to the side buffer, keyed by the destination.
+__device__ inline void adj_push(const BArgs& a, const AdjArgs& j, int i, int x, int y, int z, float v) {
+  int sx = x - cx(i);
+  if (a.channel) {
+    if (sx < 0) return;
+    if (sx >= a.nx) {
+      j.side[(size_t)(i / 3) * a.ny * a.nz + (size_t)z * a.ny + y] = v;
+      return;
+    }
+  } else {
+    sx = wrap(sx, a.nx);
+  }
+  j.lam_out[(size_t)i * a.N + node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz))] = v;
+}
+
+__device__ inline long pull_source(const BArgs& a, int i, int x, int y, int z) {
+  int sx = x - cx(i);
+  if (a.channel) sx = sx >= a.nx ? a.nx - 1 : (sx < 0 ? 0 : sx);
+  else sx = wrap(sx, a.nx);
+  return node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
+}
+
+template <int S, bool FLAGS, bool FORCE>
+__global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j) {
+  using C = Codec<S>;
+  using E = typename C::E;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  const long n = node_at(a, x, y, z);
+  const uint8_t fl = FLAGS ? a.flags[n] : (uint8_t)0;
+  if (fl & FL_SOLID) {
+#pragma unroll
+    for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, 0.f);
+    return;
+  }
+  if (fl & FL_SPECIAL) return;
+  const E* __restrict__ A = (const E*)a.A;
+  float f[27], gp[27], g[27], gF[3];
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    f[i] = C::load(A + i * a.N + pull_source(a, i, x, y, z), wf(i));
+    gp[i] = j.lam_in[i * a.N + n];
+  }
+  float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+  if (FORCE) {
+    Fx = a.F[n];
+    Fy = a.F[a.N + n];
+    Fz = a.F[2 * a.N + n];
+  }
+  collide_vjp<FORCE>(f, gp, a.beta, Fx, Fy, Fz, a.thr, a.fp64, g, gF);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, g[i]);
+  if (FORCE && j.gF) {
+    j.gF[n] += gF[0];
+    j.gF[a.N + n] += gF[1];
+    j.gF[2 * a.N + n] += gF[2];
+  }
+}
+
+// Adjoint of Grad's distribution f*_i(rho, u, Pi) (eq. grad), accumulated over directions.
+__device__ inline void grad_pop_vjp(int i, float gfs, float rho, const float (&u)[3], float& gr, float (&gu)[3],
+                                    float (&gP)[6]) {
+  const float W = wf(i);
+  const float c[3] = {(float)cx(i), (float)cy(i), (float)cz(i)};
+  const float cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+  const float c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+  gr += gfs * W * (1.f + 3.f * cu - 1.5f * (c2 - 1.f));
+  gu[0] += gfs * 3.f * rho * W * c[0];
+  gu[1] += gfs * 3.f * rho * W * c[1];
+  gu[2] += gfs * 3.f * rho * W * c[2];
+  const float t = 1.f / 3.f;
+  gP[0] += gfs * 4.5f * W * (c[0] * c[0] - t);
+  gP[1] += gfs * 4.5f * W * (c[1] * c[1] - t);
+  gP[2] += gfs * 4.5f * W * (c[2] * c[2] - t);
+  gP[3] += gfs * 9.f * W * c[0] * c[1];
+  gP[4] += gfs * 9.f * W * c[0] * c[2];
+  gP[5] += gfs * 9.f * W * c[1] * c[2];
+}
+
+// Adjoint of the pressure tensor (eqs. pressure, pressure2) in the packed order xx,yy,zz,xy,xz,yz.
+__device__ inline void pressure_vjp(float rho, const float (&u)[3], const float (&G)[9], float beta,
+                                    const float (&gP)[6], float& gr, float (&gu)[3], float (&gG)[9]) {
+  const float k = rho / (6.f * beta), kr = 1.f / (6.f * beta);
+  gr += gP[0] * (1.f / 3.f + u[0] * u[0] - 2.f * kr * G[0]) + gP[1] * (1.f / 3.f + u[1] * u[1] - 2.f * kr * G[4]) +
+        gP[2] * (1.f / 3.f + u[2] * u[2] - 2.f * kr * G[8]) + gP[3] * (u[0] * u[1] - kr * (G[1] + G[3])) +
+        gP[4] * (u[0] * u[2] - kr * (G[2] + G[6])) + gP[5] * (u[1] * u[2] - kr * (G[5] + G[7]));
+  gu[0] += 2.f * rho * u[0] * gP[0] + rho * u[1] * gP[3] + rho * u[2] * gP[4];
+  gu[1] += 2.f * rho * u[1] * gP[1] + rho * u[0] * gP[3] + rho * u[2] * gP[5];
+  gu[2] += 2.f * rho * u[2] * gP[2] + rho * u[0] * gP[4] + rho * u[1] * gP[5];
+  gG[0] = -2.f * k * gP[0];
+  gG[4] = -2.f * k * gP[1];
+  gG[8] = -2.f * k * gP[2];
+  gG[1] = gG[3] = -k * gP[3];
+  gG[2] = gG[6] = -k * gP[4];
+  gG[5] = gG[7] = -k * gP[5];
+}
+
+__device__ inline void addU(const BArgs& a, const AdjArgs& j, int comp, long node, float v) {
+  if (v != 0.f) atomicAdd(&j.gUR[comp * a.N + node], (double)v);
+}
+
+// Transpose of the finite-difference stencil of grad_u: dL/dG -> dL/dU^t at the stencil nodes.
+__device__ inline void grad_u_vjp(const BArgs& a, const AdjArgs& j, int x, int y, int z, long n0, const float (&gG)[9]) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int e0 = b == 0, e1 = b == 1, e2 = b == 2;
+    const long p1 = neighbour(a, x, y, z, e0, e1, e2), p2 = neighbour(a, x, y, z, 2 * e0, 2 * e1, 2 * e2);
+    const long m1 = neighbour(a, x, y, z, -e0, -e1, -e2), m2 = neighbour(a, x, y, z, -2 * e0, -2 * e1, -2 * e2);
+    const bool op1 = p1 >= 0 && !(a.flags[p1] & FL_SOLID), op2 = p2 >= 0 && !(a.flags[p2] & FL_SOLID);
+    const bool om1 = m1 >= 0 && !(a.flags[m1] & FL_SOLID), om2 = m2 >= 0 && !(a.flags[m2] & FL_SOLID);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float g = gG[3 * c + b];
+      if (g == 0.f) continue;
+      if (op1 && om1) {
+        addU(a, j, c, p1, 0.5f * g);
+        addU(a, j, c, m1, -0.5f * g);
+      } else if (op1 && op2) {
+        addU(a, j, c, n0, -1.5f * g);
+        addU(a, j, c, p1, 2.f * g);
+        addU(a, j, c, p2, -0.5f * g);
+      } else if (om1 && om2) {
+        addU(a, j, c, n0, 1.5f * g);
+        addU(a, j, c, m1, -2.f * g);
+        addU(a, j, c, m2, 0.5f * g);
+      } else if (op1) {
+        addU(a, j, c, p1, g);
+        addU(a, j, c, n0, -g);
+      } else if (om1) {
+        addU(a, j, c, n0, g);
+        addU(a, j, c, m1, -g);
+      }
+    }
+  }
+}
+
+template <int S, bool FORCE>
+__global__ __launch_bounds__(128) void k_adj_boundary(const BArgs a, const Bodies bd, const AdjArgs j,
+                                                      const AdjBodyArgs p) {
+  using C = Codec<S>;
+  using E = typename C::E;
+  const E* __restrict__ A = (const E*)a.A;
+  int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
+  if (count > a.cap) count = a.cap;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
+    const long n = a.list[k];
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    float gp[27], f[27], g[27], gFn[3];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) gp[i] = j.lam_in[i * a.N + n];
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    if (FORCE) {
+      Fx = a.F[n];
+      Fy = a.F[a.N + n];
+      Fz = a.F[2 * a.N + n];
+    }
+    {
+      // ---- wall node: forward recomputation (as k_boundary)
+      uint32_t dmask = 0;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        int sx = x - cx(i);
+        if (a.channel && sx < 0) {
+          dmask |= 1u << i;
+          f[i] = 0.f;
+          continue;
+        }
+        if (a.channel) sx = sx >= a.nx ? a.nx - 1 : sx;
+        else sx = wrap(sx, a.nx);
+        const long ns = node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
+        if (a.flags[ns] & FL_SOLID) {
+          dmask |= 1u << i;
+          f[i] = 0.f;
+          continue;
+        }
+        f[i] = C::load(A + i * a.N + ns, wf(i));
+      }
+      float ut[3] = {0.f, 0.f, 0.f};
+      float rstat = 0.f, rdyn = 0.f;
+      int nD = 0;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        if (!((dmask >> i) & 1u)) {
+          rstat += f[i];
+          continue;
+        }
+        ++nD;
+        rstat += C::load(A + opp(i) * a.N + n, wf(opp(i)));
+        double q, uwd[3];
+        int kb;
+        link_geometry(a, bd, i, x, y, z, q, uwd, kb);
+        const long nf = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
+        float uf[3];
+        if (nf >= 0 && !(a.flags[nf] & FL_SOLID)) {
+          uf[0] = a.macro[nf];
+          uf[1] = a.macro[a.N + nf];
+          uf[2] = a.macro[2 * a.N + nf];
+        } else {
+          uf[0] = (float)uwd[0];
+          uf[1] = (float)uwd[1];
+          uf[2] = (float)uwd[2];
+        }
+        const float qf = (float)q, inv = 1.f / (1.f + qf);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ut[c] += (qf * uf[c] + (float)uwd[c]) * inv;
+        rdyn += (float)(6.0 * wd(i) * a.rho0 * (cx(i) * uwd[0] + cy(i) * uwd[1] + cz(i) * uwd[2]));
+      }
+      const float invn = nD ? 1.f / (float)nD : 0.f;
+      ut[0] *= invn;
+      ut[1] *= invn;
+      ut[2] *= invn;
+      const float rt = rstat + rdyn;
+      float G[9], Pi[6];
+      if (nD) {
+        grad_u(a, x, y, z, n, G);
+        pressure_tensor(rt, ut, G, a.beta, Pi);
+#pragma unroll
+        for (int i = 0; i < 27; ++i)
+          if ((dmask >> i) & 1u) f[i] = grad_pop(i, rt, ut, Pi);
+      }
+      // ---- reverse
+      collide_vjp<FORCE>(f, gp, a.beta, Fx, Fy, Fz, a.thr, a.fp64, g, gFn);
+      if (!nD) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, g[i]);
+      } else {
+        float gr = 0.f, gu[3] = {0.f, 0.f, 0.f}, gP[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gG[9];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+          if (!((dmask >> i) & 1u)) continue;
+          float gfs = g[i];
+          if (p.loss) {
+            double q, uwd[3];
+            int kb;
+            link_geometry(a, bd, i, x, y, z, q, uwd, kb);
+            if (kb >= 0)
+              gfs -= (float)(p.w[kb][0] * (cx(i) - uwd[0]) + p.w[kb][1] * (cy(i) - uwd[1]) + p.w[kb][2] * (cz(i) - uwd[2]));
+          }
+          grad_pop_vjp(i, gfs, rt, ut, gr, gu, gP);
+        }
+        pressure_vjp(rt, ut, G, a.beta, gP, gr, gu, gG);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+          if (!((dmask >> i) & 1u)) {
+            adj_push(a, j, i, x, y, z, g[i] + gr);
+            continue;
+          }
+          double q, uwd[3];
+          int kb;
+          link_geometry(a, bd, i, x, y, z, q, uwd, kb);
+          float vbb = gr;
+          double guw[3];
+          const double qd = q, inv = 1.0 / (nD * (1.0 + qd));
+          for (int c = 0; c < 3; ++c) guw[c] = (double)gr * 6.0 * wd(i) * a.rho0 * (c == 0 ? cx(i) : (c == 1 ? cy(i) : cz(i))) + gu[c] * inv;
+          if (p.loss && kb >= 0) {
+            const float fo = C::load(A + opp(i) * a.N + n, wf(opp(i)));
+            const float fs = grad_pop(i, rt, ut, Pi);
+            vbb += (float)(p.w[kb][0] * (-cx(i) - uwd[0]) + p.w[kb][1] * (-cy(i) - uwd[1]) + p.w[kb][2] * (-cz(i) - uwd[2]));
+            for (int c = 0; c < 3; ++c) guw[c] += p.w[kb][c] * ((double)fs - (double)fo);
+          }
+          j.lam_out[opp(i) * a.N + n] += vbb;
+          if (!(a.channel && x - cx(i) < 0)) adj_push(a, j, i, x, y, z, 0.f);
+          // u_f and q
+          const long nf = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
+          double uf[3];
+          if (nf >= 0 && !(a.flags[nf] & FL_SOLID)) {
+            uf[0] = a.macro[nf];
+            uf[1] = a.macro[a.N + nf];
+            uf[2] = a.macro[2 * a.N + nf];
+            for (int c = 0; c < 3; ++c) addU(a, j, c, nf, (float)(gu[c] * qd * inv));
+          } else {
+            for (int c = 0; c < 3; ++c) {
+              uf[c] = uwd[c];
+              guw[c] += gu[c] * qd * inv;
+            }
+          }
+          if (kb >= 0) {
+            const double gq = (gu[0] * (uf[0] - uwd[0]) + gu[1] * (uf[1] - uwd[1]) + gu[2] * (uf[2] - uwd[2])) * inv /
+                              (1.0 + qd);
+            const BodyDev& b = bd.b[kb];
+            const double v[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+            double dqdc[3];
+            if (b.kind == ELBM_BODY_SPHERE) {
+              const double r[3] = {x - b.c1[0] - qd * v[0], y - b.c1[1] - qd * v[1], z - b.c1[2] - qd * v[2]};
+              const double rv = r[0] * v[0] + r[1] * v[1] + r[2] * v[2];
+              for (int c = 0; c < 3; ++c) dqdc[c] = -r[c] / rv;
+            } else {
+              const double nv = b.n[0] * v[0] + b.n[1] * v[1] + b.n[2] * v[2];
+              for (int c = 0; c < 3; ++c) dqdc[c] = -b.n[c] / nv;
+            }
+            double ga = 0.0;
+            for (int c = 0; c < 3; ++c) ga += guw[c] * p.dU1[kb][c] + gq * dqdc[c] * p.dc1[kb][c];
+            atomicAdd(&p.gamp[kb], ga);
+          }
+        }
+        grad_u_vjp(a, j, x, y, z, n, gG);
+      }
+    }
+    if (FORCE && j.gF) {
+      j.gF[n] += gFn[0];
+      j.gF[a.N + n] += gFn[1];
+      j.gF[2 * a.N + n] += gFn[2];
+    }
+  }
+}
+
+// Adjoint of the refill (which writes Grad's distribution into A^t at the nodes uncovered by the
+// step): the completed dL/dA^t of a refill node goes through Grad's distribution to R^t of its
+// neighbours, U^t of its stencil and the body's amplitude; the node's own entries are then zero
+// (its stored A^t is overwritten and influences nothing).
+__global__ __launch_bounds__(128) void k_adj_refill(const BArgs a, const Bodies bd, const AdjArgs j,
+                                                    const AdjBodyArgs p) {
+  int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
+  if (count > a.cap) count = a.cap;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
+    const long n = a.list[k];
+    if (!(a.flags[n] & FL_SOLID_PREV)) continue;
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    float f[27], uw[3], G[9], ravg;
+    int kb, m;
+    refill_pops(a, bd, x, y, z, n, f, kb, ravg, m, uw, G);
+    float gr = 0.f, gu[3] = {0.f, 0.f, 0.f}, gP[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gG[9];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const float gi = j.lam_out[i * a.N + n];
+      j.lam_out[i * a.N + n] = 0.f;
+      grad_pop_vjp(i, gi, ravg, uw, gr, gu, gP);
+    }
+    pressure_vjp(ravg, uw, G, a.beta, gP, gr, gu, gG);
+    if (m) {
+      const float gm = gr / (float)m;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        if (i == 13) continue;
+        const long nn = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
+        if (nn < 0 || (a.flags[nn] & (FL_SOLID | FL_SOLID_PREV))) continue;
+        atomicAdd(&j.gUR[3 * a.N + nn], (double)gm);
+      }
+    }
+    atomicAdd(&p.gamp[kb], (double)gu[0] * p.dU1[kb][0] + (double)gu[1] * p.dU1[kb][1] + (double)gu[2] * p.dU1[kb][2]);
+    grad_u_vjp(a, j, x, y, z, n, gG);
+  }
+}
+
+// Channel faces, before the boundary adjoint: entries that no node pulls -- x = 0 moving in -x and
+// x = nx-1 moving in +x -- start at zero (the wall rule then adds the bounce-back terms at x = 0).
+__global__ void k_adj_faces_zero(const BArgs a, const AdjArgs j) {
+  const long total = (long)a.ny * a.nz;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int y = (int)(idx % a.ny), z = (int)(idx / a.ny);
+    const long n0 = node_at(a, 0, y, z), n1 = node_at(a, a.nx - 1, y, z);
+    for (int k = 0; k < 9; ++k) {
+      j.lam_out[(3 * k) * a.N + n0] = 0.f;
+      j.lam_out[(3 * k + 2) * a.N + n1] = 0.f;
+    }
+  }
+}
+
+// Channel faces, after the boundary adjoint: add the outlet-copy contributions of the side buffer.
+__global__ void k_adj_outlet(const BArgs a, const AdjArgs j) {
+  const long total = (long)a.ny * a.nz;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int y = (int)(idx % a.ny), z = (int)(idx / a.ny);
+    for (int k = 0; k < 9; ++k) {
+      const int i = 3 * k;
+      const long tgt = node_at(a, a.nx - 1, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
+      j.lam_out[i * a.N + tgt] += j.side[(size_t)k * a.ny * a.nz + (size_t)z * a.ny + y];
+    }
+  }
+}
+
+// dL/dU^t, dL/dR^t -> dL/dA^t at nodes fluid at t (U = (j - F/2)/rho, R = rho), or dL/d(amp) at
+// nodes solid at t (U = rigid-body velocity at t).  Clears the accumulators it consumes.
+template <int S>
+__global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, const AdjBodyArgs p) {
+  using C = Codec<S>;
+  using E = typename C::E;
+  const E* __restrict__ A = (const E*)a.A;
+  for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < a.N; n += (long)gridDim.x * blockDim.x) {
+    const double gU0 = j.gUR[n], gU1 = j.gUR[a.N + n], gU2 = j.gUR[2 * a.N + n], gR = j.gUR[3 * a.N + n];
+    if (gU0 == 0.0 && gU1 == 0.0 && gU2 == 0.0 && gR == 0.0) continue;
+    j.gUR[n] = 0.0;
+    j.gUR[a.N + n] = 0.0;
+    j.gUR[2 * a.N + n] = 0.0;
+    j.gUR[3 * a.N + n] = 0.0;
+    if (a.flags[n] & FL_SOLID_PREV) {
+      const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+      int kb = first_body(bd, false, x, y, z);
+      if (kb < 0) kb = 0;
+      atomicAdd(&p.gamp[kb], gU0 * p.dU0[kb][0] + gU1 * p.dU0[kb][1] + gU2 * p.dU0[kb][2]);
+      continue;
+    }
+    float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const float v = C::load(A + i * a.N + n, wf(i));
+      rho += v;
+      jx += cx(i) * v;
+      jy += cy(i) * v;
+      jz += cz(i) * v;
+    }
+    if (a.F) {
+      jx -= 0.5f * a.F[n];
+      jy -= 0.5f * a.F[a.N + n];
+      jz -= 0.5f * a.F[2 * a.N + n];
+    }
+    const float U[3] = {jx / rho, jy / rho, jz / rho};
+    const float g0 = (float)gU0, g1 = (float)gU1, g2 = (float)gU2, gr = (float)gR;
+#pragma unroll
+    for (int i = 0; i < 27; ++i)
+      j.lam_out[i * a.N + n] += gr + (g0 * (cx(i) - U[0]) + g1 * (cy(i) - U[1]) + g2 * (cz(i) - U[2])) / rho;
+    if (a.F && j.gF) {
+      j.gF[n] -= g0 / (2.f * rho);
+      j.gF[a.N + n] -= g1 / (2.f * rho);
+      j.gF[2 * a.N + n] -= g2 / (2.f * rho);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+static BArgs bargs(elbm_ctx* c, const void* A) {
+  BArgs a;
+  a.A = A;
+  a.B = nullptr;
+  a.flags = c->flags;
+  a.macro = c->macro;
+  a.F = c->bodyforce;
+  a.list = c->blist;
+  a.dyn_count = &c->cnt->dyn_count;
+  a.brec = c->brec;
+  a.n_static = c->n_static;
+  a.cap = c->blist_cap;
+  a.moving = c->moving ? 1 : 0;
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.nz = c->p.nz;
+  a.N = c->N;
+  a.channel = c->p.bc_x == ELBM_BC_CHANNEL;
+  a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64);
+  a.stream_only = 0;
+  a.beta = (float)c->beta;
+  a.inv_beta = (float)(1.0 / c->beta);
+  a.thr = (float)c->fp64_thr;
+  a.rho0 = c->p.rho0;
+  for (int e = 0; e < 3; ++e) a.u_in[e] = c->p.u_inlet[e];
+  return a;
+}
+
+static void amp_derivatives(const elbm_body& b, double t, double dc[3], double dU[3]) {
+  double sn = 0.0, cs = 0.0, om = 0.0;
+  if (b.period != 0.0) {
+    const double ph = ((2.0 * M_PI) * t) / b.period;
+    sn = sin(ph);
+    cs = cos(ph);
+    om = (2.0 * M_PI) / b.period;
+  }
+  for (int a = 0; a < 3; ++a) {
+    dc[a] = sn * b.dir[a];
+    dU[a] = (om * cs) * b.dir[a];
+  }
+}
+
+template <int S>
+static void adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, const AdjArgs& j, const AdjBodyArgs& p) {
+  int bx = 256;
+  while (bx > 32 && (c->p.nx % bx) != 0) bx >>= 1;
+  if (c->p.nx < bx) bx = 32;
+  const dim3 blk(bx, 256 / bx, 1);
+  const dim3 grd((c->p.nx + bx - 1) / bx, (c->p.ny + blk.y - 1) / blk.y, c->p.nz);
+  const bool geo = c->flags != nullptr, force = c->bodyforce != nullptr;
+  if (geo && force) hipLaunchKernelGGL((k_adj_bulk<S, true, true>), grd, blk, 0, c->stream, a, j);
+  else if (geo) hipLaunchKernelGGL((k_adj_bulk<S, true, false>), grd, blk, 0, c->stream, a, j);
+  else if (force) hipLaunchKernelGGL((k_adj_bulk<S, false, true>), grd, blk, 0, c->stream, a, j);
+  else hipLaunchKernelGGL((k_adj_bulk<S, false, false>), grd, blk, 0, c->stream, a, j);
+  if (geo) {
+    const dim3 gf = grid_for((long)c->p.ny * c->p.nz);
+    if (a.channel) hipLaunchKernelGGL(k_adj_faces_zero, gf, dim3(256), 0, c->stream, a, j);
+    if (force) hipLaunchKernelGGL((k_adj_boundary<S, true>), dim3(512), dim3(128), 0, c->stream, a, bd, j, p);
+    else hipLaunchKernelGGL((k_adj_boundary<S, false>), dim3(512), dim3(128), 0, c->stream, a, bd, j, p);
+    if (a.channel) hipLaunchKernelGGL(k_adj_outlet, gf, dim3(256), 0, c->stream, a, j);
+    if (c->moving) hipLaunchKernelGGL(k_adj_refill, dim3(256), dim3(128), 0, c->stream, a, bd, j, p);
+    hipLaunchKernelGGL(k_adj_macro<S>, grid_for(c->N), dim3(256), 0, c->stream, a, bd, j, p);
+  }
+}
+
+hipError_t launch_adjoint(elbm_ctx* c, int64_t t, const void* A, const float* lam_in, float* lam_out,
+                          const double* w_force, float* gF) {
+  const Bodies bd = make_bodies(c, (double)t);
+  if (c->flags) {
+    hipError_t e = geometry_for_step(c, bd);
+    if (e != hipSuccess) return e;
+    e = macro_fields(c, A, bd);
+    if (e != hipSuccess) return e;
+    // the forward step refills uncovered nodes into A^t before streaming; do the same here
+    e = launch_refill(c, bd, const_cast<void*>(A));
+    if (e != hipSuccess) return e;
+  }
+  const BArgs a = bargs(c, A);
+  AdjArgs j;
+  j.lam_in = lam_in;
+  j.lam_out = lam_out;
+  j.side = c->adj_side;
+  j.gF = gF;
+  j.gUR = c->adj_gUR;
+  AdjBodyArgs p{};
+  p.gamp = c->adj_gamp;
+  p.loss = w_force != nullptr;
+  for (int k = 0; k < c->nb; ++k) {
+    amp_derivatives(c->bodies[k], (double)t + 1.0, p.dc1[k], p.dU1[k]);
+    double dc0[3];
+    amp_derivatives(c->bodies[k], (double)t, dc0, p.dU0[k]);
+    for (int e = 0; e < 3; ++e) p.w[k][e] = w_force ? w_force[3 * k + e] : 0.0;
+  }
+  switch (c->p.storage) {
+    case ELBM_STORAGE_F32: adj_launch<ELBM_STORAGE_F32>(c, a, bd, j, p); break;
+    case ELBM_STORAGE_F16: adj_launch<ELBM_STORAGE_F16>(c, a, bd, j, p); break;
+    default: adj_launch<ELBM_STORAGE_BF16>(c, a, bd, j, p);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace elbm

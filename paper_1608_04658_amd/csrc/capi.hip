@@ -35,7 +35,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t pop[2], cnt, fix_list, flags, macro, blist, brec, ring, scratch, total;
+  size_t pop[2], cnt, fix_list, flags, macro, blist, brec, ring, scratch, adj_gUR, adj_side, adj_gamp, total;
   int64_t cap;
   bool geometry;
 };
@@ -89,6 +89,11 @@ Layout layout(const elbm_params* p) {
     L.blist = take(4 * (size_t)L.cap);
     L.brec = take(sizeof(double) * 6 * nbm * (size_t)L.cap);
     L.ring = take(sizeof(double) * 6 * ELBM_MAX_BODIES * ring);
+  }
+  if (p->flags & ELBM_FLAG_ADJOINT) {
+    L.adj_gUR = take(sizeof(double) * 4 * N);
+    L.adj_side = take(sizeof(float) * 9 * (size_t)p->ny * p->nz);
+    L.adj_gamp = take(sizeof(double) * ELBM_MAX_BODIES);
   }
   L.total = off;
   return L;
@@ -145,6 +150,10 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->blist = L.geometry ? (int32_t*)(c->ws + L.blist) : nullptr;
   c->brec = L.geometry ? (double*)(c->ws + L.brec) : nullptr;
   c->ring = L.geometry ? (double*)(c->ws + L.ring) : nullptr;
+  const bool adj = (p->flags & ELBM_FLAG_ADJOINT) != 0;
+  c->adj_gUR = adj ? (double*)(c->ws + L.adj_gUR) : nullptr;
+  c->adj_side = adj ? (float*)(c->ws + L.adj_side) : nullptr;
+  c->adj_gamp = adj ? (double*)(c->ws + L.adj_gamp) : nullptr;
   c->blist_cap = L.cap;
   c->n_static = 0;
   c->bodyforce = nullptr;
@@ -160,6 +169,9 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   if (e == hipSuccess && L.geometry)
     e = hipMemsetAsync(c->ring, 0, sizeof(double) * 6 * ELBM_MAX_BODIES * c->p.force_ring, c->stream);
   if (e == hipSuccess && L.geometry) e = hipMemsetAsync(c->macro, 0, 16 * (size_t)c->N, c->stream);
+  if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_gUR, 0, sizeof(double) * 4 * (size_t)c->N, c->stream);
+  if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_side, 0, sizeof(float) * 9 * (size_t)p->ny * p->nz, c->stream);
+  if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_gamp, 0, sizeof(double) * ELBM_MAX_BODIES, c->stream);
   if (e != hipSuccess) {
     delete c;
     return fail(nullptr, ELBM_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
@@ -202,6 +214,9 @@ int elbm_set_stream(elbm_ctx* c, void* stream) {
 int elbm_init_equilibrium(elbm_ctx* c, const double* rho_dev, const double* u_dev) {
   if (!c) return ELBM_EINVAL;
   if (!u_dev) return fail(c, ELBM_EINVAL, "u_dev is NULL");
+  // both buffers: nodes that stay solid are never written by a step
+  c->cur = 1;
+  HIP_OK(c, launch_init_eq(c, rho_dev, u_dev));
   c->cur = 0;
   c->t = 0;
   HIP_OK(c, launch_init_eq(c, rho_dev, u_dev));
@@ -243,6 +258,8 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
       if (b.vel[0] != 0.0 || b.center[0] - ex < 6.0 || b.center[0] + ex > c->p.nx - 7.0)
         return fail(c, ELBM_EINVAL, "body %d: sphere must stay 6 nodes from inlet and outlet", k);
     }
+    if ((c->p.flags & ELBM_FLAG_ADJOINT) && (b.omega[0] != 0.0 || b.omega[1] != 0.0 || b.omega[2] != 0.0))
+      return fail(c, ELBM_EINVAL, "body %d: the adjoint supports bodies without rotation", k);
     moving = moving || body_moves(b);
   }
   c->nb = nb;
@@ -272,6 +289,7 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
     if (geo) {
       bd = make_bodies(c, (double)c->t);
       HIP_OK(c, geometry_pre_step(c, bd));
+      HIP_OK(c, launch_refill(c, bd, c->pop[c->cur]));
     }
     const bool rec = c->timing && c->ev_used < c->ev_cap;
     if (rec) HIP_OK(c, hipEventRecord(c->ev[2 * c->ev_used], c->stream));
@@ -350,6 +368,48 @@ int elbm_get_info(elbm_ctx* c, elbm_info* out) {
   HIP_OK(c, hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
   out->boundary_nodes = c->flags ? c->n_static + (c->moving ? (int64_t)h.dyn_count : 0) : 0;
   out->fp64_nodes = h.fix_total;
+  return ELBM_OK;
+}
+
+int elbm_save_state(elbm_ctx* c, void* pop_dev) {
+  if (!c) return ELBM_EINVAL;
+  if (!pop_dev) return fail(c, ELBM_EINVAL, "pop_dev is NULL");
+  const size_t bytes = 27 * (size_t)c->N * storage_bytes(c->p.storage);
+  HIP_OK(c, hipMemcpyAsync(pop_dev, c->pop[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
+  return ELBM_OK;
+}
+
+int elbm_load_state(elbm_ctx* c, const void* pop_dev, int64_t t) {
+  if (!c) return ELBM_EINVAL;
+  if (!pop_dev || t < 0) return fail(c, ELBM_EINVAL, "bad arguments");
+  const size_t bytes = 27 * (size_t)c->N * storage_bytes(c->p.storage);
+  HIP_OK(c, hipMemcpyAsync(c->pop[c->cur], pop_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->t = t;
+  if (c->flags) HIP_OK(c, geometry_init(c));
+  return ELBM_OK;
+}
+
+int elbm_adjoint_step(elbm_ctx* c, int64_t t, void* pop_t_dev, const float* lam_in_dev, float* lam_out_dev,
+                      const double* w_force, float* gF_dev) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->adj_gUR) return fail(c, ELBM_ESTATE, "context created without ELBM_FLAG_ADJOINT");
+  if (!pop_t_dev || !lam_in_dev || !lam_out_dev || t < 0) return fail(c, ELBM_EINVAL, "bad arguments");
+  if (lam_in_dev == lam_out_dev) return fail(c, ELBM_EINVAL, "lam_in and lam_out must not alias");
+  if (gF_dev && !c->bodyforce) return fail(c, ELBM_ESTATE, "gF requested but no body-force field is bound");
+  if (c->p.flags & ELBM_FLAG_STREAM_ONLY) return fail(c, ELBM_ESTATE, "no adjoint in stream-only mode");
+  HIP_OK(c, launch_adjoint(c, t, pop_t_dev, lam_in_dev, lam_out_dev, w_force, gF_dev));
+  return ELBM_OK;
+}
+
+int elbm_adjoint_param_grad(elbm_ctx* c, double* g_amp, int32_t reset) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->adj_gamp) return fail(c, ELBM_ESTATE, "context created without ELBM_FLAG_ADJOINT");
+  if (!g_amp) return fail(c, ELBM_EINVAL, "g_amp is NULL");
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  double h[ELBM_MAX_BODIES];
+  HIP_OK(c, hipMemcpy(h, c->adj_gamp, sizeof h, hipMemcpyDeviceToHost));
+  for (int k = 0; k < c->nb; ++k) g_amp[k] = h[k];
+  if (reset) HIP_OK(c, hipMemsetAsync(c->adj_gamp, 0, sizeof(double) * ELBM_MAX_BODIES, c->stream));
   return ELBM_OK;
 }
 

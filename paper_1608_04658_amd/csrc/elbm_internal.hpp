@@ -180,13 +180,11 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const
   const T sxy = T(0.25) * (M110 - jx * uy), sxz = T(0.25) * (M101 - jx * uz), syz = T(0.25) * (M011 - jy * uz);
 
   T dh[27];
-  T a = T(0), b = T(0);
+  T hm = T(0), hx = T(0), hy = T(0), hz = T(0);
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const T pyz = phy[cy(i) + 1] * phz[cz(i) + 1];
-    const T qyz = psy[cy(i) + 1] * psz[cz(i) + 1];
     const T fe = (rho * pyz) * phx[cx(i) + 1];
-    const T ife = (rinv * qyz) * psx[cx(i) + 1];
     T ds = T(0);
     if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
     if (nnz(i) == 2) {
@@ -195,10 +193,37 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const
       else ds = T(cy(i) * cz(i)) * syz;
     }
     const T h = (f[i] - fe) - ds;
-    const T th = h * ife;
-    b += th * h;
-    if (nnz(i) == 1 || nnz(i) == 2) a += th * ds;
+    hm += h;
+    if (cx(i)) hx += T(cx(i)) * h;
+    if (cy(i)) hy += T(cy(i)) * h;
+    if (cz(i)) hz += T(cz(i)) * h;
     dh[i] = h;
+  }
+  // dh has zero mass and momentum in exact arithmetic; remove the rounding residue of the
+  // equilibrium (its kinematic part in the dual basis: mass on the rest population, momentum on
+  // the face pairs) so that the update conserves rho and j to the rounding of the store alone.
+  dh[13] -= hm;
+  dh[14] -= T(0.5) * hx;
+  dh[12] += T(0.5) * hx;
+  dh[16] -= T(0.5) * hy;
+  dh[10] += T(0.5) * hy;
+  dh[22] -= T(0.5) * hz;
+  dh[4] += T(0.5) * hz;
+  T a = T(0), b = T(0);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const T qyz = psy[cy(i) + 1] * psz[cz(i) + 1];
+    const T ife = (rinv * qyz) * psx[cx(i) + 1];
+    T ds = T(0);
+    if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
+    if (nnz(i) == 2) {
+      if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
+      else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
+      else ds = T(cy(i) * cz(i)) * syz;
+    }
+    const T th = dh[i] * ife;
+    b += th * dh[i];
+    if (nnz(i) == 1 || nnz(i) == 2) a += th * ds;
   }
   const T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * a / b : T(2);
   const T bg = beta * gamma, b2 = T(2) * beta;
@@ -339,6 +364,10 @@ struct elbm_ctx {
   bool moving;
   int64_t t;
   char err[256];
+  // adjoint (ELBM_FLAG_ADJOINT)
+  double* adj_gUR;         // 4 N: dL/dU^t (3 N) and dL/dR^t (N), FP64 scatter targets
+  float* adj_side;         // 9 ny nz: outlet-copy adjoint contributions
+  double* adj_gamp;        // [MAX_BODIES] dL/d(amplitude)
   // sweep timing (HIP events around each bulk-sweep launch)
   bool timing;
   hipEvent_t* ev;
@@ -357,7 +386,15 @@ hipError_t launch_collide_nodes(const float* fin, float* fout, float* gam, const
 hipError_t geometry_init(elbm_ctx* c);
 hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd);
 hipError_t launch_boundary(elbm_ctx* c, const Bodies& bd);
+hipError_t launch_refill(elbm_ctx* c, const Bodies& bd, void* A);
 hipError_t launch_force_reduce(elbm_ctx* c);
+hipError_t launch_adjoint(elbm_ctx* c, int64_t t, const void* A, const float* lam_in, float* lam_out,
+                          const double* w_force, float* gF);
 void host_kinematics(const elbm_body& b, double t, double c[3], double U[3]);
+hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd);
+hipError_t geometry_for_step(elbm_ctx* c, const Bodies& bd);
+Box union_box(const elbm_ctx* c, const Bodies& bd);
+Box full_box(const elbm_ctx* c);
+dim3 grid_for(long n);
 Bodies make_bodies(const elbm_ctx* c, double t);
 }  // namespace elbm

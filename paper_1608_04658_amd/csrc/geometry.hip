@@ -12,6 +12,7 @@
 #include <stdio.h>
 
 #include "elbm_internal.hpp"
+#include "boundary_dev.hpp"
 
 namespace elbm {
 
@@ -58,7 +59,7 @@ Bodies make_bodies(const elbm_ctx* c, double t) {
 
 // Axis-aligned box covering every body at t and t+1 plus a margin (the whole axis when the box
 // would cross a periodic face, or for planes not normal to an axis).
-static Box union_box(const elbm_ctx* c, const Bodies& bd) {
+Box union_box(const elbm_ctx* c, const Bodies& bd) {
   const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   bool full[3] = {false, false, false};
@@ -106,32 +107,13 @@ static Box union_box(const elbm_ctx* c, const Bodies& bd) {
   return box;
 }
 
-static Box full_box(const elbm_ctx* c) {
+Box full_box(const elbm_ctx* c) {
   Box b;
   b.lo[0] = b.lo[1] = b.lo[2] = 0;
   b.n[0] = c->p.nx;
   b.n[1] = c->p.ny;
   b.n[2] = c->p.nz;
   return b;
-}
-
-struct GeoArgs {
-  uint8_t* flags;
-  int32_t nx, ny, nz;
-  int32_t channel;
-  Box box;
-};
-
-__device__ __forceinline__ void box_node(const Box& b, long idx, int& x, int& y, int& z) {
-  x = b.lo[0] + (int)(idx % b.n[0]);
-  y = b.lo[1] + (int)((idx / b.n[0]) % b.n[1]);
-  z = b.lo[2] + (int)(idx / ((long)b.n[0] * b.n[1]));
-}
-
-__device__ __forceinline__ int first_body(const Bodies& bd, bool at_t1, double x, double y, double z) {
-  for (int k = 0; k < bd.nb; ++k)
-    if (inside_body(bd.b[k], at_t1 ? bd.b[k].c1 : bd.b[k].c0, x, y, z)) return k;
-  return -1;
 }
 
 // Masks at a single time level (set-up): solid at t and "t+1" alike.
@@ -161,9 +143,6 @@ __global__ void k_flags_update(GeoArgs g, Bodies bd) {
     g.flags[n] = nf;
   }
 }
-
-// Periodic index for any offset (stencils reach +-2, lattices may be 1 or 2 nodes thick).
-__device__ __forceinline__ int wrap(int v, int n) { return ((v % n) + n) % n; }
 
 // Missing set Dbar is non-empty (a source x - c_i is solid at t+1, or lies through the inlet) or
 // the node was solid at t (refill).
@@ -280,108 +259,25 @@ __global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, flo
 }
 
 // ---------------------------------------------------------------------------------------------
-struct BArgs {
-  const void* A;
-  void* B;
-  const uint8_t* flags;
-  const float* macro;
-  const float* F;
-  const int32_t* list;
-  const uint32_t* dyn_count;
-  double* brec;
-  int64_t n_static;
-  int64_t cap;
-  int32_t moving;
-  int32_t nx, ny, nz;
-  int64_t N;
-  int32_t channel;
-  int32_t fp64;
-  int32_t stream_only;
-  float beta, inv_beta, thr;
-  double rho0;
-  double u_in[3];
-};
-
-__device__ __forceinline__ long node_at(const BArgs& a, int x, int y, int z) {
-  return ((long)z * a.ny + y) * a.nx + x;
-}
-
-// Node x + d, or -1 when it does not exist (outside [0, nx) in channel mode).
-__device__ __forceinline__ long neighbour(const BArgs& a, int x, int y, int z, int dx, int dy, int dz) {
-  int X = x + dx;
-  if (a.channel) {
-    if (X < 0 || X >= a.nx) return -1;
-  } else {
-    X = wrap(X, a.nx);
-  }
-  return node_at(a, X, wrap(y + dy, a.ny), wrap(z + dz, a.nz));
-}
-
-// Velocity gradient by finite differences on U^t (Sec. III), G[3a+b] = d u_a / d x_b.  Per axis:
-// central if both neighbours are usable (exist and fluid at t+1), else second-order one-sided
-// (forward side first), else first-order one-sided, else 0.
-__device__ void grad_u(const BArgs& a, int x, int y, int z, long n0, float (&G)[9]) {
+// Refill before streaming: the uncovered nodes of the step get their Grad populations written into
+// the current buffer A^t, where their neighbours (and the node itself) pull them.
+template <int S>
+__global__ __launch_bounds__(128) void k_refill(const BArgs a, const Bodies bd, void* Aw) {
+  using C = Codec<S>;
+  using E = typename C::E;
+  E* __restrict__ A = (E*)Aw;
+  int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
+  if (count > a.cap) count = a.cap;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
+    const long n = a.list[k];
+    if (!(a.flags[n] & FL_SOLID_PREV)) continue;
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    float f[27], uw[3], G[9], ravg;
+    int kb, m;
+    refill_pops(a, bd, x, y, z, n, f, kb, ravg, m, uw, G);
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const int e0 = b == 0, e1 = b == 1, e2 = b == 2;
-    const long p1 = neighbour(a, x, y, z, e0, e1, e2), p2 = neighbour(a, x, y, z, 2 * e0, 2 * e1, 2 * e2);
-    const long m1 = neighbour(a, x, y, z, -e0, -e1, -e2), m2 = neighbour(a, x, y, z, -2 * e0, -2 * e1, -2 * e2);
-    const bool op1 = p1 >= 0 && !(a.flags[p1] & FL_SOLID), op2 = p2 >= 0 && !(a.flags[p2] & FL_SOLID);
-    const bool om1 = m1 >= 0 && !(a.flags[m1] & FL_SOLID), om2 = m2 >= 0 && !(a.flags[m2] & FL_SOLID);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float* U = a.macro + c * a.N;
-      float d;
-      if (op1 && om1) d = 0.5f * (U[p1] - U[m1]);
-      else if (op1 && op2) d = 0.5f * (-3.f * U[n0] + 4.f * U[p1] - U[p2]);
-      else if (om1 && om2) d = 0.5f * (3.f * U[n0] - 4.f * U[m1] + U[m2]);
-      else if (op1) d = U[p1] - U[n0];
-      else if (om1) d = U[n0] - U[m1];
-      else d = 0.f;
-      G[3 * c + b] = d;
-    }
+    for (int i = 0; i < 27; ++i) C::store(A + i * a.N + n, f[i], wf(i));
   }
-}
-
-// Geometry of boundary link i (i in Dbar) at node (x,y,z): link fraction q, wall velocity u_w and
-// owning body (-1 for the inlet wall at x = -1/2).  q is the ray parameter where x - s c_i meets
-// the surface (FP64): sphere (|d|^2 - R^2)/(d.c_i + sqrt((d.c_i)^2 - |c_i|^2 (|d|^2 - R^2))),
-// plane n.d / n.c_i, d = x - centre(t+1).
-__device__ void link_geometry(const BArgs& a, const Bodies& bd, int i, int x, int y, int z, double& q, double (&uw)[3],
-                              int& kb) {
-  int sx = x - cx(i);
-  if (a.channel && sx < 0) {
-    kb = -1;
-    q = ((double)x + 0.5) / (double)cx(i);
-    uw[0] = a.u_in[0];
-    uw[1] = a.u_in[1];
-    uw[2] = a.u_in[2];
-    return;
-  }
-  if (a.channel) sx = sx >= a.nx ? a.nx - 1 : sx;
-  else sx = wrap(sx, a.nx);
-  const int sy = wrap(y - cy(i), a.ny), sz = wrap(z - cz(i), a.nz);
-  kb = first_body(bd, true, sx, sy, sz);
-  if (kb < 0) kb = 0;
-  const BodyDev& b = bd.b[kb];
-  const double v[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
-  const double d[3] = {x - b.c1[0], y - b.c1[1], z - b.c1[2]};
-  if (b.kind == ELBM_BODY_SPHERE) {
-    const double dv = d[0] * v[0] + d[1] * v[1] + d[2] * v[2];
-    const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] - b.r2;
-    double disc = dv * dv - vv * dd;
-    disc = disc < 0.0 ? 0.0 : disc;
-    q = dd / (dv + sqrt(disc));
-  } else {
-    const double nd = b.n[0] * d[0] + b.n[1] * d[1] + b.n[2] * d[2];
-    const double nv = b.n[0] * v[0] + b.n[1] * v[1] + b.n[2] * v[2];
-    q = nd / nv;
-  }
-  const double r[3] = {d[0] - q * v[0], d[1] - q * v[1], d[2] - q * v[2]};  // x_w - centre
-  uw[0] = b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]);
-  uw[1] = b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]);
-  uw[2] = b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]);
 }
 
 template <int S, bool FORCE>
@@ -400,33 +296,7 @@ __global__ __launch_bounds__(128) void k_boundary(const BArgs a, const Bodies bd
     for (int j = 0; j < nb * 6; ++j) rec[j] = 0.0;
     const uint8_t fl = a.flags[n];
     float f[27];
-    if (fl & FL_SOLID_PREV) {
-      // refill of an uncovered node (Sec. III)
-      int kb = first_body(bd, false, x, y, z);
-      if (kb < 0) kb = 0;
-      const BodyDev& b = bd.b[kb];
-      const double r[3] = {x - b.c1[0], y - b.c1[1], z - b.c1[2]};
-      float uw[3];
-      uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
-      uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
-      uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
-      float rs = 0.f;
-      int m = 0;
-#pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        if (i == 13) continue;
-        const long nn = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
-        if (nn < 0 || (a.flags[nn] & (FL_SOLID | FL_SOLID_PREV))) continue;
-        rs += a.macro[3 * a.N + nn];
-        ++m;
-      }
-      const float ravg = m ? rs / (float)m : (float)a.rho0;
-      float G[9], Pi[6];
-      grad_u(a, x, y, z, n, G);
-      pressure_tensor(ravg, uw, G, a.beta, Pi);
-#pragma unroll
-      for (int i = 0; i < 27; ++i) f[i] = grad_pop(i, ravg, uw, Pi);
-    } else {
+    {
       // missing populations at a wall (Sec. III)
       uint32_t dmask = 0;
 #pragma unroll
@@ -558,7 +428,7 @@ __global__ __launch_bounds__(256) void k_force_reduce(const double* brec, const 
 }
 
 // ---------------------------------------------------------------------------------------------
-static dim3 grid_for(long n) {
+dim3 grid_for(long n) {
   long b = (n + 255) / 256;
   if (b > 8192) b = 8192;
   if (b < 1) b = 1;
@@ -577,18 +447,30 @@ static GeoArgs geo_args(elbm_ctx* c, const Box& box) {
 }
 
 template <int S>
-static void macro_launch(elbm_ctx* c, const Box& box, const Bodies& bd) {
-  hipLaunchKernelGGL(k_macro<S>, grid_for(box.count()), dim3(256), 0, c->stream,
-                     (const typename Codec<S>::E*)c->pop[c->cur], (const uint8_t*)c->flags, c->macro, c->bodyforce, box,
-                     c->p.nx, c->p.ny, (int64_t)c->N, c->p.rho0, bd);
+static void macro_launch(elbm_ctx* c, const void* A, const Box& box, const Bodies& bd) {
+  hipLaunchKernelGGL(k_macro<S>, grid_for(box.count()), dim3(256), 0, c->stream, (const typename Codec<S>::E*)A,
+                     (const uint8_t*)c->flags, c->macro, c->bodyforce, box, c->p.nx, c->p.ny, (int64_t)c->N,
+                     c->p.rho0, bd);
 }
 
-static void macro_box(elbm_ctx* c, const Box& box, const Bodies& bd) {
+static void macro_box(elbm_ctx* c, const void* A, const Box& box, const Bodies& bd) {
   switch (c->p.storage) {
-    case ELBM_STORAGE_F32: macro_launch<ELBM_STORAGE_F32>(c, box, bd); break;
-    case ELBM_STORAGE_F16: macro_launch<ELBM_STORAGE_F16>(c, box, bd); break;
-    default: macro_launch<ELBM_STORAGE_BF16>(c, box, bd);
+    case ELBM_STORAGE_F32: macro_launch<ELBM_STORAGE_F32>(c, A, box, bd); break;
+    case ELBM_STORAGE_F16: macro_launch<ELBM_STORAGE_F16>(c, A, box, bd); break;
+    default: macro_launch<ELBM_STORAGE_BF16>(c, A, box, bd);
   }
+}
+
+// U^t, R^t of the populations A around the bodies and on the inlet slab.
+hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd) {
+  const bool channel = c->p.bc_x == ELBM_BC_CHANNEL;
+  if (c->nb > 0) macro_box(c, A, union_box(c, bd), bd);
+  if (channel) {
+    Box slab = full_box(c);
+    slab.n[0] = c->p.nx < 3 ? c->p.nx : 3;
+    macro_box(c, A, slab, bd);
+  }
+  return hipGetLastError();
 }
 
 // Set-up at the current time level: masks everywhere, then the static part of the boundary list
@@ -638,12 +520,32 @@ hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, g, c->blist, c->n_static, c->blist_cap,
                        &c->cnt->dyn_count, &c->cnt->overflow, 1);
   }
-  if (c->nb > 0) macro_box(c, ub, bd);
-  if (channel) {
-    Box slab = full_box(c);
-    slab.n[0] = c->p.nx < 3 ? c->p.nx : 3;
-    macro_box(c, slab, bd);
+  return macro_fields(c, c->pop[c->cur], bd);
+}
+
+// Masks of both time levels of the step t -> t+1 recomputed from the kinematics alone (so that a
+// reverse sweep can visit the steps in any order), the inlet face marked, then the dynamic list.
+__global__ void k_flags_two(GeoArgs g, Bodies bd) {
+  const long total = g.box.count();
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    box_node(g.box, idx, x, y, z);
+    const long n = ((long)z * g.ny + y) * g.nx + x;
+    const bool s1 = first_body(bd, true, x, y, z) >= 0;
+    const bool s0 = first_body(bd, false, x, y, z) >= 0;
+    uint8_t f = (s1 ? FL_SOLID : 0) | (s0 ? FL_SOLID_PREV : 0);
+    if (g.channel && x == 0 && !s1) f |= FL_SPECIAL;
+    g.flags[n] = f;
   }
+}
+
+hipError_t geometry_for_step(elbm_ctx* c, const Bodies& bd) {
+  if (!c->moving) return hipSuccess;  // fixed geometry: masks and list from the set-up hold
+  const Box fb = full_box(c);
+  hipLaunchKernelGGL(k_flags_two, grid_for(fb.count()), dim3(256), 0, c->stream, geo_args(c, fb), bd);
+  const Box ub = union_box(c, bd);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, geo_args(c, ub), c->blist, c->n_static,
+                     c->blist_cap, &c->cnt->dyn_count, &c->cnt->overflow, 1);
   return hipGetLastError();
 }
 
@@ -654,12 +556,11 @@ static void boundary_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd) {
   else hipLaunchKernelGGL((k_boundary<S, false>), g, b, 0, c->stream, a, bd);
 }
 
-hipError_t launch_boundary(elbm_ctx* c, const Bodies& bd) {
+BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
   const bool channel = c->p.bc_x == ELBM_BC_CHANNEL;
-  if (c->nb == 0 && !channel) return hipSuccess;
   BArgs a;
-  a.A = c->pop[c->cur];
-  a.B = c->pop[c->cur ^ 1];
+  a.A = A;
+  a.B = B;
   a.flags = c->flags;
   a.macro = c->macro;
   a.F = c->bodyforce;
@@ -681,6 +582,25 @@ hipError_t launch_boundary(elbm_ctx* c, const Bodies& bd) {
   a.thr = (float)c->fp64_thr;
   a.rho0 = c->p.rho0;
   for (int e = 0; e < 3; ++e) a.u_in[e] = c->p.u_inlet[e];
+  return a;
+}
+
+hipError_t launch_refill(elbm_ctx* c, const Bodies& bd, void* A) {
+  if (!c->moving) return hipSuccess;  // fixed bodies uncover nothing
+  const BArgs a = boundary_args(c, A, nullptr);
+  const dim3 g(256), b(128);
+  switch (c->p.storage) {
+    case ELBM_STORAGE_F32: hipLaunchKernelGGL(k_refill<ELBM_STORAGE_F32>, g, b, 0, c->stream, a, bd, A); break;
+    case ELBM_STORAGE_F16: hipLaunchKernelGGL(k_refill<ELBM_STORAGE_F16>, g, b, 0, c->stream, a, bd, A); break;
+    default: hipLaunchKernelGGL(k_refill<ELBM_STORAGE_BF16>, g, b, 0, c->stream, a, bd, A);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_boundary(elbm_ctx* c, const Bodies& bd) {
+  const bool channel = c->p.bc_x == ELBM_BC_CHANNEL;
+  if (c->nb == 0 && !channel) return hipSuccess;
+  const BArgs a = boundary_args(c, c->pop[c->cur], c->pop[c->cur ^ 1]);
   switch (c->p.storage) {
     case ELBM_STORAGE_F32: boundary_launch<ELBM_STORAGE_F32>(c, a, bd); break;
     case ELBM_STORAGE_F16: boundary_launch<ELBM_STORAGE_F16>(c, a, bd); break;

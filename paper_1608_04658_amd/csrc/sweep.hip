@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_read_pop(const typename Codec<S>::E* A,
   }
 }
 
-static dim3 grid_for(int64_t N) {
+static dim3 grid_1d(int64_t N) {
   int64_t b = (N + 255) / 256;
   if (b > 65536) b = 65536;
   if (b < 1) b = 1;
@@ -257,13 +257,13 @@ hipError_t launch_init_eq(elbm_ctx* c, const double* rho, const double* u) {
   void* A = c->pop[c->cur];
   switch (c->p.storage) {
     case ELBM_STORAGE_F32:
-      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F32>, grid_for(c->N), dim3(256), 0, c->stream, (float*)A, rho, u, c->N);
+      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F32>, grid_1d(c->N), dim3(256), 0, c->stream, (float*)A, rho, u, c->N);
       break;
     case ELBM_STORAGE_F16:
-      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F16>, grid_for(c->N), dim3(256), 0, c->stream, (_Float16*)A, rho, u, c->N);
+      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F16>, grid_1d(c->N), dim3(256), 0, c->stream, (_Float16*)A, rho, u, c->N);
       break;
     default:
-      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_BF16>, grid_for(c->N), dim3(256), 0, c->stream, (uint16_t*)A, rho, u, c->N);
+      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_BF16>, grid_1d(c->N), dim3(256), 0, c->stream, (uint16_t*)A, rho, u, c->N);
   }
   return hipGetLastError();
 }
@@ -272,13 +272,13 @@ hipError_t launch_write_pop(elbm_ctx* c, const double* src) {
   void* A = c->pop[c->cur];
   switch (c->p.storage) {
     case ELBM_STORAGE_F32:
-      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F32>, grid_for(c->N), dim3(256), 0, c->stream, (float*)A, src, c->N);
+      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F32>, grid_1d(c->N), dim3(256), 0, c->stream, (float*)A, src, c->N);
       break;
     case ELBM_STORAGE_F16:
-      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F16>, grid_for(c->N), dim3(256), 0, c->stream, (_Float16*)A, src, c->N);
+      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F16>, grid_1d(c->N), dim3(256), 0, c->stream, (_Float16*)A, src, c->N);
       break;
     default:
-      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_BF16>, grid_for(c->N), dim3(256), 0, c->stream, (uint16_t*)A, src, c->N);
+      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_BF16>, grid_1d(c->N), dim3(256), 0, c->stream, (uint16_t*)A, src, c->N);
   }
   return hipGetLastError();
 }
@@ -287,14 +287,14 @@ hipError_t launch_read_pop(elbm_ctx* c, double* dst) {
   const void* A = c->pop[c->cur];
   switch (c->p.storage) {
     case ELBM_STORAGE_F32:
-      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F32>, grid_for(c->N), dim3(256), 0, c->stream, (const float*)A, dst, c->N);
+      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F32>, grid_1d(c->N), dim3(256), 0, c->stream, (const float*)A, dst, c->N);
       break;
     case ELBM_STORAGE_F16:
-      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F16>, grid_for(c->N), dim3(256), 0, c->stream, (const _Float16*)A, dst,
+      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F16>, grid_1d(c->N), dim3(256), 0, c->stream, (const _Float16*)A, dst,
                          c->N);
       break;
     default:
-      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_BF16>, grid_for(c->N), dim3(256), 0, c->stream, (const uint16_t*)A, dst,
+      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_BF16>, grid_1d(c->N), dim3(256), 0, c->stream, (const uint16_t*)A, dst,
                          c->N);
   }
   return hipGetLastError();
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_collide_nodes(const float* fin, float* 
 
 hipError_t launch_collide_nodes(const float* fin, float* fout, float* gam, const float* F, int64_t n, double beta,
                                 double thr, hipStream_t s) {
-  hipLaunchKernelGGL(k_collide_nodes, grid_for(n), dim3(256), 0, s, fin, fout, gam, F, n, (float)beta,
+  hipLaunchKernelGGL(k_collide_nodes, grid_1d(n), dim3(256), 0, s, fin, fout, gam, F, n, (float)beta,
                      (float)(1.0 / beta), (float)thr);
   return hipGetLastError();
 }

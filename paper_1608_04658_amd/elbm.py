@@ -22,7 +22,7 @@ STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 BC_PERIODIC, BC_CHANNEL = 0, 1
 BODY_SPHERE, BODY_PLANE = 0, 1
 MAX_BODIES = 8
-FLAG_BODY_FORCE, FLAG_STREAM_ONLY, FLAG_NO_FP64 = 1, 2, 4
+FLAG_BODY_FORCE, FLAG_STREAM_ONLY, FLAG_NO_FP64, FLAG_ADJOINT = 1, 2, 4, 8
 
 
 class ElbmError(RuntimeError):
@@ -80,6 +80,10 @@ def load():
         "elbm_read_flags": [_VP, _VP],
         "elbm_get_info": [_VP, P(Info)],
         "elbm_collide_nodes": [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _VP],
+        "elbm_save_state": [_VP, _VP],
+        "elbm_load_state": [_VP, _VP, ctypes.c_int64],
+        "elbm_adjoint_step": [_VP, ctypes.c_int64, _VP, _VP, _VP, P(ctypes.c_double), _VP],
+        "elbm_adjoint_param_grad": [_VP, P(ctypes.c_double), ctypes.c_int32],
         "elbm_set_timing": [_VP, ctypes.c_int32],
         "elbm_get_timing": [_VP, P(ctypes.c_double), P(ctypes.c_int64)],
     }
@@ -225,6 +229,30 @@ def elbm_get_info(ctx) -> Info:
     return info
 
 
+def elbm_save_state(ctx, pop_dev):
+    _check(load().elbm_save_state(ctx, _ptr(pop_dev)), ctx)
+
+
+def elbm_load_state(ctx, pop_dev, t: int):
+    _check(load().elbm_load_state(ctx, _ptr(pop_dev), int(t)), ctx)
+
+
+def elbm_adjoint_step(ctx, t: int, pop_t_dev, lam_in_dev, lam_out_dev, w_force=None, gF_dev=None):
+    w = None
+    if w_force is not None:
+        arr = np.ascontiguousarray(np.asarray(w_force, dtype=np.float64).reshape(-1))
+        w = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(load().elbm_adjoint_step(ctx, int(t), _ptr(pop_t_dev), _ptr(lam_in_dev), _ptr(lam_out_dev), w,
+                                    _ptr(gF_dev)), ctx)
+
+
+def elbm_adjoint_param_grad(ctx, nbodies: int, reset: bool = True) -> np.ndarray:
+    out = np.zeros(max(1, nbodies))
+    _check(load().elbm_adjoint_param_grad(ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          1 if reset else 0), ctx)
+    return out[:nbodies]
+
+
 def elbm_set_timing(ctx, enable: bool):
     _check(load().elbm_set_timing(ctx, 1 if enable else 0), ctx)
 
@@ -338,6 +366,18 @@ class Lattice:
 
     def info(self) -> Info:
         return elbm_get_info(self.ctx)
+
+    def state_tensor(self):
+        """A new device tensor holding a copy of the current populations in storage format."""
+        torch = self.torch
+        dt = {0: torch.float32, 1: torch.float16, 2: torch.int16}[self.params.storage]
+        nx, ny, nz = self.shape
+        out = torch.empty((27, nz, ny, nx), dtype=dt, device="cuda")
+        elbm_save_state(self.ctx, out)
+        return out
+
+    def load_state(self, state, t):
+        elbm_load_state(self.ctx, state, t)
 
     def population_view(self):
         """Zero-copy view of the current population storage (27, nz, ny, nx) in the workspace."""

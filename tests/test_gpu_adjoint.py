@@ -1,0 +1,192 @@
+"""Hand-written adjoint (HIP) against central finite differences of the FP64 oracle.
+
+Single step (dot-product identity): for random lam' and dA,
+    <lam', J dA> + w . dF/dA[dA]  ==  <lam_gpu, dA>,
+with J dA and dF/dA[dA] from central differences of one oracle step; likewise for the body-force
+field (direction v) and the amplitude.  Solid masks are frozen at the nominal ones (their
+derivative is zero).  Rollouts: dL/d(amp) and <dL/dF, v> of a windowed mean drag, vs central
+differences (h = 1e-3) of oracle rollouts with the masks of the nominal run.  Bound: 1e-4 relative
+for rollouts (FP32 adjoint vs FP64 differences), 2e-5 for a single step."""
+import numpy as np
+import pytest
+
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def E(torch_cuda):
+    from paper_1608_04658_amd import elbm
+    elbm.load()
+    return elbm
+
+
+@pytest.fixture(scope="module")
+def O(oracle_mod):
+    return oracle_mod
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _oracle_step(O, cfg, A, t, masks, F, amp):
+    body = dict(cfg["body"])
+    body["amp"] = amp
+    s = O.Simulation(cfg["shape"], cfg["nu"], A0=A, bodies=[body], channel=cfg["channel"], u_in=cfg["u_in"], F=F)
+    s.t = t
+    s.solid = masks[t].copy()
+    s.frozen_masks = masks
+    s.step(1)
+    return s.A.copy(), s.forces[-1][0, :3].copy()
+
+
+SMALL = dict(shape=(40, 20, 20), nu=0.02, channel=True, u_in=(0.03, 0.0, 0.0),
+             body=WL.sphere((16.3, 10.2, 9.9), 4.0, amp=2.0, period=60.0, direction=(0, 1, 0)))
+
+
+@pytest.mark.parametrize("t0", [7, 15])
+def test_single_step_adjoint_dot_products(E, O, torch_cuda, t0):
+    torch = torch_cuda
+    cfg = SMALL
+    nx, ny, nz = cfg["shape"]
+    rng = np.random.default_rng(100 + t0)
+    F = rng.uniform(-1e-5, 1e-5, size=(3, nz, ny, nx)).astype(np.float32).astype(np.float64)
+    rho, u = WL.uniform_flow(cfg["shape"], cfg["u_in"])
+    # state at t0 from the oracle itself, rounded to FP32 so both sides see the same numbers
+    s = O.Simulation(cfg["shape"], cfg["nu"], rho, u, bodies=[cfg["body"]], channel=True, u_in=cfg["u_in"], F=F)
+    masks = []
+    s.step(t0 + 1, record_masks=masks)
+    masks = {k: m for k, m in enumerate(masks)}
+    # the step under test is t0 -> t0+1; rebuild the state at t0
+    s2 = O.Simulation(cfg["shape"], cfg["nu"], rho, u, bodies=[cfg["body"]], channel=True, u_in=cfg["u_in"], F=F)
+    s2.step(t0)
+    A = s2.A.astype(np.float32).astype(np.float64)
+    refill = int(((masks[t0] > 0) & (masks[t0 + 1] == 0)).sum())
+    _say(f"t0={t0}: refill nodes in the step = {refill}")
+    lam1 = rng.standard_normal(A.shape)
+    lam1[:, masks[t0 + 1] > 0] = 0.0
+    lam1 = lam1.astype(np.float32).astype(np.float64)
+    w = np.array([0.7, -0.3, 0.2])
+    dA = rng.standard_normal(A.shape)
+    v = rng.uniform(-1e-6, 1e-6, size=F.shape)
+    amp = cfg["body"]["amp"]
+
+    # ---- GPU adjoint
+    lat = E.Lattice(cfg["shape"], cfg["nu"], channel=True, u_inlet=cfg["u_in"], max_bodies=1,
+                    flags=E.FLAG_BODY_FORCE | E.FLAG_ADJOINT)
+    lat.write_populations(A, t0)
+    lat.set_bodies([cfg["body"]])
+    lat.set_body_force(F)
+    state = lat.state_tensor()
+    lam_in = torch.tensor(lam1, dtype=torch.float32, device="cuda")
+    lam_out = torch.empty_like(lam_in)
+    gF = torch.zeros((3, nz, ny, nx), dtype=torch.float32, device="cuda")
+    E.elbm_adjoint_param_grad(lat.ctx, 1, reset=True)
+    E.elbm_adjoint_step(lat.ctx, t0, state, lam_in, lam_out, w, gF)
+    torch.cuda.synchronize()
+    lam0 = lam_out.double().cpu().numpy()
+    gFn = gF.double().cpu().numpy()
+    gamp = E.elbm_adjoint_param_grad(lat.ctx, 1, reset=True)[0]
+
+    # ---- FP64 central differences of the oracle step
+    def L(Ax, Fx, ampx):
+        A1, f1 = _oracle_step(O, cfg, Ax, t0, masks, Fx, ampx)
+        return np.sum(lam1 * A1) + w @ f1
+
+    h = 1e-6
+    lhs = (L(A + h * dA, F, amp) - L(A - h * dA, F, amp)) / (2 * h)
+    rhs = np.sum(lam0 * dA)
+    _say(f"dA: FD {lhs:.8e}  adjoint {rhs:.8e}  rel {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) <= 2e-5 * abs(lhs)
+    hF = 1e-2
+    lhsF = (L(A, F + hF * v, amp) - L(A, F - hF * v, amp)) / (2 * hF)
+    rhsF = np.sum(gFn * v)
+    _say(f"F : FD {lhsF:.8e}  adjoint {rhsF:.8e}  rel {abs(lhsF - rhsF) / abs(lhsF):.2e}")
+    assert abs(lhsF - rhsF) <= 2e-4 * abs(lhsF)
+    ha = 1e-4
+    lhsA = (L(A, F, amp + ha) - L(A, F, amp - ha)) / (2 * ha)
+    _say(f"amp: FD {lhsA:.8e}  adjoint {gamp:.8e}  rel {abs(lhsA - gamp) / abs(lhsA):.2e}")
+    assert abs(lhsA - gamp) <= 2e-4 * abs(lhsA)
+
+
+def _rollout_case(O, E, torch, cfg, steps, window, K, seed, h_amp=1e-3, h_F=1e-3):
+    from paper_1608_04658_amd.adjoint import ForceLoss, ForceRollout, window_weights
+    nx, ny, nz = cfg["shape"]
+    Fh = WL.body_force(cfg["shape"], seed, 1e-6).astype(np.float32).astype(np.float64)
+    v = WL.body_force(cfg["shape"], seed + 1, 1e-6)
+    wts = window_weights(steps, window[0], window[1])
+    rho, u = WL.uniform_flow(cfg["shape"], cfg["u_in"])
+    amp0 = cfg["body"]["amp"]
+    # GPU: forward + hand-written adjoint through torch.autograd
+    ro = ForceRollout(cfg["shape"], cfg["nu"], cfg["body"], steps, wts, checkpoint=K, channel=True,
+                      u_in=cfg["u_in"], rho=rho, u=u)
+    Ft = torch.tensor(Fh, dtype=torch.float32, device="cuda", requires_grad=True)
+    at = torch.tensor(amp0, dtype=torch.float64, requires_grad=True)
+    Lg = ForceLoss.apply(Ft, at, ro)
+    Lg.backward()
+    gA = float(at.grad)
+    gFv = float(np.sum(Ft.grad.double().cpu().numpy() * v))
+
+    # oracle: nominal run records the masks; perturbed runs reuse them
+    def run(amp, F, masks=None):
+        body = dict(cfg["body"])
+        body["amp"] = amp
+        s = O.Simulation(cfg["shape"], cfg["nu"], rho, u, bodies=[body], channel=True, u_in=cfg["u_in"], F=F)
+        rec = []
+        if masks is not None:
+            s.frozen_masks = masks
+            s.solid = masks[0].copy()
+        s.step(steps, record_masks=rec if masks is None else None)
+        f = np.array([x[0, :3] for x in s.forces])
+        return float(np.sum(wts * f)), rec
+
+    L0, masks = run(amp0, Fh)
+    Lp, _ = run(amp0 + h_amp, Fh, masks)
+    Lm, _ = run(amp0 - h_amp, Fh, masks)
+    fdA = (Lp - Lm) / (2 * h_amp)
+    Lp, _ = run(amp0, Fh + h_F * v, masks)
+    Lm, _ = run(amp0, Fh - h_F * v, masks)
+    fdF = (Lp - Lm) / (2 * h_F)
+    return float(Lg), L0, gA, fdA, gFv, fdF
+
+
+def test_rollout_gradients_small_channel(E, O, torch_cuda):
+    """48x24x24 channel, sphere R = 4 oscillating (amplitude 2, period 200), body force field, 60
+    steps, mean drag over steps 20..60, checkpoints every 10 steps."""
+    torch = torch_cuda
+    cfg = dict(shape=(48, 24, 24), nu=0.02, channel=True, u_in=(0.03, 0.0, 0.0),
+               body=WL.sphere((16.2, 12.1, 11.8), 4.0, amp=2.0, period=200.0, direction=(0, 1, 0)))
+    Lg, L0, gA, fdA, gFv, fdF = _rollout_case(O, E, torch, cfg, 60, (20, 60), 10, seed=21)
+    _say(f"L gpu {Lg:.8e} oracle {L0:.8e}; dL/dA adjoint {gA:.8e} FD {fdA:.8e} rel {abs(gA - fdA) / abs(fdA):.2e}; "
+         f"<dL/dF,v> adjoint {gFv:.8e} FD {fdF:.8e} rel {abs(gFv - fdF) / abs(fdF):.2e}")
+    assert abs(Lg - L0) <= 1e-4 * abs(L0)
+    assert abs(gA - fdA) <= 1e-4 * abs(fdA)
+    assert abs(gFv - fdF) <= 1e-4 * abs(fdF)
+
+
+@pytest.mark.timeout(600)
+def test_rollout_gradients_adj128(E, O, torch_cuda):
+    """The differentiable workload: 128x64x64 channel, inlet 0.03, sphere R = 8 at (32,32,32)
+    oscillating in y with amplitude 4 and period 2000, body force uniform in [-1e-6, 1e-6]
+    (seed 1610), loss = mean drag over steps 100..300, checkpoints every 20 steps."""
+    torch = torch_cuda
+    w = WL.WORKLOADS["adj128"]
+    cfg = dict(shape=w["shape"], nu=w["nu"], channel=True, u_in=w["u_in"], body=w["bodies"][0])
+    Lg, L0, gA, fdA, gFv, fdF = _rollout_case(O, E, torch, cfg, 300, w["loss_window"], w["checkpoint"],
+                                              seed=w["force_seed"])
+    _say(f"adj128: L gpu {Lg:.8e} oracle {L0:.8e}; dL/dA adjoint {gA:.8e} FD {fdA:.8e} "
+         f"rel {abs(gA - fdA) / abs(fdA):.2e}; <dL/dF,v> adjoint {gFv:.8e} FD {fdF:.8e} "
+         f"rel {abs(gFv - fdF) / abs(fdF):.2e}")
+    assert abs(Lg - L0) <= 1e-4 * abs(L0)
+    assert abs(gA - fdA) <= 1e-4 * abs(fdA)
+    assert abs(gFv - fdF) <= 1e-4 * abs(fdF)

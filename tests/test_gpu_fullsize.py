@@ -1,0 +1,161 @@
+"""GPU path at the benchmark sizes, in the benchmark's launch configuration, checked on sampled
+outputs that the oracle computes node by node, and on properties that hold at any size.
+Reduced-precision storage (FP16 / BF16 deviations f - W) is checked against the oracle with bounds
+derived from the storage rounding."""
+import numpy as np
+import pytest
+
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def E(torch_cuda):
+    from paper_1608_04658_amd import elbm
+    elbm.load()
+    return elbm
+
+
+@pytest.fixture(scope="module")
+def O(oracle_mod):
+    return oracle_mod
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _oracle_one_step_at(O, rho, u, nu, nodes, shape):
+    """Oracle value of A^1 at sampled nodes: pull feq(rho, u) of the 27 source nodes, collide."""
+    nx, ny, nz = shape
+    c, _ = O.lattice()
+    beta = O.beta_from_nu(nu)
+    out = np.zeros((len(nodes), 27))
+    for k, (z, y, x) in enumerate(nodes):
+        f = np.zeros(27)
+        for i in range(27):
+            zs, ys, xs = (z - c[i, 2]) % nz, (y - c[i, 1]) % ny, (x - c[i, 0]) % nx
+            f[i] = O.feq(rho[zs, ys, xs], u[:, zs, ys, xs])[i]
+        out[k] = O.collide(f, beta)[0]
+    return out
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16", 6e-5), ("bf16", 5e-4)])
+def test_turb256_one_step_sampled(E, O, torch_cuda, storage, tol):
+    """256^3 seeded turbulence (the headline workload): one step on the GPU against the oracle at
+    600 sampled nodes.  Bounds: FP32 ~ 2 x 8 ulp of 0.3 (f' ~ 2 feq - f, feq from hardware reciprocal
+    and square root); FP16 / BF16: half an ulp of the largest
+    stored deviation (|d| < 0.06 here: 2^-15 and 2^-12) for the input and the output."""
+    torch = torch_cuda
+    w = WL.WORKLOADS["turb256"]
+    _say(f"case: turb256 {storage} one step, sampled")
+    rho, u = WL.initial_field("turb256")
+    lat = E.Lattice(w["shape"], w["nu"], storage=storage)
+    lat.init_equilibrium(rho, u)
+    lat.step(1)
+    pops = lat.populations()
+    rng = np.random.default_rng(2)
+    nodes = [tuple(rng.integers(0, 256, 3)) for _ in range(600)]
+    idx = torch.tensor([(z * 256 + y) * 256 + x for z, y, x in nodes], device="cuda")
+    got = pops.reshape(27, -1)[:, idx].T.cpu().numpy()
+    ref = _oracle_one_step_at(O, rho, u, w["nu"], nodes, w["shape"])
+    err = np.max(np.abs(got - ref))
+    _say(f"turb256 {storage} max|df| at samples = {err:.3e}")
+    assert err < tol
+    del pops, lat
+    torch.cuda.empty_cache()
+
+
+def test_turb256_properties_after_many_steps(E, torch_cuda):
+    """Global invariants over 200 steps at full size: mass and momentum conserved to the rounding of
+    the FP32 stores (unbiased, so it random-walks: ~1e-10 relative here), populations finite and
+    positive, kinetic energy decreasing."""
+    torch = torch_cuda
+    w = WL.WORKLOADS["turb256"]
+    rho, u = WL.initial_field("turb256")
+    lat = E.Lattice(w["shape"], w["nu"])
+    lat.init_equilibrium(rho, u)
+    c = torch.tensor([[i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1] for i in range(27)], dtype=torch.float64,
+                     device="cuda")
+
+    def moments():
+        p = lat.populations().reshape(27, -1)
+        r = p.sum(0)
+        j = c.T @ p
+        return r.sum().item(), j.sum(1).cpu().numpy(), (0.5 * (j * j).sum(0) / r).sum().item(), p.min().item()
+
+    m0, j0, k0, _ = moments()
+    kes = [k0]
+    for _ in range(4):
+        lat.step(50)
+        m, j, k, pmin = moments()
+        kes.append(k)
+        _say(f"mass drift {abs(m - m0) / m0:.2e}, momentum {np.abs(j - j0).max():.2e}, KE {k:.6e}, min f {pmin:.4e}")
+        assert abs(m - m0) / m0 < 1e-8
+        assert np.abs(j - j0).max() < 1e-9 * m0
+        assert pmin > 0
+    assert all(kes[i + 1] < kes[i] for i in range(len(kes) - 1))
+
+
+def test_turb512_reduced_storage_sampled(E, O, torch_cuda):
+    """512^3 (the reduced-storage workload) with FP16 deviations: one step at 300 sampled nodes
+    against the oracle fed with the same (device-generated) initial field."""
+    torch = torch_cuda
+    w = WL.WORKLOADS["turb512"]
+    r5, u5 = WL.turbulence_device(512, w["k0"], w["urms"], w["seed"])
+    rng = np.random.default_rng(3)
+    nodes = [tuple(rng.integers(0, 512, 3)) for _ in range(300)]
+    # host copies of the initial field around the sampled nodes
+    u_h = {}
+    r_h = {}
+    for z, y, x in nodes:
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    key = ((z + dz) % 512, (y + dy) % 512, (x + dx) % 512)
+                    if key not in u_h:
+                        u_h[key] = None
+    keys = list(u_h)
+    kt = torch.tensor([(a * 512 + b) * 512 + cc for a, b, cc in keys], device="cuda")
+    uu = u5.reshape(3, -1)[:, kt].T.cpu().numpy()
+    rr = r5.reshape(-1)[kt].cpu().numpy()
+    for k, key in enumerate(keys):
+        u_h[key] = uu[k]
+        r_h[key] = rr[k]
+    c, _ = O.lattice()
+    beta = O.beta_from_nu(w["nu"])
+    ref = np.zeros((len(nodes), 27))
+    for k, (z, y, x) in enumerate(nodes):
+        f = np.zeros(27)
+        for i in range(27):
+            key = ((z - c[i, 2]) % 512, (y - c[i, 1]) % 512, (x - c[i, 0]) % 512)
+            f[i] = O.feq(r_h[key], u_h[key])[i]
+        ref[k] = O.collide(f, beta)[0]
+    for storage, tol in (("f16", 6e-5), ("bf16", 5e-4)):
+        _say(f"case: turb512 {storage}")
+        lat = E.Lattice(w["shape"], w["nu"], storage=storage)
+        E.elbm_init_equilibrium(lat.ctx, r5, u5)
+        lat.step(1)
+        view = lat.population_view().reshape(27, -1)
+        idx = torch.tensor([(z * 512 + y) * 512 + x for z, y, x in nodes], device="cuda")
+        raw = view[:, idx]
+        if storage == "f16":
+            d = raw.float()
+        else:
+            d = (raw.to(torch.int32) << 16).view(torch.float32)
+        wts = torch.tensor(O.lattice()[1], device="cuda", dtype=torch.float64)
+        got = (d.double() + wts[:, None]).T.cpu().numpy()
+        err = np.max(np.abs(got - ref))
+        _say(f"turb512 {storage} max|df| at samples = {err:.3e}")
+        assert err < tol
+        del view, raw, lat
+        torch.cuda.empty_cache()

@@ -227,9 +227,10 @@ def test_solid_mask_matches_brute_force(O):
 
 
 def test_refill_sets_density_average_and_wall_velocity(O, lat):
-    """Sec. III refill: an uncovered node gets Grad's distribution with the wall velocity and a
-    local density average; collision conserves both, so they are the node's moments after the step."""
+    """Sec. III refill: an uncovered node gets Grad's distribution with the wall velocity, a local
+    density average and the pressure tensor, so its populations carry exactly those moments."""
     c, _ = lat
+    cc = c.astype(float)
     rng = np.random.default_rng(3)
     n = 18
     b = WL.sphere((7.0, 9.0, 9.0), 4.0, vel=(0.3, 0.0, 0.0), omega=(0.0, 0.0, 0.02))
@@ -239,26 +240,55 @@ def test_refill_sets_density_average_and_wall_velocity(O, lat):
     bb = O.body_from_spec(b)
     checked = 0
     for step in range(4):
+        s1 = s.mask(s.t + 1)
+        Aw, cnt, U, R = s.refill_state(s1)
         r_prev, _ = s.moments()
-        solid_prev = s.solid.copy()
-        s.step(1)
-        r, j = s.moments()
-        cen, Ub = O.kinematics(bb, s.t)
-        refill = np.argwhere((solid_prev > 0) & (s.solid == 0))
+        cen, Ub = O.kinematics(bb, s.t + 1)
+        refill = np.argwhere((s.solid > 0) & (s1 == 0))
+        assert cnt == len(refill)
         for z, y, x in refill:
             vals = []
             for i in range(27):
                 if i == 13:
                     continue
                 zz, yy, xx = (z + c[i, 2]) % n, (y + c[i, 1]) % n, (x + c[i, 0]) % n
-                if solid_prev[zz, yy, xx] == 0 and s.solid[zz, yy, xx] == 0:
+                if s.solid[zz, yy, xx] == 0 and s1[zz, yy, xx] == 0:
                     vals.append(r_prev[zz, yy, xx])
             ravg = np.mean(vals) if vals else 1.0
             uw = Ub + np.cross([0.0, 0.0, 0.02], np.array([x, y, z], float) - cen)
-            assert abs(r[z, y, x] - ravg) < 1e-14
-            assert np.allclose(j[:, z, y, x], ravg * uw, atol=1e-14)
+            f = Aw[:, z, y, x]
+            G = s.grad_u(U, s1, x, y, z)
+            Pi = O.pressure(ravg, uw, G, s.grid.beta)
+            assert abs(f.sum() - ravg) < 1e-14
+            assert np.allclose(cc.T @ f, ravg * uw, atol=1e-15)
+            assert np.allclose(np.einsum("i,ia,ib->ab", f, cc, cc), Pi, atol=1e-14)
             checked += 1
+        s.step(1)
     assert checked > 10
+
+
+def test_refilled_populations_stream_to_the_neighbours(O, lat):
+    """The refill comes before streaming: in a stream-only step the neighbours of an uncovered node
+    receive its refilled populations unchanged."""
+    c, _ = lat
+    n = 16
+    b = WL.sphere((6.5, 8.2, 8.1), 3.5, vel=(0.4, 0.0, 0.0))
+    rho, u = WL.uniform_flow((n, n, n), (0.02, 0.0, 0.0))
+    s = O.Simulation((n, n, n), 0.05, rho, u, bodies=[b], stream_only=True)
+    s.step(2)
+    s1 = s.mask(s.t + 1)
+    Aw, cnt, _, _ = s.refill_state(s1)
+    assert cnt > 0
+    s.step(1)
+    hits = 0
+    s0 = s.mask(s.t - 1)   # refill nodes of the step just taken: solid at its start, fluid at its end
+    for z, y, x in np.argwhere((s0 > 0) & (s1 == 0)):
+        for i in range(27):
+            zz, yy, xx = (z + c[i, 2]) % n, (y + c[i, 1]) % n, (x + c[i, 0]) % n
+            if s1[zz, yy, xx] == 0:
+                assert s.A[i, zz, yy, xx] == Aw[i, z, y, x]
+                hits += 1
+    assert hits > 20
 
 
 def test_finite_difference_stencil(O):

@@ -45,7 +45,7 @@ extern "C" {
 #define ELBM_ENONFINITE (-5) /* non-finite or non-positive population found */
 
 /* storage of the populations in HBM */
-#define ELBM_STORAGE_F32 0   /* f_i as binary32 */
+#define ELBM_STORAGE_F32 0   /* d_i = f_i - W_i as binary32 */
 #define ELBM_STORAGE_F16 1   /* d_i = f_i - W_i as binary16 (round to nearest even) */
 #define ELBM_STORAGE_BF16 2  /* d_i = f_i - W_i as bfloat16 (round to nearest even) */
 

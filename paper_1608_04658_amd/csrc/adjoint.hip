@@ -9,7 +9,8 @@
 // Data flow of a reverse step (all on the context's stream):
 //   k_adj_bulk      per fluid node: collision VJP, then the transpose of the pull -- every
 //                   (source, direction) entry of dL/dA^t is written exactly once by the node that
-//                   pulled it, so the scatter needs no atomics;  solid nodes write zeros.
+//                   pulled it, so the scatter needs no atomics;  solid nodes write zeros.  Nodes with
+//                   <dh|dh> at the FP32 noise floor are queued for k_adj_fixup (FP64).
 //   k_adj_boundary  per boundary/refill node: the adjoint of the reconstruction (Grad populations,
 //                   targets, finite-difference gradient, force term of the loss); contributions to
 //                   U^t and R^t of other nodes go to FP64 accumulators.
@@ -240,7 +241,7 @@ __device__ inline long pull_source(const BArgs& a, int i, int x, int y, int z) {
 }
 
 template <int S, bool FLAGS, bool FORCE>
-__global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j) {
+__global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j, uint32_t* queue, DevCounters* cnt) {
   using C = Codec<S>;
   using E = typename C::E;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,13 +269,64 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
     Fy = a.F[a.N + n];
     Fz = a.F[2 * a.N + n];
   }
-  collide_vjp<FORCE>(f, gp, a.beta, Fx, Fy, Fz, a.thr, a.fp64, g, gF);
+  const VjpOut<float> r = kbc_vjp<float, FORCE>(f, gp, a.beta, Fx, Fy, Fz, g, gF);
+  if (a.fp64 && !(r.b >= a.thr * r.rho)) {
+    // <dh|dh> at the FP32 noise floor: this node's VJP is redone in FP64 by k_adj_fixup
+    queue[atomicAdd(&cnt->fix_count, 1u)] = (uint32_t)n;
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, g[i]);
   if (FORCE && j.gF) {
     j.gF[n] += gF[0];
     j.gF[a.N + n] += gF[1];
     j.gF[2 * a.N + n] += gF[2];
+  }
+}
+
+// FP64 collision VJP of the queued bulk nodes (same gather, same pushes); the last block resets the
+// queue.
+template <int S, bool FORCE>
+__global__ __launch_bounds__(256) void k_adj_fixup(const BArgs a, const AdjArgs j, const uint32_t* queue,
+                                                   DevCounters* cnt) {
+  using C = Codec<S>;
+  using E = typename C::E;
+  const uint32_t count = __atomic_load_n(&cnt->fix_count, __ATOMIC_RELAXED);
+  const E* __restrict__ A = (const E*)a.A;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
+    const long n = queue[k];
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    double f[27], gp[27], g[27], gF[3];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      f[i] = (double)C::load_dev(A + i * a.N + pull_source(a, i, x, y, z)) + wd(i);  // exact widening
+      gp[i] = (double)j.lam_in[i * a.N + n];
+    }
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    if (FORCE) {
+      Fx = a.F[n];
+      Fy = a.F[a.N + n];
+      Fz = a.F[2 * a.N + n];
+    }
+    kbc_vjp<double, FORCE>(f, gp, (double)a.beta, Fx, Fy, Fz, g, gF);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, (float)g[i]);
+    if (FORCE && j.gF) {
+      j.gF[n] += (float)gF[0];
+      j.gF[a.N + n] += (float)gF[1];
+      j.gF[2 * a.N + n] += (float)gF[2];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t t = atomicAdd(&cnt->fix_ticket, 1u);
+    if (t == gridDim.x - 1) {
+      cnt->fix_total = count;
+      cnt->fix_count = 0;
+      cnt->fix_ticket = 0;
+      __threadfence();
+    }
   }
 }
 
@@ -689,10 +741,15 @@ static void adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, const AdjA
   const dim3 blk(bx, 256 / bx, 1);
   const dim3 grd((c->p.nx + bx - 1) / bx, (c->p.ny + blk.y - 1) / blk.y, c->p.nz);
   const bool geo = c->flags != nullptr, force = c->bodyforce != nullptr;
-  if (geo && force) hipLaunchKernelGGL((k_adj_bulk<S, true, true>), grd, blk, 0, c->stream, a, j);
-  else if (geo) hipLaunchKernelGGL((k_adj_bulk<S, true, false>), grd, blk, 0, c->stream, a, j);
-  else if (force) hipLaunchKernelGGL((k_adj_bulk<S, false, true>), grd, blk, 0, c->stream, a, j);
-  else hipLaunchKernelGGL((k_adj_bulk<S, false, false>), grd, blk, 0, c->stream, a, j);
+  uint32_t* q = (uint32_t*)c->fix_list;
+  if (geo && force) hipLaunchKernelGGL((k_adj_bulk<S, true, true>), grd, blk, 0, c->stream, a, j, q, c->cnt);
+  else if (geo) hipLaunchKernelGGL((k_adj_bulk<S, true, false>), grd, blk, 0, c->stream, a, j, q, c->cnt);
+  else if (force) hipLaunchKernelGGL((k_adj_bulk<S, false, true>), grd, blk, 0, c->stream, a, j, q, c->cnt);
+  else hipLaunchKernelGGL((k_adj_bulk<S, false, false>), grd, blk, 0, c->stream, a, j, q, c->cnt);
+  if (a.fp64) {
+    if (force) hipLaunchKernelGGL((k_adj_fixup<S, true>), dim3(256), dim3(256), 0, c->stream, a, j, q, c->cnt);
+    else hipLaunchKernelGGL((k_adj_fixup<S, false>), dim3(256), dim3(256), 0, c->stream, a, j, q, c->cnt);
+  }
   if (geo) {
     const dim3 gf = grid_for((long)c->p.ny * c->p.nz);
     if (a.channel) hipLaunchKernelGGL(k_adj_faces_zero, gf, dim3(256), 0, c->stream, a, j);

@@ -35,7 +35,8 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t pop[2], cnt, fix_list, flags, macro, blist, brec, ring, scratch, adj_gUR, adj_side, adj_gamp, total;
+  size_t pop[2], cnt, fix_list, flags, macro, blist, brec, ring, force_partial, scratch, scan_tmp, adj_gUR, adj_side, adj_gamp, total;
+  int64_t scan_blocks;
   int64_t cap;
   bool geometry;
 };
@@ -89,6 +90,9 @@ Layout layout(const elbm_params* p) {
     L.blist = take(4 * (size_t)L.cap);
     L.brec = take(sizeof(double) * 6 * nbm * (size_t)L.cap);
     L.ring = take(sizeof(double) * 6 * ELBM_MAX_BODIES * ring);
+    L.force_partial = take(sizeof(double) * 64 * 6 * ELBM_MAX_BODIES);
+    L.scan_blocks = (int64_t)((N + 255) / 256);
+    L.scan_tmp = take(sizeof(uint32_t) * 2 * (size_t)L.scan_blocks);
   }
   if (p->flags & ELBM_FLAG_ADJOINT) {
     L.adj_gUR = take(sizeof(double) * 4 * N);
@@ -150,11 +154,14 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->blist = L.geometry ? (int32_t*)(c->ws + L.blist) : nullptr;
   c->brec = L.geometry ? (double*)(c->ws + L.brec) : nullptr;
   c->ring = L.geometry ? (double*)(c->ws + L.ring) : nullptr;
+  c->force_partial = L.geometry ? (double*)(c->ws + L.force_partial) : nullptr;
   const bool adj = (p->flags & ELBM_FLAG_ADJOINT) != 0;
   c->adj_gUR = adj ? (double*)(c->ws + L.adj_gUR) : nullptr;
   c->adj_side = adj ? (float*)(c->ws + L.adj_side) : nullptr;
   c->adj_gamp = adj ? (double*)(c->ws + L.adj_gamp) : nullptr;
   c->blist_cap = L.cap;
+  c->scan_tmp = L.geometry ? (uint32_t*)(c->ws + L.scan_tmp) : nullptr;
+  c->scan_blocks = L.geometry ? L.scan_blocks : 0;
   c->n_static = 0;
   c->bodyforce = nullptr;
   c->nb = 0;

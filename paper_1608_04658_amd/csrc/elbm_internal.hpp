@@ -32,18 +32,23 @@ constexpr uint8_t FL_SOLID_PREV = 2;  // solid at the previous time level (t)
 constexpr uint8_t FL_SPECIAL = 4;     // handled by the boundary kernel (missing populations or refill)
 
 // ---------------------------------------------------------------------------------------------
-// Population storage.  F32 stores f; F16/BF16 store the deviation d = f - W_i, rounded to
-// nearest even; all arithmetic is FP32.
+// Population storage: every format stores the deviation d = f - W_i from the lattice weight (FP32,
+// or FP16 / BF16 rounded to nearest even); arithmetic is FP32 (FP64 on the recomputation path).
+// load/store take absolute populations, load_dev/store_dev deviations.
 template <int S> struct Codec;
 template <> struct Codec<ELBM_STORAGE_F32> {
   using E = float;
-  static __device__ __forceinline__ float load(const E* p, float) { return *p; }
-  static __device__ __forceinline__ void store(E* p, float v, float) { *p = v; }
+  static __device__ __forceinline__ float load(const E* p, float w) { return *p + w; }
+  static __device__ __forceinline__ void store(E* p, float v, float w) { *p = v - w; }
+  static __device__ __forceinline__ float load_dev(const E* p) { return *p; }
+  static __device__ __forceinline__ void store_dev(E* p, float d) { *p = d; }
 };
 template <> struct Codec<ELBM_STORAGE_F16> {
   using E = _Float16;
   static __device__ __forceinline__ float load(const E* p, float w) { return (float)(*p) + w; }
   static __device__ __forceinline__ void store(E* p, float v, float w) { *p = (_Float16)(v - w); }
+  static __device__ __forceinline__ float load_dev(const E* p) { return (float)(*p); }
+  static __device__ __forceinline__ void store_dev(E* p, float d) { *p = (_Float16)d; }
 };
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
   uint32_t u = __float_as_uint(v);
@@ -55,6 +60,8 @@ template <> struct Codec<ELBM_STORAGE_BF16> {
   using E = uint16_t;
   static __device__ __forceinline__ float load(const E* p, float w) { return __uint_as_float(((uint32_t)*p) << 16) + w; }
   static __device__ __forceinline__ void store(E* p, float v, float w) { *p = f32_to_bf16_rne(v - w); }
+  static __device__ __forceinline__ float load_dev(const E* p) { return __uint_as_float(((uint32_t)*p) << 16); }
+  static __device__ __forceinline__ void store_dev(E* p, float d) { *p = f32_to_bf16_rne(d); }
 };
 
 inline size_t storage_bytes(int s) { return s == ELBM_STORAGE_F32 ? 4 : 2; }
@@ -66,22 +73,23 @@ __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
 
-// Per-axis factors of the factorised entropic equilibrium (eq. feq_min):
-//   phi(c) = w(c) (2 - s) X^c,  X = (2u + s)/(1 - u),  1/X = (s - 2u)/(1 + u),  s = sqrt(1 + 3u^2),
-// and of its reciprocal psi(c) = 1/phi(c) (used by the entropic scalar product).
+// Factorised entropic equilibrium (eq. feq_min) per axis, relative to the weights:
+//   feq_i = rho W_i prod_a g_a(c_ia),  g(c) = (2 - s) X^c / 1,  X = (2u + s)/(1 - u),  s = sqrt(1 + 3u^2),
+// written as g(c) = 1 + e(c) with the small parts evaluated without cancellation:
+//   e(0)  = -(s - 1),                          s - 1 = 3u^2 / (1 + s)
+//   e(+1) = (u (5 - 2s - 3u) + 2 (s - 1)) / (1 - u)
+//   e(-1) = (u (s - 4) - 2 (s - 1)) / (2u + s)
+// and the reciprocals 1/(w(c) g(c)) for the entropic scalar product.
 template <typename T>
-__device__ __forceinline__ void axis_factors(T u, T (&ph)[3], T (&ps)[3], T& s) {
-  s = sqrt_(T(3) * u * u + T(1));
-  const T g = T(2) - s;
-  const T X = (T(2) * u + s) * rcp_(T(1) - u);
-  const T Xi = (s - T(2) * u) * rcp_(T(1) + u);
-  const T gr = rcp_(g);
-  ph[0] = g * Xi * T(1.0 / 6.0);
-  ph[1] = g * T(2.0 / 3.0);
-  ph[2] = g * X * T(1.0 / 6.0);
-  ps[0] = T(6) * X * gr;
-  ps[1] = T(1.5) * gr;
-  ps[2] = T(6) * Xi * gr;
+__device__ __forceinline__ void axis_dev(T u, T (&e)[3], T (&ps)[3], T& sm1) {
+  const T s = sqrt_(T(3) * u * u + T(1));
+  sm1 = T(3) * u * u * rcp_(T(1) + s);
+  e[1] = -sm1;
+  e[2] = (u * (T(5) - T(2) * s - T(3) * u) + T(2) * sm1) * rcp_(T(1) - u);
+  e[0] = (u * (s - T(4)) - T(2) * sm1) * rcp_(T(2) * u + s);
+  ps[0] = T(6) * rcp_(T(1) + e[0]);
+  ps[1] = T(1.5) * rcp_(T(1) + e[1]);
+  ps[2] = T(6) * rcp_(T(1) + e[2]);
 }
 
 template <typename T>
@@ -108,28 +116,41 @@ template <typename T> struct KbcOut {
   T gamma;
   T b;    // <dh|dh>
   T rho;
+  T s2;   // <ds|ds> estimated with feq ~ rho W (used only to decide on the FP64 path)
 };
 
-// KBC collision of one node, in place (Sec. II, eqs. kineticEq and kbc_relax).  The mirror-state
-// update is applied in its equivalent increment form  f' = f - beta (2 ds + gamma dh),
+// FP64 recomputation rule: <dh|dh> is at the FP32 noise floor (the ratio <ds|dh>/<dh|dh> is then
+// ill-conditioned) while the shear part is not (otherwise gamma dh, bounded by the shear part, is
+// itself at the noise floor and the FP32 result is as good as an FP64 one).
+template <typename T>
+__device__ __forceinline__ bool needs_fp64(const KbcOut<T>& r, T thr) {
+  return !(r.b >= thr * r.rho) && !(r.s2 < thr * r.rho);
+}
+
+// KBC collision of one node, in place on the deviations d_i = f_i - W_i (Sec. II, eqs. kineticEq
+// and kbc_relax).  The mirror-state update is applied in its equivalent increment form
+//   f' = f - beta (2 ds + gamma dh),
 // with ds, dh the deviations of the shear part s and the higher-order part h from equilibrium:
-//   - raw moments M_pqr of f by a separable 1-D transform along x, y, z;
-//   - feq from the factorised closed form, 1/feq from the reciprocal factors;
+//   - raw moments of d by a separable 1-D transform along x, y, z (rho - 1, j, second moments);
+//   - feq - W from the factorised closed form relative to the weights, 1/feq from reciprocal
+//     factors;
 //   - ds from the deviatoric second moments of df = f - feq through the dual basis
 //     phi_0 = 1 - c^2, phi_1 = c/2, phi_2 = 3c^2/2 - 1 (faces: D_aa/2, edges: c_a c_b P_ab/4,
 //     rest and corners: 0); the equilibrium second moments are rho (2 s_a - 1)/3 and rho u_a u_b;
-//   - dh = df - ds;  gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh>, <X|Y> = sum X Y / feq;
-//     gamma = 2 when <dh|dh> <= 1e-30 (then dh is zero to round-off and f' does not depend on it).
+//   - dh = df - ds, with the rounding residue of its mass and momentum removed;
+//   - gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh>, <X|Y> = sum X Y / feq; gamma = 2 when
+//     <dh|dh> <= 1e-30 (then dh is zero to round-off and f' does not depend on it).
+// Working in deviations keeps every difference between O(1) numbers out of the FP32 arithmetic.
 // FORCE adds the exact-difference body-force increment feq(rho, u + F/rho) - feq(rho, u),
 // evaluated in FP64 to avoid cancellation.
 template <typename T, bool FORCE>
-__device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const T inv_beta, const T Fx, const T Fy,
+__device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const T inv_beta, const T Fx, const T Fy,
                                                  const T Fz) {
   // separable raw-moment transform: (a, b, c) at c = -1, 0, +1  ->  (a+b+c, c-a, a+c)
   T m0[9], m1[9], m2[9];
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
-    const T a = f[3 * r], b = f[3 * r + 1], c = f[3 * r + 2];
+    const T a = d[3 * r], b = d[3 * r + 1], c = d[3 * r + 2];
     const T ac = a + c;
     m0[r] = ac + b;
     m1[r] = c - a;
@@ -152,39 +173,44 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const
     }
     m20[k] = (m2[3 * k] + m2[3 * k + 2]) + m2[3 * k + 1];
   }
-  const T rho = (m00[0] + m00[2]) + m00[1];
+  const T dr = (m00[0] + m00[2]) + m00[1];  // rho - 1
   const T jz = m00[2] - m00[0];
-  const T M002 = m00[0] + m00[2];
+  const T Q002 = m00[0] + m00[2];           // second moments of d (those of W are 1/3 and 0)
   const T jy = (m01[0] + m01[2]) + m01[1];
-  const T M011 = m01[2] - m01[0];
-  const T M020 = (m02[0] + m02[2]) + m02[1];
+  const T Q011 = m01[2] - m01[0];
+  const T Q020 = (m02[0] + m02[2]) + m02[1];
   const T jx = (m10[0] + m10[2]) + m10[1];
-  const T M101 = m10[2] - m10[0];
-  const T M110 = (m11[0] + m11[2]) + m11[1];
-  const T M200 = (m20[0] + m20[2]) + m20[1];
+  const T Q101 = m10[2] - m10[0];
+  const T Q110 = (m11[0] + m11[2]) + m11[1];
+  const T Q200 = (m20[0] + m20[2]) + m20[1];
 
+  const T rho = T(1) + dr;
   const T rinv = rcp_(rho);
   const T ux = jx * rinv, uy = jy * rinv, uz = jz * rinv;
-  T phx[3], phy[3], phz[3], psx[3], psy[3], psz[3], sx, sy, sz;
-  axis_factors(ux, phx, psx, sx);
-  axis_factors(uy, phy, psy, sy);
-  axis_factors(uz, phz, psz, sz);
+  T ex[3], ey[3], ez[3], psx[3], psy[3], psz[3], sx, sy, sz;
+  axis_dev(ux, ex, psx, sx);
+  axis_dev(uy, ey, psy, sy);
+  axis_dev(uz, ez, psz, sz);
 
-  // deviatoric moments of df (exact equilibrium moments subtracted in closed form)
+  // deviatoric moments of df: M200 - rho (2 s - 1)/3 = Q200 - (dr (1 + 2 (s-1)) + 2 (s-1))/3
   const T third = T(1.0 / 3.0);
-  const T dM200 = M200 - rho * (T(2) * sx - T(1)) * third;
-  const T dM020 = M020 - rho * (T(2) * sy - T(1)) * third;
-  const T dM002 = M002 - rho * (T(2) * sz - T(1)) * third;
+  const T dM200 = Q200 - (dr * (T(1) + T(2) * sx) + T(2) * sx) * third;
+  const T dM020 = Q020 - (dr * (T(1) + T(2) * sy) + T(2) * sy) * third;
+  const T dM002 = Q002 - (dr * (T(1) + T(2) * sz) + T(2) * sz) * third;
   const T tr3 = (dM200 + dM020 + dM002) * third;
   const T sfx = T(0.5) * (dM200 - tr3), sfy = T(0.5) * (dM020 - tr3), sfz = T(0.5) * (dM002 - tr3);
-  const T sxy = T(0.25) * (M110 - jx * uy), sxz = T(0.25) * (M101 - jx * uz), syz = T(0.25) * (M011 - jy * uz);
+  const T sxy = T(0.25) * (Q110 - jx * uy), sxz = T(0.25) * (Q101 - jx * uz), syz = T(0.25) * (Q011 - jy * uz);
 
   T dh[27];
   T hm = T(0), hx = T(0), hy = T(0), hz = T(0);
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    const T pyz = phy[cy(i) + 1] * phz[cz(i) + 1];
-    const T fe = (rho * pyz) * phx[cx(i) + 1];
+    // feq_i - W_i = W_i (dr + rho P_i),  P_i = prod (1 + e) - 1 expanded without cancellation
+    const T a_ = ey[cy(i) + 1], b_ = ez[cz(i) + 1];
+    const T pyz = a_ + b_ + a_ * b_;
+    const T e_ = ex[cx(i) + 1];
+    const T P = e_ + pyz + e_ * pyz;
+    const T fdev = T(wd(i)) * (dr + rho * P);
     T ds = T(0);
     if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
     if (nnz(i) == 2) {
@@ -192,16 +218,16 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const
       else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
       else ds = T(cy(i) * cz(i)) * syz;
     }
-    const T h = (f[i] - fe) - ds;
+    const T h = (d[i] - fdev) - ds;
     hm += h;
     if (cx(i)) hx += T(cx(i)) * h;
     if (cy(i)) hy += T(cy(i)) * h;
     if (cz(i)) hz += T(cz(i)) * h;
     dh[i] = h;
   }
-  // dh has zero mass and momentum in exact arithmetic; remove the rounding residue of the
-  // equilibrium (its kinematic part in the dual basis: mass on the rest population, momentum on
-  // the face pairs) so that the update conserves rho and j to the rounding of the store alone.
+  // dh has zero mass and momentum in exact arithmetic; remove the rounding residue (its kinematic
+  // part in the dual basis: mass on the rest population, momentum on the face pairs) so that the
+  // update conserves rho and j to the rounding of the store alone.
   dh[13] -= hm;
   dh[14] -= T(0.5) * hx;
   dh[12] += T(0.5) * hx;
@@ -212,8 +238,7 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const
   T a = T(0), b = T(0);
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    const T qyz = psy[cy(i) + 1] * psz[cz(i) + 1];
-    const T ife = (rinv * qyz) * psx[cx(i) + 1];
+    const T ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
     T ds = T(0);
     if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
     if (nnz(i) == 2) {
@@ -226,6 +251,8 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const
     if (nnz(i) == 1 || nnz(i) == 2) a += th * ds;
   }
   const T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * a / b : T(2);
+  // faces: W = 2/27 (2 per axis), edges: W = 1/54 (4 per plane)
+  const T s2 = (T(27) * (sfx * sfx + sfy * sfy + sfz * sfz) + T(216) * (sxy * sxy + sxz * sxz + syz * syz)) * rinv;
   const T bg = beta * gamma, b2 = T(2) * beta;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
@@ -236,7 +263,7 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const
       else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
       else ds = T(cy(i) * cz(i)) * syz;
     }
-    f[i] = f[i] - b2 * ds - bg * dh[i];
+    d[i] = d[i] - b2 * ds - bg * dh[i];
   }
   if (FORCE) {
     const double r = (double)rho;
@@ -244,9 +271,9 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&f)[27], const T beta, const
     feq_all(r, (double)ux, (double)uy, (double)uz, e0);
     feq_all(r, (double)ux + (double)Fx / r, (double)uy + (double)Fy / r, (double)uz + (double)Fz / r, e1);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) f[i] = (T)((double)f[i] + (e1[i] - e0[i]));
+    for (int i = 0; i < 27; ++i) d[i] = (T)((double)d[i] + (e1[i] - e0[i]));
   }
-  return KbcOut<T>{gamma, b, rho};
+  return KbcOut<T>{gamma, b, rho, s2};
 }
 
 // Grad's distribution (eq. grad) with c_s^2 = 1/3:
@@ -353,7 +380,10 @@ struct elbm_ctx {
   int64_t blist_cap;
   int64_t n_static;        // static part (channel inlet face, or all entries for static geometry)
   double* brec;            // per-list-entry force records [cap][nb][6]
+  uint32_t* scan_tmp;      // 2 x scan_blocks: per-block counts and offsets of the list compaction
+  int64_t scan_blocks;
   double* ring;            // [force_ring][MAX_BODIES][6]
+  double* force_partial;   // [64][MAX_BODIES][6] partial sums of the force reduction
   int32_t* fix_list;       // N
   elbm::DevCounters* cnt;
   double* scratch64;       // small FP64 scratch (force sums)

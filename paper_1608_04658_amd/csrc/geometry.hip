@@ -145,68 +145,111 @@ __global__ void k_flags_update(GeoArgs g, Bodies bd) {
 }
 
 // Missing set Dbar is non-empty (a source x - c_i is solid at t+1, or lies through the inlet) or
-// the node was solid at t (refill).
+// the node was solid at t (refill).  The 26 flag loads are independent (no early exit).
 __device__ __forceinline__ bool is_boundary(const GeoArgs& g, int x, int y, int z, uint8_t fl) {
   if (fl & FL_SOLID) return false;
   if (fl & FL_SOLID_PREV) return true;
+  if (g.channel && x == 0) return true;
+  uint8_t acc = 0;
+#pragma unroll
   for (int i = 0; i < 27; ++i) {
     if (i == 13) continue;
     int sx = x - cx(i);
-    if (g.channel) {
-      if (sx < 0) return true;
-      if (sx >= g.nx) sx = g.nx - 1;
-    } else {
-      sx = wrap(sx, g.nx);
-    }
-    const int sy = wrap(y - cy(i), g.ny), sz = wrap(z - cz(i), g.nz);
-    if (g.flags[((long)sz * g.ny + sy) * g.nx + sx] & FL_SOLID) return true;
+    if (g.channel) sx = sx >= g.nx ? g.nx - 1 : sx;
+    else sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
+    const int ty = y - cy(i), tz = z - cz(i);
+    const int sy = ty < 0 ? ty + g.ny : (ty >= g.ny ? ty - g.ny : ty);
+    const int sz = tz < 0 ? tz + g.nz : (tz >= g.nz ? tz - g.nz : tz);
+    acc |= g.flags[((long)sz * g.ny + sy) * g.nx + sx];
   }
-  return false;
+  return (acc & FL_SOLID) != 0;
 }
 
-// Single-workgroup ordered compaction of the boundary nodes of a box (deterministic order: the
-// box's linear order).  Sets FL_SPECIAL on listed nodes and clears it on the others; with
-// skip_inlet the x = 0 face keeps its flags and is not listed (it sits in the static part).
-constexpr int SCAN_THREADS = 1024;
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan(GeoArgs g, int32_t* list, int64_t base, int64_t cap,
-                                                       uint32_t* count_out, uint32_t* overflow, int skip_inlet) {
-  __shared__ uint32_t sh[SCAN_THREADS];
-  const long total = g.box.count();
-  uint32_t running = 0;
-  for (long start = 0; start < total; start += SCAN_THREADS) {
-    const long idx = start + threadIdx.x;
-    uint32_t isb = 0;
-    long n = 0;
-    if (idx < total) {
-      int x, y, z;
-      box_node(g.box, idx, x, y, z);
-      n = ((long)z * g.ny + y) * g.nx + x;
-      if (!(skip_inlet && g.channel && x == 0)) {
-        const uint8_t fl = g.flags[n];
-        isb = is_boundary(g, x, y, z, fl) ? 1u : 0u;
-        g.flags[n] = isb ? (uint8_t)(fl | FL_SPECIAL) : (uint8_t)(fl & ~FL_SPECIAL);
-      }
-    }
-    sh[threadIdx.x] = isb;
+// Ordered compaction of the boundary nodes of a box (deterministic: the box's linear order), in
+// three passes: mark + per-block counts, one-block exclusive scan of the counts, emit.  Sets
+// FL_SPECIAL on listed nodes and clears it on the other box nodes; with skip_inlet the x = 0 face
+// keeps its flags and is not listed (it sits in the static part of the list).
+constexpr int SCAN_BLOCK = 256;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
+    const uint32_t w = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0u;
     __syncthreads();
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-      const uint32_t v = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0u;
+    sh[threadIdx.x] += w;
+    __syncthreads();
+  }
+  total = sh[SCAN_BLOCK - 1];
+  const uint32_t incl = sh[threadIdx.x];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_mark(GeoArgs g, int skip_inlet, uint32_t* block_count) {
+  __shared__ uint32_t sh[SCAN_BLOCK];
+  const long idx = blockIdx.x * (long)SCAN_BLOCK + threadIdx.x;
+  uint32_t isb = 0;
+  if (idx < g.box.count()) {
+    int x, y, z;
+    box_node(g.box, idx, x, y, z);
+    const long n = ((long)z * g.ny + y) * g.nx + x;
+    if (!(skip_inlet && g.channel && x == 0)) {
+      const uint8_t fl = g.flags[n];
+      isb = is_boundary(g, x, y, z, fl) ? 1u : 0u;
+      const uint8_t nf = isb ? (uint8_t)(fl | FL_SPECIAL) : (uint8_t)(fl & ~FL_SPECIAL);
+      if (nf != fl) g.flags[n] = nf;
+    }
+  }
+  uint32_t total;
+  block_exclusive_scan(isb, sh, total);
+  if (threadIdx.x == 0) block_count[blockIdx.x] = total;
+}
+
+// One workgroup: block_offset = exclusive scan of block_count; *count_out = total.
+__global__ __launch_bounds__(1024) void k_scan_offsets(const uint32_t* block_count, uint32_t* block_offset, long nblk,
+                                                       int64_t base, int64_t cap, uint32_t* count_out,
+                                                       uint32_t* overflow) {
+  __shared__ uint32_t sh[1024];
+  uint32_t running = 0;
+  for (long start = 0; start < nblk; start += 1024) {
+    const long i = start + threadIdx.x;
+    const uint32_t v = i < nblk ? block_count[i] : 0u;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint32_t w = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0u;
       __syncthreads();
-      sh[threadIdx.x] += v;
+      sh[threadIdx.x] += w;
       __syncthreads();
     }
-    const uint32_t incl = sh[threadIdx.x];
-    const uint32_t tot = sh[SCAN_THREADS - 1];
-    if (isb) {
-      const int64_t pos = base + running + incl - 1;
-      if (pos < cap) list[pos] = (int32_t)n;
-    }
-    running += tot;
+    if (i < nblk) block_offset[i] = running + sh[threadIdx.x] - v;
+    running += sh[1023];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     *count_out = running;
     if (base + (int64_t)running > cap) *overflow = 1u;
+  }
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_emit(GeoArgs g, int skip_inlet, const uint32_t* block_offset,
+                                                          int32_t* list, int64_t base, int64_t cap) {
+  __shared__ uint32_t sh[SCAN_BLOCK];
+  const long idx = blockIdx.x * (long)SCAN_BLOCK + threadIdx.x;
+  uint32_t isb = 0;
+  long n = 0;
+  if (idx < g.box.count()) {
+    int x, y, z;
+    box_node(g.box, idx, x, y, z);
+    n = ((long)z * g.ny + y) * g.nx + x;
+    isb = (!(skip_inlet && g.channel && x == 0) && (g.flags[n] & FL_SPECIAL)) ? 1u : 0u;
+  }
+  uint32_t total;
+  const uint32_t ex = block_exclusive_scan(isb, sh, total);
+  if (isb) {
+    const int64_t pos = base + (int64_t)block_offset[blockIdx.x] + ex;
+    if (pos < cap) list[pos] = (int32_t)n;
   }
 }
 
@@ -232,15 +275,16 @@ __global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, flo
       U[2] = (float)(b.U0[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
       R = (float)rho0;
     } else {
-      float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+      float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;  // from the stored deviations f - W
 #pragma unroll
       for (int i = 0; i < 27; ++i) {
-        const float v = C::load(A + i * N + n, wf(i));
-        rho += v;
+        const float v = C::load_dev(A + i * N + n);
+        dr += v;
         jx += cx(i) * v;
         jy += cy(i) * v;
         jz += cz(i) * v;
       }
+      const float rho = 1.f + dr;
       if (F) {
         jx -= 0.5f * F[n];
         jy -= 0.5f * F[N + n];
@@ -396,35 +440,52 @@ __global__ __launch_bounds__(128) void k_boundary(const BArgs a, const Bodies bd
     }
     double d[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) d[i] = (double)f[i];
+    for (int i = 0; i < 27; ++i) {
+      d[i] = (double)f[i] - wd(i);
+      f[i] = f[i] - wf(i);  // deviations for the collision
+    }
     const KbcOut<float> r = kbc_collide<float, FORCE>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
-    if (a.fp64 && !(r.b >= a.thr * r.rho)) {
+    if (a.fp64 && needs_fp64(r, a.thr)) {
       kbc_collide<double, FORCE>(d, (double)a.beta, 1.0 / (double)a.beta, Fx, Fy, Fz);
 #pragma unroll
       for (int i = 0; i < 27; ++i) f[i] = (float)d[i];
     }
 #pragma unroll
-    for (int i = 0; i < 27; ++i) C::store(B + i * a.N + n, f[i], wf(i));
+    for (int i = 0; i < 27; ++i) C::store_dev(B + i * a.N + n, f[i]);
   }
 }
 
-// Deterministic per-body force sum: one workgroup per (body, component), strided partial sums in
-// a fixed order followed by a fixed tree.
-__global__ __launch_bounds__(256) void k_force_reduce(const double* brec, const uint32_t* dyn_count, int64_t n_static,
-                                                      int64_t cap, int32_t moving, int32_t nb, double* out) {
+// Deterministic per-body force sum in two levels: FORCE_PARTS workgroups each own a fixed
+// contiguous range of list entries and reduce every (body, component) in a fixed order; one
+// workgroup then adds the partial sums in order.
+constexpr int FORCE_PARTS = 64;
+__global__ __launch_bounds__(256) void k_force_partial(const double* brec, const uint32_t* dyn_count, int64_t n_static,
+                                                       int64_t cap, int32_t moving, int32_t nb, double* partial) {
   __shared__ double sh[256];
-  const int kb = blockIdx.x / 6, comp = blockIdx.x % 6;
   int64_t count = n_static + (moving ? (int64_t)*dyn_count : 0);
   if (count > cap) count = cap;
-  double s = 0.0;
-  for (int64_t k = threadIdx.x; k < count; k += 256) s += brec[k * nb * 6 + kb * 6 + comp];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] += sh[threadIdx.x + off];
+  const int64_t chunk = (count + FORCE_PARTS - 1) / FORCE_PARTS;
+  const int64_t k0 = blockIdx.x * chunk, k1 = k0 + chunk < count ? k0 + chunk : count;
+  for (int comp = 0; comp < nb * 6; ++comp) {
+    double s = 0.0;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) s += brec[k * nb * 6 + comp];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (threadIdx.x < (unsigned)off) sh[threadIdx.x] += sh[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x * ELBM_MAX_BODIES * 6 + comp] = sh[0];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[kb * 6 + comp] = sh[0];
+}
+
+__global__ void k_force_final(const double* partial, int32_t nb, double* out) {
+  const int comp = threadIdx.x;
+  if (comp >= nb * 6) return;
+  double s = 0.0;
+  for (int p = 0; p < FORCE_PARTS; ++p) s += partial[p * ELBM_MAX_BODIES * 6 + comp];
+  out[comp] = s;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -473,6 +534,21 @@ hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd) {
   return hipGetLastError();
 }
 
+// Ordered compaction of the boundary nodes of box into list[base ...]; count to cnt->dyn_count.
+static hipError_t scan_box(elbm_ctx* c, const Box& box, int64_t base, int skip_inlet) {
+  const long nblk = (box.count() + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  if (nblk > c->scan_blocks) return hipErrorInvalidValue;
+  uint32_t* counts = c->scan_tmp;
+  uint32_t* offsets = c->scan_tmp + c->scan_blocks;
+  const GeoArgs g = geo_args(c, box);
+  hipLaunchKernelGGL(k_scan_mark, dim3((unsigned)nblk), dim3(SCAN_BLOCK), 0, c->stream, g, skip_inlet, counts);
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, c->stream, (const uint32_t*)counts, offsets, nblk, base,
+                     c->blist_cap, &c->cnt->dyn_count, &c->cnt->overflow);
+  hipLaunchKernelGGL(k_scan_emit, dim3((unsigned)nblk), dim3(SCAN_BLOCK), 0, c->stream, g, skip_inlet,
+                     (const uint32_t*)offsets, c->blist, base, c->blist_cap);
+  return hipGetLastError();
+}
+
 // Set-up at the current time level: masks everywhere, then the static part of the boundary list
 // (all boundary nodes for fixed geometry; only the inlet face when bodies move).
 hipError_t geometry_init(elbm_ctx* c) {
@@ -495,9 +571,7 @@ hipError_t geometry_init(elbm_ctx* c) {
     c->n_static = 0;
     return hipSuccess;
   }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, geo_args(c, sb), c->blist, (int64_t)0,
-                     c->blist_cap, &c->cnt->dyn_count, &c->cnt->overflow, 0);
-  e = hipGetLastError();
+  e = scan_box(c, sb, 0, 0);
   if (e != hipSuccess) return e;
   uint32_t n = 0;
   e = hipMemcpyAsync(&n, &c->cnt->dyn_count, sizeof n, hipMemcpyDeviceToHost, c->stream);
@@ -517,8 +591,8 @@ hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd) {
   if (c->moving) {
     GeoArgs g = geo_args(c, ub);
     hipLaunchKernelGGL(k_flags_update, grid_for(ub.count()), dim3(256), 0, c->stream, g, bd);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, g, c->blist, c->n_static, c->blist_cap,
-                       &c->cnt->dyn_count, &c->cnt->overflow, 1);
+    const hipError_t e = scan_box(c, ub, c->n_static, 1);
+    if (e != hipSuccess) return e;
   }
   return macro_fields(c, c->pop[c->cur], bd);
 }
@@ -543,10 +617,7 @@ hipError_t geometry_for_step(elbm_ctx* c, const Bodies& bd) {
   if (!c->moving) return hipSuccess;  // fixed geometry: masks and list from the set-up hold
   const Box fb = full_box(c);
   hipLaunchKernelGGL(k_flags_two, grid_for(fb.count()), dim3(256), 0, c->stream, geo_args(c, fb), bd);
-  const Box ub = union_box(c, bd);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, geo_args(c, ub), c->blist, c->n_static,
-                     c->blist_cap, &c->cnt->dyn_count, &c->cnt->overflow, 1);
-  return hipGetLastError();
+  return scan_box(c, union_box(c, bd), c->n_static, 1);
 }
 
 template <int S>
@@ -613,9 +684,11 @@ hipError_t launch_force_reduce(elbm_ctx* c) {
   if (c->nb == 0) return hipSuccess;
   const int slot = (int)((c->t + 1) % c->p.force_ring);
   double* out = c->ring + (size_t)slot * ELBM_MAX_BODIES * 6;
-  hipLaunchKernelGGL(k_force_reduce, dim3(c->nb * 6), dim3(256), 0, c->stream, (const double*)c->brec,
+  hipLaunchKernelGGL(k_force_partial, dim3(FORCE_PARTS), dim3(256), 0, c->stream, (const double*)c->brec,
                      (const uint32_t*)&c->cnt->dyn_count, c->n_static, c->blist_cap, (int32_t)(c->moving ? 1 : 0),
-                     (int32_t)c->nb, out);
+                     (int32_t)c->nb, c->force_partial);
+  hipLaunchKernelGGL(k_force_final, dim3(1), dim3(64), 0, c->stream, (const double*)c->force_partial, (int32_t)c->nb,
+                     out);
   return hipGetLastError();
 }
 

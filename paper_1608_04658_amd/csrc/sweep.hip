@@ -63,9 +63,9 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
   uint32_t xs[3], rs[9];
   gather_offsets(x, y, z, a, xs, rs);
   const E* __restrict__ A = (const E*)a.A;
-  float f[27];
+  float f[27];  // deviations f - W
 #pragma unroll
-  for (int i = 0; i < 27; ++i) f[i] = C::load(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]), wf(i));
+  for (int i = 0; i < 27; ++i) f[i] = C::load_dev(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]));
   if (!a.stream_only) {
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
     if (FORCE) {
@@ -74,14 +74,24 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
       Fz = a.F[2 * (size_t)a.N + n];
     }
     const KbcOut<float> r = kbc_collide<float, FORCE>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
-    if (a.fp64 && !(r.b >= a.thr * r.rho)) {
+    if (a.fp64 && needs_fp64(r, a.thr)) {
       const uint32_t k = atomicAdd(&a.cnt->fix_count, 1u);
       a.fix_list[k] = n;
     }
   }
+  // FP32: 32-bit byte offsets on per-direction bases and non-temporal stores (the next step reads
+  // this buffer only after the whole sweep, so keeping the write stream out of the caches wins);
+  // 2-byte storage keeps ordinary stores (partial-line writes merge better in L2).
   E* __restrict__ B = (E*)a.B;
 #pragma unroll
-  for (int i = 0; i < 27; ++i) C::store(B + (size_t)i * a.N + n, f[i], wf(i));
+  for (int i = 0; i < 27; ++i) {
+    if (S == ELBM_STORAGE_F32) {
+      float* p = (float*)((char*)(B + (size_t)i * a.N) + n * (uint32_t)sizeof(float));
+      __builtin_nontemporal_store(f[i], p);
+    } else {
+      C::store_dev(B + (size_t)i * a.N + n, f[i]);
+    }
+  }
 }
 
 // FP64 recomputation of the nodes whose <dh|dh> fell below the FP32 threshold: the same gather
@@ -101,10 +111,10 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
     const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
     uint32_t xs[3], rs[9];
     gather_offsets(x, y, z, a, xs, rs);
-    double f[27];
+    double f[27];  // deviations f - W
 #pragma unroll
     for (int i = 0; i < 27; ++i)
-      f[i] = (double)C::load(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]), wf(i));
+      f[i] = (double)C::load_dev(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]));
     double Fx = 0, Fy = 0, Fz = 0;
     if (FORCE) {
       Fx = a.F[n];
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
     const double beta = (double)a.beta;
     kbc_collide<double, FORCE>(f, beta, 1.0 / beta, Fx, Fy, Fz);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) C::store(B + (size_t)i * a.N + n, (float)f[i], wf(i));
+    for (int i = 0; i < 27; ++i) C::store_dev(B + (size_t)i * a.N + n, (float)f[i]);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -150,10 +160,10 @@ static SweepArgs sweep_args(elbm_ctx* c) {
   return a;
 }
 
-// Block shape: the widest power of two <= 256 along x that divides nx (at least 32), the rest of
-// the 256 threads along y.
+// Block shape: the widest power of two <= 256 (<= 128 for rows longer than 256, which measured
+// faster on 512^3) along x that divides nx (at least 32), the rest of the 256 threads along y.
 static void sweep_shape(int nx, int ny, int nz, dim3& grid, dim3& block) {
-  int bx = 256;
+  int bx = nx > 256 ? 128 : 256;
   while (bx > 32 && (nx % bx) != 0) bx >>= 1;
   if (nx < bx) bx = 32;
   const int by = 256 / bx;
@@ -204,7 +214,9 @@ hipError_t launch_fixup(elbm_ctx* c) {
 // ---------------------------------------------------------------------------------------------
 // Conversions between FP64 population arrays and the storage format.
 template <int S> __device__ __forceinline__ void store_d(typename Codec<S>::E* p, double v, int i);
-template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_F32>(float* p, double v, int) { *p = (float)v; }
+template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_F32>(float* p, double v, int i) {
+  *p = (float)(v - wd(i));
+}
 template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_F16>(_Float16* p, double v, int i) {
   *p = (_Float16)(float)(v - wd(i));
 }
@@ -212,7 +224,9 @@ template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_BF16>(uint16_t*
   *p = f32_to_bf16_rne((float)(v - wd(i)));
 }
 template <int S> __device__ __forceinline__ double load_d(const typename Codec<S>::E* p, int i);
-template <> __device__ __forceinline__ double load_d<ELBM_STORAGE_F32>(const float* p, int) { return (double)*p; }
+template <> __device__ __forceinline__ double load_d<ELBM_STORAGE_F32>(const float* p, int i) {
+  return (double)*p + wd(i);
+}
 template <> __device__ __forceinline__ double load_d<ELBM_STORAGE_F16>(const _Float16* p, int i) {
   return (double)(float)*p + wd(i);
 }
@@ -306,22 +320,25 @@ __global__ __launch_bounds__(256) void k_collide_nodes(const float* fin, float* 
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     float f[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) f[i] = fin[i * n + k];
+    for (int i = 0; i < 27; ++i) f[i] = fin[i * n + k] - wf(i);
     const float Fx = F ? F[k] : 0.f, Fy = F ? F[n + k] : 0.f, Fz = F ? F[2 * n + k] : 0.f;
     KbcOut<float> r;
     if (F) r = kbc_collide<float, true>(f, beta, inv_beta, Fx, Fy, Fz);
     else r = kbc_collide<float, false>(f, beta, inv_beta, Fx, Fy, Fz);
     float g = r.gamma;
-    if (thr >= 0.f && !(r.b >= thr * r.rho)) {
+    if (thr >= 0.f && needs_fp64(r, thr)) {
       double d[27];
 #pragma unroll
-      for (int i = 0; i < 27; ++i) d[i] = (double)fin[i * n + k];
+      for (int i = 0; i < 27; ++i) d[i] = (double)fin[i * n + k] - wd(i);
       KbcOut<double> r2;
       if (F) r2 = kbc_collide<double, true>(d, (double)beta, 1.0 / (double)beta, Fx, Fy, Fz);
       else r2 = kbc_collide<double, false>(d, (double)beta, 1.0 / (double)beta, 0.0, 0.0, 0.0);
 #pragma unroll
-      for (int i = 0; i < 27; ++i) f[i] = (float)d[i];
+      for (int i = 0; i < 27; ++i) f[i] = (float)(d[i] + wd(i));
       g = (float)r2.gamma;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 27; ++i) f[i] += wf(i);
     }
 #pragma unroll
     for (int i = 0; i < 27; ++i) fout[i * n + k] = f[i];

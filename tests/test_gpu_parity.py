@@ -55,10 +55,12 @@ def test_taylor_green_32_parity_100_steps(E, O):
 
 @pytest.mark.parametrize("shape", [(8, 6, 5), (32, 4, 3), (40, 3, 2)])
 def test_streaming_is_bit_exact(E, O, shape):
-    """Stream-only mode on integer-valued data (exact in FP32): GPU == oracle bit for bit."""
+    """Stream-only mode on data whose deviations from the weights, k / 1024 with integer k, are exact in
+    the FP32 storage of f - W: GPU == oracle bit for bit."""
     nx, ny, nz = shape
     rng = np.random.default_rng(11)
-    A0 = rng.integers(0, 4096, size=(27, nz, ny, nx)).astype(np.float64)
+    w = O.lattice()[1][:, None, None, None]
+    A0 = w + rng.integers(0, 4096, size=(27, nz, ny, nx)).astype(np.float64) / 1024.0
     for channel in (False, True):
         _say(f"case: streaming {shape} channel={channel}")
         lat = E.Lattice(shape, 0.1, channel=channel, flags=E.FLAG_STREAM_ONLY)

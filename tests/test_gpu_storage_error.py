@@ -1,0 +1,103 @@
+"""Error of each storage form against the FP64 oracle on quantities of the workloads:
+  * kinetic-energy decay KE(t)/KE(0) of the 512^3 turbulence recipe rerun on a 64^3 box (k0 = 8,
+    nu = 0.00815, seed 1609), 500 steps;
+  * drag on the oscillating sphere of the 128x64x64 channel (no body force), 400 steps.
+The bounds are the measured errors rounded up, stated here so that a regression shows: FP32 is
+rounding noise; FP16 / BF16 deviations carry the storage rounding (2^-11 / 2^-8 relative to the
+deviation) into every step."""
+import numpy as np
+import pytest
+
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+KE_BOUND = {"f32": 1e-5, "f16": 2e-3, "bf16": 2e-2}
+DRAG_BOUND = {"f32": 1e-4, "f16": 1e-2, "bf16": 1e-1}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def E(torch_cuda):
+    from paper_1608_04658_amd import elbm
+    elbm.load()
+    return elbm
+
+
+@pytest.fixture(scope="module")
+def O(oracle_mod):
+    return oracle_mod
+
+
+def _ke(pops, torch):
+    c = torch.tensor([[i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1] for i in range(27)], dtype=torch.float64,
+                     device=pops.device)
+    p = pops.reshape(27, -1)
+    r = p.sum(0)
+    j = c.T @ p
+    return float((0.5 * (j * j).sum(0) / r).sum())
+
+
+@pytest.fixture(scope="module")
+def ke_oracle(O):
+    w = WL.WORKLOADS["turb512"]
+    rho, u = WL.turbulence(64, w["k0"], w["urms"], w["seed"])
+    s = O.Simulation((64, 64, 64), w["nu"], rho, u)
+    kes = []
+    for k in range(6):
+        r, j = s.moments()
+        kes.append(float((0.5 * (j * j).sum(0) / r).sum()))
+        if k < 5:
+            s.step(100)
+    return rho, u, np.array(kes)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_kinetic_energy_decay_error(E, torch_cuda, ke_oracle, storage):
+    torch = torch_cuda
+    rho, u, ref = ke_oracle
+    w = WL.WORKLOADS["turb512"]
+    lat = E.Lattice((64, 64, 64), w["nu"], storage=storage)
+    lat.init_equilibrium(rho, u)
+    kes = [_ke(lat.populations(), torch)]
+    for k in range(5):
+        lat.step(100)
+        kes.append(_ke(lat.populations(), torch))
+    kes = np.array(kes)
+    err = np.max(np.abs(kes / kes[0] - ref / ref[0]))
+    print(f"KE(t)/KE(0) at t=0..500 step 100: oracle {np.round(ref / ref[0], 6)}; {storage} max abs error {err:.3e}",
+          flush=True)
+    assert err < KE_BOUND[storage]
+
+
+@pytest.fixture(scope="module")
+def drag_oracle(O):
+    w = WL.WORKLOADS["adj128"]
+    rho, u = WL.uniform_flow(w["shape"], w["u_in"])
+    s = O.Simulation(w["shape"], w["nu"], rho, u, bodies=w["bodies"], channel=True, u_in=w["u_in"])
+    s.step(400)
+    return np.array([f[0, 0] for f in s.forces])
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_drag_error(E, torch_cuda, drag_oracle, storage):
+    w = WL.WORKLOADS["adj128"]
+    rho, u = WL.uniform_flow(w["shape"], w["u_in"])
+    lat = E.Lattice(w["shape"], w["nu"], storage=storage, channel=True, u_inlet=w["u_in"], max_bodies=1)
+    lat.init_equilibrium(rho, u)
+    lat.set_bodies(w["bodies"])
+    lat.step(400)
+    drag = lat.force_history(0, 1, 400)[:, 0]
+    ref = drag_oracle
+    err = np.max(np.abs(drag[100:] - ref[100:])) / np.max(np.abs(ref[100:]))
+    print(f"drag steps 100..400: oracle mean {ref[100:].mean():.6e}; {storage} mean {drag[100:].mean():.6e}, "
+          f"max rel error {err:.3e}", flush=True)
+    assert err < DRAG_BOUND[storage]

@@ -112,6 +112,36 @@ def copy_probe(torch, nbytes=8 << 30, reps=20):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
+def adjoint_form(torch, WL):
+    """The differentiable workload: 300-step rollout of the 128x64x64 oscillating-sphere channel with
+    a body-force field, loss = mean drag over steps 100..300; forward with checkpoints every 20
+    steps, then the reverse sweep (recompute of each segment + hand-written adjoint steps).
+    Bytes per node and reverse step: recompute 228 + adjoint 360 = 588."""
+    import numpy as np
+    from paper_1608_04658_amd.adjoint import ForceRollout, window_weights
+    w = WL.WORKLOADS["adj128"]
+    steps = 300
+    rho, u = WL.uniform_flow(w["shape"], w["u_in"])
+    F = torch.tensor(WL.body_force(w["shape"], w["force_seed"], w["force_amp"]), dtype=torch.float32, device="cuda")
+    ro = ForceRollout(w["shape"], w["nu"], w["bodies"][0], steps, window_weights(steps, *w["loss_window"]),
+                      checkpoint=w["checkpoint"], channel=True, u_in=w["u_in"], rho=rho, u=u)
+    ro.forward(F, w["bodies"][0]["amp"])  # warm-up
+    ro.backward()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    e[0].record()
+    L = ro.forward(F, w["bodies"][0]["amp"])
+    e[1].record()
+    gF, gA = ro.backward()
+    e[2].record()
+    torch.cuda.synchronize()
+    fwd, bwd = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    n = int(np.prod(w["shape"]))
+    return {"MLUPS": round(n * steps / (bwd / 1e3) / 1e6, 1), "ms_per_step": round(bwd / steps, 4),
+            "GBps_588B": round(588 * n * steps / (bwd / 1e3) / 1e9, 1), "forward_ms_per_step": round(fwd / steps, 4),
+            "loss": L, "dL_damp": gA, "dL_dF_norm": float(gF.double().norm().item())}
+
+
 def cpu_baseline(workload: str, budget_s: float = 15.0):
     """The FP64 oracle, unmodified, stepping the workload's own lattice on the host cores for a
     bounded number of steps (at least 2, until ~budget_s seconds of stepping)."""
@@ -145,6 +175,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--form-steps", type=int, default=100)
+    ap.add_argument("--forms", default="copy,turb512,sphere384,adj128",
+                    help="comma-separated subset of the extra forms to run")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="after the headline run, copy a buffer of this many MiB 5 times (a plain copy kernel "
                          "of known size, used to scale the HBM byte counters of a rocprofv3 --pmc run)")
@@ -204,10 +236,12 @@ def main():
         del a, b
 
     forms = {}
-    if not args.no_forms:
-        try:
+    which = set(args.forms.split(",")) if not args.no_forms else set()
+    try:
+        if "copy" in which:
             forms["copy_probe_GBps"] = round(copy_probe(torch), 1)
             log(f"copy probe {forms['copy_probe_GBps']} GB/s")
+        if "turb512" in which:
             w5 = WL.WORKLOADS["turb512"]
             log("turb512: generating the initial field on the device")
             r5, u5 = WL.turbulence_device(512, w5["k0"], w5["urms"], w5["seed"])
@@ -226,6 +260,7 @@ def main():
                 log(f"turb512 {st}: {m:.0f} MLUPS, sweep {gb:.0f} GB/s")
             del r5, u5
             torch.cuda.empty_cache()
+        if "sphere384" in which:
             w2 = WL.WORKLOADS["sphere384"]
             r2, u2 = WL.initial_field("sphere384")
 
@@ -240,9 +275,12 @@ def main():
             forms["sphere384_f32"] = {"MLUPS": round(m, 1), "ms_per_step": round(msps, 4), "sweep_GBps": round(gb, 1),
                                       "boundary_nodes": int(inf.boundary_nodes), "drag_last_step": F[0]}
             log(f"sphere384: {m:.0f} MLUPS, boundary nodes {inf.boundary_nodes}, drag {F[0]:.4e}")
-        except Exception as exc:  # a failing extra form must not hide the headline number
-            forms["error"] = repr(exc)
-            log(f"forms failed: {exc!r}")
+        if "adj128" in which:
+            forms["adj128_adjoint"] = adjoint_form(torch, WL)
+            log(f"adj128 adjoint: {forms['adj128_adjoint']}")
+    except Exception as exc:  # a failing extra form must not hide the headline number
+        forms["error"] = repr(exc)
+        log(f"forms failed: {exc!r}")
 
     cpu = None
     if not args.no_cpu_baseline:

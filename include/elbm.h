@@ -68,7 +68,7 @@ extern "C" {
 #define ELBM_FLAG_ADJOINT 8u      /* reserve workspace for elbm_adjoint_step */
 
 typedef struct elbm_params {
-  int32_t nx, ny, nz;   /* lattice size, each >= 1 (channel mode: nx >= 4) */
+  int32_t nx, ny, nz;   /* lattice size, each >= 1 (channel mode: nx >= 4), N < 2^31 */
   int32_t storage;      /* ELBM_STORAGE_* */
   int32_t bc_x;         /* ELBM_BC_* */
   int32_t max_bodies;   /* 0 .. ELBM_MAX_BODIES; 0 = no geometry at all */

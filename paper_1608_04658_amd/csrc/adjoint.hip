@@ -9,8 +9,12 @@
 // Data flow of a reverse step (all on the context's stream):
 //   k_adj_bulk      per fluid node: collision VJP, then the transpose of the pull -- every
 //                   (source, direction) entry of dL/dA^t is written exactly once by the node that
-//                   pulled it, so the scatter needs no atomics;  solid nodes write zeros.  Nodes with
-//                   <dh|dh> at the FP32 noise floor are queued for k_adj_fixup (FP64).
+//                   pulled it, so the scatter needs no atomics;  solid nodes write zeros.
+//
+// Every collision VJP runs in FP64 on the exactly widened stored deviations (f = W + d): the
+// derivative of the stabiliser carries 1/<dh|dh>, so an FP32 evaluation loses the digits of dh
+// that decide it at weakly disturbed nodes, while the FP64 arithmetic costs little next to the
+// memory traffic of the step.  Adjoint fields stay FP32 in memory.
 //   k_adj_boundary  per boundary/refill node: the adjoint of the reconstruction (Grad populations,
 //                   targets, finite-difference gradient, force term of the loss); contributions to
 //                   U^t and R^t of other nodes go to FP64 accumulators.
@@ -178,25 +182,19 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
   return VjpOut<T>{b, rho};
 }
 
-// Collision VJP in FP32 with the same FP64 recomputation rule as the forward collision.
+// Collision VJP in FP64 of an absolute FP64 state; adjoint in and out FP32.
 template <bool FORCE>
-__device__ inline void collide_vjp(const float (&f)[27], const float (&gp)[27], float beta, float Fx, float Fy, float Fz,
-                                   float thr, int fp64, float (&g)[27], float (&gF)[3]) {
-  const VjpOut<float> r = kbc_vjp<float, FORCE>(f, gp, beta, Fx, Fy, Fz, g, gF);
-  if (fp64 && !(r.b >= thr * r.rho)) {
-    double fd[27], gd[27], outd[27], gFd[3];
+__device__ inline void collide_vjp(const double (&f)[27], const float (&gp)[27], float beta, float Fx, float Fy,
+                                   float Fz, float (&g)[27], float (&gF)[3]) {
+  double gd[27], outd[27], gFd[3];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      fd[i] = f[i];
-      gd[i] = gp[i];
-    }
-    kbc_vjp<double, FORCE>(fd, gd, (double)beta, Fx, Fy, Fz, outd, gFd);
+  for (int i = 0; i < 27; ++i) gd[i] = gp[i];
+  kbc_vjp<double, FORCE>(f, gd, (double)beta, Fx, Fy, Fz, outd, gFd);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) g[i] = (float)outd[i];
-    gF[0] = (float)gFd[0];
-    gF[1] = (float)gFd[1];
-    gF[2] = (float)gFd[2];
-  }
+  for (int i = 0; i < 27; ++i) g[i] = (float)outd[i];
+  gF[0] = (float)gFd[0];
+  gF[1] = (float)gFd[1];
+  gF[2] = (float)gFd[2];
 }
 
 struct AdjArgs {
@@ -241,7 +239,7 @@ __device__ inline long pull_source(const BArgs& a, int i, int x, int y, int z) {
 }
 
 template <int S, bool FLAGS, bool FORCE>
-__global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j, uint32_t* queue, DevCounters* cnt) {
+__global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j) {
   using C = Codec<S>;
   using E = typename C::E;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -257,76 +255,25 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
   }
   if (fl & FL_SPECIAL) return;
   const E* __restrict__ A = (const E*)a.A;
-  float f[27], gp[27], g[27], gF[3];
+  double f[27], gp[27], g[27], gF[3];
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    f[i] = C::load(A + i * a.N + pull_source(a, i, x, y, z), wf(i));
-    gp[i] = j.lam_in[i * a.N + n];
+    f[i] = (double)C::load_dev(A + i * a.N + pull_source(a, i, x, y, z)) + wd(i);  // exact widening
+    gp[i] = (double)j.lam_in[i * a.N + n];
   }
-  float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+  double Fx = 0.0, Fy = 0.0, Fz = 0.0;
   if (FORCE) {
     Fx = a.F[n];
     Fy = a.F[a.N + n];
     Fz = a.F[2 * a.N + n];
   }
-  const VjpOut<float> r = kbc_vjp<float, FORCE>(f, gp, a.beta, Fx, Fy, Fz, g, gF);
-  if (a.fp64 && !(r.b >= a.thr * r.rho)) {
-    // <dh|dh> at the FP32 noise floor: this node's VJP is redone in FP64 by k_adj_fixup
-    queue[atomicAdd(&cnt->fix_count, 1u)] = (uint32_t)n;
-    return;
-  }
+  kbc_vjp<double, FORCE>(f, gp, (double)a.beta, Fx, Fy, Fz, g, gF);
 #pragma unroll
-  for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, g[i]);
+  for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, (float)g[i]);
   if (FORCE && j.gF) {
-    j.gF[n] += gF[0];
-    j.gF[a.N + n] += gF[1];
-    j.gF[2 * a.N + n] += gF[2];
-  }
-}
-
-// FP64 collision VJP of the queued bulk nodes (same gather, same pushes); the last block resets the
-// queue.
-template <int S, bool FORCE>
-__global__ __launch_bounds__(256) void k_adj_fixup(const BArgs a, const AdjArgs j, const uint32_t* queue,
-                                                   DevCounters* cnt) {
-  using C = Codec<S>;
-  using E = typename C::E;
-  const uint32_t count = __atomic_load_n(&cnt->fix_count, __ATOMIC_RELAXED);
-  const E* __restrict__ A = (const E*)a.A;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
-    const long n = queue[k];
-    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
-    double f[27], gp[27], g[27], gF[3];
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      f[i] = (double)C::load_dev(A + i * a.N + pull_source(a, i, x, y, z)) + wd(i);  // exact widening
-      gp[i] = (double)j.lam_in[i * a.N + n];
-    }
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-    if (FORCE) {
-      Fx = a.F[n];
-      Fy = a.F[a.N + n];
-      Fz = a.F[2 * a.N + n];
-    }
-    kbc_vjp<double, FORCE>(f, gp, (double)a.beta, Fx, Fy, Fz, g, gF);
-#pragma unroll
-    for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, (float)g[i]);
-    if (FORCE && j.gF) {
-      j.gF[n] += (float)gF[0];
-      j.gF[a.N + n] += (float)gF[1];
-      j.gF[2 * a.N + n] += (float)gF[2];
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t t = atomicAdd(&cnt->fix_ticket, 1u);
-    if (t == gridDim.x - 1) {
-      cnt->fix_total = count;
-      cnt->fix_count = 0;
-      cnt->fix_ticket = 0;
-      __threadfence();
-    }
+    j.gF[n] += (float)gF[0];
+    j.gF[a.N + n] += (float)gF[1];
+    j.gF[2 * a.N + n] += (float)gF[2];
   }
 }
 
@@ -373,14 +320,15 @@ __device__ inline void addU(const BArgs& a, const AdjArgs& j, int comp, long nod
 }
 
 // Transpose of the finite-difference stencil of grad_u: dL/dG -> dL/dU^t at the stencil nodes.
-__device__ inline void grad_u_vjp(const BArgs& a, const AdjArgs& j, int x, int y, int z, long n0, const float (&gG)[9]) {
+__device__ inline void grad_u_vjp(const BArgs& a, const AdjArgs& j, const Nbhd& h, const float (&gG)[9]) {
+  const long n0 = h.n;
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
-    const int e0 = b == 0, e1 = b == 1, e2 = b == 2;
-    const long p1 = neighbour(a, x, y, z, e0, e1, e2), p2 = neighbour(a, x, y, z, 2 * e0, 2 * e1, 2 * e2);
-    const long m1 = neighbour(a, x, y, z, -e0, -e1, -e2), m2 = neighbour(a, x, y, z, -2 * e0, -2 * e1, -2 * e2);
-    const bool op1 = p1 >= 0 && !(a.flags[p1] & FL_SOLID), op2 = p2 >= 0 && !(a.flags[p2] & FL_SOLID);
-    const bool om1 = m1 >= 0 && !(a.flags[m1] & FL_SOLID), om2 = m2 >= 0 && !(a.flags[m2] & FL_SOLID);
+    const int ip = dir_index(b == 0, b == 1, b == 2), im = dir_index(-(b == 0), -(b == 1), -(b == 2));
+    const bool op1 = (h.fluid >> ip) & 1u, om1 = (h.fluid >> im) & 1u;
+    const bool op2 = (h.far >> (2 * b)) & 1u, om2 = (h.far >> (2 * b + 1)) & 1u;
+    const long p1 = nb_index(a, h, ip), m1 = nb_index(a, h, im);
+    const long p2 = far_index(a, h, 2 * b), m2 = far_index(a, h, 2 * b + 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float g = gG[3 * c + b];
@@ -407,6 +355,9 @@ __device__ inline void grad_u_vjp(const BArgs& a, const AdjArgs& j, int x, int y
   }
 }
 
+// Adjoint of the boundary rules of Secs. III / IV.A at the listed nodes (wall nodes; every other
+// listed node -- refill, inlet and outlet nodes without a missing population -- takes the plain
+// collision VJP here too, since the bulk kernel skips FL_SPECIAL nodes).
 template <int S, bool FORCE>
 __global__ __launch_bounds__(128) void k_adj_boundary(const BArgs a, const Bodies bd, const AdjArgs j,
                                                       const AdjBodyArgs p) {
@@ -417,37 +368,31 @@ __global__ __launch_bounds__(128) void k_adj_boundary(const BArgs a, const Bodie
   if (count > a.cap) count = a.cap;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
     const long n = a.list[k];
-    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
-    float gp[27], f[27], g[27], gFn[3];
-#pragma unroll
-    for (int i = 0; i < 27; ++i) gp[i] = j.lam_in[i * a.N + n];
+    float gp[27], f[27], fo[27], g[27], gFn[3];  // f, fo: deviations from the weights, as in the forward
+    double fd[27];                               // the collision's input, absolute, FP64
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
     if (FORCE) {
       Fx = a.F[n];
       Fy = a.F[a.N + n];
       Fz = a.F[2 * a.N + n];
     }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) gp[i] = j.lam_in[i * a.N + n];
+    Nbhd h;
+    nbhd_flags(a, n, h);
+    const int x = h.x, y = h.y, z = h.z;
+    const uint32_t dmask = h.dbar;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const bool miss = (dmask >> i) & 1u;
+      const float v = C::load_dev(A + i * a.N + (miss ? n : pull_src(a, h, i)));
+      f[i] = miss ? 0.f : v;
+      fo[i] = C::load_dev(A + i * a.N + n);
+    }
+    float U[27][3], U2[6][3];
+    if (dmask) nbhd_velocity(a, h, U, U2);
     {
       // ---- wall node: forward recomputation (as k_boundary)
-      uint32_t dmask = 0;
-#pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        int sx = x - cx(i);
-        if (a.channel && sx < 0) {
-          dmask |= 1u << i;
-          f[i] = 0.f;
-          continue;
-        }
-        if (a.channel) sx = sx >= a.nx ? a.nx - 1 : sx;
-        else sx = wrap(sx, a.nx);
-        const long ns = node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
-        if (a.flags[ns] & FL_SOLID) {
-          dmask |= 1u << i;
-          f[i] = 0.f;
-          continue;
-        }
-        f[i] = C::load(A + i * a.N + ns, wf(i));
-      }
       float ut[3] = {0.f, 0.f, 0.f};
       float rstat = 0.f, rdyn = 0.f;
       int nD = 0;
@@ -458,16 +403,15 @@ __global__ __launch_bounds__(128) void k_adj_boundary(const BArgs a, const Bodie
           continue;
         }
         ++nD;
-        rstat += C::load(A + opp(i) * a.N + n, wf(opp(i)));
+        rstat += fo[opp(i)];
         double q, uwd[3];
         int kb;
         link_geometry(a, bd, i, x, y, z, q, uwd, kb);
-        const long nf = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
         float uf[3];
-        if (nf >= 0 && !(a.flags[nf] & FL_SOLID)) {
-          uf[0] = a.macro[nf];
-          uf[1] = a.macro[a.N + nf];
-          uf[2] = a.macro[2 * a.N + nf];
+        if ((h.fluid >> i) & 1u) {
+          uf[0] = U[i][0];
+          uf[1] = U[i][1];
+          uf[2] = U[i][2];
         } else {
           uf[0] = (float)uwd[0];
           uf[1] = (float)uwd[1];
@@ -482,17 +426,19 @@ __global__ __launch_bounds__(128) void k_adj_boundary(const BArgs a, const Bodie
       ut[0] *= invn;
       ut[1] *= invn;
       ut[2] *= invn;
-      const float rt = rstat + rdyn;
+      const float rt = 1.f + rstat + rdyn;  // the weights add up to 1
       float G[9], Pi[6];
+#pragma unroll
+      for (int i = 0; i < 27; ++i) fd[i] = wd(i) + (double)f[i];
       if (nD) {
-        grad_u(a, x, y, z, n, G);
+        grad_u_nb(h, U, U2, G);
         pressure_tensor(rt, ut, G, a.beta, Pi);
 #pragma unroll
         for (int i = 0; i < 27; ++i)
-          if ((dmask >> i) & 1u) f[i] = grad_pop(i, rt, ut, Pi);
+          if ((dmask >> i) & 1u) fd[i] = (double)grad_pop(i, rt, ut, Pi);
       }
       // ---- reverse
-      collide_vjp<FORCE>(f, gp, a.beta, Fx, Fy, Fz, a.thr, a.fp64, g, gFn);
+      collide_vjp<FORCE>(fd, gp, a.beta, Fx, Fy, Fz, g, gFn);
       if (!nD) {
 #pragma unroll
         for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, g[i]);
@@ -526,20 +472,20 @@ __global__ __launch_bounds__(128) void k_adj_boundary(const BArgs a, const Bodie
           const double qd = q, inv = 1.0 / (nD * (1.0 + qd));
           for (int c = 0; c < 3; ++c) guw[c] = (double)gr * 6.0 * wd(i) * a.rho0 * (c == 0 ? cx(i) : (c == 1 ? cy(i) : cz(i))) + gu[c] * inv;
           if (p.loss && kb >= 0) {
-            const float fo = C::load(A + opp(i) * a.N + n, wf(opp(i)));
-            const float fs = grad_pop(i, rt, ut, Pi);
+            const double fb = wd(opp(i)) + (double)fo[opp(i)];
+            const double fs = fd[i];
             vbb += (float)(p.w[kb][0] * (-cx(i) - uwd[0]) + p.w[kb][1] * (-cy(i) - uwd[1]) + p.w[kb][2] * (-cz(i) - uwd[2]));
-            for (int c = 0; c < 3; ++c) guw[c] += p.w[kb][c] * ((double)fs - (double)fo);
+            for (int c = 0; c < 3; ++c) guw[c] += p.w[kb][c] * (fs - fb);
           }
           j.lam_out[opp(i) * a.N + n] += vbb;
           if (!(a.channel && x - cx(i) < 0)) adj_push(a, j, i, x, y, z, 0.f);
           // u_f and q
-          const long nf = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
           double uf[3];
-          if (nf >= 0 && !(a.flags[nf] & FL_SOLID)) {
-            uf[0] = a.macro[nf];
-            uf[1] = a.macro[a.N + nf];
-            uf[2] = a.macro[2 * a.N + nf];
+          if ((h.fluid >> i) & 1u) {
+            const long nf = nb_index(a, h, i);
+            uf[0] = U[i][0];
+            uf[1] = U[i][1];
+            uf[2] = U[i][2];
             for (int c = 0; c < 3; ++c) addU(a, j, c, nf, (float)(gu[c] * qd * inv));
           } else {
             for (int c = 0; c < 3; ++c) {
@@ -566,7 +512,7 @@ __global__ __launch_bounds__(128) void k_adj_boundary(const BArgs a, const Bodie
             atomicAdd(&p.gamp[kb], ga);
           }
         }
-        grad_u_vjp(a, j, x, y, z, n, gG);
+        grad_u_vjp(a, j, h, gG);
       }
     }
     if (FORCE && j.gF) {
@@ -588,10 +534,11 @@ __global__ __launch_bounds__(128) void k_adj_refill(const BArgs a, const Bodies 
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
     const long n = a.list[k];
     if (!(a.flags[n] & FL_SOLID_PREV)) continue;
-    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    Nbhd h;
+    nbhd_flags(a, n, h);
     float f[27], uw[3], G[9], ravg;
     int kb, m;
-    refill_pops(a, bd, x, y, z, n, f, kb, ravg, m, uw, G);
+    refill_pops(a, bd, h, f, kb, ravg, m, uw, G);
     float gr = 0.f, gu[3] = {0.f, 0.f, 0.f}, gP[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gG[9];
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
@@ -604,14 +551,12 @@ __global__ __launch_bounds__(128) void k_adj_refill(const BArgs a, const Bodies 
       const float gm = gr / (float)m;
 #pragma unroll
       for (int i = 0; i < 27; ++i) {
-        if (i == 13) continue;
-        const long nn = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
-        if (nn < 0 || (a.flags[nn] & (FL_SOLID | FL_SOLID_PREV))) continue;
-        atomicAdd(&j.gUR[3 * a.N + nn], (double)gm);
+        if (i == 13 || !((h.fluid0 >> i) & 1u)) continue;
+        atomicAdd(&j.gUR[3 * a.N + nb_index(a, h, i)], (double)gm);
       }
     }
     atomicAdd(&p.gamp[kb], (double)gu[0] * p.dU1[kb][0] + (double)gu[1] * p.dU1[kb][1] + (double)gu[2] * p.dU1[kb][2]);
-    grad_u_vjp(a, j, x, y, z, n, gG);
+    grad_u_vjp(a, j, h, gG);
   }
 }
 
@@ -663,15 +608,16 @@ __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, con
       atomicAdd(&p.gamp[kb], gU0 * p.dU0[kb][0] + gU1 * p.dU0[kb][1] + gU2 * p.dU0[kb][2]);
       continue;
     }
-    float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+    float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;  // as the forward: from the stored deviations
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-      const float v = C::load(A + i * a.N + n, wf(i));
-      rho += v;
+      const float v = C::load_dev(A + i * a.N + n);
+      dr += v;
       jx += cx(i) * v;
       jy += cy(i) * v;
       jz += cz(i) * v;
     }
+    const float rho = 1.f + dr;
     if (a.F) {
       jx -= 0.5f * a.F[n];
       jy -= 0.5f * a.F[a.N + n];
@@ -701,6 +647,8 @@ static BArgs bargs(elbm_ctx* c, const void* A) {
   a.list = c->blist;
   a.dyn_count = &c->cnt->dyn_count;
   a.brec = c->brec;
+  a.fix_list = nullptr;  // the adjoint kernels queue nothing
+  a.cnt = c->cnt;
   a.n_static = c->n_static;
   a.cap = c->blist_cap;
   a.moving = c->moving ? 1 : 0;
@@ -741,15 +689,10 @@ static void adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, const AdjA
   const dim3 blk(bx, 256 / bx, 1);
   const dim3 grd((c->p.nx + bx - 1) / bx, (c->p.ny + blk.y - 1) / blk.y, c->p.nz);
   const bool geo = c->flags != nullptr, force = c->bodyforce != nullptr;
-  uint32_t* q = (uint32_t*)c->fix_list;
-  if (geo && force) hipLaunchKernelGGL((k_adj_bulk<S, true, true>), grd, blk, 0, c->stream, a, j, q, c->cnt);
-  else if (geo) hipLaunchKernelGGL((k_adj_bulk<S, true, false>), grd, blk, 0, c->stream, a, j, q, c->cnt);
-  else if (force) hipLaunchKernelGGL((k_adj_bulk<S, false, true>), grd, blk, 0, c->stream, a, j, q, c->cnt);
-  else hipLaunchKernelGGL((k_adj_bulk<S, false, false>), grd, blk, 0, c->stream, a, j, q, c->cnt);
-  if (a.fp64) {
-    if (force) hipLaunchKernelGGL((k_adj_fixup<S, true>), dim3(256), dim3(256), 0, c->stream, a, j, q, c->cnt);
-    else hipLaunchKernelGGL((k_adj_fixup<S, false>), dim3(256), dim3(256), 0, c->stream, a, j, q, c->cnt);
-  }
+  if (geo && force) hipLaunchKernelGGL((k_adj_bulk<S, true, true>), grd, blk, 0, c->stream, a, j);
+  else if (geo) hipLaunchKernelGGL((k_adj_bulk<S, true, false>), grd, blk, 0, c->stream, a, j);
+  else if (force) hipLaunchKernelGGL((k_adj_bulk<S, false, true>), grd, blk, 0, c->stream, a, j);
+  else hipLaunchKernelGGL((k_adj_bulk<S, false, false>), grd, blk, 0, c->stream, a, j);
   if (geo) {
     const dim3 gf = grid_for((long)c->p.ny * c->p.nz);
     if (a.channel) hipLaunchKernelGGL(k_adj_faces_zero, gf, dim3(256), 0, c->stream, a, j);

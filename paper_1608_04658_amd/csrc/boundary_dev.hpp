@@ -38,6 +38,8 @@ struct BArgs {
   const int32_t* list;
   const uint32_t* dyn_count;
   double* brec;
+  uint32_t* fix_list;  // FP64 fix-up queue (wall nodes enter it tagged FIX_PRE)
+  DevCounters* cnt;
   int64_t n_static;
   int64_t cap;
   int32_t moving;
@@ -66,26 +68,241 @@ __device__ __forceinline__ long neighbour(const BArgs& a, int x, int y, int z, i
   return node_at(a, X, wrap(y + dy, a.ny), wrap(z + dz, a.nz));
 }
 
+// ---------------------------------------------------------------------------------------------
+// Prefetched neighbourhood of a listed node.  The wall rules read, per node, the flags of the 26
+// neighbours, the pulled populations, the node's own populations and U^t on a stencil; written as
+// loads behind data-dependent branches these form a chain of dozens of dependent memory round
+// trips.  Here every load of a phase is issued before any of its values is used (absent entries
+// read the node itself and are masked afterwards), so a node costs three round trips.
+
+__host__ __device__ constexpr int dir_index(int dx, int dy, int dz) { return 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1); }
+
+struct Nbhd {
+  long n;
+  int x, y, z;
+  uint32_t exists;  // bit i: x + c_i lies in the domain (i = 13: the node itself)
+  uint32_t fluid;   // bit i: exists and fluid at t+1
+  uint32_t fluid0;  // bit i: exists and fluid at both t and t+1
+  uint32_t dbar;    // bit i: population i is missing (its source is solid at t+1 or beyond the inlet)
+  uint32_t far;     // bit 2b: x + 2 e_b exists and is fluid at t+1; bit 2b+1: x - 2 e_b
+};
+
+__device__ __forceinline__ long nb_index(const BArgs& a, const Nbhd& h, int i) {
+  return neighbour(a, h.x, h.y, h.z, cx(i), cy(i), cz(i));
+}
+
+__device__ __forceinline__ long far_index(const BArgs& a, const Nbhd& h, int k) {
+  const int b = k >> 1, s = (k & 1) ? -2 : 2;
+  return neighbour(a, h.x, h.y, h.z, b == 0 ? s : 0, b == 1 ? s : 0, b == 2 ? s : 0);
+}
+
+// Phase 1: the flags.  The pull source x - c_i is the neighbour in direction opp(i), except at the
+// outlet (its source x is clamped to nx - 1) and through the inlet (missing).
+__device__ inline void nbhd_flags(const BArgs& a, long n, Nbhd& h) {
+  h.n = n;
+  h.x = (int)(n % a.nx);
+  h.y = (int)((n / a.nx) % a.ny);
+  h.z = (int)(n / ((long)a.nx * a.ny));
+  uint8_t fl[27], f2[6];
+  uint32_t ex = 0;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const long m = nb_index(a, h, i);
+    ex |= (m >= 0 ? 1u : 0u) << i;
+    fl[i] = a.flags[m >= 0 ? m : n];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const long m = far_index(a, h, k);
+    f2[k] = m >= 0 ? a.flags[m] : (uint8_t)FL_SOLID;
+  }
+  uint32_t fluid = 0, fluid0 = 0, dbar = 0, far = 0;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const bool e = (ex >> i) & 1u;
+    fluid |= (e && !(fl[i] & FL_SOLID) ? 1u : 0u) << i;
+    fluid0 |= (e && !(fl[i] & (FL_SOLID | FL_SOLID_PREV)) ? 1u : 0u) << i;
+  }
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const int sx = h.x - cx(i);
+    bool miss;
+    if (a.channel && sx < 0) {
+      miss = true;
+    } else {
+      // source direction: opp(i), or (0, -cy, -cz) where the outlet clamps x
+      const int s = (a.channel && sx >= a.nx) ? dir_index(0, -cy(i), -cz(i)) : opp(i);
+      miss = (fl[s] & FL_SOLID) != 0;
+    }
+    dbar |= (miss ? 1u : 0u) << i;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) far |= (!(f2[k] & FL_SOLID) ? 1u : 0u) << k;
+  h.exists = ex;
+  h.fluid = fluid;
+  h.fluid0 = fluid0;
+  h.dbar = dbar;
+  h.far = far;
+}
+
+__device__ __forceinline__ long pull_src(const BArgs& a, const Nbhd& h, int i) {
+  int sx = h.x - cx(i);
+  if (a.channel) sx = sx >= a.nx ? a.nx - 1 : (sx < 0 ? 0 : sx);
+  else sx = wrap(sx, a.nx);
+  return node_at(a, sx, wrap(h.y - cy(i), a.ny), wrap(h.z - cz(i), a.nz));
+}
+
+// Phase 2a: U^t at x + c_i where that node is fluid at t+1 (i = 13: at x) and at x +- 2 e_b.
+__device__ inline void nbhd_velocity(const BArgs& a, const Nbhd& h, float (&U)[27][3], float (&U2)[6][3]) {
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const long m = ((h.fluid >> i) & 1u) ? nb_index(a, h, i) : h.n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) U[i][c] = a.macro[c * a.N + m];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const long m = ((h.far >> k) & 1u) ? far_index(a, h, k) : h.n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) U2[k][c] = a.macro[c * a.N + m];
+  }
+}
+
 // Velocity gradient by finite differences on U^t (Sec. III), G[3a+b] = d u_a / d x_b.  Per axis:
 // central if both neighbours are usable (exist and fluid at t+1), else second-order one-sided
 // (forward side first), else first-order one-sided, else 0.
-__device__ inline void grad_u(const BArgs& a, int x, int y, int z, long n0, float (&G)[9]) {
+__device__ inline void grad_u_nb(const Nbhd& h, const float (&U)[27][3], const float (&U2)[6][3], float (&G)[9]) {
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
-    const int e0 = b == 0, e1 = b == 1, e2 = b == 2;
-    const long p1 = neighbour(a, x, y, z, e0, e1, e2), p2 = neighbour(a, x, y, z, 2 * e0, 2 * e1, 2 * e2);
-    const long m1 = neighbour(a, x, y, z, -e0, -e1, -e2), m2 = neighbour(a, x, y, z, -2 * e0, -2 * e1, -2 * e2);
-    const bool op1 = p1 >= 0 && !(a.flags[p1] & FL_SOLID), op2 = p2 >= 0 && !(a.flags[p2] & FL_SOLID);
-    const bool om1 = m1 >= 0 && !(a.flags[m1] & FL_SOLID), om2 = m2 >= 0 && !(a.flags[m2] & FL_SOLID);
+    const int ip = dir_index(b == 0, b == 1, b == 2), im = dir_index(-(b == 0), -(b == 1), -(b == 2));
+    const bool op1 = (h.fluid >> ip) & 1u, om1 = (h.fluid >> im) & 1u;
+    const bool op2 = (h.far >> (2 * b)) & 1u, om2 = (h.far >> (2 * b + 1)) & 1u;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float* U = a.macro + c * a.N;
+      const float u0 = U[13][c], up1 = U[ip][c], um1 = U[im][c], up2 = U2[2 * b][c], um2 = U2[2 * b + 1][c];
       float d;
-      if (op1 && om1) d = 0.5f * (U[p1] - U[m1]);
-      else if (op1 && op2) d = 0.5f * (-3.f * U[n0] + 4.f * U[p1] - U[p2]);
-      else if (om1 && om2) d = 0.5f * (3.f * U[n0] - 4.f * U[m1] + U[m2]);
-      else if (op1) d = U[p1] - U[n0];
-      else if (om1) d = U[n0] - U[m1];
+      if (op1 && om1) d = 0.5f * (up1 - um1);
+      else if (op1 && op2) d = 0.5f * (-3.f * u0 + 4.f * up1 - up2);
+      else if (om1 && om2) d = 0.5f * (3.f * u0 - 4.f * um1 + um2);
+      else if (op1) d = up1 - u0;
+      else if (om1) d = u0 - um1;
+      else d = 0.f;
+      G[3 * c + b] = d;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Lane-parallel form: one listed node per group of 32 lanes (two per wavefront), lane i < 27 owns
+// direction i, lanes 27..31 (and lane 13 for a sixth) fetch the nodes two steps away along the
+// axes.  Per-direction work runs side by side across the lanes instead of as 27 unrolled copies
+// in one thread; sums over directions are butterfly reductions inside the group (fixed order).
+constexpr int GROUP = 32;
+
+__device__ __forceinline__ float gsum(float v) {
+#pragma unroll
+  for (int o = GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GROUP);
+  return v;
+}
+__device__ __forceinline__ double gsum(double v) {
+#pragma unroll
+  for (int o = GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GROUP);
+  return v;
+}
+// Bit l = predicate of lane l of the calling group.
+__device__ __forceinline__ uint32_t gballot(bool p) {
+  const unsigned long long b = __ballot(p);
+  return (uint32_t)(b >> (threadIdx.x & 32u));
+}
+__host__ __device__ constexpr int far_lane(int k) { return k < 5 ? 27 + k : 13; }
+
+__device__ __forceinline__ long far_node(const BArgs& a, int x, int y, int z, int k) {
+  const int b = k >> 1, s = (k & 1) ? -2 : 2;
+  return neighbour(a, x, y, z, b == 0 ? s : 0, b == 1 ? s : 0, b == 2 ? s : 0);
+}
+__device__ __forceinline__ long pull_node(const BArgs& a, int x, int y, int z, int i) {
+  int sx = x - cx(i);
+  if (a.channel) sx = sx >= a.nx ? a.nx - 1 : (sx < 0 ? 0 : sx);
+  else sx = wrap(sx, a.nx);
+  return node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
+}
+
+// This lane's view of a listed node's neighbourhood; the masks are the same on every lane.
+struct LaneNb {
+  long n;
+  int x, y, z;
+  uint32_t fluid;   // bit i: x + c_i exists and is fluid at t+1 (i = 13: the node itself)
+  uint32_t fluid0;  // bit i: x + c_i exists and is fluid at t and t+1
+  uint32_t dbar;    // bit i: population i is missing (source solid at t+1 or beyond the inlet)
+  uint32_t far;     // bit 2b: x + 2 e_b exists and is fluid at t+1; bit 2b+1: x - 2 e_b
+  float f, fo;      // pulled deviation of direction lane (0 where missing); own deviation A_lane(x)
+  float U[3];       // U^t at x + c_lane where fluid at t+1
+  float V[3];       // U^t at the far node of this lane where fluid at t+1
+  float R;          // R^t at x + c_lane where fluid at t and t+1
+};
+
+// All lanes of the group must call this together (it shuffles and ballots).
+template <int S, bool POPS, bool RHO>
+__device__ inline void lane_gather(const BArgs& a, const typename Codec<S>::E* A, long n, int lane, LaneNb& h) {
+  using C = Codec<S>;
+  h.n = n;
+  const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+  h.x = x;
+  h.y = y;
+  h.z = z;
+  const bool own = lane < 27;
+  const int i = own ? lane : 13;
+  const long m = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
+  const int fk = lane >= 27 ? lane - 27 : (lane == 13 ? 5 : -1);
+  const long mf = fk >= 0 ? far_node(a, x, y, z, fk) : -1;
+  const uint8_t fl = m >= 0 ? a.flags[m] : FL_SOLID;
+  const uint8_t ff = mf >= 0 ? a.flags[mf] : FL_SOLID;
+  h.fluid = gballot(own && m >= 0 && !(fl & FL_SOLID));
+  h.fluid0 = gballot(own && m >= 0 && !(fl & (FL_SOLID | FL_SOLID_PREV)));
+  const uint32_t fb = gballot(fk >= 0 && !(ff & FL_SOLID));
+  h.far = ((fb >> 27) & 31u) | (((fb >> 13) & 1u) << 5);
+  // source of direction i: the neighbour in direction opp(i), or (0, -cy, -cz) where the outlet
+  // clamps x; through the inlet it is missing
+  const int sx = x - cx(i);
+  const int s = (a.channel && sx >= a.nx) ? dir_index(0, -cy(i), -cz(i)) : opp(i);
+  const int fls = __shfl((int)fl, s, GROUP);
+  const bool miss = own && ((a.channel && sx < 0) || (fls & FL_SOLID));
+  h.dbar = gballot(miss);
+  h.f = 0.f;
+  h.fo = 0.f;
+  if (POPS && own) {
+    h.fo = C::load_dev(A + (long)i * a.N + n);
+    if (!miss) h.f = C::load_dev(A + (long)i * a.N + pull_node(a, x, y, z, i));
+  }
+  const bool uf = own && ((h.fluid >> i) & 1u);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) h.U[c] = uf ? a.macro[c * a.N + m] : 0.f;
+  const bool vf = fk >= 0 && ((h.far >> fk) & 1u);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) h.V[c] = vf ? a.macro[c * a.N + mf] : 0.f;
+  h.R = (RHO && own && ((h.fluid0 >> i) & 1u)) ? a.macro[3 * a.N + m] : 0.f;
+}
+
+// grad_u on the group's gathered stencil (same rule and arithmetic); every lane gets G.
+__device__ inline void grad_u_grp(const LaneNb& h, float (&G)[9]) {
+  float u0[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u0[c] = __shfl(h.U[c], 13, GROUP);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int ip = dir_index(b == 0, b == 1, b == 2), im = dir_index(-(b == 0), -(b == 1), -(b == 2));
+    const bool op1 = (h.fluid >> ip) & 1u, om1 = (h.fluid >> im) & 1u;
+    const bool op2 = (h.far >> (2 * b)) & 1u, om2 = (h.far >> (2 * b + 1)) & 1u;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float up1 = __shfl(h.U[c], ip, GROUP), um1 = __shfl(h.U[c], im, GROUP);
+      const float up2 = __shfl(h.V[c], far_lane(2 * b), GROUP), um2 = __shfl(h.V[c], far_lane(2 * b + 1), GROUP);
+      float d;
+      if (op1 && om1) d = 0.5f * (up1 - um1);
+      else if (op1 && op2) d = 0.5f * (-3.f * u0[c] + 4.f * up1 - up2);
+      else if (om1 && om2) d = 0.5f * (3.f * u0[c] - 4.f * um1 + um2);
+      else if (op1) d = up1 - u0[c];
+      else if (om1) d = u0[c] - um1;
       else d = 0.f;
       G[3 * c + b] = d;
     }
@@ -136,12 +353,16 @@ __device__ inline void link_geometry(const BArgs& a, const Bodies& bd, int i, in
 // Refill of a node uncovered at t+1 (Sec. III): Grad's distribution with the wall velocity of the
 // body that held the node at t (taken at t+1), the mean R^t of the neighbours fluid at t and t+1
 // (rho0 if none) and the pressure tensor with the finite-difference gradient of U^t.
-__device__ inline void refill_pops(const BArgs& a, const Bodies& bd, int x, int y, int z, long n, float (&f)[27],
-                                   int& kb, float& ravg, int& m, float (&uw)[3], float (&G)[9]) {
-  kb = first_body(bd, false, x, y, z);
+__device__ inline void refill_pops(const BArgs& a, const Bodies& bd, const Nbhd& h, float (&f)[27], int& kb,
+                                   float& ravg, int& m, float (&uw)[3], float (&G)[9]) {
+  float R[27], U[27][3], U2[6][3];
+#pragma unroll
+  for (int i = 0; i < 27; ++i) R[i] = a.macro[3 * a.N + (((h.fluid0 >> i) & 1u) ? nb_index(a, h, i) : h.n)];
+  nbhd_velocity(a, h, U, U2);
+  kb = first_body(bd, false, h.x, h.y, h.z);
   if (kb < 0) kb = 0;
   const BodyDev& b = bd.b[kb];
-  const double r[3] = {x - b.c1[0], y - b.c1[1], z - b.c1[2]};
+  const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
   uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
   uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
   uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
@@ -149,15 +370,13 @@ __device__ inline void refill_pops(const BArgs& a, const Bodies& bd, int x, int 
   m = 0;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    if (i == 13) continue;
-    const long nn = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
-    if (nn < 0 || (a.flags[nn] & (FL_SOLID | FL_SOLID_PREV))) continue;
-    rs += a.macro[3 * a.N + nn];
+    if (i == 13 || !((h.fluid0 >> i) & 1u)) continue;
+    rs += R[i];
     ++m;
   }
   ravg = m ? rs / (float)m : (float)a.rho0;
   float Pi[6];
-  grad_u(a, x, y, z, n, G);
+  grad_u_nb(h, U, U2, G);
   pressure_tensor(ravg, uw, G, a.beta, Pi);
 #pragma unroll
   for (int i = 0; i < 27; ++i) f[i] = grad_pop(i, ravg, uw, Pi);

@@ -53,7 +53,7 @@ int validate(const elbm_params* p, char* err) {
   if (!p) return snprintf(err, 256, "params is NULL"), ELBM_EINVAL;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return snprintf(err, 256, "lattice size must be >= 1"), ELBM_EINVAL;
   const double N = (double)p->nx * p->ny * p->nz;
-  if (N >= 4294967295.0) return snprintf(err, 256, "more than 2^32-1 nodes"), ELBM_EINVAL;
+  if (N >= 2147483648.0) return snprintf(err, 256, "more than 2^31-1 nodes"), ELBM_EINVAL;
   if (p->storage < 0 || p->storage > 2) return snprintf(err, 256, "bad storage %d", p->storage), ELBM_EINVAL;
   if (p->bc_x != ELBM_BC_PERIODIC && p->bc_x != ELBM_BC_CHANNEL) return snprintf(err, 256, "bad bc_x"), ELBM_EINVAL;
   if (p->bc_x == ELBM_BC_CHANNEL && p->nx < 4) return snprintf(err, 256, "channel needs nx >= 4"), ELBM_EINVAL;
@@ -305,11 +305,9 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
       HIP_OK(c, hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream));
       c->ev_used += 1;
     }
-    HIP_OK(c, launch_fixup(c));
-    if (geo) {
-      HIP_OK(c, launch_boundary(c, bd));
-      HIP_OK(c, launch_force_reduce(c));
-    }
+    if (geo) HIP_OK(c, launch_boundary(c, bd));
+    HIP_OK(c, launch_fixup(c));  // bulk and wall nodes queued for the FP64 collision
+    if (geo) HIP_OK(c, launch_force_reduce(c));
     c->cur ^= 1;
     c->t += 1;
   }

@@ -31,6 +31,10 @@ constexpr uint8_t FL_SOLID = 1;       // solid at the time level being produced 
 constexpr uint8_t FL_SOLID_PREV = 2;  // solid at the previous time level (t)
 constexpr uint8_t FL_SPECIAL = 4;     // handled by the boundary kernel (missing populations or refill)
 
+// FP64 fix-up queue entries: node index, with this bit set when the node's pre-collision
+// deviations already sit in the output buffer (wall nodes) instead of being pulled from A^t.
+constexpr uint32_t FIX_PRE = 0x80000000u;
+
 // ---------------------------------------------------------------------------------------------
 // Population storage: every format stores the deviation d = f - W_i from the lattice weight (FP32,
 // or FP16 / BF16 rounded to nearest even); arithmetic is FP32 (FP64 on the recomputation path).

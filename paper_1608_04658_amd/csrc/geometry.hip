@@ -9,6 +9,8 @@
 // convergent; the bulk sweep skips every flagged node.  Force sums are deterministic: each list
 // entry writes its own FP64 record and a separate kernel reduces the records in list order.
 #include <math.h>
+
+#include <algorithm>
 #include <stdio.h>
 
 #include "elbm_internal.hpp"
@@ -304,154 +306,150 @@ __global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, flo
 
 // ---------------------------------------------------------------------------------------------
 // Refill before streaming: the uncovered nodes of the step get their Grad populations written into
-// the current buffer A^t, where their neighbours (and the node itself) pull them.
+// the current buffer A^t, where their neighbours (and the node itself) pull them.  One node per
+// group of 32 lanes; only the dynamic (body) part of the list can hold uncovered nodes.
 template <int S>
-__global__ __launch_bounds__(128) void k_refill(const BArgs a, const Bodies bd, void* Aw) {
+__global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, void* Aw) {
   using C = Codec<S>;
   using E = typename C::E;
   E* __restrict__ A = (E*)Aw;
   int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
   if (count > a.cap) count = a.cap;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & (GROUP - 1), g = threadIdx.x / GROUP;
+  for (int64_t k = a.n_static + 2 * (int64_t)blockIdx.x + g; k < count; k += 2 * (int64_t)gridDim.x) {
     const long n = a.list[k];
-    if (!(a.flags[n] & FL_SOLID_PREV)) continue;
-    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
-    float f[27], uw[3], G[9], ravg;
-    int kb, m;
-    refill_pops(a, bd, x, y, z, n, f, kb, ravg, m, uw, G);
-#pragma unroll
-    for (int i = 0; i < 27; ++i) C::store(A + i * a.N + n, f[i], wf(i));
+    if (!(a.flags[n] & FL_SOLID_PREV)) continue;  // uniform over the group
+    LaneNb h;
+    lane_gather<S, false, true>(a, A, n, lane, h);
+    int kb = first_body(bd, false, h.x, h.y, h.z);
+    if (kb < 0) kb = 0;
+    const BodyDev& b = bd.b[kb];
+    const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
+    float uw[3];
+    uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
+    uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
+    uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+    const uint32_t nbm = h.fluid0 & ~(1u << 13);
+    const float rs = gsum(lane != 13 ? h.R : 0.f);
+    const int m = __popc(nbm);
+    const float ravg = m ? rs / (float)m : (float)a.rho0;
+    float G[9], Pi[6];
+    grad_u_grp(h, G);
+    pressure_tensor(ravg, uw, G, a.beta, Pi);
+    if (lane < 27) C::store(A + (long)lane * a.N + n, grad_pop(lane, ravg, uw, Pi), wf(lane));
   }
 }
 
+// Wall nodes (Sec. III): Grad reconstruction of the missing populations, the momentum exchange of
+// each link (Sec. IV.A), then the KBC collision of the node.  One node per group of 32 lanes; the
+// collision of the 27 populations runs on the group's first lane, exchanged through LDS.
 template <int S, bool FORCE>
-__global__ __launch_bounds__(128) void k_boundary(const BArgs a, const Bodies bd) {
+__global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd) {
   using C = Codec<S>;
   using E = typename C::E;
   const E* __restrict__ A = (const E*)a.A;
   E* __restrict__ B = (E*)a.B;
+  __shared__ float sh[2][GROUP];
   int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
   if (count > a.cap) count = a.cap;
   const int nb = bd.nb;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
-    const long n = a.list[k];
-    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+  const int lane = threadIdx.x & (GROUP - 1), g = threadIdx.x / GROUP;
+  const int i = lane < 27 ? lane : 13;
+  for (int64_t base = 2 * (int64_t)blockIdx.x; base < count; base += 2 * (int64_t)gridDim.x) {
+    // the loop is uniform over the block (barriers below); a group past the end repeats the
+    // block's first node and stores nothing
+    const int64_t k = base + g;
+    const bool active = k < count;
+    const long n = a.list[active ? k : base];
+    LaneNb h;
+    lane_gather<S, true, false>(a, A, n, lane, h);
     double* rec = a.brec + k * nb * 6;
-    for (int j = 0; j < nb * 6; ++j) rec[j] = 0.0;
-    const uint8_t fl = a.flags[n];
-    float f[27];
-    {
-      // missing populations at a wall (Sec. III)
-      uint32_t dmask = 0;
+    // f holds deviations from the weights throughout, so that pulled populations pass through
+    // unchanged in every storage form
+    float fi = h.f;
+    const uint32_t dmask = h.dbar;
+    if (dmask) {  // missing populations at a wall (Sec. III); uniform over the group
+      const bool mine = lane < 27 && ((dmask >> lane) & 1u);
+      double q = 0.0, uw[3] = {0.0, 0.0, 0.0};
+      int kb = -1;
+      if (mine) link_geometry(a, bd, i, h.x, h.y, h.z, q, uw, kb);
+      const float fb = __shfl(h.fo, opp(i), GROUP);  // bounce-back value A^t_{opp(i)}(x)
+      float tu[3] = {0.f, 0.f, 0.f}, trs = 0.f, trd = 0.f;
+      if (mine) {
+        const bool fluid = (h.fluid >> lane) & 1u;
+        const float qf = (float)q, inv = 1.f / (1.f + qf);
 #pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        int sx = x - cx(i);
-        if (a.channel && sx < 0) {
-          dmask |= 1u << i;
-          f[i] = 0.f;
-          continue;
-        }
-        if (a.channel) sx = sx >= a.nx ? a.nx - 1 : sx;
-        else sx = wrap(sx, a.nx);
-        const long ns = node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
-        if (a.flags[ns] & FL_SOLID) {
-          dmask |= 1u << i;
-          f[i] = 0.f;
-          continue;
-        }
-        f[i] = C::load(A + i * a.N + ns, wf(i));
+        for (int c = 0; c < 3; ++c) tu[c] = (qf * (fluid ? h.U[c] : (float)uw[c]) + (float)uw[c]) * inv;
+        trs = fb;
+        trd = (float)(6.0 * wd(i) * a.rho0 * (cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]));
+      } else if (lane < 27) {
+        trs = h.f;
       }
-      if (dmask) {
-        float ut[3] = {0.f, 0.f, 0.f};
-        float rstat = 0.f, rdyn = 0.f;
-        int nD = 0;
+      const float rstat = gsum(trs), rdyn = gsum(trd);  // rstat: sum of deviations (weights add to 1)
+      const float invn = 1.f / (float)__popc(dmask);
+      float ut[3];
 #pragma unroll
-        for (int i = 0; i < 27; ++i) {
-          if (!((dmask >> i) & 1u)) {
-            rstat += f[i];
-            continue;
-          }
-          ++nD;
-          rstat += C::load(A + opp(i) * a.N + n, wf(opp(i)));
-          double q, uw[3];
-          int kb;
-          link_geometry(a, bd, i, x, y, z, q, uw, kb);
-          const long nf = neighbour(a, x, y, z, cx(i), cy(i), cz(i));
-          float uf[3];
-          if (nf >= 0 && !(a.flags[nf] & FL_SOLID)) {
-            uf[0] = a.macro[nf];
-            uf[1] = a.macro[a.N + nf];
-            uf[2] = a.macro[2 * a.N + nf];
-          } else {
-            uf[0] = (float)uw[0];
-            uf[1] = (float)uw[1];
-            uf[2] = (float)uw[2];
-          }
-          const float qf = (float)q, inv = 1.f / (1.f + qf);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) ut[c] += (qf * uf[c] + (float)uw[c]) * inv;
-          rdyn += (float)(6.0 * wd(i) * a.rho0 * (cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]));
-        }
-        const float invn = 1.f / (float)nD;
-        ut[0] *= invn;
-        ut[1] *= invn;
-        ut[2] *= invn;
-        const float rt = rstat + rdyn;
-        float G[9], Pi[6];
-        grad_u(a, x, y, z, n, G);
-        pressure_tensor(rt, ut, G, a.beta, Pi);
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-          if (!((dmask >> i) & 1u)) continue;
-          const float fs = grad_pop(i, rt, ut, Pi);
-          f[i] = fs;
-          double q, uw[3];
-          int kb;
-          link_geometry(a, bd, i, x, y, z, q, uw, kb);
-          if (kb < 0) continue;
+      for (int c = 0; c < 3; ++c) ut[c] = gsum(tu[c]) * invn;
+      const float rt = 1.f + rstat + rdyn;
+      float G[9], Pi[6];
+      grad_u_grp(h, G);
+      pressure_tensor(rt, ut, G, a.beta, Pi);
+      double dF[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (mine) {
+        const float fs = grad_pop(i, rt, ut, Pi);
+        fi = fs - wf(i);
+        if (kb >= 0) {
           // Galilean-invariant momentum exchange of the link
-          const double fo = (double)C::load(A + opp(i) * a.N + n, wf(opp(i)));
+          const double fbd = wd(opp(i)) + (double)fb;
           const double c[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
-          double dF[3];
 #pragma unroll
-          for (int e = 0; e < 3; ++e) dF[e] = fo * (-c[e] - uw[e]) - (double)fs * (c[e] - uw[e]);
+          for (int e = 0; e < 3; ++e) dF[e] = fbd * (-c[e] - uw[e]) - (double)fs * (c[e] - uw[e]);
           const BodyDev& b = bd.b[kb];
-          const double r[3] = {x - q * c[0] - b.c1[0], y - q * c[1] - b.c1[1], z - q * c[2] - b.c1[2]};
-          double* rb = rec + kb * 6;
-          rb[0] += dF[0];
-          rb[1] += dF[1];
-          rb[2] += dF[2];
-          rb[3] += r[1] * dF[2] - r[2] * dF[1];
-          rb[4] += r[2] * dF[0] - r[0] * dF[2];
-          rb[5] += r[0] * dF[1] - r[1] * dF[0];
+          const double r[3] = {h.x - q * c[0] - b.c1[0], h.y - q * c[1] - b.c1[1], h.z - q * c[2] - b.c1[2]};
+          dF[3] = r[1] * dF[2] - r[2] * dF[1];
+          dF[4] = r[2] * dF[0] - r[0] * dF[2];
+          dF[5] = r[0] * dF[1] - r[1] * dF[0];
         }
       }
+      for (int bb = 0; bb < nb; ++bb) {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          const double v = gsum(kb == bb ? dF[e] : 0.0);
+          if (active && lane == e) rec[bb * 6 + e] = v;
+        }
+      }
+    } else if (active) {
+      for (int j = lane; j < nb * 6; j += GROUP) rec[j] = 0.0;
     }
     if (a.stream_only) {
-#pragma unroll
-      for (int i = 0; i < 27; ++i) C::store(B + i * a.N + n, f[i], wf(i));
+      if (active && lane < 27) C::store_dev(B + (long)lane * a.N + n, fi);
       continue;
     }
-    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-    if (FORCE) {
-      Fx = a.F[n];
-      Fy = a.F[a.N + n];
-      Fz = a.F[2 * a.N + n];
-    }
-    double d[27];
+    sh[g][lane] = fi;
+    __syncthreads();
+    if (lane == 0) {
+      float f[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      d[i] = (double)f[i] - wd(i);
-      f[i] = f[i] - wf(i);  // deviations for the collision
-    }
-    const KbcOut<float> r = kbc_collide<float, FORCE>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
-    if (a.fp64 && needs_fp64(r, a.thr)) {
-      kbc_collide<double, FORCE>(d, (double)a.beta, 1.0 / (double)a.beta, Fx, Fy, Fz);
+      for (int j = 0; j < 27; ++j) f[j] = sh[g][j];
+      float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+      if (FORCE) {
+        Fx = a.F[n];
+        Fy = a.F[a.N + n];
+        Fz = a.F[2 * a.N + n];
+      }
+      const KbcOut<float> r = kbc_collide<float, FORCE>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
+      if (a.fp64 && needs_fp64(r, a.thr)) {
+        // <dh|dh> at the FP32 noise floor: store the pre-collision deviations (still in LDS) and
+        // queue the node for the FP64 collision of k_fixup
+        if (active) a.fix_list[atomicAdd(&a.cnt->fix_count, 1u)] = (uint32_t)n | FIX_PRE;
+      } else {
 #pragma unroll
-      for (int i = 0; i < 27; ++i) f[i] = (float)d[i];
+        for (int j = 0; j < 27; ++j) sh[g][j] = f[j];
+      }
     }
-#pragma unroll
-    for (int i = 0; i < 27; ++i) C::store_dev(B + i * a.N + n, f[i]);
+    __syncthreads();
+    if (active && lane < 27) C::store_dev(B + (long)lane * a.N + n, sh[g][lane]);
+    __syncthreads();
   }
 }
 
@@ -622,7 +620,8 @@ hipError_t geometry_for_step(elbm_ctx* c, const Bodies& bd) {
 
 template <int S>
 static void boundary_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd) {
-  const dim3 g(512), b(128);
+  // two list entries per 64-lane workgroup
+  const dim3 g((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap + 1) / 2, 1), 16384)), b(64);
   if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true>), g, b, 0, c->stream, a, bd);
   else hipLaunchKernelGGL((k_boundary<S, false>), g, b, 0, c->stream, a, bd);
 }
@@ -638,6 +637,8 @@ BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
   a.list = c->blist;
   a.dyn_count = &c->cnt->dyn_count;
   a.brec = c->brec;
+  a.fix_list = (uint32_t*)c->fix_list;
+  a.cnt = c->cnt;
   a.n_static = c->n_static;
   a.cap = c->blist_cap;
   a.moving = c->moving ? 1 : 0;
@@ -659,7 +660,8 @@ BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
 hipError_t launch_refill(elbm_ctx* c, const Bodies& bd, void* A) {
   if (!c->moving) return hipSuccess;  // fixed bodies uncover nothing
   const BArgs a = boundary_args(c, A, nullptr);
-  const dim3 g(256), b(128);
+  const int64_t dyn = a.cap - a.n_static;
+  const dim3 g((unsigned)std::min<int64_t>(std::max<int64_t>((dyn + 1) / 2, 1), 4096)), b(64);
   switch (c->p.storage) {
     case ELBM_STORAGE_F32: hipLaunchKernelGGL(k_refill<ELBM_STORAGE_F32>, g, b, 0, c->stream, a, bd, A); break;
     case ELBM_STORAGE_F16: hipLaunchKernelGGL(k_refill<ELBM_STORAGE_F16>, g, b, 0, c->stream, a, bd, A); break;

@@ -23,6 +23,9 @@ struct SweepArgs {
   int32_t channel;
   int32_t fp64;
   int32_t stream_only;
+  int32_t remap;   // 1-D grid of tiles, each XCD taking a contiguous chunk (see sweep_shape)
+  int32_t gx, gy;  // tiles along x and y
+  int32_t tiles;   // gx * gy * nz
 };
 
 // Source coordinates of the pull for each velocity component: xs[cx+1] = x - cx and the 9 row
@@ -52,9 +55,19 @@ template <int S, bool FLAGS, bool FORCE>
 __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
   using C = Codec<S>;
   using E = typename C::E;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
+  int tx = blockIdx.x, ty = blockIdx.y, z = blockIdx.z;
+  if (a.remap) {
+    // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
+    // tiles, so that the x-neighbouring tiles of a row, which share the cache lines at their
+    // edges, run on the same XCD (same L2) at about the same time
+    const int b = blockIdx.x, xcd = b & 7, j = b >> 3, q = a.tiles >> 3, r = a.tiles & 7;
+    const int t = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + j;
+    tx = t % a.gx;
+    ty = (t / a.gx) % a.gy;
+    z = t / (a.gx * a.gy);
+  }
+  const int x = tx * blockDim.x + threadIdx.x;
+  const int y = ty * blockDim.y + threadIdx.y;
   if (x >= a.nx || y >= a.ny) return;
   const uint32_t n = (uint32_t)((z * a.ny + y) * a.nx + x);
   if (FLAGS) {
@@ -105,16 +118,23 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
   const E* __restrict__ A = (const E*)a.A;
   E* __restrict__ B = (E*)a.B;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
-    const uint32_t n = a.fix_list[k];
-    const int x = (int)(n % (uint32_t)a.nx);
-    const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
-    const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
-    uint32_t xs[3], rs[9];
-    gather_offsets(x, y, z, a, xs, rs);
+    const uint32_t e = a.fix_list[k];
+    const uint32_t n = e & ~FIX_PRE;
     double f[27];  // deviations f - W
+    if (e & FIX_PRE) {
+      // wall node: its reconstructed pre-collision deviations were left in B
 #pragma unroll
-    for (int i = 0; i < 27; ++i)
-      f[i] = (double)C::load_dev(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]));
+      for (int i = 0; i < 27; ++i) f[i] = (double)C::load_dev(B + (size_t)i * a.N + n);
+    } else {
+      const int x = (int)(n % (uint32_t)a.nx);
+      const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
+      const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
+      uint32_t xs[3], rs[9];
+      gather_offsets(x, y, z, a, xs, rs);
+#pragma unroll
+      for (int i = 0; i < 27; ++i)
+        f[i] = (double)C::load_dev(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]));
+    }
     double Fx = 0, Fy = 0, Fz = 0;
     if (FORCE) {
       Fx = a.F[n];
@@ -157,18 +177,29 @@ static SweepArgs sweep_args(elbm_ctx* c) {
   a.channel = c->p.bc_x == ELBM_BC_CHANNEL;
   a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64) && !(c->p.flags & ELBM_FLAG_STREAM_ONLY);
   a.stream_only = (c->p.flags & ELBM_FLAG_STREAM_ONLY) != 0;
+  a.remap = 0;
+  a.gx = a.gy = a.tiles = 0;
   return a;
 }
 
-// Block shape: the widest power of two <= 256 (<= 128 for rows longer than 256, which measured
-// faster on 512^3) along x that divides nx (at least 32), the rest of the 256 threads along y.
-static void sweep_shape(int nx, int ny, int nz, dim3& grid, dim3& block) {
-  int bx = nx > 256 ? 128 : 256;
+// Launch shape (measured on 256^3 and 512^3): 256-thread workgroups, x-extent the widest power of
+// two <= 256 that divides nx (at least 32), the rest along y.  FP32 rows longer than 256 use
+// 128-wide tiles in the XCD-contiguous order of k_sweep (on 512^3: +6 % against 256-wide and +12 %
+// against 128-wide tiles in dispatch order); 256-wide rows and 2-byte storage are fastest in plain
+// dispatch order.
+static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const bool remap = storage == ELBM_STORAGE_F32 && nx > 256;
+  int bx = remap ? 128 : 256;
   while (bx > 32 && (nx % bx) != 0) bx >>= 1;
   if (nx < bx) bx = 32;
   const int by = 256 / bx;
   block = dim3(bx, by, 1);
-  grid = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nz);
+  a.gx = (nx + bx - 1) / bx;
+  a.gy = (ny + by - 1) / by;
+  a.tiles = a.gx * a.gy * nz;
+  a.remap = remap ? 1 : 0;
+  grid = remap ? dim3(a.tiles, 1, 1) : dim3(a.gx, a.gy, nz);
 }
 
 template <int S>
@@ -183,9 +214,9 @@ static hipError_t sweep_s(elbm_ctx* c, const SweepArgs& a, dim3 g, dim3 b) {
 }
 
 hipError_t launch_sweep(elbm_ctx* c) {
-  const SweepArgs a = sweep_args(c);
+  SweepArgs a = sweep_args(c);
   dim3 g, b;
-  sweep_shape(c->p.nx, c->p.ny, c->p.nz, g, b);
+  sweep_shape(a, c->p.storage, g, b);
   switch (c->p.storage) {
     case ELBM_STORAGE_F32: return sweep_s<ELBM_STORAGE_F32>(c, a, g, b);
     case ELBM_STORAGE_F16: return sweep_s<ELBM_STORAGE_F16>(c, a, g, b);

@@ -7,9 +7,13 @@ the difference step): for random lam' and dA,
 with J dA and dF/dA[dA] from central differences of one oracle step; likewise for the body-force
 field (direction v) and the amplitude.  Solid masks are frozen at the nominal ones (their
 derivative is zero).  Rollouts: dL/d(amp) and <dL/dF, v> of a windowed mean drag, vs central
-differences (h = 1e-3) of oracle rollouts with the masks of the nominal run.  Bounds: a single step
-within FP32 rounding of the summed terms (1e-6 of sum |terms| for dA, 1e-5 for the body force, whose
-terms are 1e-6 smaller), 2e-4 relative for the amplitude; rollouts 1e-4 relative."""
+differences of oracle rollouts with the masks of the nominal run (amplitude step 1e-5: with larger
+steps the rollout difference quotient has not converged -- at 1e-3 it is off by 1e-3 -- because the
+stabiliser responds nonlinearly at nodes whose <dh|dh> is tiny; body-force step 1e-3, converged to
+2e-7).  Bounds: a single step within FP32 rounding of the summed terms (1e-6 of sum |terms| for dA,
+1e-5 for the body force, whose terms are 1e-6 smaller), 2e-4 relative for the amplitude; rollouts 1e-4
+relative for the amplitude and for a smooth body-force direction, 1e-6 of sum |terms| for a random
+direction (whose inner product cancels by orders of magnitude)."""
 import numpy as np
 import pytest
 
@@ -126,11 +130,18 @@ def test_single_step_adjoint_dot_products(E, O, torch_cuda, t0):
     assert abs(lhsA - gamp) <= 2e-4 * abs(lhsA)
 
 
-def _rollout_case(O, E, torch, cfg, steps, window, K, seed, h_amp=1e-3, h_F=1e-3):
+def _smooth_direction(shape):
+    """Streamwise body-force direction varying smoothly across the channel (amplitude 1e-6)."""
+    nx, ny, nz = shape
+    v = np.zeros((3, nz, ny, nx))
+    v[0] = 1e-6 * (1.0 + 0.5 * np.sin(2.0 * np.pi * np.arange(ny) / ny))[None, :, None]
+    return v
+
+
+def _rollout_case(O, E, torch, cfg, steps, window, K, seed, h_amp=1e-5, h_F=1e-3):
     from paper_1608_04658_amd.adjoint import ForceLoss, ForceRollout, window_weights
-    nx, ny, nz = cfg["shape"]
     Fh = WL.body_force(cfg["shape"], seed, 1e-6).astype(np.float32).astype(np.float64)
-    v = WL.body_force(cfg["shape"], seed + 1, 1e-6)
+    dirs = {"random": WL.body_force(cfg["shape"], seed + 1, 1e-6), "smooth": _smooth_direction(cfg["shape"])}
     wts = window_weights(steps, window[0], window[1])
     rho, u = WL.uniform_flow(cfg["shape"], cfg["u_in"])
     amp0 = cfg["body"]["amp"]
@@ -142,7 +153,7 @@ def _rollout_case(O, E, torch, cfg, steps, window, K, seed, h_amp=1e-3, h_F=1e-3
     Lg = ForceLoss.apply(Ft, at, ro)
     Lg.backward()
     gA = float(at.grad)
-    gFv = float(np.sum(Ft.grad.double().cpu().numpy() * v))
+    gF = Ft.grad.double().cpu().numpy()
 
     # oracle: nominal run records the masks; perturbed runs reuse them
     def run(amp, F, masks=None):
@@ -161,10 +172,29 @@ def _rollout_case(O, E, torch, cfg, steps, window, K, seed, h_amp=1e-3, h_F=1e-3
     Lp, _ = run(amp0 + h_amp, Fh, masks)
     Lm, _ = run(amp0 - h_amp, Fh, masks)
     fdA = (Lp - Lm) / (2 * h_amp)
-    Lp, _ = run(amp0, Fh + h_F * v, masks)
-    Lm, _ = run(amp0, Fh - h_F * v, masks)
-    fdF = (Lp - Lm) / (2 * h_F)
-    return float(Lg), L0, gA, fdA, gFv, fdF
+    res = dict(Lg=float(Lg), L0=L0, gA=gA, fdA=fdA)
+    _say(f"L gpu {float(Lg):.8e} oracle {L0:.8e}; dL/dA adjoint {gA:.8e} FD {fdA:.8e} "
+         f"rel {abs(gA - fdA) / abs(fdA):.2e}")
+    for name, v in dirs.items():
+        Lp, _ = run(amp0, Fh + h_F * v, masks)
+        Lm, _ = run(amp0, Fh - h_F * v, masks)
+        fd = (Lp - Lm) / (2 * h_F)
+        g = float(np.sum(gF * v))
+        terms = float(np.sum(np.abs(gF * v)))
+        res[name] = (g, fd, terms)
+        _say(f"<dL/dF,v_{name}> adjoint {g:.8e} FD {fd:.8e} rel {abs(g - fd) / abs(fd):.2e} "
+             f"(sum|terms| {terms:.3e}, cancellation {terms / abs(fd):.1f})")
+    return res
+
+
+def _check_rollout(r):
+    assert abs(r["Lg"] - r["L0"]) <= 1e-4 * abs(r["L0"])
+    assert abs(r["gA"] - r["fdA"]) <= 1e-4 * abs(r["fdA"])
+    g, fd, _ = r["smooth"]
+    assert abs(g - fd) <= 1e-4 * abs(fd)
+    g, fd, terms = r["random"]
+    # a random direction cancels: bound the FP32 error by the summed terms
+    assert abs(g - fd) <= 1e-6 * terms
 
 
 def test_rollout_gradients_small_channel(E, O, torch_cuda):
@@ -173,15 +203,10 @@ def test_rollout_gradients_small_channel(E, O, torch_cuda):
     torch = torch_cuda
     cfg = dict(shape=(48, 24, 24), nu=0.02, channel=True, u_in=(0.03, 0.0, 0.0),
                body=WL.sphere((16.2, 12.1, 11.8), 4.0, amp=2.0, period=200.0, direction=(0, 1, 0)))
-    Lg, L0, gA, fdA, gFv, fdF = _rollout_case(O, E, torch, cfg, 60, (20, 60), 10, seed=21)
-    _say(f"L gpu {Lg:.8e} oracle {L0:.8e}; dL/dA adjoint {gA:.8e} FD {fdA:.8e} rel {abs(gA - fdA) / abs(fdA):.2e}; "
-         f"<dL/dF,v> adjoint {gFv:.8e} FD {fdF:.8e} rel {abs(gFv - fdF) / abs(fdF):.2e}")
-    assert abs(Lg - L0) <= 1e-4 * abs(L0)
-    assert abs(gA - fdA) <= 1e-4 * abs(fdA)
-    assert abs(gFv - fdF) <= 1e-4 * abs(fdF)
+    _check_rollout(_rollout_case(O, E, torch, cfg, 60, (20, 60), 10, seed=21))
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(1200)
 def test_rollout_gradients_adj128(E, O, torch_cuda):
     """The differentiable workload: 128x64x64 channel, inlet 0.03, sphere R = 8 at (32,32,32)
     oscillating in y with amplitude 4 and period 2000, body force uniform in [-1e-6, 1e-6]
@@ -189,11 +214,4 @@ def test_rollout_gradients_adj128(E, O, torch_cuda):
     torch = torch_cuda
     w = WL.WORKLOADS["adj128"]
     cfg = dict(shape=w["shape"], nu=w["nu"], channel=True, u_in=w["u_in"], body=w["bodies"][0])
-    Lg, L0, gA, fdA, gFv, fdF = _rollout_case(O, E, torch, cfg, 300, w["loss_window"], w["checkpoint"],
-                                              seed=w["force_seed"])
-    _say(f"adj128: L gpu {Lg:.8e} oracle {L0:.8e}; dL/dA adjoint {gA:.8e} FD {fdA:.8e} "
-         f"rel {abs(gA - fdA) / abs(fdA):.2e}; <dL/dF,v> adjoint {gFv:.8e} FD {fdF:.8e} "
-         f"rel {abs(gFv - fdF) / abs(fdF):.2e}")
-    assert abs(Lg - L0) <= 1e-4 * abs(L0)
-    assert abs(gA - fdA) <= 1e-4 * abs(fdA)
-    assert abs(gFv - fdF) <= 1e-4 * abs(fdF)
+    _check_rollout(_rollout_case(O, E, torch, cfg, 300, w["loss_window"], w["checkpoint"], seed=w["force_seed"]))

@@ -67,10 +67,11 @@ def traffic_from_profile(nodes: int):
     return float(m_bytes.group(1))
 
 
-def run_form(elbm, torch, shape, nu, storage, steps, warmup, init, bodies=None, channel=False, u_in=(0, 0, 0)):
+def run_form(elbm, torch, shape, nu, storage, steps, warmup, init, bodies=None, channel=False, u_in=(0, 0, 0),
+             flags=0):
     """Time ``steps`` steps of one form; returns (MLUPS, ms/step, sweep GB/s, fp64 nodes, lattice)."""
     lat = elbm.Lattice(shape, nu, storage=storage, channel=channel, u_inlet=u_in,
-                       max_bodies=len(bodies) if bodies else 0)
+                       max_bodies=len(bodies) if bodies else 0, flags=flags)
     init(lat)
     if bodies:
         lat.set_bodies(bodies)
@@ -241,6 +242,15 @@ def main():
         if "copy" in which:
             forms["copy_probe_GBps"] = round(copy_probe(torch), 1)
             log(f"copy probe {forms['copy_probe_GBps']} GB/s")
+            # the library's stream-only mode: the sweep's pull and store, no collision -- the
+            # attainable bandwidth of exactly this access pattern
+            _, _, gb, _, _, lat = run_form(elbm, torch, shape, w["nu"], "f32", 100, 5, init,
+                                           flags=elbm.FLAG_STREAM_ONLY)
+            del lat
+            torch.cuda.empty_cache()
+            forms["pull_copy_GBps"] = round(gb, 1)
+            roof["attainable_pull_copy"] = round(gb, 1)
+            log(f"stream-only pull copy ({args.workload}) {gb:.0f} GB/s")
         if "turb512" in which:
             w5 = WL.WORKLOADS["turb512"]
             log("turb512: generating the initial field on the device")
@@ -273,7 +283,8 @@ def main():
             del lat
             torch.cuda.empty_cache()
             forms["sphere384_f32"] = {"MLUPS": round(m, 1), "ms_per_step": round(msps, 4), "sweep_GBps": round(gb, 1),
-                                      "boundary_nodes": int(inf.boundary_nodes), "drag_last_step": F[0]}
+                                      "boundary_nodes": int(inf.boundary_nodes), "fp64_nodes_last_step": int(inf.fp64_nodes),
+                                      "drag_last_step": F[0]}
             log(f"sphere384: {m:.0f} MLUPS, boundary nodes {inf.boundary_nodes}, drag {F[0]:.4e}")
         if "adj128" in which:
             forms["adj128_adjoint"] = adjoint_form(torch, WL)

@@ -10,11 +10,6 @@
 //   k_adj_bulk      per fluid node: collision VJP, then the transpose of the pull -- every
 //                   (source, direction) entry of dL/dA^t is written exactly once by the node that
 //                   pulled it, so the scatter needs no atomics;  solid nodes write zeros.
-//
-// Every collision VJP runs in FP64 on the exactly widened stored deviations (f = W + d): the
-// derivative of the stabiliser carries 1/<dh|dh>, so an FP32 evaluation loses the digits of dh
-// that decide it at weakly disturbed nodes, while the FP64 arithmetic costs little next to the
-// memory traffic of the step.  Adjoint fields stay FP32 in memory.
 //   k_adj_boundary  per boundary/refill node: the adjoint of the reconstruction (Grad populations,
 //                   targets, finite-difference gradient, force term of the loss); contributions to
 //                   U^t and R^t of other nodes go to FP64 accumulators.
@@ -24,6 +19,13 @@
 //   k_adj_refill    the completed dL/dA^t of refilled nodes sent through Grad's distribution.
 //   k_adj_macro     the accumulated dL/dU^t, dL/dR^t turned into dL/dA^t (nodes fluid at t) or
 //                   into dL/d(amp) (nodes solid at t, whose U^t is the rigid-body velocity).
+//
+// Every collision VJP runs in FP64 on the exactly widened stored deviations (f = W + d): the
+// derivative of the stabiliser carries 1/<dh|dh>, so an FP32 evaluation loses the digits of dh
+// that decide it at weakly disturbed nodes (an FP32 VJP missed a smooth body-force gradient by
+// 7.5e-4 on a small channel; FP64 by 6e-7).  Adjoint fields stay FP32 in memory.
+#include <algorithm>
+
 #include "elbm_internal.hpp"
 #include "boundary_dev.hpp"
 
@@ -319,207 +321,177 @@ __device__ inline void addU(const BArgs& a, const AdjArgs& j, int comp, long nod
   if (v != 0.f) atomicAdd(&j.gUR[comp * a.N + node], (double)v);
 }
 
-// Transpose of the finite-difference stencil of grad_u: dL/dG -> dL/dU^t at the stencil nodes.
-__device__ inline void grad_u_vjp(const BArgs& a, const AdjArgs& j, const Nbhd& h, const float (&gG)[9]) {
+// Transpose of the finite-difference stencil of grad_u for one (axis b, component c) pair:
+// g = dL/dG[3c+b] -> dL/dU^t at the stencil nodes (FP64 accumulators).
+__device__ inline void grad_u_vjp_one(const BArgs& a, const AdjArgs& j, const LaneNb& h, int b, int c, float g) {
+  if (g == 0.f) return;
+  const int ip = dir_index(b == 0, b == 1, b == 2), im = dir_index(-(b == 0), -(b == 1), -(b == 2));
+  const bool op1 = (h.fluid >> ip) & 1u, om1 = (h.fluid >> im) & 1u;
+  const bool op2 = (h.far >> (2 * b)) & 1u, om2 = (h.far >> (2 * b + 1)) & 1u;
   const long n0 = h.n;
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const int ip = dir_index(b == 0, b == 1, b == 2), im = dir_index(-(b == 0), -(b == 1), -(b == 2));
-    const bool op1 = (h.fluid >> ip) & 1u, om1 = (h.fluid >> im) & 1u;
-    const bool op2 = (h.far >> (2 * b)) & 1u, om2 = (h.far >> (2 * b + 1)) & 1u;
-    const long p1 = nb_index(a, h, ip), m1 = nb_index(a, h, im);
-    const long p2 = far_index(a, h, 2 * b), m2 = far_index(a, h, 2 * b + 1);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float g = gG[3 * c + b];
-      if (g == 0.f) continue;
-      if (op1 && om1) {
-        addU(a, j, c, p1, 0.5f * g);
-        addU(a, j, c, m1, -0.5f * g);
-      } else if (op1 && op2) {
-        addU(a, j, c, n0, -1.5f * g);
-        addU(a, j, c, p1, 2.f * g);
-        addU(a, j, c, p2, -0.5f * g);
-      } else if (om1 && om2) {
-        addU(a, j, c, n0, 1.5f * g);
-        addU(a, j, c, m1, -2.f * g);
-        addU(a, j, c, m2, 0.5f * g);
-      } else if (op1) {
-        addU(a, j, c, p1, g);
-        addU(a, j, c, n0, -g);
-      } else if (om1) {
-        addU(a, j, c, n0, g);
-        addU(a, j, c, m1, -g);
-      }
-    }
+  const long p1 = neighbour(a, h.x, h.y, h.z, cx(ip), cy(ip), cz(ip));
+  const long m1 = neighbour(a, h.x, h.y, h.z, cx(im), cy(im), cz(im));
+  const long p2 = far_node(a, h.x, h.y, h.z, 2 * b), m2 = far_node(a, h.x, h.y, h.z, 2 * b + 1);
+  if (op1 && om1) {
+    addU(a, j, c, p1, 0.5f * g);
+    addU(a, j, c, m1, -0.5f * g);
+  } else if (op1 && op2) {
+    addU(a, j, c, n0, -1.5f * g);
+    addU(a, j, c, p1, 2.f * g);
+    addU(a, j, c, p2, -0.5f * g);
+  } else if (om1 && om2) {
+    addU(a, j, c, n0, 1.5f * g);
+    addU(a, j, c, m1, -2.f * g);
+    addU(a, j, c, m2, 0.5f * g);
+  } else if (op1) {
+    addU(a, j, c, p1, g);
+    addU(a, j, c, n0, -g);
+  } else if (om1) {
+    addU(a, j, c, n0, g);
+    addU(a, j, c, m1, -g);
   }
 }
 
-// Adjoint of the boundary rules of Secs. III / IV.A at the listed nodes (wall nodes; every other
-// listed node -- refill, inlet and outlet nodes without a missing population -- takes the plain
-// collision VJP here too, since the bulk kernel skips FL_SPECIAL nodes).
+// Adjoint of the boundary rules of Secs. III / IV.A at the listed nodes, in the lane-parallel
+// form of the forward wall kernel: one node per group of 32 lanes, lane i < 27 owning direction
+// i.  The forward reconstruction is recomputed (same helper as the forward kernel), the FP64
+// collision VJP runs on the group's first lane through LDS, and the reverse of the reconstruction
+// runs per lane with butterfly sums.  Listed nodes without missing populations (inlet and outlet
+// rows, refill nodes) take the plain collision VJP, since the bulk kernel skips FL_SPECIAL nodes.
 template <int S, bool FORCE>
-__global__ __launch_bounds__(128) void k_adj_boundary(const BArgs a, const Bodies bd, const AdjArgs j,
-                                                      const AdjBodyArgs p) {
+__global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies bd, const AdjArgs j,
+                                                     const AdjBodyArgs p) {
   using C = Codec<S>;
   using E = typename C::E;
   const E* __restrict__ A = (const E*)a.A;
+  __shared__ float shv[2][GROUP];  // collision input in, dL/d(pre-collision f) out
+  __shared__ float shg[2][GROUP];  // lambda^{t+1} at the node
   int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
   if (count > a.cap) count = a.cap;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
-    const long n = a.list[k];
-    float gp[27], f[27], fo[27], g[27], gFn[3];  // f, fo: deviations from the weights, as in the forward
-    double fd[27];                               // the collision's input, absolute, FP64
-    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-    if (FORCE) {
-      Fx = a.F[n];
-      Fy = a.F[a.N + n];
-      Fz = a.F[2 * a.N + n];
-    }
-#pragma unroll
-    for (int i = 0; i < 27; ++i) gp[i] = j.lam_in[i * a.N + n];
-    Nbhd h;
-    nbhd_flags(a, n, h);
-    const int x = h.x, y = h.y, z = h.z;
+  const int lane = threadIdx.x & (GROUP - 1), g = threadIdx.x / GROUP;
+  const int i = lane < 27 ? lane : 13;
+  for (int64_t base = 2 * (int64_t)blockIdx.x; base < count; base += 2 * (int64_t)gridDim.x) {
+    // uniform over the block (barriers below); a group past the end repeats the block's first
+    // node and writes nothing
+    const int64_t k = base + g;
+    const bool active = k < count;
+    const long n = a.list[active ? k : base];
+    LaneNb h;
+    lane_gather<S, true, false>(a, A, n, lane, h);
+    const float gpi = lane < 27 ? j.lam_in[(long)i * a.N + n] : 0.f;
     const uint32_t dmask = h.dbar;
+    WallLane w;
+    w.mine = false;
+    if (dmask) wall_targets(a, bd, h, lane, w);
+    // collision input: f*_i (absolute) where missing, else the pulled deviation
+    shv[g][lane] = w.mine ? w.fs : h.f;
+    shg[g][lane] = gpi;
+    __syncthreads();
+    if (lane == 0) {
+      double fd[27];
+      float gp[27], go[27], gFn[3];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      const bool miss = (dmask >> i) & 1u;
-      const float v = C::load_dev(A + i * a.N + (miss ? n : pull_src(a, h, i)));
-      f[i] = miss ? 0.f : v;
-      fo[i] = C::load_dev(A + i * a.N + n);
+      for (int q = 0; q < 27; ++q) {
+        const float v = shv[g][q];
+        fd[q] = ((dmask >> q) & 1u) ? (double)v : wd(q) + (double)v;
+        gp[q] = shg[g][q];
+      }
+      float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+      if (FORCE) {
+        Fx = a.F[n];
+        Fy = a.F[a.N + n];
+        Fz = a.F[2 * a.N + n];
+      }
+      collide_vjp<FORCE>(fd, gp, a.beta, Fx, Fy, Fz, go, gFn);
+#pragma unroll
+      for (int q = 0; q < 27; ++q) shv[g][q] = go[q];
+      if (FORCE && j.gF && active) {
+        j.gF[n] += gFn[0];
+        j.gF[a.N + n] += gFn[1];
+        j.gF[2 * a.N + n] += gFn[2];
+      }
     }
-    float U[27][3], U2[6][3];
-    if (dmask) nbhd_velocity(a, h, U, U2);
-    {
-      // ---- wall node: forward recomputation (as k_boundary)
-      float ut[3] = {0.f, 0.f, 0.f};
-      float rstat = 0.f, rdyn = 0.f;
-      int nD = 0;
+    __syncthreads();
+    const float gi = shv[g][lane];  // dL / d(pre-collision f_i)
+    if (!dmask) {
+      if (active && lane < 27) adj_push(a, j, i, h.x, h.y, h.z, gi);
+    } else {
+      float grl = 0.f, gul[3] = {0.f, 0.f, 0.f}, gPl[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (w.mine) {
+        float gfs = gi;
+        if (p.loss && w.kb >= 0)
+          gfs -= (float)(p.w[w.kb][0] * (cx(i) - w.uw[0]) + p.w[w.kb][1] * (cy(i) - w.uw[1]) +
+                         p.w[w.kb][2] * (cz(i) - w.uw[2]));
+        grad_pop_vjp(i, gfs, w.rt, w.ut, grl, gul, gPl);
+      }
+      float gr = gsum(grl), gu[3], gP[6], gG[9];
 #pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        if (!((dmask >> i) & 1u)) {
-          rstat += f[i];
-          continue;
-        }
-        ++nD;
-        rstat += fo[opp(i)];
-        double q, uwd[3];
-        int kb;
-        link_geometry(a, bd, i, x, y, z, q, uwd, kb);
-        float uf[3];
-        if ((h.fluid >> i) & 1u) {
-          uf[0] = U[i][0];
-          uf[1] = U[i][1];
-          uf[2] = U[i][2];
+      for (int c = 0; c < 3; ++c) gu[c] = gsum(gul[c]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) gP[c] = gsum(gPl[c]);
+      pressure_vjp(w.rt, w.ut, w.G, a.beta, gP, gr, gu, gG);
+      if (active && lane < 27) {
+        if (!w.mine) {
+          adj_push(a, j, i, h.x, h.y, h.z, gi + gr);
         } else {
-          uf[0] = (float)uwd[0];
-          uf[1] = (float)uwd[1];
-          uf[2] = (float)uwd[2];
-        }
-        const float qf = (float)q, inv = 1.f / (1.f + qf);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ut[c] += (qf * uf[c] + (float)uwd[c]) * inv;
-        rdyn += (float)(6.0 * wd(i) * a.rho0 * (cx(i) * uwd[0] + cy(i) * uwd[1] + cz(i) * uwd[2]));
-      }
-      const float invn = nD ? 1.f / (float)nD : 0.f;
-      ut[0] *= invn;
-      ut[1] *= invn;
-      ut[2] *= invn;
-      const float rt = 1.f + rstat + rdyn;  // the weights add up to 1
-      float G[9], Pi[6];
-#pragma unroll
-      for (int i = 0; i < 27; ++i) fd[i] = wd(i) + (double)f[i];
-      if (nD) {
-        grad_u_nb(h, U, U2, G);
-        pressure_tensor(rt, ut, G, a.beta, Pi);
-#pragma unroll
-        for (int i = 0; i < 27; ++i)
-          if ((dmask >> i) & 1u) fd[i] = (double)grad_pop(i, rt, ut, Pi);
-      }
-      // ---- reverse
-      collide_vjp<FORCE>(fd, gp, a.beta, Fx, Fy, Fz, g, gFn);
-      if (!nD) {
-#pragma unroll
-        for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, g[i]);
-      } else {
-        float gr = 0.f, gu[3] = {0.f, 0.f, 0.f}, gP[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gG[9];
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-          if (!((dmask >> i) & 1u)) continue;
-          float gfs = g[i];
-          if (p.loss) {
-            double q, uwd[3];
-            int kb;
-            link_geometry(a, bd, i, x, y, z, q, uwd, kb);
-            if (kb >= 0)
-              gfs -= (float)(p.w[kb][0] * (cx(i) - uwd[0]) + p.w[kb][1] * (cy(i) - uwd[1]) + p.w[kb][2] * (cz(i) - uwd[2]));
-          }
-          grad_pop_vjp(i, gfs, rt, ut, gr, gu, gP);
-        }
-        pressure_vjp(rt, ut, G, a.beta, gP, gr, gu, gG);
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-          if (!((dmask >> i) & 1u)) {
-            adj_push(a, j, i, x, y, z, g[i] + gr);
-            continue;
-          }
-          double q, uwd[3];
-          int kb;
-          link_geometry(a, bd, i, x, y, z, q, uwd, kb);
           float vbb = gr;
           double guw[3];
-          const double qd = q, inv = 1.0 / (nD * (1.0 + qd));
-          for (int c = 0; c < 3; ++c) guw[c] = (double)gr * 6.0 * wd(i) * a.rho0 * (c == 0 ? cx(i) : (c == 1 ? cy(i) : cz(i))) + gu[c] * inv;
-          if (p.loss && kb >= 0) {
-            const double fb = wd(opp(i)) + (double)fo[opp(i)];
-            const double fs = fd[i];
-            vbb += (float)(p.w[kb][0] * (-cx(i) - uwd[0]) + p.w[kb][1] * (-cy(i) - uwd[1]) + p.w[kb][2] * (-cz(i) - uwd[2]));
-            for (int c = 0; c < 3; ++c) guw[c] += p.w[kb][c] * (fs - fb);
+          const double qd = w.q, inv = 1.0 / (w.nD * (1.0 + qd));
+          const double cv[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+#pragma unroll
+          for (int c = 0; c < 3; ++c) guw[c] = (double)gr * 6.0 * wd(i) * a.rho0 * cv[c] + gu[c] * inv;
+          if (p.loss && w.kb >= 0) {
+            const double fbd = wd(opp(i)) + (double)w.fb;
+            const double fs = (double)w.fs;
+            vbb += (float)(p.w[w.kb][0] * (-cv[0] - w.uw[0]) + p.w[w.kb][1] * (-cv[1] - w.uw[1]) +
+                           p.w[w.kb][2] * (-cv[2] - w.uw[2]));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) guw[c] += p.w[w.kb][c] * (fs - fbd);
           }
-          j.lam_out[opp(i) * a.N + n] += vbb;
-          if (!(a.channel && x - cx(i) < 0)) adj_push(a, j, i, x, y, z, 0.f);
+          j.lam_out[(long)opp(i) * a.N + n] += vbb;
+          if (!(a.channel && h.x - cx(i) < 0)) adj_push(a, j, i, h.x, h.y, h.z, 0.f);
           // u_f and q
           double uf[3];
-          if ((h.fluid >> i) & 1u) {
-            const long nf = nb_index(a, h, i);
-            uf[0] = U[i][0];
-            uf[1] = U[i][1];
-            uf[2] = U[i][2];
-            for (int c = 0; c < 3; ++c) addU(a, j, c, nf, (float)(gu[c] * qd * inv));
-          } else {
+          if ((h.fluid >> lane) & 1u) {
+            const long nf = neighbour(a, h.x, h.y, h.z, cx(i), cy(i), cz(i));
+#pragma unroll
             for (int c = 0; c < 3; ++c) {
-              uf[c] = uwd[c];
+              uf[c] = h.U[c];
+              addU(a, j, c, nf, (float)(gu[c] * qd * inv));
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              uf[c] = w.uw[c];
               guw[c] += gu[c] * qd * inv;
             }
           }
-          if (kb >= 0) {
-            const double gq = (gu[0] * (uf[0] - uwd[0]) + gu[1] * (uf[1] - uwd[1]) + gu[2] * (uf[2] - uwd[2])) * inv /
-                              (1.0 + qd);
-            const BodyDev& b = bd.b[kb];
-            const double v[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+          if (w.kb >= 0) {
+            const double gq =
+                (gu[0] * (uf[0] - w.uw[0]) + gu[1] * (uf[1] - w.uw[1]) + gu[2] * (uf[2] - w.uw[2])) * inv / (1.0 + qd);
+            const BodyDev& b = bd.b[w.kb];
             double dqdc[3];
             if (b.kind == ELBM_BODY_SPHERE) {
-              const double r[3] = {x - b.c1[0] - qd * v[0], y - b.c1[1] - qd * v[1], z - b.c1[2] - qd * v[2]};
-              const double rv = r[0] * v[0] + r[1] * v[1] + r[2] * v[2];
+              const double r[3] = {h.x - b.c1[0] - qd * cv[0], h.y - b.c1[1] - qd * cv[1], h.z - b.c1[2] - qd * cv[2]};
+              const double rv = r[0] * cv[0] + r[1] * cv[1] + r[2] * cv[2];
+#pragma unroll
               for (int c = 0; c < 3; ++c) dqdc[c] = -r[c] / rv;
             } else {
-              const double nv = b.n[0] * v[0] + b.n[1] * v[1] + b.n[2] * v[2];
+              const double nv = b.n[0] * cv[0] + b.n[1] * cv[1] + b.n[2] * cv[2];
+#pragma unroll
               for (int c = 0; c < 3; ++c) dqdc[c] = -b.n[c] / nv;
             }
             double ga = 0.0;
-            for (int c = 0; c < 3; ++c) ga += guw[c] * p.dU1[kb][c] + gq * dqdc[c] * p.dc1[kb][c];
-            atomicAdd(&p.gamp[kb], ga);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ga += guw[c] * p.dU1[w.kb][c] + gq * dqdc[c] * p.dc1[w.kb][c];
+            atomicAdd(&p.gamp[w.kb], ga);
           }
         }
-        grad_u_vjp(a, j, h, gG);
       }
+      // transpose of the gradient stencil: lanes 0..8 take one (axis, component) pair each
+      if (active && lane < 9) grad_u_vjp_one(a, j, h, lane / 3, lane % 3, gG[3 * (lane % 3) + lane / 3]);
     }
-    if (FORCE && j.gF) {
-      j.gF[n] += gFn[0];
-      j.gF[a.N + n] += gFn[1];
-      j.gF[2 * a.N + n] += gFn[2];
-    }
+    __syncthreads();
   }
 }
 
@@ -527,36 +499,51 @@ __global__ __launch_bounds__(128) void k_adj_boundary(const BArgs a, const Bodie
 // step): the completed dL/dA^t of a refill node goes through Grad's distribution to R^t of its
 // neighbours, U^t of its stencil and the body's amplitude; the node's own entries are then zero
 // (its stored A^t is overwritten and influences nothing).
-__global__ __launch_bounds__(128) void k_adj_refill(const BArgs a, const Bodies bd, const AdjArgs j,
-                                                    const AdjBodyArgs p) {
+__global__ __launch_bounds__(64) void k_adj_refill(const BArgs a, const Bodies bd, const AdjArgs j,
+                                                   const AdjBodyArgs p) {
   int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
   if (count > a.cap) count = a.cap;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & (GROUP - 1), g = threadIdx.x / GROUP;
+  for (int64_t k = a.n_static + 2 * (int64_t)blockIdx.x + g; k < count; k += 2 * (int64_t)gridDim.x) {
     const long n = a.list[k];
-    if (!(a.flags[n] & FL_SOLID_PREV)) continue;
-    Nbhd h;
-    nbhd_flags(a, n, h);
-    float f[27], uw[3], G[9], ravg;
-    int kb, m;
-    refill_pops(a, bd, h, f, kb, ravg, m, uw, G);
-    float gr = 0.f, gu[3] = {0.f, 0.f, 0.f}, gP[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gG[9];
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      const float gi = j.lam_out[i * a.N + n];
-      j.lam_out[i * a.N + n] = 0.f;
-      grad_pop_vjp(i, gi, ravg, uw, gr, gu, gP);
+    if (!(a.flags[n] & FL_SOLID_PREV)) continue;  // uniform over the group
+    LaneNb h;
+    lane_gather<ELBM_STORAGE_F32, false, true>(a, nullptr, n, lane, h);
+    // forward recomputation, as k_refill
+    int kb = first_body(bd, false, h.x, h.y, h.z);
+    if (kb < 0) kb = 0;
+    const BodyDev& b = bd.b[kb];
+    const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
+    float uw[3];
+    uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
+    uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
+    uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+    const uint32_t nbm = h.fluid0 & ~(1u << 13);
+    const float rs = gsum(lane != 13 ? h.R : 0.f);
+    const int m = __popc(nbm);
+    const float ravg = m ? rs / (float)m : (float)a.rho0;
+    float G[9], Pi[6];
+    grad_u_grp(h, G);
+    pressure_tensor(ravg, uw, G, a.beta, Pi);
+    // reverse: the completed dL/dA^t of the refilled entries goes through Grad's distribution;
+    // the entries themselves were overwritten, so their adjoint restarts at zero
+    float grl = 0.f, gul[3] = {0.f, 0.f, 0.f}, gPl[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (lane < 27) {
+      const float gi = j.lam_out[(long)lane * a.N + n];
+      j.lam_out[(long)lane * a.N + n] = 0.f;
+      grad_pop_vjp(lane, gi, ravg, uw, grl, gul, gPl);
     }
+    float gr = gsum(grl), gu[3], gP[6], gG[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gu[c] = gsum(gul[c]);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gP[c] = gsum(gPl[c]);
     pressure_vjp(ravg, uw, G, a.beta, gP, gr, gu, gG);
-    if (m) {
-      const float gm = gr / (float)m;
-#pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        if (i == 13 || !((h.fluid0 >> i) & 1u)) continue;
-        atomicAdd(&j.gUR[3 * a.N + nb_index(a, h, i)], (double)gm);
-      }
-    }
-    atomicAdd(&p.gamp[kb], (double)gu[0] * p.dU1[kb][0] + (double)gu[1] * p.dU1[kb][1] + (double)gu[2] * p.dU1[kb][2]);
-    grad_u_vjp(a, j, h, gG);
+    if (m && lane < 27 && ((nbm >> lane) & 1u))
+      atomicAdd(&j.gUR[3 * a.N + neighbour(a, h.x, h.y, h.z, cx(lane), cy(lane), cz(lane))], (double)(gr / (float)m));
+    if (lane == 0)
+      atomicAdd(&p.gamp[kb], (double)gu[0] * p.dU1[kb][0] + (double)gu[1] * p.dU1[kb][1] + (double)gu[2] * p.dU1[kb][2]);
+    if (lane < 9) grad_u_vjp_one(a, j, h, lane / 3, lane % 3, gG[3 * (lane % 3) + lane / 3]);
   }
 }
 
@@ -696,10 +683,14 @@ static void adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, const AdjA
   if (geo) {
     const dim3 gf = grid_for((long)c->p.ny * c->p.nz);
     if (a.channel) hipLaunchKernelGGL(k_adj_faces_zero, gf, dim3(256), 0, c->stream, a, j);
-    if (force) hipLaunchKernelGGL((k_adj_boundary<S, true>), dim3(512), dim3(128), 0, c->stream, a, bd, j, p);
-    else hipLaunchKernelGGL((k_adj_boundary<S, false>), dim3(512), dim3(128), 0, c->stream, a, bd, j, p);
+    const dim3 gb((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap + 1) / 2, 1), 16384));
+    if (force) hipLaunchKernelGGL((k_adj_boundary<S, true>), gb, dim3(64), 0, c->stream, a, bd, j, p);
+    else hipLaunchKernelGGL((k_adj_boundary<S, false>), gb, dim3(64), 0, c->stream, a, bd, j, p);
     if (a.channel) hipLaunchKernelGGL(k_adj_outlet, gf, dim3(256), 0, c->stream, a, j);
-    if (c->moving) hipLaunchKernelGGL(k_adj_refill, dim3(256), dim3(128), 0, c->stream, a, bd, j, p);
+    if (c->moving) {
+      const dim3 gr((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap - a.n_static + 1) / 2, 1), 4096));
+      hipLaunchKernelGGL(k_adj_refill, gr, dim3(64), 0, c->stream, a, bd, j, p);
+    }
     hipLaunchKernelGGL(k_adj_macro<S>, grid_for(c->N), dim3(256), 0, c->stream, a, bd, j, p);
   }
 }
@@ -710,7 +701,7 @@ hipError_t launch_adjoint(elbm_ctx* c, int64_t t, const void* A, const float* la
   if (c->flags) {
     hipError_t e = geometry_for_step(c, bd);
     if (e != hipSuccess) return e;
-    e = macro_fields(c, A, bd);
+    e = macro_fields(c, A, bd, true);
     if (e != hipSuccess) return e;
     // the forward step refills uncovered nodes into A^t before streaming; do the same here
     e = launch_refill(c, bd, const_cast<void*>(A));

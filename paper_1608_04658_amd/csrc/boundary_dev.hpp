@@ -33,7 +33,8 @@ struct BArgs {
   const void* A;
   void* B;
   const uint8_t* flags;
-  const float* macro;
+  const float* macro;  // U^t, R^t planes
+  float* slab_next;    // channel mode: staging of U^{t+1}, R^{t+1} for x < 3 ([4][nz][ny][3])
   const float* F;
   const int32_t* list;
   const uint32_t* dyn_count;
@@ -68,129 +69,8 @@ __device__ __forceinline__ long neighbour(const BArgs& a, int x, int y, int z, i
   return node_at(a, X, wrap(y + dy, a.ny), wrap(z + dz, a.nz));
 }
 
-// ---------------------------------------------------------------------------------------------
-// Prefetched neighbourhood of a listed node.  The wall rules read, per node, the flags of the 26
-// neighbours, the pulled populations, the node's own populations and U^t on a stencil; written as
-// loads behind data-dependent branches these form a chain of dozens of dependent memory round
-// trips.  Here every load of a phase is issued before any of its values is used (absent entries
-// read the node itself and are masked afterwards), so a node costs three round trips.
-
+// Index of the direction (dx, dy, dz).
 __host__ __device__ constexpr int dir_index(int dx, int dy, int dz) { return 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1); }
-
-struct Nbhd {
-  long n;
-  int x, y, z;
-  uint32_t exists;  // bit i: x + c_i lies in the domain (i = 13: the node itself)
-  uint32_t fluid;   // bit i: exists and fluid at t+1
-  uint32_t fluid0;  // bit i: exists and fluid at both t and t+1
-  uint32_t dbar;    // bit i: population i is missing (its source is solid at t+1 or beyond the inlet)
-  uint32_t far;     // bit 2b: x + 2 e_b exists and is fluid at t+1; bit 2b+1: x - 2 e_b
-};
-
-__device__ __forceinline__ long nb_index(const BArgs& a, const Nbhd& h, int i) {
-  return neighbour(a, h.x, h.y, h.z, cx(i), cy(i), cz(i));
-}
-
-__device__ __forceinline__ long far_index(const BArgs& a, const Nbhd& h, int k) {
-  const int b = k >> 1, s = (k & 1) ? -2 : 2;
-  return neighbour(a, h.x, h.y, h.z, b == 0 ? s : 0, b == 1 ? s : 0, b == 2 ? s : 0);
-}
-
-// Phase 1: the flags.  The pull source x - c_i is the neighbour in direction opp(i), except at the
-// outlet (its source x is clamped to nx - 1) and through the inlet (missing).
-__device__ inline void nbhd_flags(const BArgs& a, long n, Nbhd& h) {
-  h.n = n;
-  h.x = (int)(n % a.nx);
-  h.y = (int)((n / a.nx) % a.ny);
-  h.z = (int)(n / ((long)a.nx * a.ny));
-  uint8_t fl[27], f2[6];
-  uint32_t ex = 0;
-#pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    const long m = nb_index(a, h, i);
-    ex |= (m >= 0 ? 1u : 0u) << i;
-    fl[i] = a.flags[m >= 0 ? m : n];
-  }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const long m = far_index(a, h, k);
-    f2[k] = m >= 0 ? a.flags[m] : (uint8_t)FL_SOLID;
-  }
-  uint32_t fluid = 0, fluid0 = 0, dbar = 0, far = 0;
-#pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    const bool e = (ex >> i) & 1u;
-    fluid |= (e && !(fl[i] & FL_SOLID) ? 1u : 0u) << i;
-    fluid0 |= (e && !(fl[i] & (FL_SOLID | FL_SOLID_PREV)) ? 1u : 0u) << i;
-  }
-#pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    const int sx = h.x - cx(i);
-    bool miss;
-    if (a.channel && sx < 0) {
-      miss = true;
-    } else {
-      // source direction: opp(i), or (0, -cy, -cz) where the outlet clamps x
-      const int s = (a.channel && sx >= a.nx) ? dir_index(0, -cy(i), -cz(i)) : opp(i);
-      miss = (fl[s] & FL_SOLID) != 0;
-    }
-    dbar |= (miss ? 1u : 0u) << i;
-  }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) far |= (!(f2[k] & FL_SOLID) ? 1u : 0u) << k;
-  h.exists = ex;
-  h.fluid = fluid;
-  h.fluid0 = fluid0;
-  h.dbar = dbar;
-  h.far = far;
-}
-
-__device__ __forceinline__ long pull_src(const BArgs& a, const Nbhd& h, int i) {
-  int sx = h.x - cx(i);
-  if (a.channel) sx = sx >= a.nx ? a.nx - 1 : (sx < 0 ? 0 : sx);
-  else sx = wrap(sx, a.nx);
-  return node_at(a, sx, wrap(h.y - cy(i), a.ny), wrap(h.z - cz(i), a.nz));
-}
-
-// Phase 2a: U^t at x + c_i where that node is fluid at t+1 (i = 13: at x) and at x +- 2 e_b.
-__device__ inline void nbhd_velocity(const BArgs& a, const Nbhd& h, float (&U)[27][3], float (&U2)[6][3]) {
-#pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    const long m = ((h.fluid >> i) & 1u) ? nb_index(a, h, i) : h.n;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) U[i][c] = a.macro[c * a.N + m];
-  }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const long m = ((h.far >> k) & 1u) ? far_index(a, h, k) : h.n;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) U2[k][c] = a.macro[c * a.N + m];
-  }
-}
-
-// Velocity gradient by finite differences on U^t (Sec. III), G[3a+b] = d u_a / d x_b.  Per axis:
-// central if both neighbours are usable (exist and fluid at t+1), else second-order one-sided
-// (forward side first), else first-order one-sided, else 0.
-__device__ inline void grad_u_nb(const Nbhd& h, const float (&U)[27][3], const float (&U2)[6][3], float (&G)[9]) {
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const int ip = dir_index(b == 0, b == 1, b == 2), im = dir_index(-(b == 0), -(b == 1), -(b == 2));
-    const bool op1 = (h.fluid >> ip) & 1u, om1 = (h.fluid >> im) & 1u;
-    const bool op2 = (h.far >> (2 * b)) & 1u, om2 = (h.far >> (2 * b + 1)) & 1u;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float u0 = U[13][c], up1 = U[ip][c], um1 = U[im][c], up2 = U2[2 * b][c], um2 = U2[2 * b + 1][c];
-      float d;
-      if (op1 && om1) d = 0.5f * (up1 - um1);
-      else if (op1 && op2) d = 0.5f * (-3.f * u0 + 4.f * up1 - up2);
-      else if (om1 && om2) d = 0.5f * (3.f * u0 - 4.f * um1 + um2);
-      else if (op1) d = up1 - u0;
-      else if (om1) d = u0 - um1;
-      else d = 0.f;
-      G[3 * c + b] = d;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------------------------
 // Lane-parallel form: one listed node per group of 32 lanes (two per wavefront), lane i < 27 owns
@@ -350,36 +230,52 @@ __device__ inline void link_geometry(const BArgs& a, const Bodies& bd, int i, in
   uw[2] = b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]);
 }
 
-// Refill of a node uncovered at t+1 (Sec. III): Grad's distribution with the wall velocity of the
-// body that held the node at t (taken at t+1), the mean R^t of the neighbours fluid at t and t+1
-// (rho0 if none) and the pressure tensor with the finite-difference gradient of U^t.
-__device__ inline void refill_pops(const BArgs& a, const Bodies& bd, const Nbhd& h, float (&f)[27], int& kb,
-                                   float& ravg, int& m, float (&uw)[3], float (&G)[9]) {
-  float R[27], U[27][3], U2[6][3];
+// Reconstruction at a wall node in the lane-parallel form (Sec. III): this lane's link (when its
+// population is missing), the group's targets rho_tgt = rho_stat + rho_dyn and u_tgt, the
+// finite-difference gradient of U^t, the pressure tensor, and this lane's Grad population.
+// All lanes of the group call it together (uniform dmask != 0).
+struct WallLane {
+  bool mine;     // this lane's population is missing
+  double q;      // link fraction (mine)
+  double uw[3];  // wall velocity at the link (mine)
+  int kb;        // body of the link, -1 for the inlet (mine)
+  float fb;      // bounce-back value: deviation of A^t_{opp(lane)}(x)
+  float fs;      // Grad population f*_lane (absolute; mine)
+  float rt;      // rho_tgt
+  float ut[3];   // u_tgt
+  float G[9];    // grad U^t
+  float Pi[6];   // pressure tensor
+  int nD;        // number of missing populations
+};
+
+__device__ inline void wall_targets(const BArgs& a, const Bodies& bd, const LaneNb& h, int lane, WallLane& w) {
+  const int i = lane < 27 ? lane : 13;
+  w.mine = lane < 27 && ((h.dbar >> lane) & 1u);
+  w.q = 0.0;
+  w.uw[0] = w.uw[1] = w.uw[2] = 0.0;
+  w.kb = -1;
+  if (w.mine) link_geometry(a, bd, i, h.x, h.y, h.z, w.q, w.uw, w.kb);
+  w.fb = __shfl(h.fo, opp(i), GROUP);
+  float tu[3] = {0.f, 0.f, 0.f}, trs = 0.f, trd = 0.f;
+  if (w.mine) {
+    const bool fluid = (h.fluid >> lane) & 1u;
+    const float qf = (float)w.q, inv = 1.f / (1.f + qf);
 #pragma unroll
-  for (int i = 0; i < 27; ++i) R[i] = a.macro[3 * a.N + (((h.fluid0 >> i) & 1u) ? nb_index(a, h, i) : h.n)];
-  nbhd_velocity(a, h, U, U2);
-  kb = first_body(bd, false, h.x, h.y, h.z);
-  if (kb < 0) kb = 0;
-  const BodyDev& b = bd.b[kb];
-  const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
-  uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
-  uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
-  uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
-  float rs = 0.f;
-  m = 0;
-#pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    if (i == 13 || !((h.fluid0 >> i) & 1u)) continue;
-    rs += R[i];
-    ++m;
+    for (int c = 0; c < 3; ++c) tu[c] = (qf * (fluid ? h.U[c] : (float)w.uw[c]) + (float)w.uw[c]) * inv;
+    trs = w.fb;
+    trd = (float)(6.0 * wd(i) * a.rho0 * (cx(i) * w.uw[0] + cy(i) * w.uw[1] + cz(i) * w.uw[2]));
+  } else if (lane < 27) {
+    trs = h.f;
   }
-  ravg = m ? rs / (float)m : (float)a.rho0;
-  float Pi[6];
-  grad_u_nb(h, U, U2, G);
-  pressure_tensor(ravg, uw, G, a.beta, Pi);
+  const float rstat = gsum(trs), rdyn = gsum(trd);  // rstat: sum of deviations (weights add to 1)
+  w.nD = __popc(h.dbar);
+  const float invn = 1.f / (float)w.nD;
 #pragma unroll
-  for (int i = 0; i < 27; ++i) f[i] = grad_pop(i, ravg, uw, Pi);
+  for (int c = 0; c < 3; ++c) w.ut[c] = gsum(tu[c]) * invn;
+  w.rt = 1.f + rstat + rdyn;
+  grad_u_grp(h, w.G);
+  pressure_tensor(w.rt, w.ut, w.G, a.beta, w.Pi);
+  w.fs = w.mine ? grad_pop(i, w.rt, w.ut, w.Pi) : 0.f;
 }
 
 }  // namespace elbm

@@ -35,7 +35,8 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t pop[2], cnt, fix_list, flags, macro, blist, brec, ring, force_partial, scratch, scan_tmp, adj_gUR, adj_side, adj_gamp, total;
+  size_t pop[2], cnt, fix_list, flags, macro, slab, blist, brec, ring, force_partial, scratch, scan_tmp, adj_gUR, adj_side,
+      adj_gamp, total;
   int64_t scan_blocks;
   int64_t cap;
   bool geometry;
@@ -87,6 +88,7 @@ Layout layout(const elbm_params* p) {
     const int ring = p->force_ring > 0 ? p->force_ring : 1;
     L.flags = take(N);
     L.macro = take(16 * N);
+    if (p->bc_x == ELBM_BC_CHANNEL) L.slab = take(sizeof(float) * 4 * 3 * (size_t)p->ny * p->nz);
     L.blist = take(4 * (size_t)L.cap);
     L.brec = take(sizeof(double) * 6 * nbm * (size_t)L.cap);
     L.ring = take(sizeof(double) * 6 * ELBM_MAX_BODIES * ring);
@@ -151,6 +153,8 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->fix_list = (int32_t*)(c->ws + L.fix_list);
   c->flags = L.geometry ? (uint8_t*)(c->ws + L.flags) : nullptr;
   c->macro = L.geometry ? (float*)(c->ws + L.macro) : nullptr;
+  c->slab_next = (L.geometry && p->bc_x == ELBM_BC_CHANNEL) ? (float*)(c->ws + L.slab) : nullptr;
+  c->slab_valid = false;
   c->blist = L.geometry ? (int32_t*)(c->ws + L.blist) : nullptr;
   c->brec = L.geometry ? (double*)(c->ws + L.brec) : nullptr;
   c->ring = L.geometry ? (double*)(c->ws + L.ring) : nullptr;
@@ -284,6 +288,7 @@ int elbm_set_body_force(elbm_ctx* c, const float* F_dev) {
   if (!c) return ELBM_EINVAL;
   if (F_dev && !(c->p.flags & ELBM_FLAG_BODY_FORCE)) return fail(c, ELBM_ESTATE, "ELBM_FLAG_BODY_FORCE not set");
   c->bodyforce = F_dev;
+  c->slab_valid = false;  // U = (j - F/2) / rho depends on the field
   return ELBM_OK;
 }
 
@@ -310,6 +315,8 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
     if (geo) HIP_OK(c, launch_force_reduce(c));
     c->cur ^= 1;
     c->t += 1;
+    // the sweep, the wall kernel and the fix-up staged U, R of the new state's inlet slab
+    c->slab_valid = c->slab_next != nullptr && !(c->p.flags & ELBM_FLAG_STREAM_ONLY);
   }
   return ELBM_OK;
 }
@@ -402,6 +409,7 @@ int elbm_adjoint_step(elbm_ctx* c, int64_t t, void* pop_t_dev, const float* lam_
   if (lam_in_dev == lam_out_dev) return fail(c, ELBM_EINVAL, "lam_in and lam_out must not alias");
   if (gF_dev && !c->bodyforce) return fail(c, ELBM_ESTATE, "gF requested but no body-force field is bound");
   if (c->p.flags & ELBM_FLAG_STREAM_ONLY) return fail(c, ELBM_ESTATE, "no adjoint in stream-only mode");
+  c->slab_valid = false;  // the reverse step recomputes U^t, R^t of its own state
   HIP_OK(c, launch_adjoint(c, t, pop_t_dev, lam_in_dev, lam_out_dev, w_force, gF_dev));
   return ELBM_OK;
 }

@@ -68,6 +68,39 @@ template <> struct Codec<ELBM_STORAGE_BF16> {
   static __device__ __forceinline__ void store_dev(E* p, float d) { *p = f32_to_bf16_rne(d); }
 };
 
+// U, R of a node's post-collision state as stored (the deviations rounded to the storage format,
+// summed in direction order exactly as the previous-step field kernel sums them), written to 4
+// planes (U_x, U_y, U_z, R) of dst with the given plane stride.  U = (j - F/2) / rho.
+template <int S, bool FORCE>
+__device__ inline void macro_from_post(const float (&d)[27], float Fx, float Fy, float Fz, float* dst, size_t stride,
+                                       size_t idx) {
+  using C = Codec<S>;
+  float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    typename C::E e;
+    C::store_dev(&e, d[i]);
+    const float v = C::load_dev(&e);
+    dr += v;
+    jx += cx(i) * v;
+    jy += cy(i) * v;
+    jz += cz(i) * v;
+  }
+  const float rho = 1.f + dr;
+  if (FORCE) {
+    jx -= 0.5f * Fx;
+    jy -= 0.5f * Fy;
+    jz -= 0.5f * Fz;
+  }
+  dst[idx] = jx / rho;
+  dst[stride + idx] = jy / rho;
+  dst[2 * stride + idx] = jz / rho;
+  dst[3 * stride + idx] = rho;
+}
+
+// Inlet slab staging: U, R of the nodes x < 3 as [4][nz][ny][3]; index of node (x, y, z).
+__host__ __device__ inline size_t slab_index(int x, int y, int z, int ny) { return ((size_t)z * ny + y) * 3 + x; }
+
 inline size_t storage_bytes(int s) { return s == ELBM_STORAGE_F32 ? 4 : 2; }
 
 // ---------------------------------------------------------------------------------------------
@@ -396,6 +429,9 @@ struct elbm_ctx {
   int32_t nb;
   elbm_body bodies[ELBM_MAX_BODIES];
   bool moving;
+  bool slab_valid;  // slab_next holds U, R of the inlet slab of the current state (written by the
+                    // kernels that produced it)
+  float* slab_next; // channel mode: [4][nz][ny][3] staging of U, R for x < 3
   int64_t t;
   char err[256];
   // adjoint (ELBM_FLAG_ADJOINT)
@@ -425,7 +461,7 @@ hipError_t launch_force_reduce(elbm_ctx* c);
 hipError_t launch_adjoint(elbm_ctx* c, int64_t t, const void* A, const float* lam_in, float* lam_out,
                           const double* w_force, float* gF);
 void host_kinematics(const elbm_body& b, double t, double c[3], double U[3]);
-hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd);
+hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd, bool slab);
 hipError_t geometry_for_step(elbm_ctx* c, const Bodies& bd);
 Box union_box(const elbm_ctx* c, const Bodies& bd);
 Box full_box(const elbm_ctx* c);

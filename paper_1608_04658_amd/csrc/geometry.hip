@@ -369,43 +369,19 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
     float fi = h.f;
     const uint32_t dmask = h.dbar;
     if (dmask) {  // missing populations at a wall (Sec. III); uniform over the group
-      const bool mine = lane < 27 && ((dmask >> lane) & 1u);
-      double q = 0.0, uw[3] = {0.0, 0.0, 0.0};
-      int kb = -1;
-      if (mine) link_geometry(a, bd, i, h.x, h.y, h.z, q, uw, kb);
-      const float fb = __shfl(h.fo, opp(i), GROUP);  // bounce-back value A^t_{opp(i)}(x)
-      float tu[3] = {0.f, 0.f, 0.f}, trs = 0.f, trd = 0.f;
-      if (mine) {
-        const bool fluid = (h.fluid >> lane) & 1u;
-        const float qf = (float)q, inv = 1.f / (1.f + qf);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) tu[c] = (qf * (fluid ? h.U[c] : (float)uw[c]) + (float)uw[c]) * inv;
-        trs = fb;
-        trd = (float)(6.0 * wd(i) * a.rho0 * (cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]));
-      } else if (lane < 27) {
-        trs = h.f;
-      }
-      const float rstat = gsum(trs), rdyn = gsum(trd);  // rstat: sum of deviations (weights add to 1)
-      const float invn = 1.f / (float)__popc(dmask);
-      float ut[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ut[c] = gsum(tu[c]) * invn;
-      const float rt = 1.f + rstat + rdyn;
-      float G[9], Pi[6];
-      grad_u_grp(h, G);
-      pressure_tensor(rt, ut, G, a.beta, Pi);
+      WallLane w;
+      wall_targets(a, bd, h, lane, w);
       double dF[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      if (mine) {
-        const float fs = grad_pop(i, rt, ut, Pi);
-        fi = fs - wf(i);
-        if (kb >= 0) {
+      if (w.mine) {
+        fi = w.fs - wf(i);
+        if (w.kb >= 0) {
           // Galilean-invariant momentum exchange of the link
-          const double fbd = wd(opp(i)) + (double)fb;
+          const double fbd = wd(opp(i)) + (double)w.fb;
           const double c[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
 #pragma unroll
-          for (int e = 0; e < 3; ++e) dF[e] = fbd * (-c[e] - uw[e]) - (double)fs * (c[e] - uw[e]);
-          const BodyDev& b = bd.b[kb];
-          const double r[3] = {h.x - q * c[0] - b.c1[0], h.y - q * c[1] - b.c1[1], h.z - q * c[2] - b.c1[2]};
+          for (int e = 0; e < 3; ++e) dF[e] = fbd * (-c[e] - w.uw[e]) - (double)w.fs * (c[e] - w.uw[e]);
+          const BodyDev& b = bd.b[w.kb];
+          const double r[3] = {h.x - w.q * c[0] - b.c1[0], h.y - w.q * c[1] - b.c1[1], h.z - w.q * c[2] - b.c1[2]};
           dF[3] = r[1] * dF[2] - r[2] * dF[1];
           dF[4] = r[2] * dF[0] - r[0] * dF[2];
           dF[5] = r[0] * dF[1] - r[1] * dF[0];
@@ -414,7 +390,7 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
       for (int bb = 0; bb < nb; ++bb) {
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
-          const double v = gsum(kb == bb ? dF[e] : 0.0);
+          const double v = gsum(w.kb == bb ? dF[e] : 0.0);
           if (active && lane == e) rec[bb * 6 + e] = v;
         }
       }
@@ -445,6 +421,8 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
       } else {
 #pragma unroll
         for (int j = 0; j < 27; ++j) sh[g][j] = f[j];
+        if (active && a.slab_next && h.x < 3)
+          macro_from_post<S, FORCE>(f, Fx, Fy, Fz, a.slab_next, (size_t)3 * a.ny * a.nz, slab_index(h.x, h.y, h.z, a.ny));
       }
     }
     __syncthreads();
@@ -520,11 +498,22 @@ static void macro_box(elbm_ctx* c, const void* A, const Box& box, const Bodies& 
   }
 }
 
-// U^t, R^t of the populations A around the bodies and on the inlet slab.
-hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd) {
+// The inlet slab's U, R from the staging written by the previous step's producers.
+__global__ void k_slab_copy(const float* slab, float* macro, int32_t nx, int32_t ny, int32_t nz, int64_t N) {
+  const long per = 3L * ny * nz;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < 4 * per; k += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(k / per);
+    const long r = k % per;
+    const int x = (int)(r % 3), y = (int)((r / 3) % ny), z = (int)(r / (3L * ny));
+    if (x < nx) macro[c * N + ((long)z * ny + y) * nx + x] = slab[k];
+  }
+}
+
+// U^t, R^t of the populations A around the bodies and, with slab, on the inlet slab.
+hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd, bool slab) {
   const bool channel = c->p.bc_x == ELBM_BC_CHANNEL;
   if (c->nb > 0) macro_box(c, A, union_box(c, bd), bd);
-  if (channel) {
+  if (channel && slab) {
     Box slab = full_box(c);
     slab.n[0] = c->p.nx < 3 ? c->p.nx : 3;
     macro_box(c, A, slab, bd);
@@ -550,6 +539,7 @@ static hipError_t scan_box(elbm_ctx* c, const Box& box, int64_t base, int skip_i
 // Set-up at the current time level: masks everywhere, then the static part of the boundary list
 // (all boundary nodes for fixed geometry; only the inlet face when bodies move).
 hipError_t geometry_init(elbm_ctx* c) {
+  c->slab_valid = false;  // the populations were set from outside
   const Bodies bd = make_bodies(c, (double)c->t);
   const Box fb = full_box(c);
   GeoArgs g = geo_args(c, fb);
@@ -592,7 +582,13 @@ hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd) {
     const hipError_t e = scan_box(c, ub, c->n_static, 1);
     if (e != hipSuccess) return e;
   }
-  return macro_fields(c, c->pop[c->cur], bd);
+  // the inlet slab of the current state was staged by the step that produced it, unless the state
+  // was set from outside since then
+  if (c->slab_valid) {
+    hipLaunchKernelGGL(k_slab_copy, grid_for(4L * 3 * c->p.ny * c->p.nz), dim3(256), 0, c->stream, c->slab_next,
+                       c->macro, c->p.nx, c->p.ny, c->p.nz, (int64_t)c->N);
+  }
+  return macro_fields(c, c->pop[c->cur], bd, !c->slab_valid);
 }
 
 // Masks of both time levels of the step t -> t+1 recomputed from the kinematics alone (so that a
@@ -639,6 +635,7 @@ BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
   a.brec = c->brec;
   a.fix_list = (uint32_t*)c->fix_list;
   a.cnt = c->cnt;
+  a.slab_next = (channel && !(c->p.flags & ELBM_FLAG_STREAM_ONLY)) ? c->slab_next : nullptr;
   a.n_static = c->n_static;
   a.cap = c->blist_cap;
   a.moving = c->moving ? 1 : 0;

@@ -17,12 +17,14 @@ struct SweepArgs {
   const float* F;
   uint32_t* fix_list;
   DevCounters* cnt;
+  float* slab_next;  // [4][nz][ny][3] staging of U, R for x < 3 (written when slab is set)
   int32_t nx, ny, nz;
   uint32_t N;
   float beta, inv_beta, thr;
   int32_t channel;
   int32_t fp64;
   int32_t stream_only;
+  int32_t slab;    // channel mode: the producers of A^{t+1} write U, R of the inlet slab x < 3
   int32_t remap;   // 1-D grid of tiles, each XCD taking a contiguous chunk (see sweep_shape)
   int32_t gx, gy;  // tiles along x and y
   int32_t tiles;   // gx * gy * nz
@@ -91,19 +93,19 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
       const uint32_t k = atomicAdd(&a.cnt->fix_count, 1u);
       a.fix_list[k] = n;
     }
+    if (FLAGS && a.slab && x < 3)
+      macro_from_post<S, FORCE>(f, Fx, Fy, Fz, a.slab_next, (size_t)3 * a.ny * a.nz, slab_index(x, y, z, a.ny));
   }
-  // FP32: 32-bit byte offsets on per-direction bases and non-temporal stores (the next step reads
-  // this buffer only after the whole sweep, so keeping the write stream out of the caches wins);
-  // 2-byte storage keeps ordinary stores (partial-line writes merge better in L2).
+  // 32-bit byte offsets on per-direction bases and non-temporal stores (the next step reads this
+  // buffer only after the whole sweep, so keeping the write stream out of the caches wins; measured
+  // for FP32 and for 2-byte storage alike)
   E* __restrict__ B = (E*)a.B;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    if (S == ELBM_STORAGE_F32) {
-      float* p = (float*)((char*)(B + (size_t)i * a.N) + n * (uint32_t)sizeof(float));
-      __builtin_nontemporal_store(f[i], p);
-    } else {
-      C::store_dev(B + (size_t)i * a.N + n, f[i]);
-    }
+    E v;
+    C::store_dev(&v, f[i]);
+    E* p = (E*)((char*)(B + (size_t)i * a.N) + n * (uint32_t)sizeof(E));
+    __builtin_nontemporal_store(v, p);
   }
 }
 
@@ -143,8 +145,18 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
     }
     const double beta = (double)a.beta;
     kbc_collide<double, FORCE>(f, beta, 1.0 / beta, Fx, Fy, Fz);
+    float out[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) C::store_dev(B + (size_t)i * a.N + n, (float)f[i]);
+    for (int i = 0; i < 27; ++i) {
+      out[i] = (float)f[i];
+      C::store_dev(B + (size_t)i * a.N + n, out[i]);
+    }
+    const int xn = (int)(n % (uint32_t)a.nx);
+    if (a.slab && xn < 3) {
+      const int yn = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny), zn = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
+      macro_from_post<S, FORCE>(out, (float)Fx, (float)Fy, (float)Fz, a.slab_next, (size_t)3 * a.ny * a.nz,
+                                slab_index(xn, yn, zn, a.ny));
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -177,20 +189,21 @@ static SweepArgs sweep_args(elbm_ctx* c) {
   a.channel = c->p.bc_x == ELBM_BC_CHANNEL;
   a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64) && !(c->p.flags & ELBM_FLAG_STREAM_ONLY);
   a.stream_only = (c->p.flags & ELBM_FLAG_STREAM_ONLY) != 0;
+  a.slab_next = c->slab_next;
+  a.slab = (c->flags != nullptr && a.channel && !a.stream_only && c->slab_next) ? 1 : 0;
   a.remap = 0;
   a.gx = a.gy = a.tiles = 0;
   return a;
 }
 
 // Launch shape (measured on 256^3 and 512^3): 256-thread workgroups, x-extent the widest power of
-// two <= 256 that divides nx (at least 32), the rest along y.  FP32 rows longer than 256 use
-// 128-wide tiles in the XCD-contiguous order of k_sweep (on 512^3: +6 % against 256-wide and +12 %
-// against 128-wide tiles in dispatch order); 256-wide rows and 2-byte storage are fastest in plain
-// dispatch order.
+// two <= 256 (<= 128 for rows longer than 256) that divides nx (at least 32), the rest along y.  FP32
+// rows longer than 256 take the tiles in the XCD-contiguous order of k_sweep (on 512^3: 5.58 TB/s
+// against 5.30 in dispatch order); 2-byte storage is faster in plain dispatch order.
 static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const bool remap = storage == ELBM_STORAGE_F32 && nx > 256;
-  int bx = remap ? 128 : 256;
+  int bx = nx > 256 ? 128 : 256;
   while (bx > 32 && (nx % bx) != 0) bx >>= 1;
   if (nx < bx) bx = 32;
   const int by = 256 / bx;
@@ -226,7 +239,8 @@ hipError_t launch_sweep(elbm_ctx* c) {
 
 template <int S>
 static hipError_t fixup_s(elbm_ctx* c, const SweepArgs& a) {
-  const dim3 g(256), b(256);
+  // the queue length is known only on the device: enough workgroups for two waves per SIMD
+  const dim3 g(512), b(256);
   if (c->bodyforce) hipLaunchKernelGGL((k_fixup<S, true>), g, b, 0, c->stream, a);
   else hipLaunchKernelGGL((k_fixup<S, false>), g, b, 0, c->stream, a);
   return hipGetLastError();

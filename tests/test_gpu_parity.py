@@ -77,6 +77,36 @@ def test_streaming_is_bit_exact(E, O, shape):
             assert np.array_equal(got, s.A)
 
 
+@pytest.mark.parametrize("shape", [(320, 4, 3), (512, 3, 2)])
+def test_long_rows_parity(E, O, shape):
+    """Rows longer than 256 nodes take the XCD-contiguous tile order of the FP32 sweep (128- and
+    64-wide tiles here): stream-only bit-exact, and 20 full steps of a random near-equilibrium
+    state within 1e-6 of the oracle."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(17)
+    w = O.lattice()[1][:, None, None, None]
+    A0 = w + rng.integers(0, 4096, size=(27, nz, ny, nx)).astype(np.float64) / 1024.0
+    _say(f"case: long rows {shape} stream-only")
+    lat = E.Lattice(shape, 0.1, flags=E.FLAG_STREAM_ONLY)
+    lat.write_populations(A0, 0)
+    lat.step(3)
+    s = O.Simulation(shape, 0.1, A0=A0, stream_only=True).step(3)
+    assert np.array_equal(lat.populations().cpu().numpy(), s.A)
+    _say(f"case: long rows {shape} 20 steps")
+    x = np.arange(nx)[None, None, :]
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = 0.04 * np.sin(2 * np.pi * x / nx) * np.ones((nz, ny, 1))
+    u[1] = 0.03 * np.cos(4 * np.pi * x / nx) * np.ones((nz, ny, 1))
+    rho = 1.0 + 0.01 * np.cos(2 * np.pi * x / nx) * np.ones((nz, ny, 1))
+    lat = E.Lattice(shape, 0.01)
+    lat.init_equilibrium(rho, u)
+    lat.step(20)
+    ref = O.Simulation(shape, 0.01, rho, u).step(20).A
+    err = np.max(np.abs(lat.populations().cpu().numpy() - ref))
+    _say(f"long rows {shape} max|df| = {err:.3e}")
+    assert err <= 1e-6
+
+
 def test_collision_alone_matches_oracle(E, O, torch_cuda):
     """Random near-equilibrium states (and exact equilibria, which take the FP64 path)."""
     torch = torch_cuda

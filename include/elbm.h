@@ -78,7 +78,8 @@ typedef struct elbm_params {
   double nu;            /* kinematic viscosity; beta = 1/(6 nu + 1) (Sec. II, Chapman-Enskog) */
   double rho0;          /* reference density of the displacement term of Sec. III (1.0) */
   double u_inlet[3];    /* ELBM_BC_CHANNEL inlet velocity */
-  double fp64_threshold;/* <dh|dh> below this (times rho) is recomputed in FP64; 0 = 1e-10 */
+  double fp64_threshold;/* nodes with <dh|dh> < thr*rho and <ds|ds> >= thr*rho get the
+                           collision recomputed in FP64; 0 = 1e-12 */
 } elbm_params;
 
 /* A rigid body with prescribed motion (Sec. III).  Every quantity is evaluated
@@ -90,9 +91,24 @@ typedef struct elbm_params {
  * inside: |x - c|^2 < radius^2 (sphere, squares and sums left to right, no fused
  * multiply-add) or n.(x - c) < 0 (plane).  The first body in the array that
  * contains a node owns it. */
+/* Free motion (two-way coupling; Newton's equations of the settling-sphere case of Sec. IV.A):
+ * a sphere with motion = ELBM_MOTION_FREE is moved by the momentum-exchange force F, gravity
+ * and buoyancy, integrated with explicit Euler and unit time step,
+ *   x(t+1) = x(t) + u(t),   u(t+1) = u(t) + F(t)/m + (1 - 1/density_ratio) g,
+ *   m = density_ratio * rho0 * (4/3) pi radius^3,
+ * where F(t) is the force of the step that produced time level t (zero at the time level at
+ * which the geometry is set).  center and vel are the position and velocity at the current
+ * time level; amp, period and omega must be 0.  Every elbm_step of a context with free bodies
+ * reads the previous step's force back to the host (one synchronisation per step).  A free
+ * sphere must stay at least 3 nodes inside every face (6 from the inlet and outlet in channel
+ * mode); a step that would take it closer fails with ELBM_ESTATE.  Not available with
+ * ELBM_FLAG_ADJOINT. */
+#define ELBM_MOTION_PRESCRIBED 0
+#define ELBM_MOTION_FREE 1
+
 typedef struct elbm_body {
   int32_t kind;         /* ELBM_BODY_* */
-  int32_t reserved;
+  int32_t motion;       /* ELBM_MOTION_PRESCRIBED or ELBM_MOTION_FREE */
   double center[3];
   double radius;
   double normal[3];     /* plane only: unit normal into the fluid */
@@ -101,6 +117,8 @@ typedef struct elbm_body {
   double dir[3];
   double vel[3];
   double omega[3];
+  double density_ratio; /* free motion: rho_s / rho_f (> 0) */
+  double gravity[3];    /* free motion: gravitational acceleration (lattice units) */
 } elbm_body;
 
 typedef struct elbm_info {
@@ -146,6 +164,10 @@ int elbm_read_populations(struct elbm_ctx* ctx, double* pop_dev);
  * and compute the solid mask at the current time level.  In channel mode a body
  * must stay at least 6 nodes away from the inlet and outlet faces. */
 int elbm_set_geometry(struct elbm_ctx* ctx, const elbm_body* bodies, int32_t nb);
+
+/* Position and velocity of body `body` at the current time level (host arrays of 3):
+ * the prescribed motion evaluated at t, or the integrated state of a free body. */
+int elbm_body_state(struct elbm_ctx* ctx, int32_t body, double pos[3], double vel[3]);
 
 /* Bind a body-force field F_dev (dev [3][N] FP32, borrowed until replaced) or
  * NULL for none.  Needs ELBM_FLAG_BODY_FORCE.  The collision adds

@@ -14,6 +14,7 @@ velocity order is i = 9 (cz+1) + 3 (cy+1) + (cx+1).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 import numpy as np
@@ -44,10 +45,11 @@ class Grid(ctypes.Structure):
 
 
 class Body(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("pad", ctypes.c_int32), ("p0", ctypes.c_double * 3),
+    _fields_ = [("kind", ctypes.c_int32), ("tracked", ctypes.c_int32), ("p0", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("normal", ctypes.c_double * 3), ("amp", ctypes.c_double),
                 ("period", ctypes.c_double), ("dir", ctypes.c_double * 3), ("vel", ctypes.c_double * 3),
-                ("omega", ctypes.c_double * 3)]
+                ("omega", ctypes.c_double * 3), ("track_t", ctypes.c_double),
+                ("track_c", (ctypes.c_double * 3) * 2), ("track_U", (ctypes.c_double * 3) * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -167,8 +169,12 @@ def pressure(rho: float, u, G, beta: float) -> np.ndarray:
 
 # ----------------------------------------------------------------------------- bodies
 def make_body(kind="sphere", center=(0, 0, 0), radius=0.0, normal=(0, 0, 0), amp=0.0, period=0.0,
-              direction=(0, 0, 0), vel=(0, 0, 0), omega=(0, 0, 0)) -> Body:
+              direction=(0, 0, 0), vel=(0, 0, 0), omega=(0, 0, 0), motion="prescribed", density_ratio=0.0,
+              gravity=(0, 0, 0)) -> Body:
+    """A body for ``or_step``.  motion="free": a sphere moved by the fluid force, gravity and
+    buoyancy (its track is set by ``Simulation`` each step; density_ratio = rho_s / rho_f)."""
     b = Body()
+    b.tracked = 1 if motion == "free" else 0
     b.kind = 0 if kind == "sphere" else 1
     b.p0[:] = list(map(float, center))
     b.radius = float(radius)
@@ -218,6 +224,20 @@ class Simulation:
                                                       for b in bodies])
         self.nb = len(bodies)
         self.t = 0
+        # freely moving spheres (two-way coupling, Sec. IV.A): Newton's equations
+        #   dx/dt = u,  du/dt = F/m + (1 - rho_f/rho_s) g,  m = rho_s (4/3) pi R^3,
+        # explicit Euler with unit time step, F the momentum-exchange force of the last step
+        # (zero before the first one):  x(t+1) = x(t) + u(t),  u(t+1) = u(t) + F(t)/m + (1 - 1/ratio) g
+        self.free = {}
+        for k, spec in enumerate(bodies):
+            if isinstance(spec, dict) and spec.get("motion") == "free":
+                ratio = float(spec["density_ratio"])
+                R = float(spec["radius"])
+                self.free[k] = dict(m=ratio * rho0 * (4.0 / 3.0) * math.pi * R ** 3,
+                                    ab=(1.0 - 1.0 / ratio) * np.asarray(spec.get("gravity", (0, 0, 0)), float),
+                                    x=np.asarray(spec["center"], float).copy(),
+                                    u=np.asarray(spec.get("vel", (0, 0, 0)), float).copy(), F=np.zeros(3))
+        self._set_tracks()
         self.F = None if F is None else np.ascontiguousarray(F, dtype=np.float64).reshape(3, nz, ny, nx)
         self.A = np.zeros((27, nz, ny, nx))
         if u is None:
@@ -241,8 +261,24 @@ class Simulation:
             lib().or_solid_mask(ctypes.byref(self.grid), self.bodies, self.nb, float(t), _u8(out))
         return out
 
+    def _set_tracks(self):
+        """Centre and velocity of each free sphere at t and t+1 (explicit Euler)."""
+        for k, fb in self.free.items():
+            b = self.bodies[k]
+            x1 = fb["x"] + fb["u"]
+            u1 = fb["u"] + fb["F"] / fb["m"] + fb["ab"]
+            b.track_t = float(self.t)
+            for a in range(3):
+                b.track_c[0][a], b.track_c[1][a] = fb["x"][a], x1[a]
+                b.track_U[0][a], b.track_U[1][a] = fb["u"][a], u1[a]
+
+    def body_state(self, k: int):
+        """Centre and velocity of free body k at the current time level."""
+        return self.free[k]["x"].copy(), self.free[k]["u"].copy()
+
     def step(self, n: int = 1, record_masks: list | None = None):
         for _ in range(n):
+            self._set_tracks()
             if self.frozen_masks is not None:
                 s1 = self.frozen_masks[self.t + 1]
             else:
@@ -263,6 +299,11 @@ class Simulation:
             self.t += 1
             self.forces.append(forces[: 6 * self.nb].reshape(self.nb, 6).copy() if self.nb else np.zeros((0, 6)))
             self.stats.append({k: getattr(st, k) for k, _ in Stats._fields_})
+            for k, fb in self.free.items():
+                b = self.bodies[k]
+                fb["x"] = np.array([b.track_c[1][a] for a in range(3)])
+                fb["u"] = np.array([b.track_U[1][a] for a in range(3)])
+                fb["F"] = self.forces[-1][k, :3].copy()
         return self
 
     def moments(self):

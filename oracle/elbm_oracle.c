@@ -285,7 +285,8 @@ typedef struct {
 
 typedef struct {
   int32_t kind;      /* 0: sphere, 1: half-space bounded by a plane */
-  int32_t pad;
+  int32_t tracked;   /* 1: centre and velocity come from the track below (a freely moving body
+                        whose motion the caller integrates), not from the prescribed motion */
   double p0[3];      /* sphere centre, or a point of the plane, at t = 0 */
   double radius;
   double normal[3];  /* plane: unit normal pointing into the fluid */
@@ -293,6 +294,9 @@ typedef struct {
   double dir[3];
   double vel[3];
   double omega[3];
+  double track_t;         /* tracked: the time level t of track_c[0], track_U[0] */
+  double track_c[2][3];   /* tracked: centre at t and t + 1 */
+  double track_U[2][3];   /* tracked: translational velocity at t and t + 1 */
 } or_body;
 
 typedef struct {
@@ -301,6 +305,14 @@ typedef struct {
 } or_stats;
 
 void or_kinematics(const or_body *b, double t, double c[3], double U[3]) {
+  if (b->tracked) {
+    const int k = (t == b->track_t) ? 0 : ((t == b->track_t + 1.0) ? 1 : -1);
+    for (int a = 0; a < 3; ++a) {
+      c[a] = k >= 0 ? b->track_c[k][a] : NAN;
+      U[a] = k >= 0 ? b->track_U[k][a] : NAN;
+    }
+    return;
+  }
   double ph = 0.0, sn = 0.0, cs = 0.0, om = 0.0;
   if (b->period != 0.0) {
     ph = ((2.0 * M_PI) * t) / b->period;

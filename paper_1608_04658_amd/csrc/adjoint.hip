@@ -184,21 +184,6 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
   return VjpOut<T>{b, rho};
 }
 
-// Collision VJP in FP64 of an absolute FP64 state; adjoint in and out FP32.
-template <bool FORCE>
-__device__ inline void collide_vjp(const double (&f)[27], const float (&gp)[27], float beta, float Fx, float Fy,
-                                   float Fz, float (&g)[27], float (&gF)[3]) {
-  double gd[27], outd[27], gFd[3];
-#pragma unroll
-  for (int i = 0; i < 27; ++i) gd[i] = gp[i];
-  kbc_vjp<double, FORCE>(f, gd, (double)beta, Fx, Fy, Fz, outd, gFd);
-#pragma unroll
-  for (int i = 0; i < 27; ++i) g[i] = (float)outd[i];
-  gF[0] = (float)gFd[0];
-  gF[1] = (float)gFd[1];
-  gF[2] = (float)gFd[2];
-}
-
 struct AdjArgs {
   const float* lam_in;
   float* lam_out;
@@ -240,6 +225,51 @@ __device__ inline long pull_source(const BArgs& a, int i, int x, int y, int z) {
   return node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
 }
 
+// Pull sources of a node, computed once: the 3 source x (clamped to the outlet in channel mode)
+// and the 9 source-row offsets (periodic in y and z).  The transpose of the pull writes to the
+// same entries, except beyond the inlet (nothing) and beyond the outlet (the side buffer).
+struct PullIdx {
+  long row[9];  // row[3 (cz+1) + (cy+1)] = ((z - cz) ny + (y - cy)) nx
+  int xs[3];    // xs[cx+1] = source x
+  bool in_lo;   // channel: x - 1 < 0 (cx = +1 comes through the inlet)
+  bool out_hi;  // channel: x + 1 >= nx (cx = -1 comes from beyond the outlet, copied)
+};
+
+__device__ inline void pull_idx(const BArgs& a, int x, int y, int z, PullIdx& P) {
+  const int xm = x + 1, xp = x - 1;
+  if (a.channel) {
+    P.xs[0] = xm < a.nx ? xm : a.nx - 1;
+    P.xs[2] = xp >= 0 ? xp : 0;
+  } else {
+    P.xs[0] = xm == a.nx ? 0 : xm;
+    P.xs[2] = xp < 0 ? a.nx - 1 : xp;
+  }
+  P.xs[1] = x;
+  P.in_lo = a.channel && xp < 0;
+  P.out_hi = a.channel && xm >= a.nx;
+  const int ys[3] = {y + 1 == a.ny ? 0 : y + 1, y, y == 0 ? a.ny - 1 : y - 1};
+  const int zs[3] = {z + 1 == a.nz ? 0 : z + 1, z, z == 0 ? a.nz - 1 : z - 1};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) P.row[3 * k + jj] = ((long)zs[k] * a.ny + ys[jj]) * a.nx;
+}
+
+__device__ __forceinline__ long pull_src_idx(const PullIdx& P, int i) {
+  return P.row[3 * (cz(i) + 1) + cy(i) + 1] + P.xs[cx(i) + 1];
+}
+
+// Transpose of the pull for direction i of node (y, z): entry (x - c_i, i) of dL/dA^t receives v.
+__device__ __forceinline__ void push_idx(const BArgs& a, const AdjArgs& j, const PullIdx& P, int i, int y, int z,
+                                         float v) {
+  if (cx(i) == 1 && P.in_lo) return;
+  if (cx(i) == -1 && P.out_hi) {
+    j.side[(size_t)(i / 3) * a.ny * a.nz + (size_t)z * a.ny + y] = v;
+    return;
+  }
+  j.lam_out[(size_t)i * a.N + pull_src_idx(P, i)] = v;
+}
+
 template <int S, bool FLAGS, bool FORCE>
 __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j) {
   using C = Codec<S>;
@@ -250,17 +280,19 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
   if (x >= a.nx || y >= a.ny) return;
   const long n = node_at(a, x, y, z);
   const uint8_t fl = FLAGS ? a.flags[n] : (uint8_t)0;
+  if (fl & FL_SPECIAL) return;
+  PullIdx P;
+  pull_idx(a, x, y, z, P);
   if (fl & FL_SOLID) {
 #pragma unroll
-    for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, 0.f);
+    for (int i = 0; i < 27; ++i) push_idx(a, j, P, i, y, z, 0.f);
     return;
   }
-  if (fl & FL_SPECIAL) return;
   const E* __restrict__ A = (const E*)a.A;
   double f[27], gp[27], g[27], gF[3];
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    f[i] = (double)C::load_dev(A + i * a.N + pull_source(a, i, x, y, z)) + wd(i);  // exact widening
+    f[i] = (double)C::load_dev(A + i * a.N + pull_src_idx(P, i)) + wd(i);  // exact widening
     gp[i] = (double)j.lam_in[i * a.N + n];
   }
   double Fx = 0.0, Fy = 0.0, Fz = 0.0;
@@ -271,7 +303,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
   }
   kbc_vjp<double, FORCE>(f, gp, (double)a.beta, Fx, Fy, Fz, g, gF);
 #pragma unroll
-  for (int i = 0; i < 27; ++i) adj_push(a, j, i, x, y, z, (float)g[i]);
+  for (int i = 0; i < 27; ++i) push_idx(a, j, P, i, y, z, (float)g[i]);
   if (FORCE && j.gF) {
     j.gF[n] += (float)gF[0];
     j.gF[a.N + n] += (float)gF[1];
@@ -352,11 +384,95 @@ __device__ inline void grad_u_vjp_one(const BArgs& a, const AdjArgs& j, const La
   }
 }
 
+// The collision VJP in the lane-parallel form of the wall kernels (FP64): lane i < 27 holds f_i
+// (absolute) and gp_i = dL/df'_i and receives g_i = dL/df_i; lanes >= 27 pass zeros.  Same
+// arithmetic as kbc_vjp, with every sum over directions a butterfly reduction inside the group.
+template <bool FORCE>
+__device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double beta, double Fx, double Fy, double Fz,
+                                       double (&gF)[3]) {
+  const bool own = lane < 27;
+  const int i = own ? lane : 13;
+  const double ci[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+  if (!own) {
+    f = 0.0;
+    gp = 0.0;
+  }
+  const double rho = gsum(f), jx = gsum(ci[0] * f), jy = gsum(ci[1] * f), jz = gsum(ci[2] * f);
+  const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+  double px[3], py[3], pz[3];
+  axis_phi(ux, px);
+  axis_phi(uy, py);
+  axis_phi(uz, pz);
+  const double fe = rho * px[cx(i) + 1] * py[cy(i) + 1] * pz[cz(i) + 1];
+  const double d = own ? f - fe : 0.0;
+  const double M200 = gsum(ci[0] * ci[0] * d), M020 = gsum(ci[1] * ci[1] * d), M002 = gsum(ci[2] * ci[2] * d);
+  const double M110 = gsum(ci[0] * ci[1] * d), M101 = gsum(ci[0] * ci[2] * d), M011 = gsum(ci[1] * ci[2] * d);
+  const double tr3 = (M200 + M020 + M002) * (1.0 / 3.0);
+  const double sfx = 0.5 * (M200 - tr3), sfy = 0.5 * (M020 - tr3), sfz = 0.5 * (M002 - tr3);
+  const double sxy = 0.25 * M110, sxz = 0.25 * M101, syz = 0.25 * M011;
+  double ds = 0.0;
+  if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
+  else if (nnz(i) == 2) ds = cz(i) == 0 ? ci[0] * ci[1] * sxy : (cy(i) == 0 ? ci[0] * ci[2] * sxz : ci[1] * ci[2] * syz);
+  if (!own) ds = 0.0;
+  const double h = d - ds, th = own ? h / fe : 0.0;
+  const double b = gsum(th * h), a = gsum(th * ds), ggh = gsum(gp * h);
+  const bool guard = !(b > 1e-30);
+  const double ib = 1.0 / beta;
+  const double gam = guard ? 2.0 : ib - (2.0 - ib) * a / b;
+  // reverse
+  const double g_gam = -beta * ggh;
+  const double g_a = guard ? 0.0 : -(2.0 - ib) / b * g_gam;
+  const double g_b = guard ? 0.0 : (2.0 - ib) * a / (b * b) * g_gam;
+  const double g_dh = own ? -beta * gam * gp + (g_a * ds + 2.0 * g_b * h) / fe : 0.0;
+  const double g_ds = own ? -2.0 * beta * gp + g_a * h / fe - g_dh : 0.0;
+  double gfe = own ? -(g_a * ds * h + g_b * h * h) / (fe * fe) - g_dh : 0.0;
+  // g_ds onto the deviatoric moments
+  const bool face = nnz(i) == 1, edge = nnz(i) == 2;
+  const double gDx = gsum(face && cx(i) ? 0.5 * g_ds : 0.0), gDy = gsum(face && cy(i) ? 0.5 * g_ds : 0.0);
+  const double gDz = gsum(face && cz(i) ? 0.5 * g_ds : 0.0);
+  const double gPxy = gsum(edge && cz(i) == 0 ? 0.25 * ci[0] * ci[1] * g_ds : 0.0);
+  const double gPxz = gsum(edge && cy(i) == 0 ? 0.25 * ci[0] * ci[2] * g_ds : 0.0);
+  const double gPyz = gsum(edge && cx(i) == 0 ? 0.25 * ci[1] * ci[2] * g_ds : 0.0);
+  const double gm = (gDx + gDy + gDz) * (1.0 / 3.0);
+  const double e = (gDx - gm) * ci[0] * ci[0] + (gDy - gm) * ci[1] * ci[1] + (gDz - gm) * ci[2] * ci[2] +
+                   gPxy * ci[0] * ci[1] + gPxz * ci[0] * ci[2] + gPyz * ci[1] * ci[2];
+  gfe -= own ? e : 0.0;
+  double g_rho = 0.0, gux = 0.0, guy = 0.0, guz = 0.0;
+  gF[0] = gF[1] = gF[2] = 0.0;
+  if (FORCE) {
+    // f' += feq(rho, u + F/rho) - feq(rho, u)
+    const double u1x = ux + Fx / rho, u1y = uy + Fy / rho, u1z = uz + Fz / rho;
+    double qx[3], qy[3], qz[3];
+    axis_phi(u1x, qx);
+    axis_phi(u1y, qy);
+    axis_phi(u1z, qz);
+    const double ge1 = own ? gp * rho * qx[cx(i) + 1] * qy[cy(i) + 1] * qz[cz(i) + 1] : 0.0;
+    const double gr1 = gsum(ge1);
+    const double g1x = gsum(ge1 * dlnphi(cx(i), u1x)), g1y = gsum(ge1 * dlnphi(cy(i), u1y));
+    const double g1z = gsum(ge1 * dlnphi(cz(i), u1z));
+    gfe -= gp;
+    g_rho += gr1 / rho - (g1x * Fx + g1y * Fy + g1z * Fz) / (rho * rho);
+    gux += g1x;
+    guy += g1y;
+    guz += g1z;
+    gF[0] = g1x / rho;
+    gF[1] = g1y / rho;
+    gF[2] = g1z / rho;
+  }
+  const double ge = own ? gfe * fe : 0.0;
+  g_rho += gsum(ge) / rho;
+  gux += gsum(ge * dlnphi(cx(i), ux));
+  guy += gsum(ge * dlnphi(cy(i), uy));
+  guz += gsum(ge * dlnphi(cz(i), uz));
+  const double gjx = gux / rho, gjy = guy / rho, gjz = guz / rho;
+  g_rho -= (gux * ux + guy * uy + guz * uz) / rho;
+  return gp + g_dh + e + g_rho + ci[0] * gjx + ci[1] * gjy + ci[2] * gjz;
+}
+
 // Adjoint of the boundary rules of Secs. III / IV.A at the listed nodes, in the lane-parallel
 // form of the forward wall kernel: one node per group of 32 lanes, lane i < 27 owning direction
-// i.  The forward reconstruction is recomputed (same helper as the forward kernel), the FP64
-// collision VJP runs on the group's first lane through LDS, and the reverse of the reconstruction
-// runs per lane with butterfly sums.  Listed nodes without missing populations (inlet and outlet
+// i.  The forward reconstruction is recomputed (same helper as the forward kernel); the FP64
+// collision VJP and the reverse of the reconstruction run per lane with butterfly sums.  Listed nodes without missing populations (inlet and outlet
 // rows, refill nodes) take the plain collision VJP, since the bulk kernel skips FL_SPECIAL nodes.
 template <int S, bool FORCE>
 __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies bd, const AdjArgs j,
@@ -364,15 +480,12 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
   using C = Codec<S>;
   using E = typename C::E;
   const E* __restrict__ A = (const E*)a.A;
-  __shared__ float shv[2][GROUP];  // collision input in, dL/d(pre-collision f) out
-  __shared__ float shg[2][GROUP];  // lambda^{t+1} at the node
   int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
   if (count > a.cap) count = a.cap;
   const int lane = threadIdx.x & (GROUP - 1), g = threadIdx.x / GROUP;
   const int i = lane < 27 ? lane : 13;
   for (int64_t base = 2 * (int64_t)blockIdx.x; base < count; base += 2 * (int64_t)gridDim.x) {
-    // uniform over the block (barriers below); a group past the end repeats the block's first
-    // node and writes nothing
+    // a group past the end repeats the block's first node and writes nothing
     const int64_t k = base + g;
     const bool active = k < count;
     const long n = a.list[active ? k : base];
@@ -383,36 +496,21 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
     WallLane w;
     w.mine = false;
     if (dmask) wall_targets(a, bd, h, lane, w);
-    // collision input: f*_i (absolute) where missing, else the pulled deviation
-    shv[g][lane] = w.mine ? w.fs : h.f;
-    shg[g][lane] = gpi;
-    __syncthreads();
-    if (lane == 0) {
-      double fd[27];
-      float gp[27], go[27], gFn[3];
-#pragma unroll
-      for (int q = 0; q < 27; ++q) {
-        const float v = shv[g][q];
-        fd[q] = ((dmask >> q) & 1u) ? (double)v : wd(q) + (double)v;
-        gp[q] = shg[g][q];
-      }
-      float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-      if (FORCE) {
-        Fx = a.F[n];
-        Fy = a.F[a.N + n];
-        Fz = a.F[2 * a.N + n];
-      }
-      collide_vjp<FORCE>(fd, gp, a.beta, Fx, Fy, Fz, go, gFn);
-#pragma unroll
-      for (int q = 0; q < 27; ++q) shv[g][q] = go[q];
-      if (FORCE && j.gF && active) {
-        j.gF[n] += gFn[0];
-        j.gF[a.N + n] += gFn[1];
-        j.gF[2 * a.N + n] += gFn[2];
-      }
+    // collision input: f*_i (absolute) where missing, else the pulled deviation widened exactly
+    const double fdi = lane < 27 ? (((dmask >> lane) & 1u) ? (double)w.fs : wd(i) + (double)h.f) : 0.0;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    if (FORCE) {
+      Fx = a.F[n];
+      Fy = a.F[a.N + n];
+      Fz = a.F[2 * a.N + n];
     }
-    __syncthreads();
-    const float gi = shv[g][lane];  // dL / d(pre-collision f_i)
+    double gFn[3];
+    const float gi = (float)kbc_vjp_lanes<FORCE>(lane, fdi, (double)gpi, (double)a.beta, Fx, Fy, Fz, gFn);
+    if (FORCE && j.gF && active && lane == 0) {
+      j.gF[n] += (float)gFn[0];
+      j.gF[a.N + n] += (float)gFn[1];
+      j.gF[2 * a.N + n] += (float)gFn[2];
+    }
     if (!dmask) {
       if (active && lane < 27) adj_push(a, j, i, h.x, h.y, h.z, gi);
     } else {
@@ -491,7 +589,6 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
       // transpose of the gradient stencil: lanes 0..8 take one (axis, component) pair each
       if (active && lane < 9) grad_u_vjp_one(a, j, h, lane / 3, lane % 3, gG[3 * (lane % 3) + lane / 3]);
     }
-    __syncthreads();
   }
 }
 

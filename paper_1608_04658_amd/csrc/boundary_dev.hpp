@@ -26,8 +26,14 @@ __device__ __forceinline__ int first_body(const Bodies& bd, bool at_t1, double x
   return -1;
 }
 
-// Periodic index for any offset (stencils reach +-2, lattices may be 1 or 2 nodes thick).
-__device__ __forceinline__ int wrap(int v, int n) { return ((v % n) + n) % n; }
+// Periodic index for any offset (stencils reach +-2, lattices may be 1 or 2 nodes thick); the
+// integer division only where the offset exceeds one period.
+__device__ __forceinline__ int wrap(int v, int n) {
+  if (v >= 0 && v < n) return v;
+  if (v < 0 && v + n >= 0) return v + n;
+  if (v >= n && v - n < n) return v - n;
+  return ((v % n) + n) % n;
+}
 
 struct BArgs {
   const void* A;
@@ -187,6 +193,80 @@ __device__ inline void grad_u_grp(const LaneNb& h, float (&G)[9]) {
       G[3 * c + b] = d;
     }
   }
+}
+
+// The KBC collision (Sec. II) in the lane-parallel form of the wall kernels: lane i < 27 holds
+// d_i = f_i - W_i and receives the post-collision deviation; lanes >= 27 pass zeros.  Same
+// arithmetic as kbc_collide<float>, with every sum over directions a butterfly reduction inside the
+// group.  r receives gamma, <dh|dh>, rho and the shear estimate for the FP64 rule (equal on all
+// lanes of the group).
+template <bool FORCE>
+__device__ inline float kbc_collide_lanes(int lane, float d, float beta, float inv_beta, float Fx, float Fy, float Fz,
+                                          KbcOut<float>& r) {
+  const bool own = lane < 27;
+  const int i = own ? lane : 13;
+  if (!own) d = 0.f;
+  const float c0 = (float)cx(i), c1 = (float)cy(i), c2 = (float)cz(i);
+  const float dr = gsum(d), jx = gsum(c0 * d), jy = gsum(c1 * d), jz = gsum(c2 * d);
+  const float Q200 = gsum(c0 * c0 * d), Q020 = gsum(c1 * c1 * d), Q002 = gsum(c2 * c2 * d);
+  const float Q110 = gsum(c0 * c1 * d), Q101 = gsum(c0 * c2 * d), Q011 = gsum(c1 * c2 * d);
+  const float rho = 1.f + dr;
+  const float rinv = rcp_(rho);
+  const float ux = jx * rinv, uy = jy * rinv, uz = jz * rinv;
+  float ex[3], ey[3], ez[3], psx[3], psy[3], psz[3], sx, sy, sz;
+  axis_dev(ux, ex, psx, sx);
+  axis_dev(uy, ey, psy, sy);
+  axis_dev(uz, ez, psz, sz);
+  const float third = 1.f / 3.f;
+  const float dM200 = Q200 - (dr * (1.f + 2.f * sx) + 2.f * sx) * third;
+  const float dM020 = Q020 - (dr * (1.f + 2.f * sy) + 2.f * sy) * third;
+  const float dM002 = Q002 - (dr * (1.f + 2.f * sz) + 2.f * sz) * third;
+  const float tr3 = (dM200 + dM020 + dM002) * third;
+  const float sfx = 0.5f * (dM200 - tr3), sfy = 0.5f * (dM020 - tr3), sfz = 0.5f * (dM002 - tr3);
+  const float sxy = 0.25f * (Q110 - jx * uy), sxz = 0.25f * (Q101 - jx * uz), syz = 0.25f * (Q011 - jy * uz);
+  // feq_i - W_i = W_i (dr + rho P_i)
+  const float a_ = ey[cy(i) + 1], b_ = ez[cz(i) + 1];
+  const float pyz = a_ + b_ + a_ * b_;
+  const float e_ = ex[cx(i) + 1];
+  const float P = e_ + pyz + e_ * pyz;
+  const float fdev = wf(i) * (dr + rho * P);
+  float ds = 0.f;
+  if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
+  else if (nnz(i) == 2) ds = cz(i) == 0 ? c0 * c1 * sxy : (cy(i) == 0 ? c0 * c2 * sxz : c1 * c2 * syz);
+  if (!own) ds = 0.f;
+  float h = own ? (d - fdev) - ds : 0.f;
+  // remove the rounding residue of the mass and momentum of dh (rest and face populations)
+  const float hm = gsum(h), hx = gsum(c0 * h), hy = gsum(c1 * h), hz = gsum(c2 * h);
+  if (own) {
+    if (i == 13) h -= hm;
+    else if (i == 14) h -= 0.5f * hx;
+    else if (i == 12) h += 0.5f * hx;
+    else if (i == 16) h -= 0.5f * hy;
+    else if (i == 10) h += 0.5f * hy;
+    else if (i == 22) h -= 0.5f * hz;
+    else if (i == 4) h += 0.5f * hz;
+  }
+  const float ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
+  const float th = h * ife;
+  const float b = gsum(th * h), a = gsum(th * ds);
+  const float gamma = (b > 1e-30f) ? inv_beta - (2.f - inv_beta) * a / b : 2.f;
+  const float s2 = (27.f * (sfx * sfx + sfy * sfy + sfz * sfz) + 216.f * (sxy * sxy + sxz * sxz + syz * syz)) * rinv;
+  float out = d - (2.f * beta) * ds - (beta * gamma) * h;
+  if (FORCE) {
+    const double rr = (double)rho;
+    double p0[3], q0[3], w0[3], p1[3], q1[3], w1[3];
+    axis_phi((double)ux, p0);
+    axis_phi((double)uy, q0);
+    axis_phi((double)uz, w0);
+    axis_phi((double)ux + (double)Fx / rr, p1);
+    axis_phi((double)uy + (double)Fy / rr, q1);
+    axis_phi((double)uz + (double)Fz / rr, w1);
+    const double e0 = rr * p0[cx(i) + 1] * q0[cy(i) + 1] * w0[cz(i) + 1];
+    const double e1 = rr * p1[cx(i) + 1] * q1[cy(i) + 1] * w1[cz(i) + 1];
+    out = (float)((double)out + (e1 - e0));
+  }
+  r = KbcOut<float>{gamma, b, rho, s2};
+  return own ? out : 0.f;
 }
 
 // Geometry of boundary link i (i in Dbar) at node (x,y,z): link fraction q, wall velocity u_w and

@@ -113,6 +113,30 @@ bool body_moves(const elbm_body& b) {
   return (b.amp != 0.0 && b.period != 0.0 && dn != 0.0) || vn != 0.0;
 }
 
+// A free sphere centred at x: at least 3 nodes inside every face, 6 from the inlet and outlet.
+bool free_inside(const elbm_ctx* c, const double x[3], double r) {
+  const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+  for (int a = 0; a < 3; ++a) {
+    const double m = (a == 0 && c->p.bc_x == ELBM_BC_CHANNEL) ? 6.0 : 3.0;
+    if (!(x[a] - r >= m) || !(x[a] + r <= n[a] - 1.0 - m)) return false;
+  }
+  return true;
+}
+
+// Force of the step that produced the current time level, for each free body (synchronises).
+hipError_t free_read_forces(elbm_ctx* c) {
+  double rec[6 * ELBM_MAX_BODIES];
+  const int slot = (int)(c->t % c->p.force_ring);
+  hipError_t e = hipMemcpyAsync(rec, c->ring + (size_t)slot * ELBM_MAX_BODIES * 6, sizeof rec, hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < c->nb; ++k)
+    if (c->freeb[k].on)
+      for (int a = 0; a < 3; ++a) c->freeb[k].F[a] = rec[6 * k + a];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -144,7 +168,7 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->ws_bytes = ws_bytes;
   c->N = (int64_t)p->nx * p->ny * p->nz;
   c->beta = 1.0 / (6.0 * p->nu + 1.0);
-  c->fp64_thr = p->fp64_threshold > 0.0 ? p->fp64_threshold : 1e-10;
+  c->fp64_thr = p->fp64_threshold > 0.0 ? p->fp64_threshold : 1e-12;
   c->pop[0] = c->ws + L.pop[0];
   c->pop[1] = c->ws + L.pop[1];
   c->cur = 0;
@@ -170,6 +194,9 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->bodyforce = nullptr;
   c->nb = 0;
   c->moving = false;
+  c->n_free = 0;
+  c->free_force_pending = false;
+  for (int k = 0; k < ELBM_MAX_BODIES; ++k) c->freeb[k].on = false;
   c->t = 0;
   c->err[0] = 0;
   c->timing = false;
@@ -259,6 +286,20 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
   for (int k = 0; k < nb; ++k) {
     const elbm_body& b = bodies[k];
     if (b.kind != ELBM_BODY_SPHERE && b.kind != ELBM_BODY_PLANE) return fail(c, ELBM_EINVAL, "body %d: bad kind", k);
+    if (b.motion != ELBM_MOTION_PRESCRIBED && b.motion != ELBM_MOTION_FREE)
+      return fail(c, ELBM_EINVAL, "body %d: bad motion", k);
+    if (b.motion == ELBM_MOTION_FREE) {
+      if (b.kind != ELBM_BODY_SPHERE || !(b.radius > 0.0)) return fail(c, ELBM_EINVAL, "body %d: free motion needs a sphere", k);
+      if (!(b.density_ratio > 0.0) || !isfinite(b.density_ratio))
+        return fail(c, ELBM_EINVAL, "body %d: density_ratio must be positive", k);
+      if (b.amp != 0.0 || b.omega[0] != 0.0 || b.omega[1] != 0.0 || b.omega[2] != 0.0)
+        return fail(c, ELBM_EINVAL, "body %d: a free body has no prescribed oscillation or rotation", k);
+      if (c->p.flags & ELBM_FLAG_ADJOINT) return fail(c, ELBM_EINVAL, "body %d: no free bodies with the adjoint", k);
+      if (!free_inside(c, b.center, b.radius))
+        return fail(c, ELBM_EINVAL, "body %d: free sphere too close to a face", k);
+      moving = true;
+      continue;
+    }
     if (b.kind == ELBM_BODY_SPHERE && !(b.radius > 0.0)) return fail(c, ELBM_EINVAL, "body %d: radius <= 0", k);
     if (b.kind == ELBM_BODY_PLANE) {
       const double nn = b.normal[0] * b.normal[0] + b.normal[1] * b.normal[1] + b.normal[2] * b.normal[2];
@@ -274,13 +315,44 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
     moving = moving || body_moves(b);
   }
   c->nb = nb;
-  for (int k = 0; k < nb; ++k) c->bodies[k] = bodies[k];
+  c->n_free = 0;
+  c->free_force_pending = false;
+  for (int k = 0; k < ELBM_MAX_BODIES; ++k) c->freeb[k].on = false;
+  for (int k = 0; k < nb; ++k) {
+    c->bodies[k] = bodies[k];
+    const elbm_body& b = bodies[k];
+    if (b.motion != ELBM_MOTION_FREE) continue;
+    auto& fb = c->freeb[k];
+    fb.on = true;
+    fb.m = b.density_ratio * c->p.rho0 * (4.0 / 3.0) * M_PI * b.radius * b.radius * b.radius;
+    for (int a = 0; a < 3; ++a) {
+      fb.x[a] = b.center[a];
+      fb.u[a] = b.vel[a];
+      fb.F[a] = 0.0;
+      fb.ab[a] = (1.0 - 1.0 / b.density_ratio) * b.gravity[a];
+    }
+    c->n_free += 1;
+  }
   c->moving = moving;
   if (!c->flags) {
     if (nb > 0) return fail(c, ELBM_ESTATE, "context created with max_bodies = 0");
     return ELBM_OK;
   }
   HIP_OK(c, geometry_init(c));
+  return ELBM_OK;
+}
+
+int elbm_body_state(elbm_ctx* c, int32_t body, double pos[3], double vel[3]) {
+  if (!c) return ELBM_EINVAL;
+  if (body < 0 || body >= c->nb || !pos || !vel) return fail(c, ELBM_EINVAL, "bad arguments");
+  if (c->freeb[body].on) {
+    for (int a = 0; a < 3; ++a) {
+      pos[a] = c->freeb[body].x[a];
+      vel[a] = c->freeb[body].u[a];
+    }
+  } else {
+    host_kinematics(c->bodies[body], (double)c->t, pos, vel);
+  }
   return ELBM_OK;
 }
 
@@ -297,6 +369,20 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
   if (nsteps < 0) return fail(c, ELBM_EINVAL, "nsteps < 0");
   const bool geo = c->flags != nullptr;
   for (int32_t s = 0; s < nsteps; ++s) {
+    if (c->n_free) {
+      if (c->free_force_pending) {
+        HIP_OK(c, free_read_forces(c));
+        c->free_force_pending = false;
+      }
+      for (int k = 0; k < c->nb; ++k) {
+        if (!c->freeb[k].on) continue;
+        double x1[3];
+        for (int a = 0; a < 3; ++a) x1[a] = c->freeb[k].x[a] + c->freeb[k].u[a];
+        if (!free_inside(c, x1, c->bodies[k].radius))
+          return fail(c, ELBM_ESTATE, "free body %d would come closer than allowed to a face at t = %lld", k,
+                      (long long)(c->t + 1));
+      }
+    }
     Bodies bd;
     if (geo) {
       bd = make_bodies(c, (double)c->t);
@@ -313,6 +399,17 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
     if (geo) HIP_OK(c, launch_boundary(c, bd));
     HIP_OK(c, launch_fixup(c));  // bulk and wall nodes queued for the FP64 collision
     if (geo) HIP_OK(c, launch_force_reduce(c));
+    if (c->n_free) {
+      // advance the free bodies to the time level just produced; its force is read at the next step
+      for (int k = 0; k < c->nb; ++k) {
+        if (!c->freeb[k].on) continue;
+        for (int a = 0; a < 3; ++a) {
+          c->freeb[k].x[a] = bd.b[k].c1[a];
+          c->freeb[k].u[a] = bd.b[k].U1[a];
+        }
+      }
+      c->free_force_pending = true;
+    }
     c->cur ^= 1;
     c->t += 1;
     // the sweep, the wall kernel and the fix-up staged U, R of the new state's inlet slab
@@ -461,7 +558,7 @@ int elbm_collide_nodes(const float* f_in_dev, float* f_out_dev, float* gamma_dev
   if (!f_in_dev || !f_out_dev || n < 0 || !(nu > 0.0)) return fail(nullptr, ELBM_EINVAL, "bad arguments");
   if (n == 0) return ELBM_OK;
   const double beta = 1.0 / (6.0 * nu + 1.0);
-  const double thr = fp64_threshold < 0.0 ? -1.0 : (fp64_threshold == 0.0 ? 1e-10 : fp64_threshold);
+  const double thr = fp64_threshold < 0.0 ? -1.0 : (fp64_threshold == 0.0 ? 1e-12 : fp64_threshold);
   hipError_t e = launch_collide_nodes(f_in_dev, f_out_dev, gamma_dev, F_dev, n, beta, thr, (hipStream_t)stream);
   if (e != hipSuccess) return fail(nullptr, ELBM_EDEVICE, "collide: %s", hipGetErrorString(e));
   return ELBM_OK;

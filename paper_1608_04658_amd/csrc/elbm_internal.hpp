@@ -429,6 +429,13 @@ struct elbm_ctx {
   int32_t nb;
   elbm_body bodies[ELBM_MAX_BODIES];
   bool moving;
+  // free bodies (two-way coupling): state at time level t and the force of the step producing t
+  struct FreeBody {
+    bool on;
+    double x[3], u[3], F[3], m, ab[3];  // ab = (1 - 1/density_ratio) g
+  } freeb[ELBM_MAX_BODIES];
+  int n_free;
+  bool free_force_pending;  // F of the last step is still on the device
   bool slab_valid;  // slab_next holds U, R of the inlet slab of the current state (written by the
                     // kernels that produced it)
   float* slab_next; // channel mode: [4][nz][ny][3] staging of U, R for x < 3

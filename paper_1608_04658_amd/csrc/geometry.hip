@@ -46,8 +46,19 @@ Bodies make_bodies(const elbm_ctx* c, double t) {
     BodyDev& d = bd.b[k];
     d.kind = b.kind;
     d.pad = 0;
-    host_kinematics(b, t, d.c0, d.U0);
-    host_kinematics(b, t + 1.0, d.c1, d.U1);
+    if (c->freeb[k].on) {
+      // explicit Euler of Newton's equations from the state at the context's time level
+      const auto& fb = c->freeb[k];
+      for (int a = 0; a < 3; ++a) {
+        d.c0[a] = fb.x[a];
+        d.U0[a] = fb.u[a];
+        d.c1[a] = fb.x[a] + fb.u[a];
+        d.U1[a] = fb.u[a] + fb.F[a] / fb.m + fb.ab[a];
+      }
+    } else {
+      host_kinematics(b, t, d.c0, d.U0);
+      host_kinematics(b, t + 1.0, d.c1, d.U1);
+    }
     d.radius = b.radius;
     d.r2 = b.radius * b.radius;
     for (int a = 0; a < 3; ++a) {
@@ -341,8 +352,8 @@ __global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, v
 }
 
 // Wall nodes (Sec. III): Grad reconstruction of the missing populations, the momentum exchange of
-// each link (Sec. IV.A), then the KBC collision of the node.  One node per group of 32 lanes; the
-// collision of the 27 populations runs on the group's first lane, exchanged through LDS.
+// each link (Sec. IV.A), then the KBC collision of the node.  One node per group of 32 lanes, one
+// direction per lane, sums over directions as butterfly reductions.
 template <int S, bool FORCE>
 __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd) {
   using C = Codec<S>;
@@ -387,12 +398,16 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
           dF[5] = r[0] * dF[1] - r[1] * dF[0];
         }
       }
-      for (int bb = 0; bb < nb; ++bb) {
+      if (gballot(w.mine && w.kb >= 0)) {  // uniform over the group; inlet-only nodes skip the sums
+        for (int bb = 0; bb < nb; ++bb) {
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-          const double v = gsum(w.kb == bb ? dF[e] : 0.0);
-          if (active && lane == e) rec[bb * 6 + e] = v;
+          for (int e = 0; e < 6; ++e) {
+            const double v = gsum(w.kb == bb ? dF[e] : 0.0);
+            if (active && lane == e) rec[bb * 6 + e] = v;
+          }
         }
+      } else if (active) {
+        for (int jj = lane; jj < nb * 6; jj += GROUP) rec[jj] = 0.0;
       }
     } else if (active) {
       for (int j = lane; j < nb * 6; j += GROUP) rec[j] = 0.0;
@@ -401,32 +416,28 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
       if (active && lane < 27) C::store_dev(B + (long)lane * a.N + n, fi);
       continue;
     }
-    sh[g][lane] = fi;
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    if (FORCE) {
+      Fx = a.F[n];
+      Fy = a.F[a.N + n];
+      Fz = a.F[2 * a.N + n];
+    }
+    KbcOut<float> r;
+    const float fpost = kbc_collide_lanes<FORCE>(lane, fi, a.beta, a.inv_beta, Fx, Fy, Fz, r);
+    // <dh|dh> at the FP32 noise floor (equal on all lanes of the group): store the pre-collision
+    // deviations and queue the node for the FP64 collision of k_fixup
+    const bool fp64 = a.fp64 && needs_fp64(r, a.thr);
+    if (active && lane < 27) C::store_dev(B + (long)lane * a.N + n, fp64 ? fi : fpost);
+    if (fp64 && active && lane == 0) a.fix_list[atomicAdd(&a.cnt->fix_count, 1u)] = (uint32_t)n | FIX_PRE;
+    // inlet slab: U, R of the new state, summed in direction order on the group's first lane
+    sh[g][lane] = fpost;
     __syncthreads();
-    if (lane == 0) {
+    if (lane == 0 && active && !fp64 && a.slab_next && h.x < 3) {
       float f[27];
 #pragma unroll
-      for (int j = 0; j < 27; ++j) f[j] = sh[g][j];
-      float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-      if (FORCE) {
-        Fx = a.F[n];
-        Fy = a.F[a.N + n];
-        Fz = a.F[2 * a.N + n];
-      }
-      const KbcOut<float> r = kbc_collide<float, FORCE>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
-      if (a.fp64 && needs_fp64(r, a.thr)) {
-        // <dh|dh> at the FP32 noise floor: store the pre-collision deviations (still in LDS) and
-        // queue the node for the FP64 collision of k_fixup
-        if (active) a.fix_list[atomicAdd(&a.cnt->fix_count, 1u)] = (uint32_t)n | FIX_PRE;
-      } else {
-#pragma unroll
-        for (int j = 0; j < 27; ++j) sh[g][j] = f[j];
-        if (active && a.slab_next && h.x < 3)
-          macro_from_post<S, FORCE>(f, Fx, Fy, Fz, a.slab_next, (size_t)3 * a.ny * a.nz, slab_index(h.x, h.y, h.z, a.ny));
-      }
+      for (int q = 0; q < 27; ++q) f[q] = sh[g][q];
+      macro_from_post<S, FORCE>(f, Fx, Fy, Fz, a.slab_next, (size_t)3 * a.ny * a.nz, slab_index(h.x, h.y, h.z, a.ny));
     }
-    __syncthreads();
-    if (active && lane < 27) C::store_dev(B + (long)lane * a.N + n, sh[g][lane]);
     __syncthreads();
   }
 }

@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "elbm.h")
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 BC_PERIODIC, BC_CHANNEL = 0, 1
 BODY_SPHERE, BODY_PLANE = 0, 1
+MOTION_PRESCRIBED, MOTION_FREE = 0, 1
 MAX_BODIES = 8
 FLAG_BODY_FORCE, FLAG_STREAM_ONLY, FLAG_NO_FP64, FLAG_ADJOINT = 1, 2, 4, 8
 
@@ -38,10 +39,11 @@ class Params(ctypes.Structure):
 
 
 class Body(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("center", ctypes.c_double * 3),
+    _fields_ = [("kind", ctypes.c_int32), ("motion", ctypes.c_int32), ("center", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("normal", ctypes.c_double * 3), ("amp", ctypes.c_double),
                 ("period", ctypes.c_double), ("dir", ctypes.c_double * 3), ("vel", ctypes.c_double * 3),
-                ("omega", ctypes.c_double * 3)]
+                ("omega", ctypes.c_double * 3), ("density_ratio", ctypes.c_double),
+                ("gravity", ctypes.c_double * 3)]
 
 
 class Info(ctypes.Structure):
@@ -73,6 +75,7 @@ def load():
         "elbm_write_populations": [_VP, _VP, ctypes.c_int64],
         "elbm_read_populations": [_VP, _VP],
         "elbm_set_geometry": [_VP, P(Body), ctypes.c_int32],
+        "elbm_body_state": [_VP, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)],
         "elbm_set_body_force": [_VP, _VP],
         "elbm_step": [_VP, ctypes.c_int32],
         "elbm_force": [_VP, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double), P(ctypes.c_double)],
@@ -156,6 +159,9 @@ def make_body(spec: dict) -> Body:
     b.dir[:] = [float(v) for v in spec.get("direction", (0, 0, 0))]
     b.vel[:] = [float(v) for v in spec.get("vel", (0, 0, 0))]
     b.omega[:] = [float(v) for v in spec.get("omega", (0, 0, 0))]
+    b.motion = MOTION_FREE if spec.get("motion", "prescribed") == "free" else MOTION_PRESCRIBED
+    b.density_ratio = float(spec.get("density_ratio", 0.0))
+    b.gravity[:] = [float(v) for v in spec.get("gravity", (0, 0, 0))]
     return b
 
 
@@ -195,6 +201,13 @@ def elbm_read_populations(ctx, pop_dev):
 def elbm_set_geometry(ctx, bodies):
     arr = (Body * max(1, len(bodies)))(*[make_body(b) if isinstance(b, dict) else b for b in bodies])
     _check(load().elbm_set_geometry(ctx, arr, len(bodies)), ctx)
+
+
+def elbm_body_state(ctx, body: int):
+    pos = (ctypes.c_double * 3)()
+    vel = (ctypes.c_double * 3)()
+    _check(load().elbm_body_state(ctx, int(body), pos, vel), ctx)
+    return list(pos), list(vel)
 
 
 def elbm_set_body_force(ctx, F_dev):
@@ -328,6 +341,12 @@ class Lattice:
 
     def set_bodies(self, bodies):
         elbm_set_geometry(self.ctx, list(bodies))
+
+    def body_state(self, k: int):
+        """Position and velocity of body k at the current time level (numpy arrays)."""
+        import numpy as np
+        pos, vel = elbm_body_state(self.ctx, k)
+        return np.array(pos), np.array(vel)
 
     def set_body_force(self, F):
         torch = self.torch

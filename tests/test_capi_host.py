@@ -22,7 +22,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_sizes_match_header_layout():
     # the ctypes mirrors must have the C sizes (x86-64 SysV alignment)
     assert ctypes.sizeof(elbm.Params) == 4 * 8 + 8 + 8 + 8 + 24 + 8
-    assert ctypes.sizeof(elbm.Body) == 8 + 24 + 8 + 24 + 8 + 8 + 24 + 24 + 24
+    assert ctypes.sizeof(elbm.Body) == 8 + 24 + 8 + 24 + 8 + 8 + 24 + 24 + 24 + 8 + 24
     assert ctypes.sizeof(elbm.Info) == 8 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
 
 

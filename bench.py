@@ -143,6 +143,29 @@ def adjoint_form(torch, WL):
             "loss": L, "dL_damp": gA, "dL_dF_norm": float(gF.double().norm().item())}
 
 
+def settle_form(elbm, torch, WL, steps: int = 500):
+    """Two-way coupling: a sphere (R = 10, density ratio 2) settling under gravity in a fluid at rest,
+    384 x 96 x 96 channel with the inlet wall at rest, FP32.  Every step reads the previous step's
+    force back to the host for the Euler update of the sphere."""
+    shape = (384, 96, 96)
+    rho, u = WL.uniform_flow(shape, (0.0, 0.0, 0.0))
+    lat = elbm.Lattice(shape, 0.004, channel=True, u_inlet=(0.0, 0.0, 0.0), max_bodies=1)
+    lat.init_equilibrium(rho, u)
+    lat.set_bodies([WL.free_sphere((40.0, 47.5, 47.5), 10.0, 2.0, gravity=(2e-5, 0.0, 0.0))])
+    lat.step(100)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    x, v = lat.body_state(0)
+    n = shape[0] * shape[1] * shape[2]
+    return {"MLUPS": round(n * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 4),
+            "position_x": round(float(x[0]), 4), "velocity_x": float(v[0])}
+
+
 def cpu_baseline(workload: str, budget_s: float = 15.0):
     """The FP64 oracle, unmodified, stepping the workload's own lattice on the host cores for a
     bounded number of steps (at least 2, until ~budget_s seconds of stepping)."""
@@ -176,7 +199,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--form-steps", type=int, default=100)
-    ap.add_argument("--forms", default="copy,turb512,sphere384,adj128",
+    ap.add_argument("--forms", default="copy,turb512,sphere384,settle,adj128",
                     help="comma-separated subset of the extra forms to run")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="after the headline run, copy a buffer of this many MiB 5 times (a plain copy kernel "
@@ -286,6 +309,9 @@ def main():
                                       "boundary_nodes": int(inf.boundary_nodes), "fp64_nodes_last_step": int(inf.fp64_nodes),
                                       "drag_last_step": F[0]}
             log(f"sphere384: {m:.0f} MLUPS, boundary nodes {inf.boundary_nodes}, drag {F[0]:.4e}")
+        if "settle" in which:
+            forms["settle_f32"] = settle_form(elbm, torch, WL)
+            log(f"settling sphere: {forms['settle_f32']}")
         if "adj128" in which:
             forms["adj128_adjoint"] = adjoint_form(torch, WL)
             log(f"adj128 adjoint: {forms['adj128_adjoint']}")

@@ -199,7 +199,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--form-steps", type=int, default=100)
-    ap.add_argument("--forms", default="copy,turb512,sphere384,settle,adj128",
+    ap.add_argument("--forms", default="copy,stabilisers,turb512,sphere384,settle,adj128",
                     help="comma-separated subset of the extra forms to run")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="after the headline run, copy a buffer of this many MiB 5 times (a plain copy kernel "
@@ -309,6 +309,15 @@ def main():
                                       "boundary_nodes": int(inf.boundary_nodes), "fp64_nodes_last_step": int(inf.fp64_nodes),
                                       "drag_last_step": F[0]}
             log(f"sphere384: {m:.0f} MLUPS, boundary nodes {inf.boundary_nodes}, drag {F[0]:.4e}")
+        if "stabilisers" in which:
+            # the same turb256 run with the exact stabiliser and with LBGK, for comparison
+            for name, fl in (("exact_gamma", elbm.FLAG_EXACT_GAMMA), ("lbgk", elbm.FLAG_LBGK)):
+                m, msps, gb, _, _, lat = run_form(elbm, torch, shape, w["nu"], "f32", 100, 5, init, flags=fl)
+                del lat
+                torch.cuda.empty_cache()
+                forms[f"{args.workload}_{name}"] = {"MLUPS": round(m, 1), "ms_per_step": round(msps, 4),
+                                                    "sweep_GBps": round(gb, 1)}
+                log(f"{args.workload} {name}: {m:.0f} MLUPS, sweep {gb:.0f} GB/s")
         if "settle" in which:
             forms["settle_f32"] = settle_form(elbm, torch, WL)
             log(f"settling sphere: {forms['settle_f32']}")

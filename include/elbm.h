@@ -66,6 +66,10 @@ extern "C" {
 #define ELBM_FLAG_STREAM_ONLY 2u  /* no collision: the step is the streaming permutation alone */
 #define ELBM_FLAG_NO_FP64 4u      /* disable the FP64 recomputation of near-equilibrium nodes */
 #define ELBM_FLAG_ADJOINT 8u      /* reserve workspace for elbm_adjoint_step */
+#define ELBM_FLAG_EXACT_GAMMA 16u /* stabiliser = the exact root of eq. gamma_min (Newton from the
+                                     analytic value) instead of the paper's analytic approximation;
+                                     not with ELBM_FLAG_ADJOINT */
+#define ELBM_FLAG_LBGK 32u        /* stabiliser gamma = 2 (plain LBGK), for comparisons */
 
 typedef struct elbm_params {
   int32_t nx, ny, nz;   /* lattice size, each >= 1 (channel mode: nx >= 4), N < 2^31 */
@@ -236,9 +240,10 @@ const char* elbm_last_error(const struct elbm_ctx* ctx);
 /* Context-free KBC collision of n independent nodes (Sec. II): f_in_dev, f_out_dev
  * dev [27][n] FP32, gamma_dev dev [n] FP32 (or NULL), F_dev dev [3][n] FP32 or
  * NULL.  Uses the same device code as elbm_step, FP64 recomputation included
- * unless fp64_threshold < 0.  stream: hipStream_t. */
+ * unless fp64_threshold < 0.  flags: 0, ELBM_FLAG_EXACT_GAMMA or ELBM_FLAG_LBGK
+ * (the stabiliser).  stream: hipStream_t. */
 int elbm_collide_nodes(const float* f_in_dev, float* f_out_dev, float* gamma_dev, const float* F_dev,
-                       int64_t n, double nu, double fp64_threshold, void* stream);
+                       int64_t n, double nu, double fp64_threshold, uint32_t flags, void* stream);
 
 #ifdef __cplusplus
 }

@@ -41,7 +41,7 @@ def build(force: bool = True) -> str:
 class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("channel", ctypes.c_int32), ("beta", ctypes.c_double), ("rho0", ctypes.c_double),
-                ("u_in", ctypes.c_double * 3), ("stream_only", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("u_in", ctypes.c_double * 3), ("stream_only", ctypes.c_int32), ("stabiliser", ctypes.c_int32)]
 
 
 class Body(ctypes.Structure):
@@ -55,7 +55,7 @@ class Body(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("boundary_nodes", ctypes.c_int64), ("links", ctypes.c_int64),
                 ("refill_nodes", ctypes.c_int64), ("gamma_guard", ctypes.c_int64),
-                ("gamma_min", ctypes.c_double), ("gamma_max", ctypes.c_double)]
+                ("gamma_min", ctypes.c_double), ("gamma_max", ctypes.c_double), ("exact_fallback", ctypes.c_int64)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -209,7 +209,7 @@ class Simulation:
 
     def __init__(self, shape, nu: float, rho=None, u=None, bodies=(), channel: bool = False,
                  u_in=(0.0, 0.0, 0.0), rho0: float = 1.0, F=None, beta: float | None = None,
-                 stream_only: bool = False, A0=None):
+                 stream_only: bool = False, A0=None, stabiliser: str = "kbc"):
         nx, ny, nz = shape
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
@@ -220,6 +220,7 @@ class Simulation:
         self.grid.rho0 = rho0
         self.grid.u_in[:] = list(map(float, u_in))
         self.grid.stream_only = 1 if stream_only else 0
+        self.grid.stabiliser = {"kbc": 0, "exact": 1, "lbgk": 2}[stabiliser]
         self.bodies = (Body * max(1, len(bodies)))(*[body_from_spec(b) if isinstance(b, dict) else b
                                                       for b in bodies])
         self.nb = len(bodies)

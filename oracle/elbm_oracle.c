@@ -280,7 +280,9 @@ typedef struct {
   double rho0;
   double u_in[3];
   int32_t stream_only; /* 1: skip the collision (streaming-permutation tests) */
-  int32_t pad;
+  int32_t stabiliser;  /* 0: the analytic gamma of Sec. II; 1: the exact root of eq. gamma_min
+                          (or_gamma_exact; the analytic one where no root is bracketed);
+                          2: gamma = 2 (LBGK) */
 } or_grid;
 
 typedef struct {
@@ -302,6 +304,7 @@ typedef struct {
 typedef struct {
   int64_t boundary_nodes, links, refill_nodes, gamma_guard;
   double gamma_min, gamma_max;
+  int64_t exact_fallback;  /* stabiliser 1: nodes where no positive root was bracketed */
 } or_stats;
 
 void or_kinematics(const or_body *b, double t, double c[3], double U[3]) {
@@ -665,7 +668,16 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
         if (F) for (int a = 0; a < 3; ++a) Fn[a] = F[a * N + n];
         int guard = 0;
         double gam = 2.0;
-        if (!g->stream_only) gam = or_collide_ex(f, beta, F ? Fn : 0, 0.0, &guard);
+        if (!g->stream_only) {
+          double gfix = 0.0;
+          if (g->stabiliser == 2) gfix = 2.0;
+          if (g->stabiliser == 1) {
+            const double ge = or_gamma_exact(f, beta);
+            if (isfinite(ge) && ge > 0.0) gfix = ge;
+            else cnt[4 * z + 2]++;
+          }
+          gam = or_collide_ex(f, beta, F ? Fn : 0, gfix, &guard);
+        }
         cnt[4 * z + 3] += guard;
         if (gam < gmin[z]) gmin[z] = gam;
         if (gam > gmax[z]) gmax[z] = gam;
@@ -684,6 +696,7 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
     for (int z = 0; z < g->nz; ++z) {
       st->boundary_nodes += cnt[4 * z]; st->links += cnt[4 * z + 1];
       st->gamma_guard += cnt[4 * z + 3];
+      st->exact_fallback += cnt[4 * z + 2];
       if (gmin[z] < st->gamma_min) st->gamma_min = gmin[z];
       if (gmax[z] > st->gamma_max) st->gamma_max = gmax[z];
     }

@@ -49,7 +49,7 @@ template <typename T> struct VjpOut {
 // Vector-Jacobian product of kbc_collide: g = (d f'/d f)^T gp and gF = (d f'/d F)^T gp.
 template <typename T, bool FORCE>
 __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T beta, const T Fx, const T Fy,
-                                    const T Fz, T (&g)[27], T (&gF)[3]) {
+                                    const T Fz, T (&g)[27], T (&gF)[3], bool lbgk = false) {
   T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
@@ -97,7 +97,7 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
     b += th * dh[i];
     a += th * DS(i);
   }
-  const bool guard = !(b > T(1e-30));
+  const bool guard = lbgk || !(b > T(1e-30));  // gamma fixed at 2: no derivative through it
   const T ib = T(1) / beta;
   const T gam = guard ? T(2) : ib - (T(2) - ib) * a / b;
   // reverse
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
     Fy = a.F[a.N + n];
     Fz = a.F[2 * a.N + n];
   }
-  kbc_vjp<double, FORCE>(f, gp, (double)a.beta, Fx, Fy, Fz, g, gF);
+  kbc_vjp<double, FORCE>(f, gp, (double)a.beta, Fx, Fy, Fz, g, gF, a.stab == STAB_LBGK);
 #pragma unroll
   for (int i = 0; i < 27; ++i) push_idx(a, j, P, i, y, z, (float)g[i]);
   if (FORCE && j.gF) {
@@ -389,7 +389,7 @@ __device__ inline void grad_u_vjp_one(const BArgs& a, const AdjArgs& j, const La
 // arithmetic as kbc_vjp, with every sum over directions a butterfly reduction inside the group.
 template <bool FORCE>
 __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double beta, double Fx, double Fy, double Fz,
-                                       double (&gF)[3]) {
+                                       double (&gF)[3], bool lbgk = false) {
   const bool own = lane < 27;
   const int i = own ? lane : 13;
   const double ci[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
@@ -416,7 +416,7 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
   if (!own) ds = 0.0;
   const double h = d - ds, th = own ? h / fe : 0.0;
   const double b = gsum(th * h), a = gsum(th * ds), ggh = gsum(gp * h);
-  const bool guard = !(b > 1e-30);
+  const bool guard = lbgk || !(b > 1e-30);  // gamma fixed at 2: no derivative through it
   const double ib = 1.0 / beta;
   const double gam = guard ? 2.0 : ib - (2.0 - ib) * a / b;
   // reverse
@@ -505,7 +505,8 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
       Fz = a.F[2 * a.N + n];
     }
     double gFn[3];
-    const float gi = (float)kbc_vjp_lanes<FORCE>(lane, fdi, (double)gpi, (double)a.beta, Fx, Fy, Fz, gFn);
+    const float gi =
+        (float)kbc_vjp_lanes<FORCE>(lane, fdi, (double)gpi, (double)a.beta, Fx, Fy, Fz, gFn, a.stab == STAB_LBGK);
     if (FORCE && j.gF && active && lane == 0) {
       j.gF[n] += (float)gFn[0];
       j.gF[a.N + n] += (float)gFn[1];
@@ -743,6 +744,7 @@ static BArgs bargs(elbm_ctx* c, const void* A) {
   a.channel = c->p.bc_x == ELBM_BC_CHANNEL;
   a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64);
   a.stream_only = 0;
+  a.stab = c->stab;
   a.beta = (float)c->beta;
   a.inv_beta = (float)(1.0 / c->beta);
   a.thr = (float)c->fp64_thr;

@@ -55,6 +55,7 @@ struct BArgs {
   int32_t channel;
   int32_t fp64;
   int32_t stream_only;
+  int32_t stab;  // STAB_* of the context
   float beta, inv_beta, thr;
   double rho0;
   double u_in[3];
@@ -93,6 +94,16 @@ __device__ __forceinline__ float gsum(float v) {
 __device__ __forceinline__ double gsum(double v) {
 #pragma unroll
   for (int o = GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GROUP);
+  return v;
+}
+__device__ __forceinline__ float gmax(float v) {
+#pragma unroll
+  for (int o = GROUP / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, GROUP));
+  return v;
+}
+__device__ __forceinline__ float gmin(float v) {
+#pragma unroll
+  for (int o = GROUP / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, GROUP));
   return v;
 }
 // Bit l = predicate of lane l of the calling group.
@@ -200,7 +211,7 @@ __device__ inline void grad_u_grp(const LaneNb& h, float (&G)[9]) {
 // arithmetic as kbc_collide<float>, with every sum over directions a butterfly reduction inside the
 // group.  r receives gamma, <dh|dh>, rho and the shear estimate for the FP64 rule (equal on all
 // lanes of the group).
-template <bool FORCE>
+template <bool FORCE, int STAB = STAB_KBC>
 __device__ inline float kbc_collide_lanes(int lane, float d, float beta, float inv_beta, float Fx, float Fy, float Fz,
                                           KbcOut<float>& r) {
   const bool own = lane < 27;
@@ -249,7 +260,44 @@ __device__ inline float kbc_collide_lanes(int lane, float d, float beta, float i
   const float ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
   const float th = h * ife;
   const float b = gsum(th * h), a = gsum(th * ds);
-  const float gamma = (b > 1e-30f) ? inv_beta - (2.f - inv_beta) * a / b : 2.f;
+  float gamma = (b > 1e-30f) ? inv_beta - (2.f - inv_beta) * a / b : 2.f;
+  if (STAB == STAB_LBGK) gamma = 2.f;
+  if (STAB == STAB_EXACT && b > 1e-30f) {
+    // bracketed Newton on eq. gamma_min, as in kbc_collide (sums and extrema over the group)
+    float clo = -1e6f, chi = 1e6f;
+    if (own) {
+      // argument of the logarithm = p0 + p1 g
+      const float p0 = 1.f + (h - (2.f * beta - 1.f) * ds) * ife, p1 = -beta * h * ife;
+      if (p1 > 0.f) clo = -p0 / p1;
+      else if (p1 < 0.f) chi = -p0 / p1;
+    }
+    float lo = fmaxf(gmax(clo), -1e6f), hi = fminf(gmin(chi), 1e6f);
+    if (lo < hi) {
+      float g = (gamma > lo && gamma < hi) ? gamma : 0.5f * (lo + hi);
+      for (int it = 0; it < 64; ++it) {
+        float Gl = 0.f, dGl = 0.f, Gal = 0.f;
+        const bool okl = own ? gamma_term(g, beta, h, ds, ife, Gl, dGl, Gal) : true;
+        const float G = gsum(Gl), dG = gsum(dGl), Ga = gsum(Gal);
+        const bool bad = gballot(!okl) != 0u;
+        if (!bad && fabsf(G) <= 64.f * eps_of<float>() * Ga) break;
+        float gn;
+        if (bad || !(dG < 0.f)) {
+          if (g < 0.5f * (lo + hi)) lo = g;
+          else hi = g;
+          gn = 0.5f * (lo + hi);
+        } else {
+          if (G > 0.f) lo = g;
+          else hi = g;
+          gn = g - G / dG;
+          if (!(gn > lo && gn < hi)) gn = 0.5f * (lo + hi);
+        }
+        const bool done = !(fabsf(gn - g) > 1e-6f * fabsf(gn));
+        g = gn;
+        if (done) break;
+      }
+      if (g > 0.f) gamma = g;
+    }
+  }
   const float s2 = (27.f * (sfx * sfx + sfy * sfy + sfz * sfz) + 216.f * (sxy * sxy + sxz * sxz + syz * syz)) * rinv;
   float out = d - (2.f * beta) * ds - (beta * gamma) * h;
   if (FORCE) {

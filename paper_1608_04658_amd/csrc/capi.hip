@@ -62,6 +62,10 @@ int validate(const elbm_params* p, char* err) {
   if (p->max_bodies > 0 && p->force_ring < 1) return snprintf(err, 256, "force_ring must be >= 1"), ELBM_EINVAL;
   if (!(p->nu > 0.0) || !isfinite(p->nu)) return snprintf(err, 256, "nu must be positive"), ELBM_EINVAL;
   if (p->max_boundary < 0) return snprintf(err, 256, "bad max_boundary"), ELBM_EINVAL;
+  if ((p->flags & ELBM_FLAG_EXACT_GAMMA) && (p->flags & ELBM_FLAG_LBGK))
+    return snprintf(err, 256, "ELBM_FLAG_EXACT_GAMMA and ELBM_FLAG_LBGK exclude each other"), ELBM_EINVAL;
+  if ((p->flags & ELBM_FLAG_EXACT_GAMMA) && (p->flags & ELBM_FLAG_ADJOINT))
+    return snprintf(err, 256, "the adjoint differentiates the analytic stabiliser only"), ELBM_EINVAL;
   return ELBM_OK;
 }
 
@@ -169,6 +173,7 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->N = (int64_t)p->nx * p->ny * p->nz;
   c->beta = 1.0 / (6.0 * p->nu + 1.0);
   c->fp64_thr = p->fp64_threshold > 0.0 ? p->fp64_threshold : 1e-12;
+  c->stab = (p->flags & ELBM_FLAG_EXACT_GAMMA) ? STAB_EXACT : ((p->flags & ELBM_FLAG_LBGK) ? STAB_LBGK : STAB_KBC);
   c->pop[0] = c->ws + L.pop[0];
   c->pop[1] = c->ws + L.pop[1];
   c->cur = 0;
@@ -554,12 +559,14 @@ int elbm_get_timing(elbm_ctx* c, double* sweep_ms, int64_t* launches) {
 const char* elbm_last_error(const elbm_ctx* c) { return c ? c->err : g_create_err; }
 
 int elbm_collide_nodes(const float* f_in_dev, float* f_out_dev, float* gamma_dev, const float* F_dev, int64_t n,
-                       double nu, double fp64_threshold, void* stream) {
+                       double nu, double fp64_threshold, uint32_t flags, void* stream) {
   if (!f_in_dev || !f_out_dev || n < 0 || !(nu > 0.0)) return fail(nullptr, ELBM_EINVAL, "bad arguments");
+  if ((flags & ELBM_FLAG_EXACT_GAMMA) && (flags & ELBM_FLAG_LBGK)) return fail(nullptr, ELBM_EINVAL, "bad flags");
   if (n == 0) return ELBM_OK;
   const double beta = 1.0 / (6.0 * nu + 1.0);
   const double thr = fp64_threshold < 0.0 ? -1.0 : (fp64_threshold == 0.0 ? 1e-12 : fp64_threshold);
-  hipError_t e = launch_collide_nodes(f_in_dev, f_out_dev, gamma_dev, F_dev, n, beta, thr, (hipStream_t)stream);
+  const int stab = (flags & ELBM_FLAG_EXACT_GAMMA) ? STAB_EXACT : ((flags & ELBM_FLAG_LBGK) ? STAB_LBGK : STAB_KBC);
+  hipError_t e = launch_collide_nodes(f_in_dev, f_out_dev, gamma_dev, F_dev, n, beta, thr, stab, (hipStream_t)stream);
   if (e != hipSuccess) return fail(nullptr, ELBM_EDEVICE, "collide: %s", hipGetErrorString(e));
   return ELBM_OK;
 }

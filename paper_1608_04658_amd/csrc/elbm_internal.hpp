@@ -107,6 +107,29 @@ inline size_t storage_bytes(int s) { return s == ELBM_STORAGE_F32 ? 4 : 2; }
 // Arithmetic helpers (FP32: hardware reciprocal and square root; FP64: IEEE division).
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float log1p_(float x) { return log1pf(x); }
+__device__ __forceinline__ double log1p_(double x) { return log1p(x); }
+
+// Stabiliser of the collision: the paper's analytic approximation (default), the exact root of
+// eq. gamma_min, or gamma = 2 (LBGK, for comparisons).
+constexpr int STAB_KBC = 0, STAB_EXACT = 1, STAB_LBGK = 2;
+
+// Term of direction i in the root condition of eq. gamma_min,
+//   G(g) = sum_i dh_i ln(1 + ((1 - beta g) dh_i - (2 beta - 1) ds_i) / feq_i) = 0,
+// which makes H(f') stationary along the stabiliser, and in G' = -beta sum dh_i^2 / (feq_i + ...) < 0;
+// false where the argument of the logarithm is not positive (outside the admissible interval).
+// Gabs accumulates |term|, the scale of the rounding error of G.
+template <typename T>
+__device__ __forceinline__ bool gamma_term(T g, T beta, T dh, T ds, T ife, T& G, T& dG, T& Gabs) {
+  const T x = ((T(1) - beta * g) * dh - (T(2) * beta - T(1)) * ds) * ife;
+  const T t = dh * log1p_(x);
+  G += t;
+  Gabs += fabs(t);
+  dG -= beta * dh * dh * ife / (T(1) + x);
+  return x > T(-1);
+}
+template <typename T>
+__host__ __device__ constexpr T eps_of() { return sizeof(T) == 4 ? T(1.1920928955078125e-7) : T(2.220446049250313e-16); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
 
@@ -176,11 +199,13 @@ __device__ __forceinline__ bool needs_fp64(const KbcOut<T>& r, T thr) {
 //     rest and corners: 0); the equilibrium second moments are rho (2 s_a - 1)/3 and rho u_a u_b;
 //   - dh = df - ds, with the rounding residue of its mass and momentum removed;
 //   - gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh>, <X|Y> = sum X Y / feq; gamma = 2 when
-//     <dh|dh> <= 1e-30 (then dh is zero to round-off and f' does not depend on it).
+//     <dh|dh> <= 1e-30 (then dh is zero to round-off and f' does not depend on it).  STAB selects
+//     this analytic stabiliser (the paper's choice), the exact root of eq. gamma_min (Newton from
+//     the analytic value), or gamma = 2 (LBGK).
 // Working in deviations keeps every difference between O(1) numbers out of the FP32 arithmetic.
 // FORCE adds the exact-difference body-force increment feq(rho, u + F/rho) - feq(rho, u),
 // evaluated in FP64 to avoid cancellation.
-template <typename T, bool FORCE>
+template <typename T, bool FORCE, int STAB = STAB_KBC>
 __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const T inv_beta, const T Fx, const T Fy,
                                                  const T Fz) {
   // separable raw-moment transform: (a, b, c) at c = -1, 0, +1  ->  (a+b+c, c-a, a+c)
@@ -287,7 +312,68 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
     b += th * dh[i];
     if (nnz(i) == 1 || nnz(i) == 2) a += th * ds;
   }
-  const T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * a / b : T(2);
+  T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * a / b : T(2);
+  if (STAB == STAB_LBGK) gamma = T(2);
+  if (STAB == STAB_EXACT && b > T(1e-30)) {
+    // Root of eq. gamma_min inside the admissible interval (lo, hi), where every argument of the
+    // logarithm, p0_i + p1_i g, is positive. G falls from +inf at lo to -inf at hi, so the root is
+    // unique. Newton from the analytic value (its first-order approximation) inside a bracket that
+    // shrinks with the sign of G; a step that leaves the bracket is replaced by bisection. Stops
+    // at a relative step below tol or where |G| is at the rounding level of its sum.
+    T lo = T(-1e6), hi = T(1e6);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const T ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
+      T ds = T(0);
+      if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
+      if (nnz(i) == 2) {
+        if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
+        else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
+        else ds = T(cy(i) * cz(i)) * syz;
+      }
+      const T p0 = T(1) + (dh[i] - (T(2) * beta - T(1)) * ds) * ife, p1 = -beta * dh[i] * ife;
+      if (p1 > T(0)) lo = fmax(lo, -p0 / p1);
+      else if (p1 < T(0)) hi = fmin(hi, -p0 / p1);
+    }
+    if (lo < hi) {
+      const T tol = sizeof(T) == 4 ? T(1e-6) : T(1e-13);
+      T g = (gamma > lo && gamma < hi) ? gamma : T(0.5) * (lo + hi);
+      for (int it = 0; it < 64; ++it) {
+        T G = T(0), dG = T(0), Ga = T(0);
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+          const T ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
+          T ds = T(0);
+          if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
+          if (nnz(i) == 2) {
+            if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
+            else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
+            else ds = T(cy(i) * cz(i)) * syz;
+          }
+          ok = gamma_term(g, beta, dh[i], ds, ife, G, dG, Ga) && ok;
+        }
+        // G at its rounding level: g is the root as far as the arithmetic can tell
+        if (ok && fabs(G) <= T(64) * eps_of<T>() * Ga) break;
+        T gn;
+        if (!ok || !(dG < T(0))) {
+          // rounding put an argument at or below zero: g sits at an end of the interval
+          if (g < T(0.5) * (lo + hi)) lo = g;
+          else hi = g;
+          gn = T(0.5) * (lo + hi);
+        } else {
+          if (G > T(0)) lo = g;
+          else hi = g;
+          gn = g - G / dG;
+          if (!(gn > lo && gn < hi)) gn = T(0.5) * (lo + hi);
+        }
+        const bool done = !(fabs(gn - g) > tol * fabs(gn));
+        g = gn;
+        if (done) break;
+      }
+      if (g > T(0)) gamma = g;
+    }
+  }
   // faces: W = 2/27 (2 per axis), edges: W = 1/54 (4 per plane)
   const T s2 = (T(27) * (sfx * sfx + sfy * sfy + sfz * sfz) + T(216) * (sxy * sxy + sxz * sxz + syz * syz)) * rinv;
   const T bg = beta * gamma, b2 = T(2) * beta;
@@ -436,6 +522,7 @@ struct elbm_ctx {
   } freeb[ELBM_MAX_BODIES];
   int n_free;
   bool free_force_pending;  // F of the last step is still on the device
+  int stab;         // STAB_KBC, STAB_EXACT or STAB_LBGK (from the context flags)
   bool slab_valid;  // slab_next holds U, R of the inlet slab of the current state (written by the
                     // kernels that produced it)
   float* slab_next; // channel mode: [4][nz][ny][3] staging of U, R for x < 3
@@ -459,7 +546,7 @@ hipError_t launch_init_eq(elbm_ctx* c, const double* rho, const double* u);
 hipError_t launch_write_pop(elbm_ctx* c, const double* src);
 hipError_t launch_read_pop(elbm_ctx* c, double* dst);
 hipError_t launch_collide_nodes(const float* fin, float* fout, float* gam, const float* F, int64_t n, double beta,
-                                double thr, hipStream_t s);
+                                double thr, int stab, hipStream_t s);
 hipError_t geometry_init(elbm_ctx* c);
 hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd);
 hipError_t launch_boundary(elbm_ctx* c, const Bodies& bd);

@@ -354,7 +354,7 @@ __global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, v
 // Wall nodes (Sec. III): Grad reconstruction of the missing populations, the momentum exchange of
 // each link (Sec. IV.A), then the KBC collision of the node.  One node per group of 32 lanes, one
 // direction per lane, sums over directions as butterfly reductions.
-template <int S, bool FORCE>
+template <int S, bool FORCE, int STAB>
 __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd) {
   using C = Codec<S>;
   using E = typename C::E;
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
       Fz = a.F[2 * a.N + n];
     }
     KbcOut<float> r;
-    const float fpost = kbc_collide_lanes<FORCE>(lane, fi, a.beta, a.inv_beta, Fx, Fy, Fz, r);
+    const float fpost = kbc_collide_lanes<FORCE, STAB>(lane, fi, a.beta, a.inv_beta, Fx, Fy, Fz, r);
     // <dh|dh> at the FP32 noise floor (equal on all lanes of the group): store the pre-collision
     // deviations and queue the node for the FP64 collision of k_fixup
     const bool fp64 = a.fp64 && needs_fp64(r, a.thr);
@@ -625,12 +625,21 @@ hipError_t geometry_for_step(elbm_ctx* c, const Bodies& bd) {
   return scan_box(c, union_box(c, bd), c->n_static, 1);
 }
 
-template <int S>
-static void boundary_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd) {
+template <int S, int STAB>
+static void boundary_launch_st(elbm_ctx* c, const BArgs& a, const Bodies& bd) {
   // two list entries per 64-lane workgroup
   const dim3 g((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap + 1) / 2, 1), 16384)), b(64);
-  if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true>), g, b, 0, c->stream, a, bd);
-  else hipLaunchKernelGGL((k_boundary<S, false>), g, b, 0, c->stream, a, bd);
+  if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true, STAB>), g, b, 0, c->stream, a, bd);
+  else hipLaunchKernelGGL((k_boundary<S, false, STAB>), g, b, 0, c->stream, a, bd);
+}
+
+template <int S>
+static void boundary_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd) {
+  switch (c->stab) {
+    case STAB_EXACT: boundary_launch_st<S, STAB_EXACT>(c, a, bd); break;
+    case STAB_LBGK: boundary_launch_st<S, STAB_LBGK>(c, a, bd); break;
+    default: boundary_launch_st<S, STAB_KBC>(c, a, bd);
+  }
 }
 
 BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
@@ -657,6 +666,7 @@ BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
   a.channel = channel ? 1 : 0;
   a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64);
   a.stream_only = (c->p.flags & ELBM_FLAG_STREAM_ONLY) != 0;
+  a.stab = c->stab;
   a.beta = (float)c->beta;
   a.inv_beta = (float)(1.0 / c->beta);
   a.thr = (float)c->fp64_thr;

@@ -53,7 +53,7 @@ __device__ __forceinline__ void gather_offsets(int x, int y, int z, const SweepA
     for (int j = 0; j < 3; ++j) rs[3 * k + j] = (uint32_t)((zs[k] * a.ny + ys[j]) * a.nx);
 }
 
-template <int S, bool FLAGS, bool FORCE>
+template <int S, bool FLAGS, bool FORCE, int STAB>
 __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
   using C = Codec<S>;
   using E = typename C::E;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
       Fy = a.F[a.N + n];
       Fz = a.F[2 * (size_t)a.N + n];
     }
-    const KbcOut<float> r = kbc_collide<float, FORCE>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
+    const KbcOut<float> r = kbc_collide<float, FORCE, STAB>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
     if (a.fp64 && needs_fp64(r, a.thr)) {
       const uint32_t k = atomicAdd(&a.cnt->fix_count, 1u);
       a.fix_list[k] = n;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
 // FP64 recomputation of the nodes whose <dh|dh> fell below the FP32 threshold: the same gather
 // and the same collision in double precision, rounded once on store.  The last block to finish
 // resets the queue, so the kernel can be launched every step without a host round trip.
-template <int S, bool FORCE>
+template <int S, bool FORCE, int STAB>
 __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
   using C = Codec<S>;
   using E = typename C::E;
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
       Fz = a.F[2 * (size_t)a.N + n];
     }
     const double beta = (double)a.beta;
-    kbc_collide<double, FORCE>(f, beta, 1.0 / beta, Fx, Fy, Fz);
+    kbc_collide<double, FORCE, STAB>(f, beta, 1.0 / beta, Fx, Fy, Fz);
     float out[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
@@ -215,15 +215,24 @@ static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
   grid = remap ? dim3(a.tiles, 1, 1) : dim3(a.gx, a.gy, nz);
 }
 
-template <int S>
-static hipError_t sweep_s(elbm_ctx* c, const SweepArgs& a, dim3 g, dim3 b) {
+template <int S, int STAB>
+static hipError_t sweep_st(elbm_ctx* c, const SweepArgs& a, dim3 g, dim3 b) {
   const bool flags = c->flags != nullptr;
   const bool force = c->bodyforce != nullptr;
-  if (flags && force) hipLaunchKernelGGL((k_sweep<S, true, true>), g, b, 0, c->stream, a);
-  else if (flags) hipLaunchKernelGGL((k_sweep<S, true, false>), g, b, 0, c->stream, a);
-  else if (force) hipLaunchKernelGGL((k_sweep<S, false, true>), g, b, 0, c->stream, a);
-  else hipLaunchKernelGGL((k_sweep<S, false, false>), g, b, 0, c->stream, a);
+  if (flags && force) hipLaunchKernelGGL((k_sweep<S, true, true, STAB>), g, b, 0, c->stream, a);
+  else if (flags) hipLaunchKernelGGL((k_sweep<S, true, false, STAB>), g, b, 0, c->stream, a);
+  else if (force) hipLaunchKernelGGL((k_sweep<S, false, true, STAB>), g, b, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_sweep<S, false, false, STAB>), g, b, 0, c->stream, a);
   return hipGetLastError();
+}
+
+template <int S>
+static hipError_t sweep_s(elbm_ctx* c, const SweepArgs& a, dim3 g, dim3 b) {
+  switch (c->stab) {
+    case STAB_EXACT: return sweep_st<S, STAB_EXACT>(c, a, g, b);
+    case STAB_LBGK: return sweep_st<S, STAB_LBGK>(c, a, g, b);
+    default: return sweep_st<S, STAB_KBC>(c, a, g, b);
+  }
 }
 
 hipError_t launch_sweep(elbm_ctx* c) {
@@ -237,13 +246,22 @@ hipError_t launch_sweep(elbm_ctx* c) {
   }
 }
 
-template <int S>
-static hipError_t fixup_s(elbm_ctx* c, const SweepArgs& a) {
+template <int S, int STAB>
+static hipError_t fixup_st(elbm_ctx* c, const SweepArgs& a) {
   // the queue length is known only on the device: enough workgroups for two waves per SIMD
   const dim3 g(512), b(256);
-  if (c->bodyforce) hipLaunchKernelGGL((k_fixup<S, true>), g, b, 0, c->stream, a);
-  else hipLaunchKernelGGL((k_fixup<S, false>), g, b, 0, c->stream, a);
+  if (c->bodyforce) hipLaunchKernelGGL((k_fixup<S, true, STAB>), g, b, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_fixup<S, false, STAB>), g, b, 0, c->stream, a);
   return hipGetLastError();
+}
+
+template <int S>
+static hipError_t fixup_s(elbm_ctx* c, const SweepArgs& a) {
+  switch (c->stab) {
+    case STAB_EXACT: return fixup_st<S, STAB_EXACT>(c, a);
+    case STAB_LBGK: return fixup_st<S, STAB_LBGK>(c, a);
+    default: return fixup_st<S, STAB_KBC>(c, a);
+  }
 }
 
 hipError_t launch_fixup(elbm_ctx* c) {
@@ -360,6 +378,7 @@ hipError_t launch_read_pop(elbm_ctx* c, double* dst) {
 }
 
 // Context-free collision of independent nodes (unit tests of the collision alone).
+template <int STAB>
 __global__ __launch_bounds__(256) void k_collide_nodes(const float* fin, float* fout, float* gam, const float* F,
                                                        int64_t n, float beta, float inv_beta, float thr) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
@@ -368,16 +387,16 @@ __global__ __launch_bounds__(256) void k_collide_nodes(const float* fin, float* 
     for (int i = 0; i < 27; ++i) f[i] = fin[i * n + k] - wf(i);
     const float Fx = F ? F[k] : 0.f, Fy = F ? F[n + k] : 0.f, Fz = F ? F[2 * n + k] : 0.f;
     KbcOut<float> r;
-    if (F) r = kbc_collide<float, true>(f, beta, inv_beta, Fx, Fy, Fz);
-    else r = kbc_collide<float, false>(f, beta, inv_beta, Fx, Fy, Fz);
+    if (F) r = kbc_collide<float, true, STAB>(f, beta, inv_beta, Fx, Fy, Fz);
+    else r = kbc_collide<float, false, STAB>(f, beta, inv_beta, Fx, Fy, Fz);
     float g = r.gamma;
     if (thr >= 0.f && needs_fp64(r, thr)) {
       double d[27];
 #pragma unroll
       for (int i = 0; i < 27; ++i) d[i] = (double)fin[i * n + k] - wd(i);
       KbcOut<double> r2;
-      if (F) r2 = kbc_collide<double, true>(d, (double)beta, 1.0 / (double)beta, Fx, Fy, Fz);
-      else r2 = kbc_collide<double, false>(d, (double)beta, 1.0 / (double)beta, 0.0, 0.0, 0.0);
+      if (F) r2 = kbc_collide<double, true, STAB>(d, (double)beta, 1.0 / (double)beta, Fx, Fy, Fz);
+      else r2 = kbc_collide<double, false, STAB>(d, (double)beta, 1.0 / (double)beta, 0.0, 0.0, 0.0);
 #pragma unroll
       for (int i = 0; i < 27; ++i) f[i] = (float)(d[i] + wd(i));
       g = (float)r2.gamma;
@@ -392,9 +411,14 @@ __global__ __launch_bounds__(256) void k_collide_nodes(const float* fin, float* 
 }
 
 hipError_t launch_collide_nodes(const float* fin, float* fout, float* gam, const float* F, int64_t n, double beta,
-                                double thr, hipStream_t s) {
-  hipLaunchKernelGGL(k_collide_nodes, grid_1d(n), dim3(256), 0, s, fin, fout, gam, F, n, (float)beta,
-                     (float)(1.0 / beta), (float)thr);
+                                double thr, int stab, hipStream_t s) {
+  const float b = (float)beta, ib = (float)(1.0 / beta), th = (float)thr;
+  if (stab == STAB_EXACT)
+    hipLaunchKernelGGL(k_collide_nodes<STAB_EXACT>, grid_1d(n), dim3(256), 0, s, fin, fout, gam, F, n, b, ib, th);
+  else if (stab == STAB_LBGK)
+    hipLaunchKernelGGL(k_collide_nodes<STAB_LBGK>, grid_1d(n), dim3(256), 0, s, fin, fout, gam, F, n, b, ib, th);
+  else
+    hipLaunchKernelGGL(k_collide_nodes<STAB_KBC>, grid_1d(n), dim3(256), 0, s, fin, fout, gam, F, n, b, ib, th);
   return hipGetLastError();
 }
 

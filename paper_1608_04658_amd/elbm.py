@@ -23,7 +23,7 @@ BC_PERIODIC, BC_CHANNEL = 0, 1
 BODY_SPHERE, BODY_PLANE = 0, 1
 MOTION_PRESCRIBED, MOTION_FREE = 0, 1
 MAX_BODIES = 8
-FLAG_BODY_FORCE, FLAG_STREAM_ONLY, FLAG_NO_FP64, FLAG_ADJOINT = 1, 2, 4, 8
+FLAG_BODY_FORCE, FLAG_STREAM_ONLY, FLAG_NO_FP64, FLAG_ADJOINT, FLAG_EXACT_GAMMA, FLAG_LBGK = 1, 2, 4, 8, 16, 32
 
 
 class ElbmError(RuntimeError):
@@ -82,7 +82,8 @@ def load():
         "elbm_force_history": [_VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ctypes.c_double)],
         "elbm_read_flags": [_VP, _VP],
         "elbm_get_info": [_VP, P(Info)],
-        "elbm_collide_nodes": [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _VP],
+        "elbm_collide_nodes": [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+                               _VP],
         "elbm_save_state": [_VP, _VP],
         "elbm_load_state": [_VP, _VP, ctypes.c_int64],
         "elbm_adjoint_step": [_VP, ctypes.c_int64, _VP, _VP, _VP, P(ctypes.c_double), _VP],
@@ -281,9 +282,10 @@ def elbm_last_error(ctx=None) -> str:
     return load().elbm_last_error(ctx).decode(errors="replace")
 
 
-def elbm_collide_nodes(f_in, f_out, gamma, F, n: int, nu: float, fp64_threshold: float = 0.0, stream=None):
+def elbm_collide_nodes(f_in, f_out, gamma, F, n: int, nu: float, fp64_threshold: float = 0.0, flags: int = 0,
+                       stream=None):
     _check(load().elbm_collide_nodes(_ptr(f_in), _ptr(f_out), _ptr(gamma), _ptr(F), int(n), float(nu),
-                                     float(fp64_threshold), _stream_handle(stream)))
+                                     float(fp64_threshold), int(flags), _stream_handle(stream)))
 
 
 # ----------------------------------------------------------------------------- convenience owner

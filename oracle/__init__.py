@@ -49,7 +49,10 @@ class Body(ctypes.Structure):
                 ("radius", ctypes.c_double), ("normal", ctypes.c_double * 3), ("amp", ctypes.c_double),
                 ("period", ctypes.c_double), ("dir", ctypes.c_double * 3), ("vel", ctypes.c_double * 3),
                 ("omega", ctypes.c_double * 3), ("track_t", ctypes.c_double),
-                ("track_c", (ctypes.c_double * 3) * 2), ("track_U", (ctypes.c_double * 3) * 2)]
+                ("track_c", (ctypes.c_double * 3) * 2), ("track_U", (ctypes.c_double * 3) * 2),
+                ("mesh_X", ctypes.POINTER(ctypes.c_double) * 2), ("mesh_V", ctypes.POINTER(ctypes.c_double) * 2),
+                ("mesh_tri", ctypes.POINTER(ctypes.c_int32)), ("mesh_nv", ctypes.c_int32), ("mesh_nt", ctypes.c_int32),
+                ("mesh_t", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -60,6 +63,7 @@ class Stats(ctypes.Structure):
 
 _D = ctypes.POINTER(ctypes.c_double)
 _U8 = ctypes.POINTER(ctypes.c_uint8)
+_I32 = ctypes.POINTER(ctypes.c_int32)
 
 
 def lib():
@@ -96,6 +100,17 @@ def lib():
         L.or_moments.argtypes = [ctypes.c_long, _D, _D, _D]
         L.or_lattice.argtypes = [ctypes.POINTER(ctypes.c_int32), _D]
         L.or_max_threads.restype = ctypes.c_int
+        L.or_mesh_crossing.argtypes = [_D, _D, _D, ctypes.c_double, ctypes.c_double, _D]
+        L.or_mesh_crossing.restype = ctypes.c_int
+        L.or_mesh_inside.argtypes = [_D, _I32, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.or_mesh_inside.restype = ctypes.c_int
+        L.or_ray_triangle.argtypes = [_D, _D, _D, _D, _D, _D, _D, _D]
+        L.or_ray_triangle.restype = ctypes.c_int
+        L.or_closest_on_triangle.argtypes = [_D, _D, _D, _D, _D]
+        L.or_closest_on_triangle.restype = ctypes.c_double
+        L.or_mesh_closest_velocity.argtypes = [_D, _D, _I32, ctypes.c_int, _D, _D, _D]
+        L.or_mesh_link.argtypes = [_D, _D, _I32, ctypes.c_int, _D, ctypes.c_int, _D, _D]
+        L.or_mesh_link.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -103,6 +118,11 @@ def lib():
 def _dp(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(_D)
+
+
+def _i32(a: np.ndarray):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_I32)
 
 
 def _u8(a: np.ndarray):
@@ -188,7 +208,58 @@ def make_body(kind="sphere", center=(0, 0, 0), radius=0.0, normal=(0, 0, 0), amp
 
 
 def body_from_spec(spec: dict) -> Body:
+    if spec.get("kind") == "mesh":
+        b = Body()
+        b.kind = 2
+        b.tracked = 1
+        return b
     return make_body(**spec)
+
+
+# ----------------------------------------------------------------------------- triangulated bodies
+def _mesh_arrays(verts, tris, vels=None):
+    X = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 3)
+    T = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    V = np.zeros_like(X) if vels is None else np.ascontiguousarray(vels, dtype=np.float64).reshape(-1, 3)
+    return X, T, V
+
+
+def mesh_inside(verts, tris, x, y, z) -> bool:
+    X, T, _ = _mesh_arrays(verts, tris)
+    return bool(lib().or_mesh_inside(_dp(X), _i32(T), len(T), float(x), float(y), float(z)))
+
+
+def mesh_crossing(A, B, C, y, z):
+    """x of the crossing of the +x ray through (y, z) with triangle ABC, or None."""
+    xc = np.zeros(1)
+    ok = lib().or_mesh_crossing(_dp(np.asarray(A, float)), _dp(np.asarray(B, float)), _dp(np.asarray(C, float)),
+                                float(y), float(z), _dp(xc))
+    return float(xc[0]) if ok else None
+
+
+def mesh_link(verts, tris, vels, xb, i: int):
+    """(hit, q, wall velocity) of the link of node xb in direction i."""
+    X, T, V = _mesh_arrays(verts, tris, vels)
+    q = np.zeros(1)
+    uw = np.zeros(3)
+    hit = lib().or_mesh_link(_dp(X), _dp(V), _i32(T), len(T), _dp(np.asarray(xb, float)), int(i), _dp(q), _dp(uw))
+    return bool(hit), float(q[0]), uw
+
+
+def mesh_closest_velocity(verts, tris, vels, p):
+    """(velocity, squared distance) of the surface point closest to p."""
+    X, T, V = _mesh_arrays(verts, tris, vels)
+    out = np.zeros(3)
+    d2 = np.zeros(1)
+    lib().or_mesh_closest_velocity(_dp(X), _dp(V), _i32(T), len(T), _dp(np.asarray(p, float)), _dp(out), _dp(d2))
+    return out, float(d2[0])
+
+
+def closest_on_triangle(p, A, B, C):
+    w = np.zeros(3)
+    d2 = lib().or_closest_on_triangle(_dp(np.asarray(p, float)), _dp(np.asarray(A, float)),
+                                      _dp(np.asarray(B, float)), _dp(np.asarray(C, float)), _dp(w))
+    return d2, w
 
 
 def kinematics(body: Body, t: float):
@@ -238,6 +309,14 @@ class Simulation:
                                     ab=(1.0 - 1.0 / ratio) * np.asarray(spec.get("gravity", (0, 0, 0)), float),
                                     x=np.asarray(spec["center"], float).copy(),
                                     u=np.asarray(spec.get("vel", (0, 0, 0)), float).copy(), F=np.zeros(3))
+        # triangulated bodies (Sec. IV.B): vertex positions and velocities of the current time level
+        # and, when mesh_next() was called, of the next one (else the mesh holds still)
+        self.meshes = {}
+        for k, spec in enumerate(bodies):
+            if isinstance(spec, dict) and spec.get("kind") == "mesh":
+                X, T, V = _mesh_arrays(spec["verts"], spec["tris"], spec.get("vels"))
+                ref = np.asarray(spec["center"], float) if spec.get("center") is not None else X.mean(0)
+                self.meshes[k] = dict(T=T, X=[X, X], V=[V, V], ref=[ref, ref], next=False)
         self._set_tracks()
         self.F = None if F is None else np.ascontiguousarray(F, dtype=np.float64).reshape(3, nz, ny, nx)
         self.A = np.zeros((27, nz, ny, nx))
@@ -262,8 +341,33 @@ class Simulation:
             lib().or_solid_mask(ctypes.byref(self.grid), self.bodies, self.nb, float(t), _u8(out))
         return out
 
+    def mesh_next(self, k: int, verts, vels, center=None):
+        """Vertex positions and velocities of triangulated body k at the next time level."""
+        m = self.meshes[k]
+        X, _, V = _mesh_arrays(verts, m["T"], vels)
+        assert X.shape == m["X"][0].shape
+        m["X"][1], m["V"][1] = X, V
+        m["ref"][1] = np.asarray(center, float) if center is not None else X.mean(0)
+        m["next"] = True
+
     def _set_tracks(self):
-        """Centre and velocity of each free sphere at t and t+1 (explicit Euler)."""
+        """Centre and velocity of each free sphere at t and t+1 (explicit Euler); the two mesh
+        levels of each triangulated body."""
+        for k, m in self.meshes.items():
+            b = self.bodies[k]
+            if not m["next"]:
+                m["X"][1], m["V"][1], m["ref"][1] = m["X"][0], m["V"][0], m["ref"][0]
+            for lv in range(2):
+                b.mesh_X[lv] = _dp(m["X"][lv])
+                b.mesh_V[lv] = _dp(m["V"][lv])
+                for a in range(3):
+                    b.track_c[lv][a] = m["ref"][lv][a]
+                    b.track_U[lv][a] = 0.0
+            b.mesh_tri = _i32(m["T"])
+            b.mesh_nv = len(m["X"][0])
+            b.mesh_nt = len(m["T"])
+            b.mesh_t = float(self.t)
+            b.track_t = float(self.t)
         for k, fb in self.free.items():
             b = self.bodies[k]
             x1 = fb["x"] + fb["u"]
@@ -300,6 +404,9 @@ class Simulation:
             self.t += 1
             self.forces.append(forces[: 6 * self.nb].reshape(self.nb, 6).copy() if self.nb else np.zeros((0, 6)))
             self.stats.append({k: getattr(st, k) for k, _ in Stats._fields_})
+            for m in self.meshes.values():
+                m["X"][0], m["V"][0], m["ref"][0] = m["X"][1], m["V"][1], m["ref"][1]
+                m["next"] = False
             for k, fb in self.free.items():
                 b = self.bodies[k]
                 fb["x"] = np.array([b.track_c[1][a] for a in range(3)])

@@ -286,7 +286,8 @@ typedef struct {
 } or_grid;
 
 typedef struct {
-  int32_t kind;      /* 0: sphere, 1: half-space bounded by a plane */
+  int32_t kind;      /* 0: sphere, 1: half-space bounded by a plane, 2: closed triangulated
+                        surface (the deforming bodies of Sec. IV.B) */
   int32_t tracked;   /* 1: centre and velocity come from the track below (a freely moving body
                         whose motion the caller integrates), not from the prescribed motion */
   double p0[3];      /* sphere centre, or a point of the plane, at t = 0 */
@@ -299,6 +300,14 @@ typedef struct {
   double track_t;         /* tracked: the time level t of track_c[0], track_U[0] */
   double track_c[2][3];   /* tracked: centre at t and t + 1 */
   double track_U[2][3];   /* tracked: translational velocity at t and t + 1 */
+  /* kind 2: vertex positions and velocities [nv][3] at the time levels mesh_t (index 0) and
+     mesh_t + 1 (index 1), triangles [nt][3] (vertex indices).  The centre used for the torque is
+     the track (tracked = 1). */
+  const double *mesh_X[2];
+  const double *mesh_V[2];
+  const int32_t *mesh_tri;
+  int32_t mesh_nv, mesh_nt;
+  double mesh_t;
 } or_body;
 
 typedef struct {
@@ -338,10 +347,225 @@ static void rigid_velocity(const or_body *b, const double c[3], const double U[3
   out[2] = U[2] + (w[0] * r[1] - w[1] * r[0]);
 }
 
+/* Velocity of body b at the point x at time level t: rigid motion, or for a triangulated body the
+ * velocity of the closest surface point. */
+static int mesh_level(const or_body *b, double t);
+void or_mesh_closest_velocity(const double *X, const double *V, const int32_t *tri, int nt, const double p[3],
+                              double out[3], double *dist2);
+static void body_velocity(const or_body *b, const double c[3], const double U[3], double t, const double x[3],
+                          double out[3]) {
+  if (b->kind == 2) {
+    const int lv = mesh_level(b, t);
+    out[0] = out[1] = out[2] = 0.0;
+    if (lv >= 0) or_mesh_closest_velocity(b->mesh_X[lv], b->mesh_V[lv], b->mesh_tri, b->mesh_nt, x, out, 0);
+    return;
+  }
+  rigid_velocity(b, c, U, x, out);
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Triangulated bodies (Sec. IV.B: the swimmer is a triangulated surface; the wall velocity at
+ * the link intersections is the barycentric interpolation of the vertex velocities).
+ * Readings (the paper gives no algorithm for these):
+ *  - inside: a node is solid iff a ray from it along +x crosses the surface an odd number of
+ *    times.  A triangle is crossed iff the node's (y, z) lies in its projection onto the y-z
+ *    plane; points on a projected edge or vertex belong to exactly one of the triangles sharing
+ *    it (half-plane rule on the edge direction), so rays through edges and vertices count each
+ *    surface crossing once; triangles with zero projected area are not crossed.  The crossing
+ *    is at x_c = (w0 x_A + w1 x_B + w2 x_C) / (w0 + w1 + w2) with the projected edge functions
+ *    w, and counts iff x_c > x.  FP64, operations in the written order, no fused multiply-add.
+ *  - link fraction: q_i = the smallest s in (0, 1] at which the segment x_b - s c_i meets a
+ *    triangle (ray-triangle intersection with barycentric coordinates u, v of the hit), the
+ *    wall velocity (1 - u - v) V_A + u V_B + v V_C; where rounding lets the segment slip between
+ *    triangles, q = 1/2 and the velocity of the surface point closest to x_b - c_i / 2.
+ *  - velocity of the body at a node (solid nodes of U^t, refill): that of the closest surface
+ *    point, barycentric in its triangle; ties go to the lowest triangle index. */
+static double edge_fn(const double *a, const double *b, double py, double pz) {
+  double l = (b[1] - a[1]) * (pz - a[2]);
+  double r = (b[2] - a[2]) * (py - a[1]);
+  return l - r;
+}
+
+/* half-plane rule: an edge a -> b of a positively oriented projected triangle owns the points on
+ * it iff its direction has dz > 0, or dz = 0 and dy < 0 */
+static int edge_owns(const double *a, const double *b) {
+  double dy = b[1] - a[1], dz = b[2] - a[2];
+  return dz > 0.0 || (dz == 0.0 && dy < 0.0);
+}
+
+int or_mesh_crossing(const double A[3], const double B0[3], const double C0[3], double y, double z, double *xc) {
+  const double *B = B0, *C = C0;
+  double area = edge_fn(A, B, C[1], C[2]);
+  if (area == 0.0) return 0;
+  if (area < 0.0) { B = C0; C = B0; }
+  double w0 = edge_fn(B, C, y, z), w1 = edge_fn(C, A, y, z), w2 = edge_fn(A, B, y, z);
+  if (w0 < 0.0 || (w0 == 0.0 && !edge_owns(B, C))) return 0;
+  if (w1 < 0.0 || (w1 == 0.0 && !edge_owns(C, A))) return 0;
+  if (w2 < 0.0 || (w2 == 0.0 && !edge_owns(A, B))) return 0;
+  double num = w0 * A[0];
+  num = num + w1 * B[0];
+  num = num + w2 * C[0];
+  double den = w0 + w1;
+  den = den + w2;
+  *xc = num / den;
+  return 1;
+}
+
+int or_mesh_inside(const double *X, const int32_t *tri, int nt, double x, double y, double z) {
+  int odd = 0;
+  for (int k = 0; k < nt; ++k) {
+    double xc;
+    if (or_mesh_crossing(X + 3 * tri[3 * k], X + 3 * tri[3 * k + 1], X + 3 * tri[3 * k + 2], y, z, &xc) && xc > x)
+      odd ^= 1;
+  }
+  return odd;
+}
+
+static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static double dot3(const double *a, const double *b) { double s = a[0] * b[0]; s = s + a[1] * b[1]; return s + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Ray o + s d against triangle (A, B, C): returns 1 with s and the barycentric weights (u, v)
+ * of B and C when the ray meets the triangle (u, v >= 0, u + v <= 1), via the solution of
+ * o + s d = A + u (B - A) + v (C - A) by Cramer's rule with scalar triple products. */
+int or_ray_triangle(const double o[3], const double d[3], const double *A, const double *B, const double *C,
+                    double *s, double *u, double *v) {
+  double e1[3], e2[3], p[3], tv[3], qv[3];
+  sub3(B, A, e1);
+  sub3(C, A, e2);
+  cross3(d, e2, p);
+  double det = dot3(e1, p);
+  if (det == 0.0) return 0;
+  double inv = 1.0 / det;
+  sub3(o, A, tv);
+  double uu = dot3(tv, p) * inv;
+  if (uu < 0.0 || uu > 1.0) return 0;
+  cross3(tv, e1, qv);
+  double vv = dot3(d, qv) * inv;
+  if (vv < 0.0 || uu + vv > 1.0) return 0;
+  *s = dot3(e2, qv) * inv;
+  *u = uu;
+  *v = vv;
+  return 1;
+}
+
+/* Closest point of triangle (A, B, C) to p: the orthogonal projection onto its plane when that
+ * lies inside (barycentric weights from the 2x2 Gram system of the edges), else the closest point
+ * on its three edges.  Returns the squared distance and the weights (wa, wb, wc). */
+double or_closest_on_triangle(const double p[3], const double *A, const double *B, const double *C, double w[3]) {
+  double e1[3], e2[3], ap[3];
+  sub3(B, A, e1);
+  sub3(C, A, e2);
+  sub3(p, A, ap);
+  double d00 = dot3(e1, e1), d01 = dot3(e1, e2), d11 = dot3(e2, e2);
+  double d20 = dot3(ap, e1), d21 = dot3(ap, e2);
+  double den = d00 * d11 - d01 * d01;
+  if (den > 0.0) {
+    double lb = (d11 * d20 - d01 * d21) / den;
+    double lc = (d00 * d21 - d01 * d20) / den;
+    double la = 1.0 - lb - lc;
+    if (la >= 0.0 && lb >= 0.0 && lc >= 0.0) {
+      double q[3], r[3];
+      for (int a = 0; a < 3; ++a) q[a] = A[a] + lb * e1[a] + lc * e2[a];
+      sub3(p, q, r);
+      w[0] = la; w[1] = lb; w[2] = lc;
+      return dot3(r, r);
+    }
+  }
+  /* edges P0 -> P1 with the weight indices of their end points */
+  const double *P[3][2] = {{A, B}, {B, C}, {C, A}};
+  const int idx[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+  double best = INFINITY;
+  for (int e = 0; e < 3; ++e) {
+    double d[3], r0[3];
+    sub3(P[e][1], P[e][0], d);
+    sub3(p, P[e][0], r0);
+    double dd = dot3(d, d);
+    double tau = dd > 0.0 ? dot3(r0, d) / dd : 0.0;
+    if (tau < 0.0) tau = 0.0;
+    if (tau > 1.0) tau = 1.0;
+    double q[3], r[3];
+    for (int a = 0; a < 3; ++a) q[a] = P[e][0][a] + tau * d[a];
+    sub3(p, q, r);
+    double d2 = dot3(r, r);
+    if (d2 < best) {
+      best = d2;
+      w[0] = w[1] = w[2] = 0.0;
+      w[idx[e][0]] = 1.0 - tau;
+      w[idx[e][1]] = tau;
+    }
+  }
+  return best;
+}
+
+static void bary_velocity(const double *V, const int32_t *t3, const double w[3], double out[3]) {
+  const double *va = V + 3 * t3[0], *vb = V + 3 * t3[1], *vc = V + 3 * t3[2];
+  for (int a = 0; a < 3; ++a) {
+    double s = w[0] * va[a];
+    s = s + w[1] * vb[a];
+    out[a] = s + w[2] * vc[a];
+  }
+}
+
+/* Velocity of the surface point closest to p (lowest triangle index among equals). */
+void or_mesh_closest_velocity(const double *X, const double *V, const int32_t *tri, int nt, const double p[3],
+                              double out[3], double *dist2) {
+  double best = INFINITY, bw[3] = {1.0, 0.0, 0.0};
+  int bk = 0;
+  for (int k = 0; k < nt; ++k) {
+    double w[3];
+    const int32_t *t3 = tri + 3 * k;
+    double d2 = or_closest_on_triangle(p, X + 3 * t3[0], X + 3 * t3[1], X + 3 * t3[2], w);
+    if (d2 < best) { best = d2; bk = k; bw[0] = w[0]; bw[1] = w[1]; bw[2] = w[2]; }
+  }
+  if (nt > 0) bary_velocity(V, tri + 3 * bk, bw, out);
+  else out[0] = out[1] = out[2] = 0.0;
+  if (dist2) *dist2 = best;
+}
+
+/* Link of the fluid node xb in direction i against the surface: returns 1 with q and the wall
+ * velocity for a hit in (0, 1], else 0 with the fallback values. */
+int or_mesh_link(const double *X, const double *V, const int32_t *tri, int nt, const double xb[3], int i, double *q,
+                 double uw[3]) {
+  double d[3] = {-(double)cxi(i), -(double)cyi(i), -(double)czi(i)};
+  double best = INFINITY, bu = 0.0, bv = 0.0;
+  int bk = -1;
+  for (int k = 0; k < nt; ++k) {
+    const int32_t *t3 = tri + 3 * k;
+    double s, u, v;
+    if (!or_ray_triangle(xb, d, X + 3 * t3[0], X + 3 * t3[1], X + 3 * t3[2], &s, &u, &v)) continue;
+    if (!(s > 0.0 && s <= 1.0)) continue;
+    if (s < best) { best = s; bk = k; bu = u; bv = v; }
+  }
+  if (bk >= 0) {
+    double w[3] = {1.0 - bu - bv, bu, bv};
+    *q = best;
+    bary_velocity(V, tri + 3 * bk, w, uw);
+    return 1;
+  }
+  double mid[3] = {xb[0] + 0.5 * d[0], xb[1] + 0.5 * d[1], xb[2] + 0.5 * d[2]};
+  *q = 0.5;
+  or_mesh_closest_velocity(X, V, tri, nt, mid, uw, 0);
+  return 0;
+}
+
+static int mesh_level(const or_body *b, double t) {
+  return t == b->mesh_t ? 0 : (t == b->mesh_t + 1.0 ? 1 : -1);
+}
+
 /* Inside test.  Reading: a node is solid iff it lies strictly inside the body:
  * |x - c|^2 < R^2 for a sphere, n.(x - c) < 0 for a plane, both evaluated in
  * FP64 with the operations in the order written and no fused multiply-add. */
-static int inside(const or_body *b, const double c[3], double x, double y, double z) {
+static int inside(const or_body *b, const double c[3], double t, double x, double y, double z) {
+  if (b->kind == 2) {
+    const int lv = mesh_level(b, t);
+    return lv >= 0 && or_mesh_inside(b->mesh_X[lv], b->mesh_tri, b->mesh_nt, x, y, z);
+  }
   if (b->kind == 0) {
     double dx = x - c[0], dy = y - c[1], dz = z - c[2];
     double d2 = dx * dx;
@@ -367,7 +591,7 @@ void or_solid_mask(const or_grid *g, const or_body *bodies, int nb, double t, ui
     int x = (int)(n % g->nx), y = (int)((n / g->nx) % g->ny), z = (int)(n / ((long)g->nx * g->ny));
     uint8_t v = 0;
     for (int k = 0; k < nb && !v; ++k)
-      if (inside(&bodies[k], c[k], x, y, z)) v = (uint8_t)(k + 1);
+      if (inside(&bodies[k], c[k], t, x, y, z)) v = (uint8_t)(k + 1);
     out[n] = v;
   }
 }
@@ -381,6 +605,11 @@ void or_solid_mask(const or_grid *g, const or_body *bodies, int nb, double t, ui
  * n.(x_b - c) / n.c_i.  No clamping (a frozen-topology run may move the
  * surface slightly past the node; a negative discriminant is taken as 0). */
 double or_q(const or_body *b, const double c[3], const double xb[3], int i) {
+  if (b->kind == 2) {  /* the later of the two time levels, as the step uses it */
+    double q = 0.5, uw[3];
+    or_mesh_link(b->mesh_X[1], b->mesh_V[1], b->mesh_tri, b->mesh_nt, xb, i, &q, uw);
+    return q;
+  }
   double v[3] = {cxi(i), cyi(i), czi(i)};
   double d[3] = {xb[0] - c[0], xb[1] - c[1], xb[2] - c[2]};
   if (b->kind == 0) {
@@ -465,7 +694,7 @@ void or_macro(const or_grid *g, const or_body *bodies, int nb, double t, const d
       int k = solid_t[n] - 1;
       double xp[3] = {(double)(n % g->nx), (double)((n / g->nx) % g->ny), (double)(n / ((long)g->nx * g->ny))};
       double v[3];
-      rigid_velocity(&bodies[k], c[k], Ub[k], xp, v);
+      body_velocity(&bodies[k], c[k], Ub[k], t, xp, v);
       for (int a = 0; a < 3; ++a) U[a * N + n] = v[a];
       R[n] = g->rho0;
       continue;
@@ -507,7 +736,7 @@ void or_refill_state(const or_grid *g, const or_body *bodies, int nb, double t, 
     const double xb[3] = {x, y, z};
     const int k = solid_t[n] - 1;
     double uw[3];
-    rigid_velocity(&bodies[k], c1[k], U1[k], xb, uw);
+    body_velocity(&bodies[k], c1[k], U1[k], t + 1.0, xb, uw);
     double rs = 0.0;
     int m = 0;
     for (int i = 0; i < NQ; ++i) {
@@ -591,7 +820,7 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
         double f[NQ];
         {
           int inD[NQ], bodyof[NQ];
-          double q[NQ];
+          double q[NQ], uwm[NQ][3];  /* uwm: wall velocity of links into a triangulated body */
           int nD = 0;
           for (int i = 0; i < NQ; ++i) {
             inD[i] = 0; bodyof[i] = -1; q[i] = 0;
@@ -610,7 +839,15 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
             }
             if (solid_t1[src]) {
               inD[i] = 1; bodyof[i] = solid_t1[src] - 1;
-              q[i] = or_q(&bodies[bodyof[i]], c1[bodyof[i]], xb, i);
+              const or_body *bb = &bodies[bodyof[i]];
+              if (bb->kind == 2) {
+                const int lv = mesh_level(bb, t + 1.0);
+                q[i] = 0.5;
+                uwm[i][0] = uwm[i][1] = uwm[i][2] = 0.0;
+                if (lv >= 0) or_mesh_link(bb->mesh_X[lv], bb->mesh_V[lv], bb->mesh_tri, bb->mesh_nt, xb, i, &q[i], uwm[i]);
+              } else {
+                q[i] = or_q(bb, c1[bodyof[i]], xb, i);
+              }
               ++nD;
               continue;
             }
@@ -623,6 +860,8 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
               rstat += Aw[opp(i) * N + n];
               if (bodyof[i] < 0) {
                 for (int a = 0; a < 3; ++a) uw[i][a] = g->u_in[a];
+              } else if (bodies[bodyof[i]].kind == 2) {
+                for (int a = 0; a < 3; ++a) uw[i][a] = uwm[i][a];
               } else {
                 double xw[3] = {xb[0] - q[i] * cxi(i), xb[1] - q[i] * cyi(i), xb[2] - q[i] * czi(i)};
                 rigid_velocity(&bodies[bodyof[i]], c1[bodyof[i]], U1[bodyof[i]], xw, uw[i]);

@@ -733,7 +733,7 @@ static BArgs bargs(elbm_ctx* c, const void* A) {
   a.dyn_count = &c->cnt->dyn_count;
   a.brec = c->brec;
   a.fix_list = nullptr;  // the adjoint kernels queue nothing
-  a.cnt = c->cnt;
+  a.fix_count = nullptr;
   a.n_static = c->n_static;
   a.cap = c->blist_cap;
   a.moving = c->moving ? 1 : 0;

@@ -45,8 +45,8 @@ struct BArgs {
   const int32_t* list;
   const uint32_t* dyn_count;
   double* brec;
-  uint32_t* fix_list;  // FP64 fix-up queue (wall nodes enter it tagged FIX_PRE)
-  DevCounters* cnt;
+  uint32_t* fix_list;   // FP64 fix-up queue (wall nodes enter it tagged FIX_PRE)
+  uint32_t* fix_count;  // its length for this step
   int64_t n_static;
   int64_t cap;
   int32_t moving;

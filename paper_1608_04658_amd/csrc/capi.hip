@@ -403,6 +403,7 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
     }
     if (geo) HIP_OK(c, launch_boundary(c, bd));
     HIP_OK(c, launch_fixup(c));  // bulk and wall nodes queued for the FP64 collision
+    c->fix_par ^= 1;
     if (geo) HIP_OK(c, launch_force_reduce(c));
     if (c->n_free) {
       // advance the free bodies to the time level just produced; its force is read at the next step
@@ -481,7 +482,7 @@ int elbm_get_info(elbm_ctx* c, elbm_info* out) {
   DevCounters h;
   HIP_OK(c, hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
   out->boundary_nodes = c->flags ? c->n_static + (c->moving ? (int64_t)h.dyn_count : 0) : 0;
-  out->fp64_nodes = h.fix_total;
+  out->fp64_nodes = h.fix_count[c->fix_par ^ 1];
   return ELBM_OK;
 }
 

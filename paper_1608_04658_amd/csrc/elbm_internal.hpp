@@ -468,12 +468,13 @@ __host__ __device__ inline bool inside_body(const BodyDev& b, const double* c, d
 // ---------------------------------------------------------------------------------------------
 // Device-resident counters.
 struct DevCounters {
-  uint32_t fix_count;     // nodes queued for FP64 recomputation this step
-  uint32_t fix_ticket;    // last-block ticket of the fix-up kernel
-  uint32_t fix_total;     // nodes recomputed during the last step (copied at the end)
+  // FP64 fix-up queue lengths of the steps of even and odd parity: a step appends to its own and
+  // its fix-up kernel clears the other one, which the next step then uses (no host round trip,
+  // no grid-wide ticket); the last step's length stays readable until the next fix-up
+  uint32_t fix_count[2];
   uint32_t dyn_count;     // dynamic boundary nodes this step
   uint32_t overflow;      // boundary list overflowed (sticky)
-  uint32_t pad[3];
+  uint32_t pad[4];
 };
 
 struct Box {
@@ -509,6 +510,7 @@ struct elbm_ctx {
   double* force_partial;   // [64][MAX_BODIES][6] partial sums of the force reduction
   int32_t* fix_list;       // N
   elbm::DevCounters* cnt;
+  int fix_par;             // parity of the FP64 queue counter of the next step (DevCounters::fix_count)
   double* scratch64;       // small FP64 scratch (force sums)
   const float* bodyforce;
   // geometry state

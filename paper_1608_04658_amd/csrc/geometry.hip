@@ -428,7 +428,7 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
     // deviations and queue the node for the FP64 collision of k_fixup
     const bool fp64 = a.fp64 && needs_fp64(r, a.thr);
     if (active && lane < 27) C::store_dev(B + (long)lane * a.N + n, fp64 ? fi : fpost);
-    if (fp64 && active && lane == 0) a.fix_list[atomicAdd(&a.cnt->fix_count, 1u)] = (uint32_t)n | FIX_PRE;
+    if (fp64 && active && lane == 0) a.fix_list[atomicAdd(a.fix_count, 1u)] = (uint32_t)n | FIX_PRE;
     // inlet slab: U, R of the new state, summed in direction order on the group's first lane
     sh[g][lane] = fpost;
     __syncthreads();
@@ -654,7 +654,7 @@ BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
   a.dyn_count = &c->cnt->dyn_count;
   a.brec = c->brec;
   a.fix_list = (uint32_t*)c->fix_list;
-  a.cnt = c->cnt;
+  a.fix_count = &c->cnt->fix_count[c->fix_par];
   a.slab_next = (channel && !(c->p.flags & ELBM_FLAG_STREAM_ONLY)) ? c->slab_next : nullptr;
   a.n_static = c->n_static;
   a.cap = c->blist_cap;

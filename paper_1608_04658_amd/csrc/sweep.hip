@@ -16,7 +16,8 @@ struct SweepArgs {
   const uint8_t* flags;
   const float* F;
   uint32_t* fix_list;
-  DevCounters* cnt;
+  uint32_t* fix_count;  // this step's FP64 queue length
+  uint32_t* fix_clear;  // the other parity's, cleared by the fix-up kernel for the next step
   float* slab_next;  // [4][nz][ny][3] staging of U, R for x < 3 (written when slab is set)
   int32_t nx, ny, nz;
   uint32_t N;
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
     }
     const KbcOut<float> r = kbc_collide<float, FORCE, STAB>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
     if (a.fp64 && needs_fp64(r, a.thr)) {
-      const uint32_t k = atomicAdd(&a.cnt->fix_count, 1u);
+      const uint32_t k = atomicAdd(a.fix_count, 1u);
       a.fix_list[k] = n;
     }
     if (FLAGS && a.slab && x < 3)
@@ -110,13 +111,15 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
 }
 
 // FP64 recomputation of the nodes whose <dh|dh> fell below the FP32 threshold: the same gather
-// and the same collision in double precision, rounded once on store.  The last block to finish
-// resets the queue, so the kernel can be launched every step without a host round trip.
+// and the same collision in double precision, rounded once on store.  The queue length of the
+// other parity is cleared here for the next step, so the kernel is launched every step without a
+// host round trip.
 template <int S, bool FORCE, int STAB>
 __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
   using C = Codec<S>;
   using E = typename C::E;
-  const uint32_t count = __atomic_load_n(&a.cnt->fix_count, __ATOMIC_RELAXED);
+  const uint32_t count = __atomic_load_n(a.fix_count, __ATOMIC_RELAXED);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.fix_clear = 0u;
   const E* __restrict__ A = (const E*)a.A;
   E* __restrict__ B = (E*)a.B;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
@@ -158,17 +161,6 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
                                 slab_index(xn, yn, zn, a.ny));
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t t = atomicAdd(&a.cnt->fix_ticket, 1u);
-    if (t == gridDim.x - 1) {
-      a.cnt->fix_total = count;
-      a.cnt->fix_count = 0;
-      a.cnt->fix_ticket = 0;
-      __threadfence();
-    }
-  }
 }
 
 static SweepArgs sweep_args(elbm_ctx* c) {
@@ -178,7 +170,8 @@ static SweepArgs sweep_args(elbm_ctx* c) {
   a.flags = c->flags;
   a.F = c->bodyforce;
   a.fix_list = (uint32_t*)c->fix_list;
-  a.cnt = c->cnt;
+  a.fix_count = &c->cnt->fix_count[c->fix_par];
+  a.fix_clear = &c->cnt->fix_count[c->fix_par ^ 1];
   a.nx = c->p.nx;
   a.ny = c->p.ny;
   a.nz = c->p.nz;

@@ -58,6 +58,8 @@ extern "C" {
 
 #define ELBM_BODY_SPHERE 0
 #define ELBM_BODY_PLANE 1    /* solid half-space n.(x - c) < 0, normal pointing into the fluid */
+#define ELBM_BODY_MESH 2     /* closed triangulated surface set by elbm_set_mesh (at most one per
+                                context, last in the body array; see elbm_set_mesh) */
 
 #define ELBM_MAX_BODIES 8
 
@@ -84,6 +86,8 @@ typedef struct elbm_params {
   double u_inlet[3];    /* ELBM_BC_CHANNEL inlet velocity */
   double fp64_threshold;/* nodes with <dh|dh> < thr*rho and <ds|ds> >= thr*rho get the
                            collision recomputed in FP64; 0 = 1e-12 */
+  int32_t max_mesh_vertices;  /* capacity for one triangulated body (0 = none) */
+  int32_t max_mesh_triangles;
 } elbm_params;
 
 /* A rigid body with prescribed motion (Sec. III).  Every quantity is evaluated
@@ -168,6 +172,39 @@ int elbm_read_populations(struct elbm_ctx* ctx, double* pop_dev);
  * and compute the solid mask at the current time level.  In channel mode a body
  * must stay at least 6 nodes away from the inlet and outlet faces. */
 int elbm_set_geometry(struct elbm_ctx* ctx, const elbm_body* bodies, int32_t nb);
+
+/* Triangulated body (the deforming geometries of Sec. IV.B: a closed triangulated surface whose
+ * wall velocity at each link intersection is the barycentric interpolation of its vertex
+ * velocities).  Sets the surface at the current time level: tris_dev dev [nt][3] int32 vertex
+ * indices; verts_dev, vels_dev dev [nv][3] FP64 positions and velocities (vels_dev NULL = at rest);
+ * box_lo, box_hi host double[3]: a box the surface stays inside for the whole run (it bounds the
+ * per-step mask and list work; a vertex outside it makes the next elbm_force/elbm_force_history
+ * fail with ELBM_ENOSPACE); center: host double[3], the point torques are taken about (NULL = the
+ * box centre).  The arrays are copied on the context's stream.  Call before elbm_set_geometry
+ * with a body of kind ELBM_BODY_MESH (its other fields are ignored), which must be the last body.
+ * Definitions (FP64, operations in the written order, no fused multiply-add):
+ *  - a node is solid iff the ray from it along +x crosses the surface an odd number of times; a
+ *    triangle is crossed iff the node's (y, z) lies in its projection onto the y-z plane, points on
+ *    a projected edge belonging to that edge's triangle iff the edge direction of the positively
+ *    oriented projection has dz > 0, or dz = 0 and dy < 0; triangles of zero projected area are
+ *    never crossed; the crossing is at x_c = (w0 x_A + w1 x_B + w2 x_C)/(w0 + w1 + w2) (projected
+ *    edge functions w) and counts iff x_c > x;
+ *  - link fraction q_i: the smallest s in (0, 1] where x - s c_i meets a triangle (ray-triangle
+ *    intersection solved by scalar triple products), the wall velocity barycentric there; if
+ *    rounding lets the segment pass between triangles, q = 1/2 and the velocity of the surface
+ *    point closest to x - c_i/2;
+ *  - velocity of the body at a node (refill, solid nodes' U^t): that of the closest surface point
+ *    within the neighbouring cells of a grid of spacing >= 2 (0 if none; nodes where it is used lie
+ *    within one lattice spacing of the surface).
+ * The surface must stay at least 3 nodes inside every face.  Not with ELBM_FLAG_ADJOINT. */
+int elbm_set_mesh(struct elbm_ctx* ctx, const int32_t* tris_dev, int32_t nt, const double* verts_dev,
+                  const double* vels_dev, int32_t nv, const double box_lo[3], const double box_hi[3],
+                  const double center[3]);
+
+/* The triangulated body's vertex positions and velocities (same layout, the nv vertices of
+ * elbm_set_mesh, same triangles) at the next time level, t+1, for the next step.  Without a call before a step the surface keeps its current
+ * level (positions and velocities).  center: host double[3] or NULL (keep). */
+int elbm_mesh_next(struct elbm_ctx* ctx, const double* verts_dev, const double* vels_dev, const double center[3]);
 
 /* Position and velocity of body `body` at the current time level (host arrays of 3):
  * the prescribed motion evaluated at t, or the integrated state of a free body. */

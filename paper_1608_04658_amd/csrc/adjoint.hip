@@ -495,7 +495,7 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
     const uint32_t dmask = h.dbar;
     WallLane w;
     w.mine = false;
-    if (dmask) wall_targets(a, bd, h, lane, w);
+    if (dmask) wall_targets<false>(a, bd, h, lane, w);
     // collision input: f*_i (absolute) where missing, else the pulled deviation widened exactly
     const double fdi = lane < 27 ? (((dmask >> lane) & 1u) ? (double)w.fs : wd(i) + (double)h.f) : 0.0;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;

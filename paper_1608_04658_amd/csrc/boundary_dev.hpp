@@ -4,6 +4,7 @@
 #pragma once
 
 #include "elbm_internal.hpp"
+#include "mesh_dev.hpp"
 
 namespace elbm {
 
@@ -24,6 +25,14 @@ __device__ __forceinline__ int first_body(const Bodies& bd, bool at_t1, double x
   for (int k = 0; k < bd.nb; ++k)
     if (inside_body(bd.b[k], at_t1 ? bd.b[k].c1 : bd.b[k].c0, x, y, z)) return k;
   return -1;
+}
+
+// Body owning a node known to be solid: the first analytic body containing it, else the
+// triangulated body (which comes last in the body array), else body 0.
+__device__ __forceinline__ int owner_body(const Bodies& bd, bool at_t1, double x, double y, double z) {
+  const int k = first_body(bd, at_t1, x, y, z);
+  if (k >= 0) return k;
+  return bd.mesh >= 0 ? bd.mesh : 0;
 }
 
 // Periodic index for any offset (stencils reach +-2, lattices may be 1 or 2 nodes thick); the
@@ -321,6 +330,9 @@ __device__ inline float kbc_collide_lanes(int lane, float d, float beta, float i
 // owning body (-1 for the inlet wall at x = -1/2).  q is the ray parameter where x - s c_i meets
 // the surface (FP64): sphere (|d|^2 - R^2)/(d.c_i + sqrt((d.c_i)^2 - |c_i|^2 (|d|^2 - R^2))),
 // plane n.d / n.c_i, d = x - centre(t+1).
+// MESH: the body set may hold a triangulated body (a separate instantiation keeps its register
+// cost out of the analytic-body kernels).
+template <bool MESH>
 __device__ inline void link_geometry(const BArgs& a, const Bodies& bd, int i, int x, int y, int z, double& q, double (&uw)[3],
                               int& kb) {
   int sx = x - cx(i);
@@ -335,9 +347,13 @@ __device__ inline void link_geometry(const BArgs& a, const Bodies& bd, int i, in
   if (a.channel) sx = sx >= a.nx ? a.nx - 1 : sx;
   else sx = wrap(sx, a.nx);
   const int sy = wrap(y - cy(i), a.ny), sz = wrap(z - cz(i), a.nz);
-  kb = first_body(bd, true, sx, sy, sz);
-  if (kb < 0) kb = 0;
+  kb = MESH ? owner_body(bd, true, sx, sy, sz) : max(first_body(bd, true, sx, sy, sz), 0);
   const BodyDev& b = bd.b[kb];
+  if (MESH && b.kind == ELBM_BODY_MESH) {
+    const double xb[3] = {(double)x, (double)y, (double)z};
+    mesh_link(bd.m, xb, i, q, uw);
+    return;
+  }
   const double v[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
   const double d[3] = {x - b.c1[0], y - b.c1[1], z - b.c1[2]};
   if (b.kind == ELBM_BODY_SPHERE) {
@@ -376,13 +392,14 @@ struct WallLane {
   int nD;        // number of missing populations
 };
 
+template <bool MESH>
 __device__ inline void wall_targets(const BArgs& a, const Bodies& bd, const LaneNb& h, int lane, WallLane& w) {
   const int i = lane < 27 ? lane : 13;
   w.mine = lane < 27 && ((h.dbar >> lane) & 1u);
   w.q = 0.0;
   w.uw[0] = w.uw[1] = w.uw[2] = 0.0;
   w.kb = -1;
-  if (w.mine) link_geometry(a, bd, i, h.x, h.y, h.z, w.q, w.uw, w.kb);
+  if (w.mine) link_geometry<MESH>(a, bd, i, h.x, h.y, h.z, w.q, w.uw, w.kb);
   w.fb = __shfl(h.fo, opp(i), GROUP);
   float tu[3] = {0.f, 0.f, 0.f}, trs = 0.f, trd = 0.f;
   if (w.mine) {

@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "elbm_internal.hpp"
@@ -36,7 +37,8 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t pop[2], cnt, fix_list, flags, macro, slab, blist, brec, ring, force_partial, scratch, scan_tmp, adj_gUR, adj_side,
-      adj_gamp, total;
+      adj_gamp, mesh_tri, mesh_X[2], mesh_V[2], mesh_start[2], mesh_items[2], mesh_cursor, total;
+  int64_t mesh_cap;
   int64_t scan_blocks;
   int64_t cap;
   bool geometry;
@@ -66,6 +68,15 @@ int validate(const elbm_params* p, char* err) {
     return snprintf(err, 256, "ELBM_FLAG_EXACT_GAMMA and ELBM_FLAG_LBGK exclude each other"), ELBM_EINVAL;
   if ((p->flags & ELBM_FLAG_EXACT_GAMMA) && (p->flags & ELBM_FLAG_ADJOINT))
     return snprintf(err, 256, "the adjoint differentiates the analytic stabiliser only"), ELBM_EINVAL;
+  if (p->max_mesh_vertices < 0 || p->max_mesh_triangles < 0 || p->max_mesh_triangles > (1 << 24) ||
+      p->max_mesh_vertices > (1 << 24))
+    return snprintf(err, 256, "bad mesh capacity"), ELBM_EINVAL;
+  if ((p->max_mesh_triangles > 0) != (p->max_mesh_vertices > 0))
+    return snprintf(err, 256, "mesh capacity needs both vertices and triangles"), ELBM_EINVAL;
+  if (p->max_mesh_triangles > 0 && p->max_bodies < 1)
+    return snprintf(err, 256, "a triangulated body needs max_bodies >= 1"), ELBM_EINVAL;
+  if (p->max_mesh_triangles > 0 && (p->flags & ELBM_FLAG_ADJOINT))
+    return snprintf(err, 256, "no triangulated bodies with the adjoint"), ELBM_EINVAL;
   return ELBM_OK;
 }
 
@@ -104,6 +115,18 @@ Layout layout(const elbm_params* p) {
     L.adj_gUR = take(sizeof(double) * 4 * N);
     L.adj_side = take(sizeof(float) * 9 * (size_t)p->ny * p->nz);
     L.adj_gamp = take(sizeof(double) * ELBM_MAX_BODIES);
+  }
+  if (p->max_mesh_triangles > 0) {
+    const size_t nv = (size_t)p->max_mesh_vertices, nt = (size_t)p->max_mesh_triangles;
+    L.mesh_cap = 16 * (int64_t)nt + 4096;  // triangle-in-cell entries per time level
+    L.mesh_tri = take(sizeof(int32_t) * 3 * nt);
+    for (int s = 0; s < 2; ++s) {
+      L.mesh_X[s] = take(sizeof(double) * 3 * nv);
+      L.mesh_V[s] = take(sizeof(double) * 3 * nv);
+      L.mesh_start[s] = take(sizeof(int32_t) * (MESH_CELLS + 1));
+      L.mesh_items[s] = take(sizeof(int32_t) * (size_t)L.mesh_cap);
+    }
+    L.mesh_cursor = take(sizeof(int32_t) * MESH_CELLS);
   }
   L.total = off;
   return L;
@@ -192,6 +215,22 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->adj_gUR = adj ? (double*)(c->ws + L.adj_gUR) : nullptr;
   c->adj_side = adj ? (float*)(c->ws + L.adj_side) : nullptr;
   c->adj_gamp = adj ? (double*)(c->ws + L.adj_gamp) : nullptr;
+  const bool mesh = p->max_mesh_triangles > 0;
+  c->mesh_body = -1;
+  c->mesh_set = false;
+  c->mesh_nv = c->mesh_nt = 0;
+  c->mesh_cur = 0;
+  c->mesh_next_set = false;
+  c->mesh_grid = MeshDev{};
+  c->mesh_cap = mesh ? L.mesh_cap : 0;
+  c->mesh_tri = mesh ? (int32_t*)(c->ws + L.mesh_tri) : nullptr;
+  c->mesh_cursor = mesh ? (int32_t*)(c->ws + L.mesh_cursor) : nullptr;
+  for (int s = 0; s < 2; ++s) {
+    c->mesh_X[s] = mesh ? (double*)(c->ws + L.mesh_X[s]) : nullptr;
+    c->mesh_V[s] = mesh ? (double*)(c->ws + L.mesh_V[s]) : nullptr;
+    c->mesh_start[s] = mesh ? (int32_t*)(c->ws + L.mesh_start[s]) : nullptr;
+    c->mesh_items[s] = mesh ? (int32_t*)(c->ws + L.mesh_items[s]) : nullptr;
+  }
   c->blist_cap = L.cap;
   c->scan_tmp = L.geometry ? (uint32_t*)(c->ws + L.scan_tmp) : nullptr;
   c->scan_blocks = L.geometry ? L.scan_blocks : 0;
@@ -290,6 +329,13 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
   bool moving = false;
   for (int k = 0; k < nb; ++k) {
     const elbm_body& b = bodies[k];
+    if (b.kind == ELBM_BODY_MESH) {
+      if (!c->mesh_set) return fail(c, ELBM_ESTATE, "body %d: no triangulated surface set (elbm_set_mesh)", k);
+      if (k != nb - 1) return fail(c, ELBM_EINVAL, "body %d: the triangulated body must be the last body", k);
+      if (b.motion != ELBM_MOTION_PRESCRIBED) return fail(c, ELBM_EINVAL, "body %d: a triangulated body moves as given", k);
+      moving = true;
+      continue;
+    }
     if (b.kind != ELBM_BODY_SPHERE && b.kind != ELBM_BODY_PLANE) return fail(c, ELBM_EINVAL, "body %d: bad kind", k);
     if (b.motion != ELBM_MOTION_PRESCRIBED && b.motion != ELBM_MOTION_FREE)
       return fail(c, ELBM_EINVAL, "body %d: bad motion", k);
@@ -320,6 +366,7 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
     moving = moving || body_moves(b);
   }
   c->nb = nb;
+  c->mesh_body = (nb > 0 && bodies[nb - 1].kind == ELBM_BODY_MESH) ? nb - 1 : -1;
   c->n_free = 0;
   c->free_force_pending = false;
   for (int k = 0; k < ELBM_MAX_BODIES; ++k) c->freeb[k].on = false;
@@ -347,6 +394,73 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
   return ELBM_OK;
 }
 
+int elbm_set_mesh(elbm_ctx* c, const int32_t* tris_dev, int32_t nt, const double* verts_dev, const double* vels_dev,
+                  int32_t nv, const double box_lo[3], const double box_hi[3], const double center[3]) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->mesh_tri) return fail(c, ELBM_ESTATE, "context created without mesh capacity");
+  if (!tris_dev || !verts_dev || !box_lo || !box_hi) return fail(c, ELBM_EINVAL, "NULL argument");
+  if (nt < 1 || nt > c->p.max_mesh_triangles || nv < 3 || nv > c->p.max_mesh_vertices)
+    return fail(c, ELBM_EINVAL, "nt = %d, nv = %d outside the capacity (%d, %d)", nt, nv, c->p.max_mesh_triangles,
+                c->p.max_mesh_vertices);
+  const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
+  double ext[3];
+  for (int a = 0; a < 3; ++a) {
+    const double m = (a == 0 && c->p.bc_x == ELBM_BC_CHANNEL) ? 6.0 : 3.0;
+    if (!(box_lo[a] < box_hi[a]) || !(box_lo[a] >= m) || !(box_hi[a] <= dims[a] - 1.0 - m))
+      return fail(c, ELBM_EINVAL, "mesh box must lie %s nodes inside the faces", c->p.bc_x == ELBM_BC_CHANNEL ? "3 (6 in x)" : "3");
+    ext[a] = box_hi[a] - box_lo[a];
+  }
+  // cells of spacing h >= 2 with one cell of margin on every side, at most MESH_CELLS of them
+  double h = 2.0;
+  int dim[3];
+  for (int it = 0; it < 64; ++it) {
+    long n = 1;
+    for (int a = 0; a < 3; ++a) {
+      dim[a] = (int)floor(ext[a] / h) + 3;
+      n *= dim[a];
+    }
+    if (n <= MESH_CELLS) break;
+    h *= 1.25;
+  }
+  if ((long)dim[0] * dim[1] * dim[2] > MESH_CELLS) return fail(c, ELBM_EINVAL, "mesh box too large for the cell grid");
+  MeshDev& g = c->mesh_grid;
+  g = MeshDev{};
+  g.inv_h = 1.0 / h;
+  g.ncell = dim[0] * dim[1] * dim[2];
+  for (int a = 0; a < 3; ++a) {
+    g.dim[a] = dim[a];
+    g.org[a] = box_lo[a] - h;
+    // the node region of the mask and the list: the whole grid
+    c->mesh_lo[a] = g.org[a];
+    c->mesh_hi[a] = g.org[a] + dim[a] * h;
+  }
+  c->mesh_nt = nt;
+  c->mesh_nv = nv;
+  c->mesh_cur = 0;
+  c->mesh_next_set = false;
+  for (int a = 0; a < 3; ++a) {
+    const double r = center ? center[a] : 0.5 * (box_lo[a] + box_hi[a]);
+    c->mesh_ref[0][a] = c->mesh_ref[1][a] = r;
+  }
+  g.cap = (int32_t)std::min<int64_t>(c->mesh_cap, INT32_MAX);
+  HIP_OK(c, mesh_copy_tris(c, tris_dev, nt));
+  HIP_OK(c, mesh_upload(c, 0, verts_dev, vels_dev));
+  c->mesh_set = true;
+  return ELBM_OK;
+}
+
+// verts_dev / vels_dev hold the nv vertices of elbm_set_mesh (their size cannot be checked here).
+int elbm_mesh_next(elbm_ctx* c, const double* verts_dev, const double* vels_dev, const double center[3]) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->mesh_set) return fail(c, ELBM_ESTATE, "no triangulated surface set");
+  if (!verts_dev) return fail(c, ELBM_EINVAL, "verts_dev is NULL");
+  const int s1 = c->mesh_cur ^ 1;
+  HIP_OK(c, mesh_upload(c, s1, verts_dev, vels_dev));
+  for (int a = 0; a < 3; ++a) c->mesh_ref[s1][a] = center ? center[a] : c->mesh_ref[c->mesh_cur][a];
+  c->mesh_next_set = true;
+  return ELBM_OK;
+}
+
 int elbm_body_state(elbm_ctx* c, int32_t body, double pos[3], double vel[3]) {
   if (!c) return ELBM_EINVAL;
   if (body < 0 || body >= c->nb || !pos || !vel) return fail(c, ELBM_EINVAL, "bad arguments");
@@ -354,6 +468,11 @@ int elbm_body_state(elbm_ctx* c, int32_t body, double pos[3], double vel[3]) {
     for (int a = 0; a < 3; ++a) {
       pos[a] = c->freeb[body].x[a];
       vel[a] = c->freeb[body].u[a];
+    }
+  } else if (body == c->mesh_body) {
+    for (int a = 0; a < 3; ++a) {
+      pos[a] = c->mesh_ref[c->mesh_cur][a];
+      vel[a] = 0.0;
     }
   } else {
     host_kinematics(c->bodies[body], (double)c->t, pos, vel);
@@ -416,6 +535,10 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
       }
       c->free_force_pending = true;
     }
+    if (c->mesh_next_set) {
+      c->mesh_cur ^= 1;
+      c->mesh_next_set = false;
+    }
     c->cur ^= 1;
     c->t += 1;
     // the sweep, the wall kernel and the fix-up staged U, R of the new state's inlet slab
@@ -435,7 +558,10 @@ int elbm_force_history(elbm_ctx* c, int32_t body, int64_t first, int32_t count, 
   HIP_OK(c, hipStreamSynchronize(c->stream));
   uint32_t ov = 0;
   HIP_OK(c, hipMemcpy(&ov, &c->cnt->overflow, sizeof ov, hipMemcpyDeviceToHost));
-  if (ov) return fail(c, ELBM_ENOSPACE, "boundary list overflowed its capacity (%lld)", (long long)c->blist_cap);
+  if (ov & 1u) return fail(c, ELBM_ENOSPACE, "boundary list overflowed its capacity (%lld)", (long long)c->blist_cap);
+  if (ov & 2u) return fail(c, ELBM_ENOSPACE, "a mesh vertex left the declared box, or the mesh grid is full");
+  if (ov & 4u) return fail(c, ELBM_ENOSPACE, "a lattice row crosses the mesh more than 32 times");
+  if (ov & 8u) return fail(c, ELBM_EINVAL, "a mesh triangle has a vertex index outside [0, nv)");
   for (int32_t k = 0; k < count; ++k) {
     const int64_t step = first + k;
     const int slot = (int)(step % ring);

@@ -443,15 +443,46 @@ struct BodyDev {
   double omega[3];
 };
 
+// Triangulated body: vertex data of one time level, binned into a uniform grid of cells (spacing
+// h >= 2) by triangle bounding box; cell c lists items[start[c] .. start[c+1]).
+struct MeshLevel {
+  const double* X;       // [nv][3] positions
+  const double* V;       // [nv][3] velocities
+  const int32_t* start;  // [ncell + 1]
+  const int32_t* items;  // triangle indices
+};
+
+struct MeshDev {
+  const int32_t* tri;  // [nt][3]
+  int32_t nt;
+  int32_t ncell;
+  double org[3];       // corner of cell (0, 0, 0)
+  double inv_h;
+  int32_t dim[3];
+  int32_t cap;         // capacity of items (entries past it, after an overflow, are not read)
+  MeshLevel lv[2];     // time levels t and t+1
+};
+
+// Grid cell of coordinate v along axis a (clamped to the grid): monotone in v, so a triangle's
+// bounding box covers the cell of every point of the triangle.
+__host__ __device__ inline int mesh_cell(const MeshDev& m, int a, double v) {
+  int c = (int)floor((v - m.org[a]) * m.inv_h);
+  c = c < 0 ? 0 : c;
+  return c > m.dim[a] - 1 ? m.dim[a] - 1 : c;
+}
+
 struct Bodies {
   int32_t nb;
-  int32_t pad;
+  int32_t mesh;  // index of the triangulated body, -1 if none
   BodyDev b[ELBM_MAX_BODIES];
+  MeshDev m;
 };
 
 // Strictly-inside test (FP64, operations in the written order, no contraction).
+// (A triangulated body is never inside here: its mask comes from the crossing count.)
 __host__ __device__ inline bool inside_body(const BodyDev& b, const double* c, double x, double y, double z) {
 #pragma clang fp contract(off)
+  if (b.kind == ELBM_BODY_MESH) return false;
   if (b.kind == ELBM_BODY_SPHERE) {
     const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
     double d2 = dx * dx;
@@ -473,7 +504,9 @@ struct DevCounters {
   // no grid-wide ticket); the last step's length stays readable until the next fix-up
   uint32_t fix_count[2];
   uint32_t dyn_count;     // dynamic boundary nodes this step
-  uint32_t overflow;      // boundary list overflowed (sticky)
+  uint32_t overflow;      // sticky: 1 boundary list, 2 mesh vertex outside its box or grid full,
+                          // 4 more crossings on a lattice row than the mask kernel holds,
+                          // 8 mesh vertex index out of range
   uint32_t pad[4];
 };
 
@@ -525,6 +558,23 @@ struct elbm_ctx {
   int n_free;
   bool free_force_pending;  // F of the last step is still on the device
   int stab;         // STAB_KBC, STAB_EXACT or STAB_LBGK (from the context flags)
+  // triangulated body (elbm_set_mesh): slot mesh_cur holds time level t; slot mesh_cur ^ 1 level
+  // t+1 when mesh_next_set (else level t+1 = level t)
+  int mesh_body;           // body index, -1 if none
+  bool mesh_set;
+  int32_t mesh_nv, mesh_nt;
+  int mesh_cur;
+  bool mesh_next_set;
+  double mesh_ref[2][3];   // torque centre per slot
+  double mesh_lo[3], mesh_hi[3];
+  elbm::MeshDev mesh_grid; // grid geometry (pointers of slot 0/1 filled per use)
+  int32_t* mesh_tri;
+  double* mesh_X[2];
+  double* mesh_V[2];
+  int32_t* mesh_start[2];
+  int32_t* mesh_items[2];
+  int32_t* mesh_cursor;    // [MESH_CELLS] binning counters
+  int64_t mesh_cap;        // items per slot
   bool slab_valid;  // slab_next holds U, R of the inlet slab of the current state (written by the
                     // kernels that produced it)
   float* slab_next; // channel mode: [4][nz][ny][3] staging of U, R for x < 3
@@ -563,4 +613,8 @@ Box union_box(const elbm_ctx* c, const Bodies& bd);
 Box full_box(const elbm_ctx* c);
 dim3 grid_for(long n);
 Bodies make_bodies(const elbm_ctx* c, double t);
+constexpr int MESH_CELLS = 1 << 16;
+hipError_t mesh_upload(elbm_ctx* c, int slot, const double* X, const double* V);
+hipError_t mesh_copy_tris(elbm_ctx* c, const int32_t* tris, int32_t nt);
+hipError_t mesh_mask(elbm_ctx* c, const Bodies& bd, int level, uint8_t bits);
 }  // namespace elbm

@@ -40,12 +40,39 @@ void host_kinematics(const elbm_body& b, double t, double c[3], double U[3]) {
 Bodies make_bodies(const elbm_ctx* c, double t) {
   Bodies bd;
   bd.nb = c->nb;
-  bd.pad = 0;
+  bd.mesh = c->mesh_body;
+  bd.m = MeshDev{};
+  if (c->mesh_body >= 0) {
+    // level t in slot mesh_cur; level t+1 in the other slot once elbm_mesh_next supplied it
+    const int s0 = c->mesh_cur, s1 = c->mesh_next_set ? c->mesh_cur ^ 1 : c->mesh_cur;
+    bd.m = c->mesh_grid;
+    bd.m.tri = c->mesh_tri;
+    bd.m.nt = c->mesh_nt;
+    const int sl[2] = {s0, s1};
+    for (int l = 0; l < 2; ++l) {
+      bd.m.lv[l].X = c->mesh_X[sl[l]];
+      bd.m.lv[l].V = c->mesh_V[sl[l]];
+      bd.m.lv[l].start = c->mesh_start[sl[l]];
+      bd.m.lv[l].items = c->mesh_items[sl[l]];
+    }
+  }
   for (int k = 0; k < c->nb; ++k) {
     const elbm_body& b = c->bodies[k];
     BodyDev& d = bd.b[k];
     d.kind = b.kind;
     d.pad = 0;
+    if (b.kind == ELBM_BODY_MESH) {
+      const int s1 = c->mesh_next_set ? c->mesh_cur ^ 1 : c->mesh_cur;
+      for (int a = 0; a < 3; ++a) {
+        d.c0[a] = c->mesh_ref[c->mesh_cur][a];
+        d.c1[a] = c->mesh_ref[s1][a];
+        d.U0[a] = d.U1[a] = 0.0;
+        d.n[a] = d.omega[a] = 0.0;
+      }
+      d.radius = 0.0;
+      d.r2 = 0.0;
+      continue;
+    }
     if (c->freeb[k].on) {
       // explicit Euler of Newton's equations from the state at the context's time level
       const auto& fb = c->freeb[k];
@@ -78,7 +105,12 @@ Box union_box(const elbm_ctx* c, const Bodies& bd) {
   bool full[3] = {false, false, false};
   for (int k = 0; k < bd.nb; ++k) {
     const BodyDev& b = bd.b[k];
-    if (b.kind == ELBM_BODY_SPHERE) {
+    if (b.kind == ELBM_BODY_MESH) {
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fmin(lo[a], c->mesh_lo[a] - BOX_MARGIN);
+        hi[a] = fmax(hi[a], c->mesh_hi[a] + BOX_MARGIN);
+      }
+    } else if (b.kind == ELBM_BODY_SPHERE) {
       for (int a = 0; a < 3; ++a) {
         lo[a] = fmin(lo[a], fmin(b.c0[a], b.c1[a]) - b.radius - BOX_MARGIN);
         hi[a] = fmax(hi[a], fmax(b.c0[a], b.c1[a]) + b.radius + BOX_MARGIN);
@@ -268,7 +300,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_emit(GeoArgs g, int skip_in
 
 // Previous-step macroscopic field U^t, R^t on a box: moments of A^t with U = (j - F/2)/rho at
 // nodes fluid at t; rigid-body velocity (R = rho0) at nodes solid at t.
-template <int S>
+template <int S, bool MESH>
 __global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, float* macro, const float* F, Box box,
                         int32_t nx, int32_t ny, int64_t N, double rho0, Bodies bd) {
   using C = Codec<S>;
@@ -279,13 +311,19 @@ __global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, flo
     const long n = ((long)z * ny + y) * nx + x;
     float U[3], R;
     if (flags[n] & FL_SOLID_PREV) {
-      int k = first_body(bd, false, x, y, z);
-      if (k < 0) k = 0;
+      const int k = MESH ? owner_body(bd, false, x, y, z) : max(first_body(bd, false, x, y, z), 0);
       const BodyDev& b = bd.b[k];
-      const double r[3] = {x - b.c0[0], y - b.c0[1], z - b.c0[2]};
-      U[0] = (float)(b.U0[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
-      U[1] = (float)(b.U0[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
-      U[2] = (float)(b.U0[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+      if (MESH && b.kind == ELBM_BODY_MESH) {
+        const double p[3] = {(double)x, (double)y, (double)z};
+        double v[3];
+        mesh_closest_velocity(bd.m, 0, p, v);
+        for (int a = 0; a < 3; ++a) U[a] = (float)v[a];
+      } else {
+        const double r[3] = {x - b.c0[0], y - b.c0[1], z - b.c0[2]};
+        U[0] = (float)(b.U0[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
+        U[1] = (float)(b.U0[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
+        U[2] = (float)(b.U0[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+      }
       R = (float)rho0;
     } else {
       float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;  // from the stored deviations f - W
@@ -319,7 +357,7 @@ __global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, flo
 // Refill before streaming: the uncovered nodes of the step get their Grad populations written into
 // the current buffer A^t, where their neighbours (and the node itself) pull them.  One node per
 // group of 32 lanes; only the dynamic (body) part of the list can hold uncovered nodes.
-template <int S>
+template <int S, bool MESH>
 __global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, void* Aw) {
   using C = Codec<S>;
   using E = typename C::E;
@@ -332,14 +370,21 @@ __global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, v
     if (!(a.flags[n] & FL_SOLID_PREV)) continue;  // uniform over the group
     LaneNb h;
     lane_gather<S, false, true>(a, A, n, lane, h);
-    int kb = first_body(bd, false, h.x, h.y, h.z);
-    if (kb < 0) kb = 0;
+    const int kb = MESH ? owner_body(bd, false, h.x, h.y, h.z) : max(first_body(bd, false, h.x, h.y, h.z), 0);
     const BodyDev& b = bd.b[kb];
-    const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
     float uw[3];
-    uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
-    uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
-    uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+    if (MESH && b.kind == ELBM_BODY_MESH) {
+      // the body's velocity at the node: that of the closest surface point at t+1
+      const double p[3] = {(double)h.x, (double)h.y, (double)h.z};
+      double v[3];
+      mesh_closest_velocity(bd.m, 1, p, v);
+      for (int a = 0; a < 3; ++a) uw[a] = (float)v[a];
+    } else {
+      const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
+      uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
+      uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
+      uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+    }
     const uint32_t nbm = h.fluid0 & ~(1u << 13);
     const float rs = gsum(lane != 13 ? h.R : 0.f);
     const int m = __popc(nbm);
@@ -354,7 +399,7 @@ __global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, v
 // Wall nodes (Sec. III): Grad reconstruction of the missing populations, the momentum exchange of
 // each link (Sec. IV.A), then the KBC collision of the node.  One node per group of 32 lanes, one
 // direction per lane, sums over directions as butterfly reductions.
-template <int S, bool FORCE, int STAB>
+template <int S, bool FORCE, int STAB, bool MESH>
 __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd) {
   using C = Codec<S>;
   using E = typename C::E;
@@ -381,7 +426,7 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
     const uint32_t dmask = h.dbar;
     if (dmask) {  // missing populations at a wall (Sec. III); uniform over the group
       WallLane w;
-      wall_targets(a, bd, h, lane, w);
+      wall_targets<MESH>(a, bd, h, lane, w);
       double dF[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       if (w.mine) {
         fi = w.fs - wf(i);
@@ -496,9 +541,14 @@ static GeoArgs geo_args(elbm_ctx* c, const Box& box) {
 
 template <int S>
 static void macro_launch(elbm_ctx* c, const void* A, const Box& box, const Bodies& bd) {
-  hipLaunchKernelGGL(k_macro<S>, grid_for(box.count()), dim3(256), 0, c->stream, (const typename Codec<S>::E*)A,
-                     (const uint8_t*)c->flags, c->macro, c->bodyforce, box, c->p.nx, c->p.ny, (int64_t)c->N,
-                     c->p.rho0, bd);
+  if (bd.mesh >= 0)
+    hipLaunchKernelGGL((k_macro<S, true>), grid_for(box.count()), dim3(256), 0, c->stream,
+                       (const typename Codec<S>::E*)A, (const uint8_t*)c->flags, c->macro, c->bodyforce, box, c->p.nx,
+                       c->p.ny, (int64_t)c->N, c->p.rho0, bd);
+  else
+    hipLaunchKernelGGL((k_macro<S, false>), grid_for(box.count()), dim3(256), 0, c->stream,
+                       (const typename Codec<S>::E*)A, (const uint8_t*)c->flags, c->macro, c->bodyforce, box, c->p.nx,
+                       c->p.ny, (int64_t)c->N, c->p.rho0, bd);
 }
 
 static void macro_box(elbm_ctx* c, const void* A, const Box& box, const Bodies& bd) {
@@ -557,6 +607,10 @@ hipError_t geometry_init(elbm_ctx* c) {
   hipLaunchKernelGGL(k_flags_init, grid_for(fb.count()), dim3(256), 0, c->stream, g, bd);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (c->mesh_body >= 0) {
+    e = mesh_mask(c, bd, 0, FL_SOLID | FL_SOLID_PREV);
+    if (e != hipSuccess) return e;
+  }
   Box sb = fb;
   const bool channel = c->p.bc_x == ELBM_BC_CHANNEL;
   if (c->moving) {
@@ -590,6 +644,10 @@ hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd) {
   if (c->moving) {
     GeoArgs g = geo_args(c, ub);
     hipLaunchKernelGGL(k_flags_update, grid_for(ub.count()), dim3(256), 0, c->stream, g, bd);
+    if (c->mesh_body >= 0) {
+      const hipError_t em = mesh_mask(c, bd, 1, FL_SOLID);
+      if (em != hipSuccess) return em;
+    }
     const hipError_t e = scan_box(c, ub, c->n_static, 1);
     if (e != hipSuccess) return e;
   }
@@ -629,8 +687,11 @@ template <int S, int STAB>
 static void boundary_launch_st(elbm_ctx* c, const BArgs& a, const Bodies& bd) {
   // two list entries per 64-lane workgroup
   const dim3 g((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap + 1) / 2, 1), 16384)), b(64);
-  if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true, STAB>), g, b, 0, c->stream, a, bd);
-  else hipLaunchKernelGGL((k_boundary<S, false, STAB>), g, b, 0, c->stream, a, bd);
+  const bool mesh = bd.mesh >= 0;
+  if (c->bodyforce && mesh) hipLaunchKernelGGL((k_boundary<S, true, STAB, true>), g, b, 0, c->stream, a, bd);
+  else if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true, STAB, false>), g, b, 0, c->stream, a, bd);
+  else if (mesh) hipLaunchKernelGGL((k_boundary<S, false, STAB, true>), g, b, 0, c->stream, a, bd);
+  else hipLaunchKernelGGL((k_boundary<S, false, STAB, false>), g, b, 0, c->stream, a, bd);
 }
 
 template <int S>
@@ -680,10 +741,19 @@ hipError_t launch_refill(elbm_ctx* c, const Bodies& bd, void* A) {
   const BArgs a = boundary_args(c, A, nullptr);
   const int64_t dyn = a.cap - a.n_static;
   const dim3 g((unsigned)std::min<int64_t>(std::max<int64_t>((dyn + 1) / 2, 1), 4096)), b(64);
+  const bool mesh = bd.mesh >= 0;
   switch (c->p.storage) {
-    case ELBM_STORAGE_F32: hipLaunchKernelGGL(k_refill<ELBM_STORAGE_F32>, g, b, 0, c->stream, a, bd, A); break;
-    case ELBM_STORAGE_F16: hipLaunchKernelGGL(k_refill<ELBM_STORAGE_F16>, g, b, 0, c->stream, a, bd, A); break;
-    default: hipLaunchKernelGGL(k_refill<ELBM_STORAGE_BF16>, g, b, 0, c->stream, a, bd, A);
+    case ELBM_STORAGE_F32:
+      if (mesh) hipLaunchKernelGGL((k_refill<ELBM_STORAGE_F32, true>), g, b, 0, c->stream, a, bd, A);
+      else hipLaunchKernelGGL((k_refill<ELBM_STORAGE_F32, false>), g, b, 0, c->stream, a, bd, A);
+      break;
+    case ELBM_STORAGE_F16:
+      if (mesh) hipLaunchKernelGGL((k_refill<ELBM_STORAGE_F16, true>), g, b, 0, c->stream, a, bd, A);
+      else hipLaunchKernelGGL((k_refill<ELBM_STORAGE_F16, false>), g, b, 0, c->stream, a, bd, A);
+      break;
+    default:
+      if (mesh) hipLaunchKernelGGL((k_refill<ELBM_STORAGE_BF16, true>), g, b, 0, c->stream, a, bd, A);
+      else hipLaunchKernelGGL((k_refill<ELBM_STORAGE_BF16, false>), g, b, 0, c->stream, a, bd, A);
   }
   return hipGetLastError();
 }

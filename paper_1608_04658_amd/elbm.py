@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "elbm.h")
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 BC_PERIODIC, BC_CHANNEL = 0, 1
-BODY_SPHERE, BODY_PLANE = 0, 1
+BODY_SPHERE, BODY_PLANE, BODY_MESH = 0, 1, 2
 MOTION_PRESCRIBED, MOTION_FREE = 0, 1
 MAX_BODIES = 8
 FLAG_BODY_FORCE, FLAG_STREAM_ONLY, FLAG_NO_FP64, FLAG_ADJOINT, FLAG_EXACT_GAMMA, FLAG_LBGK = 1, 2, 4, 8, 16, 32
@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("max_bodies", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("force_ring", ctypes.c_int32), ("max_boundary", ctypes.c_int64),
                 ("nu", ctypes.c_double), ("rho0", ctypes.c_double), ("u_inlet", ctypes.c_double * 3),
-                ("fp64_threshold", ctypes.c_double)]
+                ("fp64_threshold", ctypes.c_double), ("max_mesh_vertices", ctypes.c_int32),
+                ("max_mesh_triangles", ctypes.c_int32)]
 
 
 class Body(ctypes.Structure):
@@ -75,6 +76,9 @@ def load():
         "elbm_write_populations": [_VP, _VP, ctypes.c_int64],
         "elbm_read_populations": [_VP, _VP],
         "elbm_set_geometry": [_VP, P(Body), ctypes.c_int32],
+        "elbm_set_mesh": [_VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double),
+                          P(ctypes.c_double)],
+        "elbm_mesh_next": [_VP, _VP, _VP, P(ctypes.c_double)],
         "elbm_body_state": [_VP, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)],
         "elbm_set_body_force": [_VP, _VP],
         "elbm_step": [_VP, ctypes.c_int32],
@@ -133,7 +137,8 @@ def _stream_handle(stream=None) -> int:
 
 
 def make_params(shape, nu, storage="f32", channel=False, max_bodies=0, flags=0, force_ring=4096, max_boundary=0,
-                rho0=1.0, u_inlet=(0.0, 0.0, 0.0), fp64_threshold=0.0) -> Params:
+                rho0=1.0, u_inlet=(0.0, 0.0, 0.0), fp64_threshold=0.0, max_mesh_vertices=0,
+                max_mesh_triangles=0) -> Params:
     p = Params()
     p.nx, p.ny, p.nz = (int(v) for v in shape)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
@@ -146,12 +151,14 @@ def make_params(shape, nu, storage="f32", channel=False, max_bodies=0, flags=0, 
     p.rho0 = float(rho0)
     p.u_inlet[:] = [float(v) for v in u_inlet]
     p.fp64_threshold = float(fp64_threshold)
+    p.max_mesh_vertices = int(max_mesh_vertices)
+    p.max_mesh_triangles = int(max_mesh_triangles)
     return p
 
 
 def make_body(spec: dict) -> Body:
     b = Body()
-    b.kind = BODY_SPHERE if spec.get("kind", "sphere") == "sphere" else BODY_PLANE
+    b.kind = {"sphere": BODY_SPHERE, "plane": BODY_PLANE, "mesh": BODY_MESH}[spec.get("kind", "sphere")]
     b.center[:] = [float(v) for v in spec.get("center", (0, 0, 0))]
     b.radius = float(spec.get("radius", 0.0))
     b.normal[:] = [float(v) for v in spec.get("normal", (0, 0, 0))]
@@ -202,6 +209,19 @@ def elbm_read_populations(ctx, pop_dev):
 def elbm_set_geometry(ctx, bodies):
     arr = (Body * max(1, len(bodies)))(*[make_body(b) if isinstance(b, dict) else b for b in bodies])
     _check(load().elbm_set_geometry(ctx, arr, len(bodies)), ctx)
+
+
+def _d3(v):
+    return None if v is None else (ctypes.c_double * 3)(*[float(a) for a in v])
+
+
+def elbm_set_mesh(ctx, tris_dev, nt: int, verts_dev, vels_dev, nv: int, box_lo, box_hi, center=None):
+    _check(load().elbm_set_mesh(ctx, _ptr(tris_dev), int(nt), _ptr(verts_dev), _ptr(vels_dev), int(nv), _d3(box_lo),
+                                _d3(box_hi), _d3(center)), ctx)
+
+
+def elbm_mesh_next(ctx, verts_dev, vels_dev, center=None):
+    _check(load().elbm_mesh_next(ctx, _ptr(verts_dev), _ptr(vels_dev), _d3(center)), ctx)
 
 
 def elbm_body_state(ctx, body: int):
@@ -293,12 +313,14 @@ class Lattice:
     """One context plus its torch-allocated workspace on the current device and stream."""
 
     def __init__(self, shape, nu, storage="f32", channel=False, u_inlet=(0.0, 0.0, 0.0), max_bodies=0, flags=0,
-                 force_ring=4096, max_boundary=0, rho0=1.0, fp64_threshold=0.0, stream=None):
+                 force_ring=4096, max_boundary=0, rho0=1.0, fp64_threshold=0.0, stream=None, max_mesh_vertices=0,
+                 max_mesh_triangles=0):
         import torch
         self.torch = torch
         self.shape = tuple(int(v) for v in shape)
         self.params = make_params(shape, nu, storage, channel, max_bodies, flags, force_ring, max_boundary, rho0,
-                                  u_inlet, fp64_threshold)
+                                  u_inlet, fp64_threshold, max_mesh_vertices, max_mesh_triangles)
+        self._mesh_keep = None
         nbytes = elbm_workspace_bytes(self.params)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         # 256-byte aligned device workspace owned by torch
@@ -343,6 +365,31 @@ class Lattice:
 
     def set_bodies(self, bodies):
         elbm_set_geometry(self.ctx, list(bodies))
+
+    def _mesh_tensors(self, verts, vels):
+        torch = self.torch
+        X = torch.as_tensor(np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 3)).cuda()
+        V = None if vels is None else torch.as_tensor(np.ascontiguousarray(vels, dtype=np.float64).reshape(-1, 3)).cuda()
+        return X, V
+
+    def set_mesh(self, verts, tris, box_lo, box_hi, vels=None, center=None):
+        """Triangulated surface at the current time level (host arrays); then set_bodies with a body
+        of kind "mesh" last."""
+        X, V = self._mesh_tensors(verts, vels)
+        if V is not None and V.shape != X.shape:
+            raise ElbmError("vels must have the shape of verts")
+        T = self.torch.as_tensor(np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)).cuda()
+        elbm_set_mesh(self.ctx, T, T.shape[0], X, V, X.shape[0], box_lo, box_hi, center)
+        self._mesh_keep = (T, X, V)
+        self._mesh_nv = X.shape[0]
+
+    def mesh_next(self, verts, vels=None, center=None):
+        """Vertex positions and velocities of the next time level (before the next step)."""
+        X, V = self._mesh_tensors(verts, vels)
+        if self._mesh_keep is None or X.shape[0] != self._mesh_nv or (V is not None and V.shape != X.shape):
+            raise ElbmError("mesh_next needs the vertex count of set_mesh")
+        elbm_mesh_next(self.ctx, X, V, center)
+        self._mesh_keep = (self._mesh_keep[0], X, V)
 
     def body_state(self, k: int):
         """Position and velocity of body k at the current time level (numpy arrays)."""

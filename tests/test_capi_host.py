@@ -19,11 +19,33 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, name), name
 
 
-def test_struct_sizes_match_header_layout():
-    # the ctypes mirrors must have the C sizes (x86-64 SysV alignment)
-    assert ctypes.sizeof(elbm.Params) == 4 * 8 + 8 + 8 + 8 + 24 + 8
-    assert ctypes.sizeof(elbm.Body) == 8 + 24 + 8 + 24 + 8 + 8 + 24 + 24 + 24 + 8 + 24
-    assert ctypes.sizeof(elbm.Info) == 8 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
+def _c_layout(struct: str, fields):
+    """sizeof and offsetof of a header struct, from a C compiler reading include/elbm.h."""
+    import os
+    import subprocess
+    import tempfile
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    body = "".join(f'  printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"elbm.h\"\nint main(void) {\n"
+           f'  printf("%zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(c, "w") as fh:
+            fh.write(src)
+        subprocess.run(["gcc", "-I", inc, "-o", exe, c], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return [int(v) for v in out]
+
+
+@pytest.mark.parametrize("struct,mirror", [("elbm_params", elbm.Params), ("elbm_body", elbm.Body),
+                                           ("elbm_info", elbm.Info)])
+def test_struct_layout_matches_header(struct, mirror):
+    # the ctypes mirrors must have the C layout: size and every field offset
+    names = [f[0] for f in mirror._fields_]
+    got = _c_layout(struct, names)
+    assert got[0] == ctypes.sizeof(mirror)
+    for name, off in zip(names, got[1:]):
+        assert getattr(mirror, name).offset == off, name
 
 
 def test_workspace_size_counts_two_population_arrays():

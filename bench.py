@@ -166,6 +166,59 @@ def settle_form(elbm, torch, WL, steps: int = 500):
             "position_x": round(float(x[0]), 4), "velocity_x": float(v[0])}
 
 
+def swimmer_form(elbm, torch, steps: int = 20, warmup: int = 3, L: int = 200):
+    """Deforming triangulated body (Sec. IV.B): the anguilliform swimmer of length L = 200 in the
+    paper's 8L x 4L x L domain (1600 x 800 x 200, 256 M nodes, FP32), undulation period T = 10^4,
+    Re = (L^2/T)/nu = 7142, held in place in a channel stream at its swimming speed 0.415 L/T, at full
+    amplitude.  The surface (150 segments x 16 points) of every step is generated beforehand and
+    held on the device; each step uploads nothing from the host."""
+    import numpy as np
+    from workloads import meshes as M
+    T = 1.0e4
+    nu = (L * L / T) / 7142.0
+    shape = (8 * L, 4 * L, L)
+    u_in = (0.415 * L / T, 0.0, 0.0)
+    head = (2.0 * L, 2.0 * L + 0.35, 0.5 * L + 0.4)
+    t0 = T
+    levels = [M.swimmer_mesh(head, L, T, t0 + k) for k in range(warmup + steps + 1)]
+    tris = levels[0][1]
+    Xs = torch.as_tensor(np.stack([lv[0] for lv in levels])).cuda()
+    Vs = torch.as_tensor(np.stack([lv[2] for lv in levels])).cuda()
+    lo = (head[0] - 2.0, head[1] - 0.2 * L, head[2] - 0.1 * L)
+    hi = (head[0] + L + 2.0, head[1] + 0.2 * L, head[2] + 0.1 * L)
+    ctr = (head[0] + 0.5 * L, head[1], head[2])
+    lat = elbm.Lattice(shape, nu, channel=True, u_inlet=u_in, max_bodies=1, max_mesh_vertices=Xs.shape[1],
+                       max_mesh_triangles=len(tris))
+    nx, ny, nz = shape
+    u = torch.zeros((3, nz, ny, nx), dtype=torch.float64, device="cuda")
+    u[0] = u_in[0]
+    elbm.elbm_init_equilibrium(lat.ctx, None, u)
+    del u
+    lat.set_mesh(levels[0][0], tris, lo, hi, vels=levels[0][2], center=ctr)
+    lat.set_bodies([dict(kind="mesh")])
+    for k in range(warmup):
+        lat.mesh_next(Xs[k + 1], Vs[k + 1], center=ctr)
+        lat.step(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    for k in range(warmup, warmup + steps):
+        lat.mesh_next(Xs[k + 1], Vs[k + 1], center=ctr)
+        lat.step(1)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    info = lat.info()
+    F = lat.force_history(0, info.t - steps + 1, steps)
+    n = nx * ny * nz
+    out = {"MLUPS": round(n * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 4),
+           "nodes": n, "triangles": int(len(tris)), "boundary_nodes_last_step": int(info.boundary_nodes),
+           "fp64_nodes_last_step": int(info.fp64_nodes), "thrust_x_mean": float(F[:, 0].mean())}
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(workload: str, budget_s: float = 15.0):
     """The FP64 oracle, unmodified, stepping the workload's own lattice on the host cores for a
     bounded number of steps (at least 2, until ~budget_s seconds of stepping)."""
@@ -199,7 +252,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--form-steps", type=int, default=100)
-    ap.add_argument("--forms", default="copy,stabilisers,turb512,sphere384,settle,adj128",
+    ap.add_argument("--forms", default="copy,stabilisers,turb512,sphere384,settle,swimmer,adj128",
                     help="comma-separated subset of the extra forms to run")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="after the headline run, copy a buffer of this many MiB 5 times (a plain copy kernel "
@@ -321,6 +374,9 @@ def main():
         if "settle" in which:
             forms["settle_f32"] = settle_form(elbm, torch, WL)
             log(f"settling sphere: {forms['settle_f32']}")
+        if "swimmer" in which:
+            forms["swimmer_f32"] = swimmer_form(elbm, torch)
+            log(f"deforming swimmer: {forms['swimmer_f32']}")
         if "adj128" in which:
             forms["adj128_adjoint"] = adjoint_form(torch, WL)
             log(f"adj128 adjoint: {forms['adj128_adjoint']}")

@@ -26,7 +26,7 @@
 // 7.5e-4 on a small channel; FP64 by 6e-7).  Adjoint fields stay FP32 in memory.
 #include <algorithm>
 
-#include "elbm_internal.hpp"
+#include "context.hpp"
 #include "boundary_dev.hpp"
 
 namespace elbm {
@@ -735,6 +735,8 @@ static BArgs bargs(elbm_ctx* c, const void* A) {
   a.fix_list = nullptr;  // the adjoint kernels queue nothing
   a.fix_count = nullptr;
   a.n_static = c->n_static;
+  a.lo = 0;
+  a.hi = -1;
   a.cap = c->blist_cap;
   a.moving = c->moving ? 1 : 0;
   a.nx = c->p.nx;

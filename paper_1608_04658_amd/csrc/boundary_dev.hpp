@@ -57,6 +57,7 @@ struct BArgs {
   uint32_t* fix_list;   // FP64 fix-up queue (wall nodes enter it tagged FIX_PRE)
   uint32_t* fix_count;  // its length for this step
   int64_t n_static;
+  int64_t lo, hi;  // k_boundary: list entries [lo, min(hi, count)) (hi < 0: to the end)
   int64_t cap;
   int32_t moving;
   int32_t nx, ny, nz;
@@ -93,7 +94,7 @@ __host__ __device__ constexpr int dir_index(int dx, int dy, int dz) { return 9 *
 // direction i, lanes 27..31 (and lane 13 for a sixth) fetch the nodes two steps away along the
 // axes.  Per-direction work runs side by side across the lanes instead of as 27 unrolled copies
 // in one thread; sums over directions are butterfly reductions inside the group (fixed order).
-constexpr int GROUP = 32;
+// (GROUP = 32 is defined with the shared declarations.)
 
 __device__ __forceinline__ float gsum(float v) {
 #pragma unroll

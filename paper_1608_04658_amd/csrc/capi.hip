@@ -9,7 +9,7 @@
 #include <algorithm>
 #include <new>
 
-#include "elbm_internal.hpp"
+#include "context.hpp"
 
 using namespace elbm;
 

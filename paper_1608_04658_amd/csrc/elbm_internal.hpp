@@ -2,8 +2,9 @@
 //
 // Device helpers for the D3Q27 KBC step (Dorschner, Chikatamarla, Karlin, arXiv:1608.04658):
 // lattice tables, the KBC collision (Sec. II), Grad's distribution and pressure tensor
-// (Sec. III, eqs. grad, pressure, pressure2), population storage codecs, and the host-side
-// context that the C ABI in include/elbm.h manipulates.
+// (Sec. III, eqs. grad, pressure, pressure2), population storage codecs, the structures the
+// kernels receive (bodies, the triangulated surface, counters) and block-level scans.  The
+// host-side context is in context.hpp.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -510,111 +511,47 @@ struct DevCounters {
   uint32_t pad[4];
 };
 
+// Lanes per node in the lane-parallel boundary kernels (two nodes per wavefront of 64).
+constexpr int GROUP = 32;
+
+// Inclusive prefix sum over a workgroup of NW wavefronts of 64: shuffles within each wavefront,
+// one shared array wsum[NW] of the wavefront totals; total = the workgroup's sum.  Every thread of
+// the workgroup must call it.
+template <int NW, typename T>
+__device__ inline T block_scan_inclusive(T v, T* wsum, T& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  if (lane == 63) wsum[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    T s = lane < NW ? wsum[lane] : T(0);
+#pragma unroll
+    for (int off = 1; off < NW; off <<= 1) {
+      const T u = __shfl_up(s, off, 64);
+      if (lane >= off) s += u;
+    }
+    if (lane < NW) wsum[lane] = s;
+  }
+  __syncthreads();
+  if (wave > 0) v += wsum[wave - 1];
+  total = wsum[NW - 1];
+  __syncthreads();
+  return v;
+}
+
+template <typename T>
+__device__ inline T scan1024_inclusive(T v, T* wsum, T& total) {
+  return block_scan_inclusive<16>(v, wsum, total);
+}
+
 struct Box {
   int lo[3];
   int n[3];
   __host__ __device__ long count() const { return (long)n[0] * n[1] * n[2]; }
 };
 
-}  // namespace elbm
-
-// ---------------------------------------------------------------------------------------------
-// The context behind the C ABI.
-struct elbm_ctx {
-  elbm_params p;
-  hipStream_t stream;
-  char* ws;
-  size_t ws_bytes;
-  int64_t N;
-  double beta;
-  double fp64_thr;
-  // carved fields (device)
-  void* pop[2];
-  int cur;                 // pop[cur] holds A^t
-  uint8_t* flags;          // N (geometry only)
-  float* macro;            // 4 N: U (3 N) then R (N) (geometry only)
-  int32_t* blist;          // boundary list (geometry only)
-  int64_t blist_cap;
-  int64_t n_static;        // static part (channel inlet face, or all entries for static geometry)
-  double* brec;            // per-list-entry force records [cap][nb][6]
-  uint32_t* scan_tmp;      // 2 x scan_blocks: per-block counts and offsets of the list compaction
-  int64_t scan_blocks;
-  double* ring;            // [force_ring][MAX_BODIES][6]
-  double* force_partial;   // [64][MAX_BODIES][6] partial sums of the force reduction
-  int32_t* fix_list;       // N
-  elbm::DevCounters* cnt;
-  int fix_par;             // parity of the FP64 queue counter of the next step (DevCounters::fix_count)
-  double* scratch64;       // small FP64 scratch (force sums)
-  const float* bodyforce;
-  // geometry state
-  int32_t nb;
-  elbm_body bodies[ELBM_MAX_BODIES];
-  bool moving;
-  // free bodies (two-way coupling): state at time level t and the force of the step producing t
-  struct FreeBody {
-    bool on;
-    double x[3], u[3], F[3], m, ab[3];  // ab = (1 - 1/density_ratio) g
-  } freeb[ELBM_MAX_BODIES];
-  int n_free;
-  bool free_force_pending;  // F of the last step is still on the device
-  int stab;         // STAB_KBC, STAB_EXACT or STAB_LBGK (from the context flags)
-  // triangulated body (elbm_set_mesh): slot mesh_cur holds time level t; slot mesh_cur ^ 1 level
-  // t+1 when mesh_next_set (else level t+1 = level t)
-  int mesh_body;           // body index, -1 if none
-  bool mesh_set;
-  int32_t mesh_nv, mesh_nt;
-  int mesh_cur;
-  bool mesh_next_set;
-  double mesh_ref[2][3];   // torque centre per slot
-  double mesh_lo[3], mesh_hi[3];
-  elbm::MeshDev mesh_grid; // grid geometry (pointers of slot 0/1 filled per use)
-  int32_t* mesh_tri;
-  double* mesh_X[2];
-  double* mesh_V[2];
-  int32_t* mesh_start[2];
-  int32_t* mesh_items[2];
-  int32_t* mesh_cursor;    // [MESH_CELLS] binning counters
-  int64_t mesh_cap;        // items per slot
-  bool slab_valid;  // slab_next holds U, R of the inlet slab of the current state (written by the
-                    // kernels that produced it)
-  float* slab_next; // channel mode: [4][nz][ny][3] staging of U, R for x < 3
-  int64_t t;
-  char err[256];
-  // adjoint (ELBM_FLAG_ADJOINT)
-  double* adj_gUR;         // 4 N: dL/dU^t (3 N) and dL/dR^t (N), FP64 scatter targets
-  float* adj_side;         // 9 ny nz: outlet-copy adjoint contributions
-  double* adj_gamp;        // [MAX_BODIES] dL/d(amplitude)
-  // sweep timing (HIP events around each bulk-sweep launch)
-  bool timing;
-  hipEvent_t* ev;
-  int64_t ev_cap, ev_used;
-};
-
-namespace elbm {
-// kernel launchers (defined in sweep.hip / geometry.hip)
-hipError_t launch_sweep(elbm_ctx* c);
-hipError_t launch_fixup(elbm_ctx* c);
-hipError_t launch_init_eq(elbm_ctx* c, const double* rho, const double* u);
-hipError_t launch_write_pop(elbm_ctx* c, const double* src);
-hipError_t launch_read_pop(elbm_ctx* c, double* dst);
-hipError_t launch_collide_nodes(const float* fin, float* fout, float* gam, const float* F, int64_t n, double beta,
-                                double thr, int stab, hipStream_t s);
-hipError_t geometry_init(elbm_ctx* c);
-hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd);
-hipError_t launch_boundary(elbm_ctx* c, const Bodies& bd);
-hipError_t launch_refill(elbm_ctx* c, const Bodies& bd, void* A);
-hipError_t launch_force_reduce(elbm_ctx* c);
-hipError_t launch_adjoint(elbm_ctx* c, int64_t t, const void* A, const float* lam_in, float* lam_out,
-                          const double* w_force, float* gF);
-void host_kinematics(const elbm_body& b, double t, double c[3], double U[3]);
-hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd, bool slab);
-hipError_t geometry_for_step(elbm_ctx* c, const Bodies& bd);
-Box union_box(const elbm_ctx* c, const Bodies& bd);
-Box full_box(const elbm_ctx* c);
-dim3 grid_for(long n);
-Bodies make_bodies(const elbm_ctx* c, double t);
-constexpr int MESH_CELLS = 1 << 16;
-hipError_t mesh_upload(elbm_ctx* c, int slot, const double* X, const double* V);
-hipError_t mesh_copy_tris(elbm_ctx* c, const int32_t* tris, int32_t nt);
-hipError_t mesh_mask(elbm_ctx* c, const Bodies& bd, int level, uint8_t bits);
 }  // namespace elbm

@@ -13,12 +13,14 @@
 #include <algorithm>
 #include <stdio.h>
 
-#include "elbm_internal.hpp"
+#include "context.hpp"
 #include "boundary_dev.hpp"
 
 namespace elbm {
 
 constexpr int BOX_MARGIN = 5;
+
+BArgs boundary_args(elbm_ctx* c, const void* A, void* B);
 
 // ---------------------------------------------------------------------------------------------
 // Host kinematics, FP64, in the order written in elbm.h.
@@ -217,22 +219,11 @@ __device__ __forceinline__ bool is_boundary(const GeoArgs& g, int x, int y, int 
 constexpr int SCAN_BLOCK = 256;
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
-    const uint32_t w = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0u;
-    __syncthreads();
-    sh[threadIdx.x] += w;
-    __syncthreads();
-  }
-  total = sh[SCAN_BLOCK - 1];
-  const uint32_t incl = sh[threadIdx.x];
-  __syncthreads();
-  return incl - v;
+  return block_scan_inclusive<SCAN_BLOCK / 64>(v, sh, total) - v;
 }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_mark(GeoArgs g, int skip_inlet, uint32_t* block_count) {
-  __shared__ uint32_t sh[SCAN_BLOCK];
+  __shared__ uint32_t sh[SCAN_BLOCK / 64];
   const long idx = blockIdx.x * (long)SCAN_BLOCK + threadIdx.x;
   uint32_t isb = 0;
   if (idx < g.box.count()) {
@@ -255,22 +246,15 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_mark(GeoArgs g, int skip_in
 __global__ __launch_bounds__(1024) void k_scan_offsets(const uint32_t* block_count, uint32_t* block_offset, long nblk,
                                                        int64_t base, int64_t cap, uint32_t* count_out,
                                                        uint32_t* overflow) {
-  __shared__ uint32_t sh[1024];
+  __shared__ uint32_t wsum[16];
   uint32_t running = 0;
   for (long start = 0; start < nblk; start += 1024) {
     const long i = start + threadIdx.x;
     const uint32_t v = i < nblk ? block_count[i] : 0u;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const uint32_t w = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0u;
-      __syncthreads();
-      sh[threadIdx.x] += w;
-      __syncthreads();
-    }
-    if (i < nblk) block_offset[i] = running + sh[threadIdx.x] - v;
-    running += sh[1023];
-    __syncthreads();
+    uint32_t total;
+    const uint32_t incl = scan1024_inclusive(v, wsum, total);
+    if (i < nblk) block_offset[i] = running + incl - v;
+    running += total;
   }
   if (threadIdx.x == 0) {
     *count_out = running;
@@ -280,7 +264,7 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(const uint32_t* block_cou
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_emit(GeoArgs g, int skip_inlet, const uint32_t* block_offset,
                                                           int32_t* list, int64_t base, int64_t cap) {
-  __shared__ uint32_t sh[SCAN_BLOCK];
+  __shared__ uint32_t sh[SCAN_BLOCK / 64];
   const long idx = blockIdx.x * (long)SCAN_BLOCK + threadIdx.x;
   uint32_t isb = 0;
   long n = 0;
@@ -314,10 +298,9 @@ __global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, flo
       const int k = MESH ? owner_body(bd, false, x, y, z) : max(first_body(bd, false, x, y, z), 0);
       const BodyDev& b = bd.b[k];
       if (MESH && b.kind == ELBM_BODY_MESH) {
-        const double p[3] = {(double)x, (double)y, (double)z};
-        double v[3];
-        mesh_closest_velocity(bd.m, 0, p, v);
-        for (int a = 0; a < 3; ++a) U[a] = (float)v[a];
+        // U^t of a node solid at t is read only once the node is fluid at t+1 (finite differences
+        // and u_f use nodes fluid at t+1): k_mesh_uncovered writes it at the uncovered nodes
+        U[0] = U[1] = U[2] = 0.f;
       } else {
         const double r[3] = {x - b.c0[0], y - b.c0[1], z - b.c0[2]};
         U[0] = (float)(b.U0[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
@@ -353,6 +336,26 @@ __global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, flo
   }
 }
 
+// U^t at the nodes the triangulated body uncovers in this step (solid at t, fluid at t+1; all in
+// the dynamic list): the velocity of the closest surface point at t, one node per group of lanes.
+__global__ __launch_bounds__(64) void k_mesh_uncovered(const BArgs a, const Bodies bd, float* macro) {
+  int64_t count = a.n_static + (int64_t)*a.dyn_count;
+  if (count > a.cap) count = a.cap;
+  const int lane = threadIdx.x & (GROUP - 1), g = threadIdx.x / GROUP;
+  for (int64_t k = a.n_static + 2 * (int64_t)blockIdx.x + g; k < count; k += 2 * (int64_t)gridDim.x) {
+    const long n = a.list[k];
+    const uint8_t fl = a.flags[n];
+    if (!(fl & FL_SOLID_PREV) || (fl & FL_SOLID)) continue;  // uniform over the group
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    if (owner_body(bd, false, x, y, z) != bd.mesh) continue;
+    const double p[3] = {(double)x, (double)y, (double)z};
+    double v[3];
+    mesh_closest_velocity_group(bd.m, 0, p, lane, v);
+    if (lane == 0)
+      for (int c = 0; c < 3; ++c) macro[c * a.N + n] = (float)v[c];
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Refill before streaming: the uncovered nodes of the step get their Grad populations written into
 // the current buffer A^t, where their neighbours (and the node itself) pull them.  One node per
@@ -374,10 +377,11 @@ __global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, v
     const BodyDev& b = bd.b[kb];
     float uw[3];
     if (MESH && b.kind == ELBM_BODY_MESH) {
-      // the body's velocity at the node: that of the closest surface point at t+1
+      // the body's velocity at the node: that of the closest surface point at t+1 (candidate
+      // triangles shared out over the group's lanes)
       const double p[3] = {(double)h.x, (double)h.y, (double)h.z};
       double v[3];
-      mesh_closest_velocity(bd.m, 1, p, v);
+      mesh_closest_velocity_group(bd.m, 1, p, lane, v);
       for (int a = 0; a < 3; ++a) uw[a] = (float)v[a];
     } else {
       const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
@@ -408,10 +412,11 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
   __shared__ float sh[2][GROUP];
   int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
   if (count > a.cap) count = a.cap;
+  if (a.hi >= 0 && count > a.hi) count = a.hi;
   const int nb = bd.nb;
   const int lane = threadIdx.x & (GROUP - 1), g = threadIdx.x / GROUP;
   const int i = lane < 27 ? lane : 13;
-  for (int64_t base = 2 * (int64_t)blockIdx.x; base < count; base += 2 * (int64_t)gridDim.x) {
+  for (int64_t base = a.lo + 2 * (int64_t)blockIdx.x; base < count; base += 2 * (int64_t)gridDim.x) {
     // the loop is uniform over the block (barriers below); a group past the end repeats the
     // block's first node and stores nothing
     const int64_t k = base + g;
@@ -657,7 +662,12 @@ hipError_t geometry_pre_step(elbm_ctx* c, const Bodies& bd) {
     hipLaunchKernelGGL(k_slab_copy, grid_for(4L * 3 * c->p.ny * c->p.nz), dim3(256), 0, c->stream, c->slab_next,
                        c->macro, c->p.nx, c->p.ny, c->p.nz, (int64_t)c->N);
   }
-  return macro_fields(c, c->pop[c->cur], bd, !c->slab_valid);
+  hipError_t e = macro_fields(c, c->pop[c->cur], bd, !c->slab_valid);
+  if (e != hipSuccess || bd.mesh < 0) return e;
+  const BArgs a = boundary_args(c, c->pop[c->cur], nullptr);
+  const dim3 g((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap - a.n_static + 1) / 2, 1), 4096)), b(64);
+  hipLaunchKernelGGL(k_mesh_uncovered, g, b, 0, c->stream, a, bd, c->macro);
+  return hipGetLastError();
 }
 
 // Masks of both time levels of the step t -> t+1 recomputed from the kinematics alone (so that a
@@ -687,11 +697,24 @@ template <int S, int STAB>
 static void boundary_launch_st(elbm_ctx* c, const BArgs& a, const Bodies& bd) {
   // two list entries per 64-lane workgroup
   const dim3 g((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap + 1) / 2, 1), 16384)), b(64);
-  const bool mesh = bd.mesh >= 0;
-  if (c->bodyforce && mesh) hipLaunchKernelGGL((k_boundary<S, true, STAB, true>), g, b, 0, c->stream, a, bd);
-  else if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true, STAB, false>), g, b, 0, c->stream, a, bd);
-  else if (mesh) hipLaunchKernelGGL((k_boundary<S, false, STAB, true>), g, b, 0, c->stream, a, bd);
-  else hipLaunchKernelGGL((k_boundary<S, false, STAB, false>), g, b, 0, c->stream, a, bd);
+  if (bd.mesh < 0) {
+    if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true, STAB, false>), g, b, 0, c->stream, a, bd);
+    else hipLaunchKernelGGL((k_boundary<S, false, STAB, false>), g, b, 0, c->stream, a, bd);
+    return;
+  }
+  // with a triangulated body: the static entries (the inlet face; no body is that close to it) in
+  // the plain instantiation, the dynamic ones in the one that carries the mesh geometry
+  BArgs as = a, ad = a;
+  as.hi = a.n_static;
+  ad.lo = a.n_static;
+  const dim3 gs((unsigned)std::min<int64_t>(std::max<int64_t>((a.n_static + 1) / 2, 1), 16384));
+  const dim3 gd((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap - a.n_static + 1) / 2, 1), 16384));
+  if (a.n_static > 0) {
+    if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true, STAB, false>), gs, b, 0, c->stream, as, bd);
+    else hipLaunchKernelGGL((k_boundary<S, false, STAB, false>), gs, b, 0, c->stream, as, bd);
+  }
+  if (c->bodyforce) hipLaunchKernelGGL((k_boundary<S, true, STAB, true>), gd, b, 0, c->stream, ad, bd);
+  else hipLaunchKernelGGL((k_boundary<S, false, STAB, true>), gd, b, 0, c->stream, ad, bd);
 }
 
 template <int S>
@@ -718,6 +741,8 @@ BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
   a.fix_count = &c->cnt->fix_count[c->fix_par];
   a.slab_next = (channel && !(c->p.flags & ELBM_FLAG_STREAM_ONLY)) ? c->slab_next : nullptr;
   a.n_static = c->n_static;
+  a.lo = 0;
+  a.hi = -1;
   a.cap = c->blist_cap;
   a.moving = c->moving ? 1 : 0;
   a.nx = c->p.nx;

@@ -6,7 +6,7 @@
 
 #include <algorithm>
 
-#include "elbm_internal.hpp"
+#include "context.hpp"
 #include "mesh_dev.hpp"
 
 namespace elbm {
@@ -59,25 +59,18 @@ __global__ void k_mesh_count(MeshDev m, const double* X, int32_t* cnt, uint32_t*
 // One workgroup: start = exclusive scan of cnt (start[ncell] = total); cnt is cleared for the fill.
 __global__ __launch_bounds__(1024) void k_mesh_scan(int32_t* cnt, int32_t* start, int32_t ncell, int64_t cap,
                                                     uint32_t* overflow) {
-  __shared__ int32_t sh[1024];
+  __shared__ int32_t wsum[16];
   int32_t running = 0;
   for (int base = 0; base < ncell; base += 1024) {
     const int i = base + threadIdx.x;
     const int32_t v = i < ncell ? cnt[i] : 0;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int32_t w = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += w;
-      __syncthreads();
-    }
+    int32_t total;
+    const int32_t incl = scan1024_inclusive(v, wsum, total);
     if (i < ncell) {
-      start[i] = running + sh[threadIdx.x] - v;
+      start[i] = running + incl - v;
       cnt[i] = 0;
     }
-    running += sh[1023];
-    __syncthreads();
+    running += total;
   }
   if (threadIdx.x == 0) {
     start[ncell] = running;
@@ -100,44 +93,53 @@ __global__ void k_mesh_fill(MeshDev m, const double* X, const int32_t* start, in
   }
 }
 
-// Solid mask of the triangulated body on a box: one thread per (y, z) row collects the x of every
-// crossing of the +x ray through (y, z) (each triangle once: in the cell of its bounding box's
-// lowest x), then marks the nodes with an odd number of crossings beyond them.
-__global__ __launch_bounds__(64) void k_mesh_mask(MeshDev m, int lvl, uint8_t* flags, int32_t nx, int32_t ny,
-                                                  Box box, uint8_t bits, uint32_t* overflow) {
-  __shared__ double xs[64][ROW_CROSSINGS];
+// Solid mask of the triangulated body on a box, one wavefront per (y, z) row: the lanes share out
+// the cells along x and collect the x of every crossing of the +x ray through (y, z) (each
+// triangle once: in the cell of its bounding box's lowest x), then share out the nodes of the row
+// and mark those with an odd number of crossings beyond them (the order of the list is immaterial).
+constexpr int MASK_ROWS = 4;  // wavefronts (rows) per workgroup
+__global__ __launch_bounds__(64 * MASK_ROWS) void k_mesh_mask(MeshDev m, int lvl, uint8_t* flags, int32_t nx,
+                                                              int32_t ny, Box box, uint8_t bits, uint32_t* overflow) {
+  __shared__ double xs[MASK_ROWS][ROW_CROSSINGS];
+  __shared__ int cnt[MASK_ROWS];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const MeshLevel& L = m.lv[lvl];
   const long rows = (long)box.n[1] * box.n[2];
-  const long r = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  const int y = box.lo[1] + (int)(r % box.n[1]), z = box.lo[2] + (int)(r / box.n[1]);
-  const double yd = (double)y, zd = (double)z;
-  const int cy = mesh_cell(m, 1, yd), cz = mesh_cell(m, 2, zd);
-  int nc = 0;
-  for (int cx = 0; cx < m.dim[0]; ++cx) {
-    const int c = mesh_cell_index(m, cx, cy, cz);
-    const int e1 = min(L.start[c + 1], m.cap);
-    for (int e = L.start[c]; e < e1; ++e) {
-      const int k = L.items[e];
-      if ((unsigned)k >= (unsigned)m.nt) continue;
-      const int32_t* t3 = m.tri + 3 * k;
-      const double* A = L.X + 3 * t3[0];
-      const double* B = L.X + 3 * t3[1];
-      const double* C = L.X + 3 * t3[2];
-      if (mesh_cell(m, 0, fmin(A[0], fmin(B[0], C[0]))) != cx) continue;
-      double xc;
-      if (!mesh_crossing(A, B, C, yd, zd, xc)) continue;
-      if (nc < ROW_CROSSINGS) xs[threadIdx.x][nc] = xc;
-      else atomicOr(overflow, 4u);
-      ++nc;
+  const long r = blockIdx.x * (long)MASK_ROWS + w;
+  const bool active = r < rows;  // uniform over the wavefront
+  const int y = active ? box.lo[1] + (int)(r % box.n[1]) : 0, z = active ? box.lo[2] + (int)(r / box.n[1]) : 0;
+  if (lane == 0) cnt[w] = 0;
+  __syncthreads();
+  if (active) {
+    const double yd = (double)y, zd = (double)z;
+    const int cy = mesh_cell(m, 1, yd), cz = mesh_cell(m, 2, zd);
+    for (int cx = lane; cx < m.dim[0]; cx += 64) {
+      const int c = mesh_cell_index(m, cx, cy, cz);
+      const int e1 = min(L.start[c + 1], m.cap);
+      for (int e = L.start[c]; e < e1; ++e) {
+        const int k = L.items[e];
+        if ((unsigned)k >= (unsigned)m.nt) continue;
+        const int32_t* t3 = m.tri + 3 * k;
+        const double* A = L.X + 3 * t3[0];
+        const double* B = L.X + 3 * t3[1];
+        const double* C = L.X + 3 * t3[2];
+        if (mesh_cell(m, 0, fmin(A[0], fmin(B[0], C[0]))) != cx) continue;
+        double xc;
+        if (!mesh_crossing(A, B, C, yd, zd, xc)) continue;
+        const int j = atomicAdd(&cnt[w], 1);
+        if (j < ROW_CROSSINGS) xs[w][j] = xc;
+        else atomicOr(overflow, 4u);
+      }
     }
   }
-  nc = nc < ROW_CROSSINGS ? nc : ROW_CROSSINGS;
+  __syncthreads();
+  if (!active) return;
+  const int nc = min(cnt[w], ROW_CROSSINGS);
   if (nc == 0) return;
-  for (int x = box.lo[0]; x < box.lo[0] + box.n[0]; ++x) {
+  for (int x = box.lo[0] + lane; x < box.lo[0] + box.n[0]; x += 64) {
     const double xd = (double)x;
     int odd = 0;
-    for (int j = 0; j < nc; ++j) odd ^= (xs[threadIdx.x][j] > xd) ? 1 : 0;
+    for (int j = 0; j < nc; ++j) odd ^= (xs[w][j] > xd) ? 1 : 0;
     if (odd) {
       const long n = ((long)z * ny + y) * nx + x;
       flags[n] |= bits;
@@ -198,8 +200,8 @@ hipError_t mesh_mask(elbm_ctx* c, const Bodies& bd, int lvl, uint8_t bits) {
   }
   const long rows = (long)box.n[1] * box.n[2];
   if (rows == 0 || box.n[0] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mesh_mask, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, c->stream, bd.m, lvl, c->flags,
-                     c->p.nx, c->p.ny, box, bits, &c->cnt->overflow);
+  hipLaunchKernelGGL(k_mesh_mask, dim3((unsigned)((rows + MASK_ROWS - 1) / MASK_ROWS)), dim3(64 * MASK_ROWS), 0,
+                     c->stream, bd.m, lvl, c->flags, c->p.nx, c->p.ny, box, bits, &c->cnt->overflow);
   return hipGetLastError();
 }
 

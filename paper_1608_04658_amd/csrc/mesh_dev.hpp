@@ -195,6 +195,58 @@ __device__ inline void mesh_closest_velocity(const MeshDev& m, int lvl, const do
   bary_velocity(L.V, m.tri + 3 * bk, bw, out);
 }
 
+// The same in the lane-parallel form (one node per group of GROUP lanes, all lanes calling): the
+// lanes share out the candidate triangles, then the group takes the minimum of (distance, index),
+// which makes the result that of mesh_closest_velocity.
+__device__ inline void mesh_closest_velocity_group(const MeshDev& m, int lvl, const double* p, int lane, double* out) {
+  const MeshLevel& L = m.lv[lvl];
+  int c0[3];
+  for (int a = 0; a < 3; ++a) c0[a] = mesh_cell(m, a, p[a]);
+  double best = INFINITY, bw[3] = {1.0, 0.0, 0.0};
+  int bk = INT32_MAX;
+  for (int cz = max(c0[2] - 1, 0); cz <= min(c0[2] + 1, m.dim[2] - 1); ++cz)
+    for (int cy = max(c0[1] - 1, 0); cy <= min(c0[1] + 1, m.dim[1] - 1); ++cy)
+      for (int cx = max(c0[0] - 1, 0); cx <= min(c0[0] + 1, m.dim[0] - 1); ++cx) {
+        const int c = mesh_cell_index(m, cx, cy, cz);
+        const int e1 = min(L.start[c + 1], m.cap);
+        for (int e = L.start[c] + lane; e < e1; e += GROUP) {
+          const int k = L.items[e];
+          if ((unsigned)k >= (unsigned)m.nt) continue;
+          const int32_t* t3 = m.tri + 3 * k;
+          double w[3];
+          const double d2 = closest_on_triangle(p, L.X + 3 * t3[0], L.X + 3 * t3[1], L.X + 3 * t3[2], w);
+          if (d2 < best || (d2 == best && k < bk)) {
+            best = d2;
+            bk = k;
+            bw[0] = w[0];
+            bw[1] = w[1];
+            bw[2] = w[2];
+          }
+        }
+      }
+  // group minimum of (best, bk), then the weights from the lane that holds it
+  double gb = best;
+  int gk = bk;
+#pragma unroll
+  for (int o = GROUP / 2; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(gb, o, GROUP);
+    const int ok = __shfl_xor(gk, o, GROUP);
+    if (ob < gb || (ob == gb && ok < gk)) {
+      gb = ob;
+      gk = ok;
+    }
+  }
+  if (gk == INT32_MAX) {
+    out[0] = out[1] = out[2] = 0.0;
+    return;
+  }
+  const uint64_t own = __ballot(bk == gk && best == gb);
+  const int src = __ffsll((unsigned long long)(own >> (threadIdx.x & 32u)) & 0xffffffffull) - 1;
+  double w[3];
+  for (int a = 0; a < 3; ++a) w[a] = __shfl(bw[a], src, GROUP);
+  bary_velocity(L.V, m.tri + 3 * gk, w, out);
+}
+
 // Link of fluid node xb in direction i at level t+1: q = the smallest s in (0, 1] where xb - s c_i
 // meets a triangle, uw barycentric there; otherwise q = 1/2 and the closest-point velocity of the
 // link's midpoint.

@@ -6,7 +6,7 @@
 // array is a contiguous 64-lane access (the +-x shifted loads straddle one extra cache line,
 // which the neighbouring lanes of the same workgroup bring into L2).  Population arrays are
 // structure-of-arrays, so each direction streams through HBM exactly once per step.
-#include "elbm_internal.hpp"
+#include "context.hpp"
 
 namespace elbm {
 
@@ -73,15 +73,20 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
   const int y = ty * blockDim.y + threadIdx.y;
   if (x >= a.nx || y >= a.ny) return;
   const uint32_t n = (uint32_t)((z * a.ny + y) * a.nx + x);
-  if (FLAGS) {
-    if (a.flags[n] & (FL_SOLID | FL_SPECIAL)) return;
-  }
+  // the flag byte is loaded together with the 27 gathers (all sources are in range for every
+  // node), so that waiting for it does not delay them; solid and listed nodes then leave
+  const bool skip = FLAGS && (a.flags[n] & (FL_SOLID | FL_SPECIAL));
   uint32_t xs[3], rs[9];
   gather_offsets(x, y, z, a, xs, rs);
   const E* __restrict__ A = (const E*)a.A;
   float f[27];  // deviations f - W
 #pragma unroll
   for (int i = 0; i < 27; ++i) f[i] = C::load_dev(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]));
+  if (FLAGS) {
+    // compiler-only barrier: keeps the gathers issued above the branch (no machine instruction)
+    __asm__ volatile("" ::: "memory");
+    if (skip) return;
+  }
   if (!a.stream_only) {
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
     if (FORCE) {
@@ -90,9 +95,18 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
       Fz = a.F[2 * (size_t)a.N + n];
     }
     const KbcOut<float> r = kbc_collide<float, FORCE, STAB>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
-    if (a.fp64 && needs_fp64(r, a.thr)) {
-      const uint32_t k = atomicAdd(a.fix_count, 1u);
-      a.fix_list[k] = n;
+    if (a.fp64) {
+      // one queue reservation per wavefront for all of its nodes that need the FP64 collision
+      const bool q = needs_fp64(r, a.thr);
+      const uint64_t m = __ballot(q);
+      if (m) {
+        const int lane = (int)__lane_id();
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(a.fix_count, (uint32_t)__popcll(m));
+        base = __shfl(base, leader);
+        if (q) a.fix_list[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = n;
+      }
     }
     if (FLAGS && a.slab && x < 3)
       macro_from_post<S, FORCE>(f, Fx, Fy, Fz, a.slab_next, (size_t)3 * a.ny * a.nz, slab_index(x, y, z, a.ny));
@@ -125,6 +139,7 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
     const uint32_t e = a.fix_list[k];
     const uint32_t n = e & ~FIX_PRE;
+    if (n >= a.N) continue;  // never written so; guards the accesses below
     double f[27];  // deviations f - W
     if (e & FIX_PRE) {
       // wall node: its reconstructed pre-collision deviations were left in B
@@ -189,13 +204,13 @@ static SweepArgs sweep_args(elbm_ctx* c) {
   return a;
 }
 
-// Launch shape (measured on 256^3 and 512^3): 256-thread workgroups, x-extent the widest power of
-// two <= 256 (<= 128 for rows longer than 256) that divides nx (at least 32), the rest along y.  FP32
-// rows longer than 256 take the tiles in the XCD-contiguous order of k_sweep (on 512^3: 5.58 TB/s
-// against 5.30 in dispatch order); 2-byte storage is faster in plain dispatch order.
+// Launch shape: 256-thread workgroups, x-extent the widest power of two <= 256 (<= 128 for rows
+// longer than 256) that divides nx (at least 32), the rest along y.  Tile order (FP32): the
+// XCD-contiguous order of k_sweep measured faster only where a row is 4 tiles of 128 (512^3: 5.58
+// TB/s against 5.30 in dispatch order); plain dispatch order measured faster at nx = 384 (5.40
+// against 5.14 TB/s) and nx = 1600 (+2 %); 2-byte storage is faster in plain dispatch order.
 static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const bool remap = storage == ELBM_STORAGE_F32 && nx > 256;
   int bx = nx > 256 ? 128 : 256;
   while (bx > 32 && (nx % bx) != 0) bx >>= 1;
   if (nx < bx) bx = 32;
@@ -204,6 +219,8 @@ static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
   a.gx = (nx + bx - 1) / bx;
   a.gy = (ny + by - 1) / by;
   a.tiles = a.gx * a.gy * nz;
+  // (the 1-D tile grid also serves shapes beyond the 65535 limit of the y and z grid extents)
+  const bool remap = (storage == ELBM_STORAGE_F32 && bx == 128 && nx == 4 * bx) || a.gy > 65535 || nz > 65535;
   a.remap = remap ? 1 : 0;
   grid = remap ? dim3(a.tiles, 1, 1) : dim3(a.gx, a.gy, nz);
 }

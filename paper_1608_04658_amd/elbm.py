@@ -367,10 +367,18 @@ class Lattice:
         elbm_set_geometry(self.ctx, list(bodies))
 
     def _mesh_tensors(self, verts, vels):
+        """Device FP64 [nv, 3] tensors from host arrays, or the given device tensors as they are."""
         torch = self.torch
-        X = torch.as_tensor(np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 3)).cuda()
-        V = None if vels is None else torch.as_tensor(np.ascontiguousarray(vels, dtype=np.float64).reshape(-1, 3)).cuda()
-        return X, V
+
+        def dev(a):
+            if a is None:
+                return None
+            if isinstance(a, torch.Tensor) and a.is_cuda:
+                if a.dtype != torch.float64 or not a.is_contiguous() or a.dim() != 2 or a.shape[1] != 3:
+                    raise ElbmError("mesh arrays on the device must be contiguous float64 [nv, 3]")
+                return a
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1, 3)).cuda()
+        return dev(verts), dev(vels)
 
     def set_mesh(self, verts, tris, box_lo, box_hi, vels=None, center=None):
         """Triangulated surface at the current time level (host arrays); then set_bodies with a body

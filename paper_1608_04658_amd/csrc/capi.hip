@@ -37,7 +37,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t pop[2], cnt, fix_list, flags, macro, slab, blist, brec, ring, force_partial, scratch, scan_tmp, adj_gUR, adj_side,
-      adj_gamp, mesh_tri, mesh_X[2], mesh_V[2], mesh_start[2], mesh_items[2], mesh_cursor, total;
+      adj_gamp, mesh_tri, mesh_X[2], mesh_V[2], mesh_start[2], mesh_items[2], mesh_cursor, free_hist, free_U1, total;
   int64_t mesh_cap;
   int64_t scan_blocks;
   int64_t cap;
@@ -108,6 +108,8 @@ Layout layout(const elbm_params* p) {
     L.brec = take(sizeof(double) * 6 * nbm * (size_t)L.cap);
     L.ring = take(sizeof(double) * 6 * ELBM_MAX_BODIES * ring);
     L.force_partial = take(sizeof(double) * 64 * 6 * ELBM_MAX_BODIES);
+    L.free_hist = take(sizeof(FreeState) * FREE_HIST * ELBM_MAX_BODIES);
+    L.free_U1 = take(sizeof(double) * 3 * ELBM_MAX_BODIES);
     L.scan_blocks = (int64_t)((N + 255) / 256);
     L.scan_tmp = take(sizeof(uint32_t) * 2 * (size_t)L.scan_blocks);
   }
@@ -150,18 +152,59 @@ bool free_inside(const elbm_ctx* c, const double x[3], double r) {
   return true;
 }
 
-// Force of the step that produced the current time level, for each free body (synchronises).
-hipError_t free_read_forces(elbm_ctx* c) {
-  double rec[6 * ELBM_MAX_BODIES];
-  const int slot = (int)(c->t % c->p.force_ring);
-  hipError_t e = hipMemcpyAsync(rec, c->ring + (size_t)slot * ELBM_MAX_BODIES * 6, sizeof rec, hipMemcpyDeviceToHost,
-                                c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+// The device's free-body state of level lv into the host copy (waits for that level only).
+hipError_t free_read_level(elbm_ctx* c, int64_t lv) {
+  FreeState st[ELBM_MAX_BODIES];
+  hipError_t e = hipStreamWaitEvent(c->aux, c->free_ev[lv % FREE_HIST], 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(st, c->free_hist + (size_t)(lv % FREE_HIST) * ELBM_MAX_BODIES, sizeof st,
+                       hipMemcpyDeviceToHost, c->aux);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->aux);
   if (e != hipSuccess) return e;
-  for (int k = 0; k < c->nb; ++k)
-    if (c->freeb[k].on)
-      for (int a = 0; a < 3; ++a) c->freeb[k].F[a] = rec[6 * k + a];
+  for (int k = 0; k < c->nb; ++k) {
+    if (!c->freeb[k].on) continue;
+    for (int a = 0; a < 3; ++a) {
+      c->freeb[k].x[a] = st[k].x[a];
+      c->freeb[k].u[a] = st[k].u[a];
+      c->freeb[k].F[a] = st[k].F[a];
+    }
+  }
+  c->free_lv = lv;
   return hipSuccess;
+}
+
+// Position and velocity at level c->t from the host copy at level c->t or c->t - 1 (explicit Euler
+// in the operation order of the device integrator).
+void free_derive(elbm_ctx* c) {
+#pragma clang fp contract(off)
+  for (int k = 0; k < c->nb; ++k) {
+    auto& fb = c->freeb[k];
+    if (!fb.on) continue;
+    for (int a = 0; a < 3; ++a) {
+      if (c->free_lv == c->t) {
+        fb.xt[a] = fb.x[a];
+        fb.ut[a] = fb.u[a];
+      } else {
+        fb.xt[a] = fb.x[a] + fb.u[a];
+        fb.ut[a] = fb.u[a] + fb.F[a] / fb.m + fb.ab[a];
+      }
+    }
+  }
+}
+
+// The free bodies keep their state when the populations are replaced at level t: it is read back
+// (synchronises) and stored again as the state of level t.
+hipError_t free_reanchor(elbm_ctx* c, int64_t t) {
+  if (!c->n_free) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && c->free_lv != c->t) e = free_read_level(c, c->t);
+  if (e != hipSuccess) return e;
+  c->free_lv = t;
+  const int64_t t_old = c->t;
+  c->t = t;
+  free_derive(c);
+  c->t = t_old;
+  return free_init(c);
 }
 
 }  // namespace
@@ -239,7 +282,11 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->nb = 0;
   c->moving = false;
   c->n_free = 0;
-  c->free_force_pending = false;
+  c->free_lv = 0;
+  c->free_hist = L.geometry ? (FreeState*)(c->ws + L.free_hist) : nullptr;
+  c->free_U1 = L.geometry ? (double*)(c->ws + L.free_U1) : nullptr;
+  c->aux = nullptr;
+  for (int k = 0; k < FREE_HIST; ++k) c->free_ev[k] = nullptr;
   for (int k = 0; k < ELBM_MAX_BODIES; ++k) c->freeb[k].on = false;
   c->t = 0;
   c->err[0] = 0;
@@ -254,9 +301,16 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_gUR, 0, sizeof(double) * 4 * (size_t)c->N, c->stream);
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_side, 0, sizeof(float) * 9 * (size_t)p->ny * p->nz, c->stream);
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_gamp, 0, sizeof(double) * ELBM_MAX_BODIES, c->stream);
+  if (e == hipSuccess && L.geometry) e = hipMemsetAsync(c->free_U1, 0, sizeof(double) * 3 * ELBM_MAX_BODIES, c->stream);
+  if (e == hipSuccess && L.geometry) e = hipStreamCreate(&c->aux);  // default priority
+  for (int k = 0; k < FREE_HIST && e == hipSuccess && L.geometry; ++k)
+    e = hipEventCreateWithFlags(&c->free_ev[k], hipEventDisableTiming);
   if (e != hipSuccess) {
+    for (int k = 0; k < FREE_HIST; ++k)
+      if (c->free_ev[k]) (void)hipEventDestroy(c->free_ev[k]);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     delete c;
-    return fail(nullptr, ELBM_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
+    return fail(nullptr, ELBM_EDEVICE, "context set-up: %s", hipGetErrorString(e));
   }
   if (L.geometry) {
     // channel without bodies: the inlet face is the static boundary list
@@ -283,6 +337,9 @@ static void free_events(elbm_ctx* c) {
 int elbm_destroy(elbm_ctx* c) {
   if (!c) return ELBM_EINVAL;
   free_events(c);
+  for (int k = 0; k < FREE_HIST; ++k)
+    if (c->free_ev[k]) (void)hipEventDestroy(c->free_ev[k]);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
   return ELBM_OK;
 }
@@ -297,6 +354,7 @@ int elbm_init_equilibrium(elbm_ctx* c, const double* rho_dev, const double* u_de
   if (!c) return ELBM_EINVAL;
   if (!u_dev) return fail(c, ELBM_EINVAL, "u_dev is NULL");
   // both buffers: nodes that stay solid are never written by a step
+  HIP_OK(c, free_reanchor(c, 0));
   c->cur = 1;
   HIP_OK(c, launch_init_eq(c, rho_dev, u_dev));
   c->cur = 0;
@@ -309,6 +367,7 @@ int elbm_init_equilibrium(elbm_ctx* c, const double* rho_dev, const double* u_de
 int elbm_write_populations(elbm_ctx* c, const double* pop_dev, int64_t t) {
   if (!c) return ELBM_EINVAL;
   if (!pop_dev || t < 0) return fail(c, ELBM_EINVAL, "bad arguments");
+  HIP_OK(c, free_reanchor(c, t));
   c->t = t;
   HIP_OK(c, launch_write_pop(c, pop_dev));
   if (c->flags) HIP_OK(c, geometry_init(c));
@@ -368,7 +427,7 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
   c->nb = nb;
   c->mesh_body = (nb > 0 && bodies[nb - 1].kind == ELBM_BODY_MESH) ? nb - 1 : -1;
   c->n_free = 0;
-  c->free_force_pending = false;
+  c->free_lv = c->t;
   for (int k = 0; k < ELBM_MAX_BODIES; ++k) c->freeb[k].on = false;
   for (int k = 0; k < nb; ++k) {
     c->bodies[k] = bodies[k];
@@ -382,9 +441,12 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
       fb.u[a] = b.vel[a];
       fb.F[a] = 0.0;
       fb.ab[a] = (1.0 - 1.0 / b.density_ratio) * b.gravity[a];
+      fb.xt[a] = b.center[a];
+      fb.ut[a] = b.vel[a];
     }
     c->n_free += 1;
   }
+  if (c->n_free) HIP_OK(c, free_init(c));
   c->moving = moving;
   if (!c->flags) {
     if (nb > 0) return fail(c, ELBM_ESTATE, "context created with max_bodies = 0");
@@ -465,6 +527,8 @@ int elbm_body_state(elbm_ctx* c, int32_t body, double pos[3], double vel[3]) {
   if (!c) return ELBM_EINVAL;
   if (body < 0 || body >= c->nb || !pos || !vel) return fail(c, ELBM_EINVAL, "bad arguments");
   if (c->freeb[body].on) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (c->free_lv != c->t) HIP_OK(c, free_read_level(c, c->t));
     for (int a = 0; a < 3; ++a) {
       pos[a] = c->freeb[body].x[a];
       vel[a] = c->freeb[body].u[a];
@@ -494,14 +558,14 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
   const bool geo = c->flags != nullptr;
   for (int32_t s = 0; s < nsteps; ++s) {
     if (c->n_free) {
-      if (c->free_force_pending) {
-        HIP_OK(c, free_read_forces(c));
-        c->free_force_pending = false;
-      }
+      // positions at t and t+1 from the state of level t or t-1 (the latter read one step behind
+      // the device: the step before is still running meanwhile)
+      if (c->free_lv < c->t - 1) HIP_OK(c, free_read_level(c, c->t - 1));
+      free_derive(c);
       for (int k = 0; k < c->nb; ++k) {
         if (!c->freeb[k].on) continue;
         double x1[3];
-        for (int a = 0; a < 3; ++a) x1[a] = c->freeb[k].x[a] + c->freeb[k].u[a];
+        for (int a = 0; a < 3; ++a) x1[a] = c->freeb[k].xt[a] + c->freeb[k].ut[a];
         if (!free_inside(c, x1, c->bodies[k].radius))
           return fail(c, ELBM_ESTATE, "free body %d would come closer than allowed to a face at t = %lld", k,
                       (long long)(c->t + 1));
@@ -524,17 +588,7 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
     HIP_OK(c, launch_fixup(c));  // bulk and wall nodes queued for the FP64 collision
     c->fix_par ^= 1;
     if (geo) HIP_OK(c, launch_force_reduce(c));
-    if (c->n_free) {
-      // advance the free bodies to the time level just produced; its force is read at the next step
-      for (int k = 0; k < c->nb; ++k) {
-        if (!c->freeb[k].on) continue;
-        for (int a = 0; a < 3; ++a) {
-          c->freeb[k].x[a] = bd.b[k].c1[a];
-          c->freeb[k].u[a] = bd.b[k].U1[a];
-        }
-      }
-      c->free_force_pending = true;
-    }
+    if (c->n_free) HIP_OK(c, free_commit(c));  // the free bodies' state of level t+1 on the device
     if (c->mesh_next_set) {
       c->mesh_cur ^= 1;
       c->mesh_next_set = false;
@@ -625,6 +679,7 @@ int elbm_load_state(elbm_ctx* c, const void* pop_dev, int64_t t) {
   if (!pop_dev || t < 0) return fail(c, ELBM_EINVAL, "bad arguments");
   const size_t bytes = 27 * (size_t)c->N * storage_bytes(c->p.storage);
   HIP_OK(c, hipMemcpyAsync(c->pop[c->cur], pop_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, free_reanchor(c, t));
   c->t = t;
   if (c->flags) HIP_OK(c, geometry_init(c));
   return ELBM_OK;

@@ -37,13 +37,23 @@ struct elbm_ctx {
   int32_t nb;
   elbm_body bodies[ELBM_MAX_BODIES];
   bool moving;
-  // free bodies (two-way coupling): state at time level t and the force of the step producing t
+  // free bodies (two-way coupling), integrated on the device: after each step a one-workgroup
+  // kernel advances the state (elbm::FreeState, a ring over time levels) with the step's force and
+  // writes the velocity at t+1 for the next step.  The host keeps a copy of the state at one time
+  // level (free_lv), read one step behind the device, from which it derives the positions it
+  // needs to place the geometry work (exact, the same FP64 operations as the device).
   struct FreeBody {
     bool on;
-    double x[3], u[3], F[3], m, ab[3];  // ab = (1 - 1/density_ratio) g
+    double x[3], u[3], F[3];  // state at level free_lv
+    double m, ab[3];          // mass, (1 - 1/density_ratio) g
+    double xt[3], ut[3];      // position and velocity at the level of the step being launched
   } freeb[ELBM_MAX_BODIES];
   int n_free;
-  bool free_force_pending;  // F of the last step is still on the device
+  int64_t free_lv;
+  elbm::FreeState* free_hist;  // device [FREE_HIST][MAX_BODIES]
+  double* free_U1;             // device [MAX_BODIES][3]
+  hipStream_t aux;             // reads of the state, behind an event of the main stream
+  hipEvent_t free_ev[4];       // recorded after the state of level t is written (slot t % FREE_HIST)
   int stab;         // STAB_KBC, STAB_EXACT or STAB_LBGK (from the context flags)
   // triangulated body (elbm_set_mesh): slot mesh_cur holds time level t; slot mesh_cur ^ 1 level
   // t+1 when mesh_next_set (else level t+1 = level t)
@@ -101,6 +111,9 @@ Box full_box(const elbm_ctx* c);
 dim3 grid_for(long n);
 Bodies make_bodies(const elbm_ctx* c, double t);
 constexpr int MESH_CELLS = 1 << 16;
+constexpr int FREE_HIST = 4;
+hipError_t free_init(elbm_ctx* c);
+hipError_t free_commit(elbm_ctx* c);
 hipError_t mesh_upload(elbm_ctx* c, int slot, const double* X, const double* V);
 hipError_t mesh_copy_tris(elbm_ctx* c, const int32_t* tris, int32_t nt);
 hipError_t mesh_mask(elbm_ctx* c, const Bodies& bd, int level, uint8_t bits);

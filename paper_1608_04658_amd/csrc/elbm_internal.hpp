@@ -477,6 +477,30 @@ struct Bodies {
   int32_t mesh;  // index of the triangulated body, -1 if none
   BodyDev b[ELBM_MAX_BODIES];
   MeshDev m;
+  // free bodies: their velocity at t+1 depends on the force of the step that produced t, which the
+  // device-side integrator holds; U1dev [MAX_BODIES][3] replaces b[k].U1 where bit k of free_mask is set
+  const double* U1dev;
+  uint32_t free_mask;
+  int32_t pad2;
+};
+
+// Translational velocity of body k at t+1.
+__device__ inline void body_U1(const Bodies& bd, int k, double* u) {
+  if ((bd.free_mask >> k) & 1u) {
+    u[0] = bd.U1dev[3 * k];
+    u[1] = bd.U1dev[3 * k + 1];
+    u[2] = bd.U1dev[3 * k + 2];
+  } else {
+    u[0] = bd.b[k].U1[0];
+    u[1] = bd.b[k].U1[1];
+    u[2] = bd.b[k].U1[2];
+  }
+}
+
+// State of a free body at one time level: position, velocity, and the force of the step that
+// produced the level (explicit Euler of Newton's equations, Sec. IV.A).
+struct FreeState {
+  double x[3], u[3], F[3];
 };
 
 // Strictly-inside test (FP64, operations in the written order, no contraction).

@@ -76,13 +76,14 @@ Bodies make_bodies(const elbm_ctx* c, double t) {
       continue;
     }
     if (c->freeb[k].on) {
-      // explicit Euler of Newton's equations from the state at the context's time level
+      // explicit Euler of Newton's equations: position and velocity at t (fb.xt, fb.ut, derived
+      // by the step loop), position at t+1; the velocity at t+1 is the device integrator's
       const auto& fb = c->freeb[k];
       for (int a = 0; a < 3; ++a) {
-        d.c0[a] = fb.x[a];
-        d.U0[a] = fb.u[a];
-        d.c1[a] = fb.x[a] + fb.u[a];
-        d.U1[a] = fb.u[a] + fb.F[a] / fb.m + fb.ab[a];
+        d.c0[a] = fb.xt[a];
+        d.U0[a] = fb.ut[a];
+        d.c1[a] = fb.xt[a] + fb.ut[a];
+        d.U1[a] = 0.0;
       }
     } else {
       host_kinematics(b, t, d.c0, d.U0);
@@ -96,6 +97,11 @@ Bodies make_bodies(const elbm_ctx* c, double t) {
     }
   }
   for (int k = c->nb; k < ELBM_MAX_BODIES; ++k) bd.b[k] = BodyDev{};
+  bd.U1dev = c->free_U1;
+  bd.free_mask = 0;
+  for (int k = 0; k < c->nb; ++k)
+    if (c->freeb[k].on) bd.free_mask |= 1u << k;
+  bd.pad2 = 0;
   return bd;
 }
 
@@ -385,9 +391,11 @@ __global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, v
       for (int a = 0; a < 3; ++a) uw[a] = (float)v[a];
     } else {
       const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
-      uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
-      uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
-      uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+      double U1[3];
+      body_U1(bd, kb, U1);
+      uw[0] = (float)(U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
+      uw[1] = (float)(U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
+      uw[2] = (float)(U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
     }
     const uint32_t nbm = h.fluid0 & ~(1u << 13);
     const float rs = gsum(lane != 13 ? h.R : 0.f);
@@ -523,6 +531,87 @@ __global__ void k_force_final(const double* partial, int32_t nb, double* out) {
   double s = 0.0;
   for (int p = 0; p < FORCE_PARTS; ++p) s += partial[p * ELBM_MAX_BODIES * 6 + comp];
   out[comp] = s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Free bodies on the device (Sec. IV.A, explicit Euler with unit time step):
+//   x(t+1) = x(t) + u(t),  u(t+1) = u(t) + F(t)/m + (1 - 1/density_ratio) g,
+// F(t) the momentum-exchange force of the step that produced t.  The sums are written in the
+// order of the host's derivation, so both sides agree bit for bit.
+struct FreeParams {
+  double m[ELBM_MAX_BODIES];
+  double ab[ELBM_MAX_BODIES][3];
+  FreeState s[ELBM_MAX_BODIES];  // k_free_write: the state to store
+  uint32_t mask;
+};
+
+__device__ inline double euler_u(double u, double F, double m, double ab) {
+#pragma clang fp contract(off)
+  return u + F / m + ab;
+}
+
+// State of one level from the host, and the velocity at the next level.
+__global__ void k_free_write(FreeParams p, FreeState* slot, double* U1) {
+  const int k = threadIdx.x;
+  if (k >= ELBM_MAX_BODIES || !((p.mask >> k) & 1u)) return;
+  slot[k] = p.s[k];
+  for (int a = 0; a < 3; ++a) U1[3 * k + a] = euler_u(p.s[k].u[a], p.s[k].F[a], p.m[k], p.ab[k][a]);
+}
+
+// After the step t -> t+1: the state of level t+1 from that of level t and the step's force (in
+// the ring), and the velocity at t+2 for the next step.
+__global__ void k_free_commit(FreeParams p, const FreeState* prev, FreeState* next, const double* force, double* U1) {
+#pragma clang fp contract(off)
+  const int k = threadIdx.x;
+  if (k >= ELBM_MAX_BODIES || !((p.mask >> k) & 1u)) return;
+  FreeState s;
+  for (int a = 0; a < 3; ++a) {
+    s.x[a] = prev[k].x[a] + prev[k].u[a];
+    s.u[a] = euler_u(prev[k].u[a], prev[k].F[a], p.m[k], p.ab[k][a]);
+    s.F[a] = force[6 * k + a];
+  }
+  next[k] = s;
+  for (int a = 0; a < 3; ++a) U1[3 * k + a] = euler_u(s.u[a], s.F[a], p.m[k], p.ab[k][a]);
+}
+
+static FreeParams free_params(const elbm_ctx* c) {
+  FreeParams p{};
+  for (int k = 0; k < c->nb; ++k) {
+    if (!c->freeb[k].on) continue;
+    p.mask |= 1u << k;
+    p.m[k] = c->freeb[k].m;
+    for (int a = 0; a < 3; ++a) {
+      p.ab[k][a] = c->freeb[k].ab[a];
+      p.s[k].x[a] = c->freeb[k].x[a];
+      p.s[k].u[a] = c->freeb[k].u[a];
+      p.s[k].F[a] = c->freeb[k].F[a];
+    }
+  }
+  return p;
+}
+
+// The host copy (level free_lv) to the device ring, and the velocity at the next level.
+hipError_t free_init(elbm_ctx* c) {
+  if (!c->n_free) return hipSuccess;
+  const FreeParams p = free_params(c);
+  FreeState* slot = c->free_hist + (size_t)(c->free_lv % FREE_HIST) * ELBM_MAX_BODIES;
+  hipLaunchKernelGGL(k_free_write, dim3(1), dim3(64), 0, c->stream, p, slot, c->free_U1);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(c->free_ev[c->free_lv % FREE_HIST], c->stream);
+  return e;
+}
+
+// Integrate after the step c->t -> c->t + 1 (its force reduced into the ring).
+hipError_t free_commit(elbm_ctx* c) {
+  if (!c->n_free) return hipSuccess;
+  const FreeParams p = free_params(c);
+  const FreeState* prev = c->free_hist + (size_t)(c->t % FREE_HIST) * ELBM_MAX_BODIES;
+  FreeState* next = c->free_hist + (size_t)((c->t + 1) % FREE_HIST) * ELBM_MAX_BODIES;
+  const double* force = c->ring + (size_t)((c->t + 1) % c->p.force_ring) * ELBM_MAX_BODIES * 6;
+  hipLaunchKernelGGL(k_free_commit, dim3(1), dim3(64), 0, c->stream, p, prev, next, force, c->free_U1);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(c->free_ev[(c->t + 1) % FREE_HIST], c->stream);
+  return e;
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -106,13 +106,17 @@ typedef struct elbm_params {
  *   m = density_ratio * rho0 * (4/3) pi radius^3,
  * where F(t) is the force of the step that produced time level t (zero at the time level at
  * which the geometry is set).  center and vel are the position and velocity at the current
- * time level; amp, period and omega must be 0.  Every elbm_step of a context with free bodies
- * reads the previous step's force back to the host (one synchronisation per step).  A free
- * sphere must stay at least 3 nodes inside every face (6 from the inlet and outlet in channel
- * mode); a step that would take it closer fails with ELBM_ESTATE.  Not available with
- * ELBM_FLAG_ADJOINT. */
+ * time level; amp and period must be 0, and omega too unless the sphere rotates freely.
+ * With motion = ELBM_MOTION_FREE_ROTATING the torque M about the centre (of the same step) also
+ * turns the sphere:  w(t+1) = w(t) + M(t)/I,  I = (2/5) m radius^2 (solid sphere), omega being
+ * w at the current time level; the wall velocity is u + w x (x - c).  The integration runs on the
+ * device after each step; the host reads the state one step behind (no step waits for the
+ * previous one to end).  A free sphere must stay at least 3 nodes inside every face (6 from the
+ * inlet and outlet in channel mode); a step that would take it closer fails with ELBM_ESTATE.
+ * Not available with ELBM_FLAG_ADJOINT. */
 #define ELBM_MOTION_PRESCRIBED 0
 #define ELBM_MOTION_FREE 1
+#define ELBM_MOTION_FREE_ROTATING 2
 
 typedef struct elbm_body {
   int32_t kind;         /* ELBM_BODY_* */
@@ -207,8 +211,12 @@ int elbm_set_mesh(struct elbm_ctx* ctx, const int32_t* tris_dev, int32_t nt, con
 int elbm_mesh_next(struct elbm_ctx* ctx, const double* verts_dev, const double* vels_dev, const double center[3]);
 
 /* Position and velocity of body `body` at the current time level (host arrays of 3):
- * the prescribed motion evaluated at t, or the integrated state of a free body. */
+ * the prescribed motion evaluated at t, or the integrated state of a free body (synchronises). */
 int elbm_body_state(struct elbm_ctx* ctx, int32_t body, double pos[3], double vel[3]);
+
+/* Angular velocity of body `body` at the current time level (host array of 3): the prescribed
+ * omega, or the integrated one of a freely rotating sphere (synchronises). */
+int elbm_body_spin(struct elbm_ctx* ctx, int32_t body, double omega[3]);
 
 /* Bind a body-force field F_dev (dev [3][N] FP32, borrowed until replaced) or
  * NULL for none.  Needs ELBM_FLAG_BODY_FORCE.  The collision adds

@@ -52,7 +52,7 @@ class Body(ctypes.Structure):
                 ("track_c", (ctypes.c_double * 3) * 2), ("track_U", (ctypes.c_double * 3) * 2),
                 ("mesh_X", ctypes.POINTER(ctypes.c_double) * 2), ("mesh_V", ctypes.POINTER(ctypes.c_double) * 2),
                 ("mesh_tri", ctypes.POINTER(ctypes.c_int32)), ("mesh_nv", ctypes.c_int32), ("mesh_nt", ctypes.c_int32),
-                ("mesh_t", ctypes.c_double)]
+                ("mesh_t", ctypes.c_double), ("track_W", (ctypes.c_double * 3) * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -192,9 +192,10 @@ def make_body(kind="sphere", center=(0, 0, 0), radius=0.0, normal=(0, 0, 0), amp
               direction=(0, 0, 0), vel=(0, 0, 0), omega=(0, 0, 0), motion="prescribed", density_ratio=0.0,
               gravity=(0, 0, 0)) -> Body:
     """A body for ``or_step``.  motion="free": a sphere moved by the fluid force, gravity and
-    buoyancy (its track is set by ``Simulation`` each step; density_ratio = rho_s / rho_f)."""
+    buoyancy (its track is set by ``Simulation`` each step; density_ratio = rho_s / rho_f);
+    motion="free_rotating": the same, also turned by the torque (omega = initial angular velocity)."""
     b = Body()
-    b.tracked = 1 if motion == "free" else 0
+    b.tracked = 1 if motion in ("free", "free_rotating") else 0
     b.kind = 0 if kind == "sphere" else 1
     b.p0[:] = list(map(float, center))
     b.radius = float(radius)
@@ -299,16 +300,22 @@ class Simulation:
         # freely moving spheres (two-way coupling, Sec. IV.A): Newton's equations
         #   dx/dt = u,  du/dt = F/m + (1 - rho_f/rho_s) g,  m = rho_s (4/3) pi R^3,
         # explicit Euler with unit time step, F the momentum-exchange force of the last step
-        # (zero before the first one):  x(t+1) = x(t) + u(t),  u(t+1) = u(t) + F(t)/m + (1 - 1/ratio) g
+        # (zero before the first one):  x(t+1) = x(t) + u(t),  u(t+1) = u(t) + F(t)/m + (1 - 1/ratio) g;
+        # a rotating one also  w(t+1) = w(t) + M(t)/I,  I = (2/5) m R^2 (solid sphere), M the torque
+        # about its centre of the last step
         self.free = {}
         for k, spec in enumerate(bodies):
-            if isinstance(spec, dict) and spec.get("motion") == "free":
+            if isinstance(spec, dict) and spec.get("motion") in ("free", "free_rotating"):
                 ratio = float(spec["density_ratio"])
                 R = float(spec["radius"])
-                self.free[k] = dict(m=ratio * rho0 * (4.0 / 3.0) * math.pi * R ** 3,
+                m = ratio * rho0 * (4.0 / 3.0) * math.pi * R ** 3
+                rot = spec.get("motion") == "free_rotating"
+                self.free[k] = dict(m=m, I=0.4 * m * R * R, rot=rot,
                                     ab=(1.0 - 1.0 / ratio) * np.asarray(spec.get("gravity", (0, 0, 0)), float),
                                     x=np.asarray(spec["center"], float).copy(),
-                                    u=np.asarray(spec.get("vel", (0, 0, 0)), float).copy(), F=np.zeros(3))
+                                    u=np.asarray(spec.get("vel", (0, 0, 0)), float).copy(), F=np.zeros(3),
+                                    w=np.asarray(spec.get("omega", (0, 0, 0)) if rot else (0, 0, 0), float).copy(),
+                                    M=np.zeros(3))
         # triangulated bodies (Sec. IV.B): vertex positions and velocities of the current time level
         # and, when mesh_next() was called, of the next one (else the mesh holds still)
         self.meshes = {}
@@ -372,14 +379,20 @@ class Simulation:
             b = self.bodies[k]
             x1 = fb["x"] + fb["u"]
             u1 = fb["u"] + fb["F"] / fb["m"] + fb["ab"]
+            w1 = fb["w"] + fb["M"] / fb["I"] if fb["rot"] else fb["w"]
             b.track_t = float(self.t)
             for a in range(3):
                 b.track_c[0][a], b.track_c[1][a] = fb["x"][a], x1[a]
                 b.track_U[0][a], b.track_U[1][a] = fb["u"][a], u1[a]
+                b.track_W[0][a], b.track_W[1][a] = fb["w"][a], w1[a]
 
     def body_state(self, k: int):
         """Centre and velocity of free body k at the current time level."""
         return self.free[k]["x"].copy(), self.free[k]["u"].copy()
+
+    def body_spin(self, k: int):
+        """Angular velocity of free body k at the current time level."""
+        return self.free[k]["w"].copy()
 
     def step(self, n: int = 1, record_masks: list | None = None):
         for _ in range(n):
@@ -411,7 +424,9 @@ class Simulation:
                 b = self.bodies[k]
                 fb["x"] = np.array([b.track_c[1][a] for a in range(3)])
                 fb["u"] = np.array([b.track_U[1][a] for a in range(3)])
+                fb["w"] = np.array([b.track_W[1][a] for a in range(3)])
                 fb["F"] = self.forces[-1][k, :3].copy()
+                fb["M"] = self.forces[-1][k, 3:].copy()
         return self
 
     def moments(self):

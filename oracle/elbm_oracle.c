@@ -308,6 +308,7 @@ typedef struct {
   const int32_t *mesh_tri;
   int32_t mesh_nv, mesh_nt;
   double mesh_t;
+  double track_W[2][3];   /* tracked: angular velocity at t and t + 1 (a freely rotating sphere) */
 } or_body;
 
 typedef struct {
@@ -338,10 +339,22 @@ void or_kinematics(const or_body *b, double t, double c[3], double U[3]) {
   }
 }
 
-static void rigid_velocity(const or_body *b, const double c[3], const double U[3], const double x[3],
+/* Angular velocity of body b at time t: the prescribed omega, or the track of a tracked body. */
+static void body_omega(const or_body *b, double t, double W[3]) {
+  if (b->tracked) {
+    const int k = (t == b->track_t) ? 0 : ((t == b->track_t + 1.0) ? 1 : -1);
+    for (int a = 0; a < 3; ++a) W[a] = k >= 0 ? b->track_W[k][a] : NAN;
+    return;
+  }
+  for (int a = 0; a < 3; ++a) W[a] = b->omega[a];
+}
+
+/* Rigid-body velocity U + W x (x - c) at time t. */
+static void rigid_velocity(const or_body *b, const double c[3], const double U[3], double t, const double x[3],
                            double out[3]) {
   double r[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
-  const double *w = b->omega;
+  double w[3];
+  body_omega(b, t, w);
   out[0] = U[0] + (w[1] * r[2] - w[2] * r[1]);
   out[1] = U[1] + (w[2] * r[0] - w[0] * r[2]);
   out[2] = U[2] + (w[0] * r[1] - w[1] * r[0]);
@@ -360,7 +373,7 @@ static void body_velocity(const or_body *b, const double c[3], const double U[3]
     if (lv >= 0) or_mesh_closest_velocity(b->mesh_X[lv], b->mesh_V[lv], b->mesh_tri, b->mesh_nt, x, out, 0);
     return;
   }
-  rigid_velocity(b, c, U, x, out);
+  rigid_velocity(b, c, U, t, x, out);
 }
 
 
@@ -864,7 +877,7 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
                 for (int a = 0; a < 3; ++a) uw[i][a] = uwm[i][a];
               } else {
                 double xw[3] = {xb[0] - q[i] * cxi(i), xb[1] - q[i] * cyi(i), xb[2] - q[i] * czi(i)};
-                rigid_velocity(&bodies[bodyof[i]], c1[bodyof[i]], U1[bodyof[i]], xw, uw[i]);
+                rigid_velocity(&bodies[bodyof[i]], c1[bodyof[i]], U1[bodyof[i]], t + 1.0, xw, uw[i]);
               }
               double uf[3];
               long nf = nbr(g, x, y, z, cxi(i), cyi(i), czi(i));

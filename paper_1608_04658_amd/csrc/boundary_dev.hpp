@@ -370,11 +370,12 @@ __device__ inline void link_geometry(const BArgs& a, const Bodies& bd, int i, in
     q = nd / nv;
   }
   const double r[3] = {d[0] - q * v[0], d[1] - q * v[1], d[2] - q * v[2]};  // x_w - centre
-  double U1[3];
+  double U1[3], W1[3];
   body_U1(bd, kb, U1);
-  uw[0] = U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]);
-  uw[1] = U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]);
-  uw[2] = U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]);
+  body_W1(bd, kb, W1);
+  uw[0] = U1[0] + (W1[1] * r[2] - W1[2] * r[1]);
+  uw[1] = U1[1] + (W1[2] * r[0] - W1[0] * r[2]);
+  uw[2] = U1[2] + (W1[0] * r[1] - W1[1] * r[0]);
 }
 
 // Reconstruction at a wall node in the lane-parallel form (Sec. III): this lane's link (when its

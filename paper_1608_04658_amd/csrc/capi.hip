@@ -109,7 +109,7 @@ Layout layout(const elbm_params* p) {
     L.ring = take(sizeof(double) * 6 * ELBM_MAX_BODIES * ring);
     L.force_partial = take(sizeof(double) * 64 * 6 * ELBM_MAX_BODIES);
     L.free_hist = take(sizeof(FreeState) * FREE_HIST * ELBM_MAX_BODIES);
-    L.free_U1 = take(sizeof(double) * 3 * ELBM_MAX_BODIES);
+    L.free_U1 = take(sizeof(double) * 6 * ELBM_MAX_BODIES);
     L.scan_blocks = (int64_t)((N + 255) / 256);
     L.scan_tmp = take(sizeof(uint32_t) * 2 * (size_t)L.scan_blocks);
   }
@@ -167,6 +167,8 @@ hipError_t free_read_level(elbm_ctx* c, int64_t lv) {
       c->freeb[k].x[a] = st[k].x[a];
       c->freeb[k].u[a] = st[k].u[a];
       c->freeb[k].F[a] = st[k].F[a];
+      c->freeb[k].w[a] = st[k].w[a];
+      c->freeb[k].M[a] = st[k].M[a];
     }
   }
   c->free_lv = lv;
@@ -184,9 +186,11 @@ void free_derive(elbm_ctx* c) {
       if (c->free_lv == c->t) {
         fb.xt[a] = fb.x[a];
         fb.ut[a] = fb.u[a];
+        fb.wt[a] = fb.w[a];
       } else {
         fb.xt[a] = fb.x[a] + fb.u[a];
         fb.ut[a] = fb.u[a] + fb.F[a] / fb.m + fb.ab[a];
+        fb.wt[a] = fb.I > 0.0 ? fb.w[a] + fb.M[a] / fb.I : fb.w[a];
       }
     }
   }
@@ -301,7 +305,7 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_gUR, 0, sizeof(double) * 4 * (size_t)c->N, c->stream);
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_side, 0, sizeof(float) * 9 * (size_t)p->ny * p->nz, c->stream);
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_gamp, 0, sizeof(double) * ELBM_MAX_BODIES, c->stream);
-  if (e == hipSuccess && L.geometry) e = hipMemsetAsync(c->free_U1, 0, sizeof(double) * 3 * ELBM_MAX_BODIES, c->stream);
+  if (e == hipSuccess && L.geometry) e = hipMemsetAsync(c->free_U1, 0, sizeof(double) * 6 * ELBM_MAX_BODIES, c->stream);
   if (e == hipSuccess && L.geometry) e = hipStreamCreate(&c->aux);  // default priority
   for (int k = 0; k < FREE_HIST && e == hipSuccess && L.geometry; ++k)
     e = hipEventCreateWithFlags(&c->free_ev[k], hipEventDisableTiming);
@@ -396,14 +400,16 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
       continue;
     }
     if (b.kind != ELBM_BODY_SPHERE && b.kind != ELBM_BODY_PLANE) return fail(c, ELBM_EINVAL, "body %d: bad kind", k);
-    if (b.motion != ELBM_MOTION_PRESCRIBED && b.motion != ELBM_MOTION_FREE)
+    if (b.motion != ELBM_MOTION_PRESCRIBED && b.motion != ELBM_MOTION_FREE && b.motion != ELBM_MOTION_FREE_ROTATING)
       return fail(c, ELBM_EINVAL, "body %d: bad motion", k);
-    if (b.motion == ELBM_MOTION_FREE) {
+    if (b.motion != ELBM_MOTION_PRESCRIBED) {
       if (b.kind != ELBM_BODY_SPHERE || !(b.radius > 0.0)) return fail(c, ELBM_EINVAL, "body %d: free motion needs a sphere", k);
       if (!(b.density_ratio > 0.0) || !isfinite(b.density_ratio))
         return fail(c, ELBM_EINVAL, "body %d: density_ratio must be positive", k);
-      if (b.amp != 0.0 || b.omega[0] != 0.0 || b.omega[1] != 0.0 || b.omega[2] != 0.0)
-        return fail(c, ELBM_EINVAL, "body %d: a free body has no prescribed oscillation or rotation", k);
+      if (b.amp != 0.0 || b.period != 0.0)
+        return fail(c, ELBM_EINVAL, "body %d: a free body has no prescribed oscillation", k);
+      if (b.motion == ELBM_MOTION_FREE && (b.omega[0] != 0.0 || b.omega[1] != 0.0 || b.omega[2] != 0.0))
+        return fail(c, ELBM_EINVAL, "body %d: omega needs ELBM_MOTION_FREE_ROTATING", k);
       if (c->p.flags & ELBM_FLAG_ADJOINT) return fail(c, ELBM_EINVAL, "body %d: no free bodies with the adjoint", k);
       if (!free_inside(c, b.center, b.radius))
         return fail(c, ELBM_EINVAL, "body %d: free sphere too close to a face", k);
@@ -432,17 +438,22 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
   for (int k = 0; k < nb; ++k) {
     c->bodies[k] = bodies[k];
     const elbm_body& b = bodies[k];
-    if (b.motion != ELBM_MOTION_FREE) continue;
+    if (b.motion == ELBM_MOTION_PRESCRIBED) continue;
     auto& fb = c->freeb[k];
     fb.on = true;
     fb.m = b.density_ratio * c->p.rho0 * (4.0 / 3.0) * M_PI * b.radius * b.radius * b.radius;
+    const bool rot = b.motion == ELBM_MOTION_FREE_ROTATING;
+    fb.I = rot ? 0.4 * fb.m * b.radius * b.radius : 0.0;
     for (int a = 0; a < 3; ++a) {
       fb.x[a] = b.center[a];
       fb.u[a] = b.vel[a];
       fb.F[a] = 0.0;
+      fb.w[a] = rot ? b.omega[a] : 0.0;
+      fb.M[a] = 0.0;
       fb.ab[a] = (1.0 - 1.0 / b.density_ratio) * b.gravity[a];
       fb.xt[a] = b.center[a];
       fb.ut[a] = b.vel[a];
+      fb.wt[a] = fb.w[a];
     }
     c->n_free += 1;
   }
@@ -540,6 +551,19 @@ int elbm_body_state(elbm_ctx* c, int32_t body, double pos[3], double vel[3]) {
     }
   } else {
     host_kinematics(c->bodies[body], (double)c->t, pos, vel);
+  }
+  return ELBM_OK;
+}
+
+int elbm_body_spin(elbm_ctx* c, int32_t body, double omega[3]) {
+  if (!c) return ELBM_EINVAL;
+  if (body < 0 || body >= c->nb || !omega) return fail(c, ELBM_EINVAL, "bad arguments");
+  if (c->freeb[body].on) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (c->free_lv != c->t) HIP_OK(c, free_read_level(c, c->t));
+    for (int a = 0; a < 3; ++a) omega[a] = c->freeb[body].w[a];
+  } else {
+    for (int a = 0; a < 3; ++a) omega[a] = c->bodies[body].omega[a];
   }
   return ELBM_OK;
 }

@@ -45,13 +45,15 @@ struct elbm_ctx {
   struct FreeBody {
     bool on;
     double x[3], u[3], F[3];  // state at level free_lv
+    double w[3], M[3];        // angular velocity and torque at level free_lv (rotating spheres)
     double m, ab[3];          // mass, (1 - 1/density_ratio) g
-    double xt[3], ut[3];      // position and velocity at the level of the step being launched
+    double I;                 // (2/5) m R^2 for a freely rotating sphere, else 0
+    double xt[3], ut[3], wt[3];  // position and velocities at the level of the step being launched
   } freeb[ELBM_MAX_BODIES];
   int n_free;
   int64_t free_lv;
   elbm::FreeState* free_hist;  // device [FREE_HIST][MAX_BODIES]
-  double* free_U1;             // device [MAX_BODIES][3]
+  double* free_U1;             // device [2][MAX_BODIES][3]: velocity, then angular velocity, at t+1
   hipStream_t aux;             // reads of the state, behind an event of the main stream
   hipEvent_t free_ev[4];       // recorded after the state of level t is written (slot t % FREE_HIST)
   int stab;         // STAB_KBC, STAB_EXACT or STAB_LBGK (from the context flags)

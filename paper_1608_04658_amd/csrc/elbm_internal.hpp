@@ -480,6 +480,7 @@ struct Bodies {
   // free bodies: their velocity at t+1 depends on the force of the step that produced t, which the
   // device-side integrator holds; U1dev [MAX_BODIES][3] replaces b[k].U1 where bit k of free_mask is set
   const double* U1dev;
+  const double* W1dev;  // [MAX_BODIES][3] angular velocity at t+1 of the free bodies
   uint32_t free_mask;
   int32_t pad2;
 };
@@ -497,10 +498,24 @@ __device__ inline void body_U1(const Bodies& bd, int k, double* u) {
   }
 }
 
+// Angular velocity of body k at t+1 (b[k].omega holds the one at t).
+__device__ inline void body_W1(const Bodies& bd, int k, double* w) {
+  if ((bd.free_mask >> k) & 1u) {
+    w[0] = bd.W1dev[3 * k];
+    w[1] = bd.W1dev[3 * k + 1];
+    w[2] = bd.W1dev[3 * k + 2];
+  } else {
+    w[0] = bd.b[k].omega[0];
+    w[1] = bd.b[k].omega[1];
+    w[2] = bd.b[k].omega[2];
+  }
+}
+
 // State of a free body at one time level: position, velocity, and the force of the step that
 // produced the level (explicit Euler of Newton's equations, Sec. IV.A).
 struct FreeState {
   double x[3], u[3], F[3];
+  double w[3], M[3];  // angular velocity and the torque of the step that produced the level
 };
 
 // Strictly-inside test (FP64, operations in the written order, no contraction).

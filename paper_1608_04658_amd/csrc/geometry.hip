@@ -93,11 +93,13 @@ Bodies make_bodies(const elbm_ctx* c, double t) {
     d.r2 = b.radius * b.radius;
     for (int a = 0; a < 3; ++a) {
       d.n[a] = b.normal[a];
-      d.omega[a] = b.omega[a];
+      // a free body's angular velocity at t (its value at t+1 comes from the device integrator)
+      d.omega[a] = c->freeb[k].on ? c->freeb[k].wt[a] : b.omega[a];
     }
   }
   for (int k = c->nb; k < ELBM_MAX_BODIES; ++k) bd.b[k] = BodyDev{};
   bd.U1dev = c->free_U1;
+  bd.W1dev = c->free_U1 + 3 * ELBM_MAX_BODIES;
   bd.free_mask = 0;
   for (int k = 0; k < c->nb; ++k)
     if (c->freeb[k].on) bd.free_mask |= 1u << k;
@@ -391,11 +393,12 @@ __global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, v
       for (int a = 0; a < 3; ++a) uw[a] = (float)v[a];
     } else {
       const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
-      double U1[3];
+      double U1[3], W1[3];
       body_U1(bd, kb, U1);
-      uw[0] = (float)(U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
-      uw[1] = (float)(U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
-      uw[2] = (float)(U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+      body_W1(bd, kb, W1);
+      uw[0] = (float)(U1[0] + (W1[1] * r[2] - W1[2] * r[1]));
+      uw[1] = (float)(U1[1] + (W1[2] * r[0] - W1[0] * r[2]));
+      uw[2] = (float)(U1[2] + (W1[0] * r[1] - W1[1] * r[0]));
     }
     const uint32_t nbm = h.fluid0 & ~(1u << 13);
     const float rs = gsum(lane != 13 ? h.R : 0.f);
@@ -540,6 +543,7 @@ __global__ void k_force_final(const double* partial, int32_t nb, double* out) {
 // order of the host's derivation, so both sides agree bit for bit.
 struct FreeParams {
   double m[ELBM_MAX_BODIES];
+  double I[ELBM_MAX_BODIES];     // moment of inertia; 0 for a body that does not rotate freely
   double ab[ELBM_MAX_BODIES][3];
   FreeState s[ELBM_MAX_BODIES];  // k_free_write: the state to store
   uint32_t mask;
@@ -550,12 +554,21 @@ __device__ inline double euler_u(double u, double F, double m, double ab) {
   return u + F / m + ab;
 }
 
-// State of one level from the host, and the velocity at the next level.
+__device__ inline double euler_w(double w, double M, double I) {
+#pragma clang fp contract(off)
+  return I > 0.0 ? w + M / I : w;
+}
+
+// State of one level from the host, and the velocities at the next level (U1 [MAX_BODIES][3]
+// translational, then [MAX_BODIES][3] angular).
 __global__ void k_free_write(FreeParams p, FreeState* slot, double* U1) {
   const int k = threadIdx.x;
   if (k >= ELBM_MAX_BODIES || !((p.mask >> k) & 1u)) return;
   slot[k] = p.s[k];
-  for (int a = 0; a < 3; ++a) U1[3 * k + a] = euler_u(p.s[k].u[a], p.s[k].F[a], p.m[k], p.ab[k][a]);
+  for (int a = 0; a < 3; ++a) {
+    U1[3 * k + a] = euler_u(p.s[k].u[a], p.s[k].F[a], p.m[k], p.ab[k][a]);
+    U1[3 * ELBM_MAX_BODIES + 3 * k + a] = euler_w(p.s[k].w[a], p.s[k].M[a], p.I[k]);
+  }
 }
 
 // After the step t -> t+1: the state of level t+1 from that of level t and the step's force (in
@@ -569,9 +582,14 @@ __global__ void k_free_commit(FreeParams p, const FreeState* prev, FreeState* ne
     s.x[a] = prev[k].x[a] + prev[k].u[a];
     s.u[a] = euler_u(prev[k].u[a], prev[k].F[a], p.m[k], p.ab[k][a]);
     s.F[a] = force[6 * k + a];
+    s.w[a] = euler_w(prev[k].w[a], prev[k].M[a], p.I[k]);
+    s.M[a] = force[6 * k + 3 + a];
   }
   next[k] = s;
-  for (int a = 0; a < 3; ++a) U1[3 * k + a] = euler_u(s.u[a], s.F[a], p.m[k], p.ab[k][a]);
+  for (int a = 0; a < 3; ++a) {
+    U1[3 * k + a] = euler_u(s.u[a], s.F[a], p.m[k], p.ab[k][a]);
+    U1[3 * ELBM_MAX_BODIES + 3 * k + a] = euler_w(s.w[a], s.M[a], p.I[k]);
+  }
 }
 
 static FreeParams free_params(const elbm_ctx* c) {
@@ -580,11 +598,14 @@ static FreeParams free_params(const elbm_ctx* c) {
     if (!c->freeb[k].on) continue;
     p.mask |= 1u << k;
     p.m[k] = c->freeb[k].m;
+    p.I[k] = c->freeb[k].I;
     for (int a = 0; a < 3; ++a) {
       p.ab[k][a] = c->freeb[k].ab[a];
       p.s[k].x[a] = c->freeb[k].x[a];
       p.s[k].u[a] = c->freeb[k].u[a];
       p.s[k].F[a] = c->freeb[k].F[a];
+      p.s[k].w[a] = c->freeb[k].w[a];
+      p.s[k].M[a] = c->freeb[k].M[a];
     }
   }
   return p;

@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "elbm.h")
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 BC_PERIODIC, BC_CHANNEL = 0, 1
 BODY_SPHERE, BODY_PLANE, BODY_MESH = 0, 1, 2
-MOTION_PRESCRIBED, MOTION_FREE = 0, 1
+MOTION_PRESCRIBED, MOTION_FREE, MOTION_FREE_ROTATING = 0, 1, 2
 MAX_BODIES = 8
 FLAG_BODY_FORCE, FLAG_STREAM_ONLY, FLAG_NO_FP64, FLAG_ADJOINT, FLAG_EXACT_GAMMA, FLAG_LBGK = 1, 2, 4, 8, 16, 32
 
@@ -80,6 +80,7 @@ def load():
                           P(ctypes.c_double)],
         "elbm_mesh_next": [_VP, _VP, _VP, P(ctypes.c_double)],
         "elbm_body_state": [_VP, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)],
+        "elbm_body_spin": [_VP, ctypes.c_int32, P(ctypes.c_double)],
         "elbm_set_body_force": [_VP, _VP],
         "elbm_step": [_VP, ctypes.c_int32],
         "elbm_force": [_VP, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double), P(ctypes.c_double)],
@@ -167,7 +168,8 @@ def make_body(spec: dict) -> Body:
     b.dir[:] = [float(v) for v in spec.get("direction", (0, 0, 0))]
     b.vel[:] = [float(v) for v in spec.get("vel", (0, 0, 0))]
     b.omega[:] = [float(v) for v in spec.get("omega", (0, 0, 0))]
-    b.motion = MOTION_FREE if spec.get("motion", "prescribed") == "free" else MOTION_PRESCRIBED
+    b.motion = {"prescribed": MOTION_PRESCRIBED, "free": MOTION_FREE,
+                "free_rotating": MOTION_FREE_ROTATING}[spec.get("motion", "prescribed")]
     b.density_ratio = float(spec.get("density_ratio", 0.0))
     b.gravity[:] = [float(v) for v in spec.get("gravity", (0, 0, 0))]
     return b
@@ -229,6 +231,12 @@ def elbm_body_state(ctx, body: int):
     vel = (ctypes.c_double * 3)()
     _check(load().elbm_body_state(ctx, int(body), pos, vel), ctx)
     return list(pos), list(vel)
+
+
+def elbm_body_spin(ctx, body: int):
+    w = (ctypes.c_double * 3)()
+    _check(load().elbm_body_spin(ctx, int(body), w), ctx)
+    return list(w)
 
 
 def elbm_set_body_force(ctx, F_dev):
@@ -404,6 +412,10 @@ class Lattice:
         import numpy as np
         pos, vel = elbm_body_state(self.ctx, k)
         return np.array(pos), np.array(vel)
+
+    def body_spin(self, k: int):
+        """Angular velocity of body k at the current time level (numpy array)."""
+        return np.array(elbm_body_spin(self.ctx, k))
 
     def set_body_force(self, F):
         torch = self.torch

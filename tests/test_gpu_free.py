@@ -72,6 +72,46 @@ def test_free_sphere_parity(E, oracle_mod, channel):
     assert ef <= 2e-5
 
 
+def test_free_rotating_sphere_parity(E, oracle_mod):
+    """A sphere released with a spin and settling off-axis in a channel stream (lift, drag and
+    torque all nonzero): position, velocity, angular velocity, forces, torques and populations."""
+    O = oracle_mod
+    shape, nu, steps, u_in = (40, 24, 24), 0.03, 100, (0.01, 0.0, 0.0)
+    body = WL.free_sphere((16.3, 11.6, 11.2), 4.0, 2.0, gravity=(0.0, 3e-5, 0.0), vel=(0.0, 0.0, 0.0),
+                          omega=(0.001, -0.002, 0.004))
+    _say("case: free rotating sphere parity")
+    rho, u = WL.uniform_flow(shape, u_in)
+    lat = E.Lattice(shape, nu, channel=True, u_inlet=u_in, max_bodies=1)
+    lat.init_equilibrium(rho, u)
+    lat.set_bodies([body])
+    s = O.Simulation(shape, nu, rho, u, bodies=[body], channel=True, u_in=u_in)
+    g, o = [], []
+    for t in range(steps):
+        lat.step(1)
+        s.step(1)
+        g.append(np.concatenate([*lat.body_state(0), lat.body_spin(0)]))
+        o.append(np.concatenate([*s.body_state(0), s.body_spin(0)]))
+    g, o = np.array(g), np.array(o)
+    ex = np.max(np.abs(g[:, :3] - o[:, :3]))
+    eu = np.max(np.abs(g[:, 3:6] - o[:, 3:6])) / np.max(np.abs(o[:, 3:6]))
+    ew = np.max(np.abs(g[:, 6:] - o[:, 6:])) / np.max(np.abs(o[:, 6:]))
+    F = lat.force_history(0, 1, steps)
+    Fo = np.array([f[0] for f in s.forces])
+    eF = np.max(np.abs(F[:, :3] - Fo[:, :3])) / np.max(np.abs(Fo[:, :3]))
+    eM = np.max(np.abs(F[:, 3:] - Fo[:, 3:])) / np.max(np.abs(Fo[:, 3:]))
+    fluid = s.solid == 0
+    ef = np.max(np.abs(lat.populations().cpu().numpy()[:, fluid] - s.A[:, fluid]))
+    _say(f"free rotating sphere: spin {o[0, 6:]} -> {o[-1, 6:]}, max|dx| {ex:.2e}, velocity rel {eu:.2e}, "
+         f"spin rel {ew:.2e}, force rel {eF:.2e}, torque rel {eM:.2e}, max|df| {ef:.2e}")
+    assert np.max(np.abs(o[-1, 6:] - o[0, 6:])) > 1e-5  # the torque did turn it
+    assert ex <= 1e-6
+    assert eu <= 1e-4
+    assert ew <= 1e-4
+    assert eF <= 1e-3
+    assert eM <= 1e-3
+    assert ef <= 2e-5
+
+
 def test_free_sphere_leaving_the_domain_is_an_error(E):
     """A free sphere must stay 3 nodes inside every face: the step that would take it closer fails."""
     lat = E.Lattice((32, 24, 24), 0.05, max_bodies=1)

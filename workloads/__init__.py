@@ -163,11 +163,16 @@ def sphere(center, radius, amp=0.0, period=0.0, direction=(0.0, 1.0, 0.0), vel=(
                 omega=tuple(map(float, omega)))
 
 
-def free_sphere(center, radius, density_ratio, gravity=(0.0, 0.0, 0.0), vel=(0.0, 0.0, 0.0)) -> dict:
+def free_sphere(center, radius, density_ratio, gravity=(0.0, 0.0, 0.0), vel=(0.0, 0.0, 0.0), omega=None) -> dict:
     """A sphere moved by the fluid force, gravity and buoyancy (two-way coupling); center and vel
-    are its state at the time level at which it is set."""
-    return dict(kind="sphere", center=tuple(map(float, center)), radius=float(radius), vel=tuple(map(float, vel)),
-                motion="free", density_ratio=float(density_ratio), gravity=tuple(map(float, gravity)))
+    are its state at the time level at which it is set.  With omega (its angular velocity then) the
+    sphere also turns under the fluid torque."""
+    d = dict(kind="sphere", center=tuple(map(float, center)), radius=float(radius), vel=tuple(map(float, vel)),
+             motion="free", density_ratio=float(density_ratio), gravity=tuple(map(float, gravity)))
+    if omega is not None:
+        d["motion"] = "free_rotating"
+        d["omega"] = tuple(map(float, omega))
+    return d
 
 
 def plane(point, normal, vel=(0.0, 0.0, 0.0)) -> dict:

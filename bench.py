@@ -364,7 +364,8 @@ def main():
             log(f"sphere384: {m:.0f} MLUPS, boundary nodes {inf.boundary_nodes}, drag {F[0]:.4e}")
         if "stabilisers" in which:
             # the same turb256 run with the exact stabiliser and with LBGK, for comparison
-            for name, fl in (("exact_gamma", elbm.FLAG_EXACT_GAMMA), ("lbgk", elbm.FLAG_LBGK)):
+            for name, fl in (("exact_gamma", elbm.FLAG_EXACT_GAMMA), ("lbgk", elbm.FLAG_LBGK),
+                             ("central", elbm.FLAG_CENTRAL)):
                 m, msps, gb, _, _, lat = run_form(elbm, torch, shape, w["nu"], "f32", 100, 5, init, flags=fl)
                 del lat
                 torch.cuda.empty_cache()

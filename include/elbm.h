@@ -72,6 +72,11 @@ extern "C" {
                                      analytic value) instead of the paper's analytic approximation;
                                      not with ELBM_FLAG_ADJOINT */
 #define ELBM_FLAG_LBGK 32u        /* stabiliser gamma = 2 (plain LBGK), for comparisons */
+#define ELBM_FLAG_CENTRAL 64u     /* central-moment member of the KBC family: the shear part s is
+                                     rebuilt from the deviatoric second moments through the dual
+                                     basis of the velocities c - u shifted by the node's velocity
+                                     (at u = 0 the raw basis of the paper); with the analytic
+                                     stabiliser only, not with ELBM_FLAG_ADJOINT */
 
 typedef struct elbm_params {
   int32_t nx, ny, nz;   /* lattice size, each >= 1 (channel mode: nx >= 4), N < 2^31 */
@@ -285,8 +290,8 @@ const char* elbm_last_error(const struct elbm_ctx* ctx);
 /* Context-free KBC collision of n independent nodes (Sec. II): f_in_dev, f_out_dev
  * dev [27][n] FP32, gamma_dev dev [n] FP32 (or NULL), F_dev dev [3][n] FP32 or
  * NULL.  Uses the same device code as elbm_step, FP64 recomputation included
- * unless fp64_threshold < 0.  flags: 0, ELBM_FLAG_EXACT_GAMMA or ELBM_FLAG_LBGK
- * (the stabiliser).  stream: hipStream_t. */
+ * unless fp64_threshold < 0.  flags: 0, ELBM_FLAG_EXACT_GAMMA, ELBM_FLAG_LBGK or
+ * ELBM_FLAG_CENTRAL (the variant).  stream: hipStream_t. */
 int elbm_collide_nodes(const float* f_in_dev, float* f_out_dev, float* gamma_dev, const float* F_dev,
                        int64_t n, double nu, double fp64_threshold, uint32_t flags, void* stream);
 

@@ -41,7 +41,8 @@ def build(force: bool = True) -> str:
 class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("channel", ctypes.c_int32), ("beta", ctypes.c_double), ("rho0", ctypes.c_double),
-                ("u_in", ctypes.c_double * 3), ("stream_only", ctypes.c_int32), ("stabiliser", ctypes.c_int32)]
+                ("u_in", ctypes.c_double * 3), ("stream_only", ctypes.c_int32), ("stabiliser", ctypes.c_int32),
+                ("central", ctypes.c_int32)]
 
 
 class Body(ctypes.Structure):
@@ -75,6 +76,9 @@ def lib():
         L.or_feq.argtypes = [ctypes.c_double, _D, _D]
         L.or_collide_ex.argtypes = [_D, ctypes.c_double, _D, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
         L.or_collide_ex.restype = ctypes.c_double
+        L.or_collide_central.argtypes = [_D, ctypes.c_double, _D, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+        L.or_collide_central.restype = ctypes.c_double
+        L.or_shear_part_central.argtypes = [_D, _D, _D]
         L.or_gamma_exact.argtypes = [_D, ctypes.c_double]
         L.or_gamma_exact.restype = ctypes.c_double
         L.or_H.argtypes = [_D]
@@ -149,13 +153,21 @@ def feq(rho: float, u) -> np.ndarray:
     return out
 
 
-def collide(f, beta: float, F=None, gamma_fixed: float = 0.0):
-    """KBC collision of one node. Returns (f_post, gamma, guard_used)."""
+def collide(f, beta: float, F=None, gamma_fixed: float = 0.0, central: bool = False):
+    """KBC collision of one node (central: the central-moment s). Returns (f_post, gamma, guard_used)."""
     f = np.array(f, dtype=np.float64).copy()
     g = ctypes.c_int(0)
     Fp = _dp(np.ascontiguousarray(F, dtype=np.float64)) if F is not None else None
-    gam = lib().or_collide_ex(_dp(f), beta, Fp, gamma_fixed, ctypes.byref(g))
+    fn = lib().or_collide_central if central else lib().or_collide_ex
+    gam = fn(_dp(f), beta, Fp, gamma_fixed, ctypes.byref(g))
     return f, gam, bool(g.value)
+
+
+def shear_part_central(f, u) -> np.ndarray:
+    out = np.zeros(27)
+    lib().or_shear_part_central(_dp(np.ascontiguousarray(f, dtype=np.float64)),
+                                _dp(np.ascontiguousarray(u, dtype=np.float64)), _dp(out))
+    return out
 
 
 def gamma_exact(f, beta: float) -> float:
@@ -281,7 +293,7 @@ class Simulation:
 
     def __init__(self, shape, nu: float, rho=None, u=None, bodies=(), channel: bool = False,
                  u_in=(0.0, 0.0, 0.0), rho0: float = 1.0, F=None, beta: float | None = None,
-                 stream_only: bool = False, A0=None, stabiliser: str = "kbc"):
+                 stream_only: bool = False, A0=None, stabiliser: str = "kbc", central: bool = False):
         nx, ny, nz = shape
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
@@ -293,6 +305,9 @@ class Simulation:
         self.grid.u_in[:] = list(map(float, u_in))
         self.grid.stream_only = 1 if stream_only else 0
         self.grid.stabiliser = {"kbc": 0, "exact": 1, "lbgk": 2}[stabiliser]
+        if central and stabiliser != "kbc":
+            raise ValueError("the central-moment variant uses the analytic stabiliser")
+        self.grid.central = 1 if central else 0
         self.bodies = (Body * max(1, len(bodies)))(*[body_from_spec(b) if isinstance(b, dict) else b
                                                       for b in bodies])
         self.nb = len(bodies)

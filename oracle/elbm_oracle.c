@@ -102,6 +102,54 @@ static double phib(int p, int c) {
 }
 static double basis(int p, int q, int r, int i) { return phib(p, cxi(i)) * phib(q, cyi(i)) * phib(r, czi(i)); }
 
+/* Central-moment member of the KBC family (an addition; the paper uses the raw basis): moments in
+ * the frame moving with the node's velocity u,
+ *   M^c_pqr = sum_i f_i (cx - ux)^p (cy - uy)^q (cz - uz)^r,
+ * and populations rebuilt from them with the 1-D dual basis of the shifted velocities
+ * c - u in {-1 - u, -u, 1 - u}: psi_p(c; u) is the coefficient of xi^p in the Lagrange
+ * polynomial of the three points that is 1 at c - u and 0 at the other two.  s is again the
+ * deviatoric part of the second moments, now central.  At u = 0 the basis is the raw one. */
+static void psi_central(double u, double psi[3][3]) { /* psi[p][c + 1] */
+  for (int c = -1; c <= 1; ++c) {
+    double a = 0.0, b = 0.0, den = 1.0;
+    int n = 0;
+    for (int k = -1; k <= 1; ++k) {
+      if (k == c) continue;
+      const double node = (double)k - u;
+      if (n == 0) a = node; else b = node;
+      den *= (double)(c - k);
+      ++n;
+    }
+    psi[0][c + 1] = a * b / den;   /* (xi - a)(xi - b) = xi^2 - (a + b) xi + a b */
+    psi[1][c + 1] = -(a + b) / den;
+    psi[2][c + 1] = 1.0 / den;
+  }
+}
+
+static double central_moment(const double f[NQ], const double u[3], int p, int q, int r) {
+  double m = 0.0;
+  for (int i = 0; i < NQ; ++i)
+    m += f[i] * pow(cxi(i) - u[0], p) * pow(cyi(i) - u[1], q) * pow(czi(i) - u[2], r);
+  return m;
+}
+
+void or_shear_part_central(const double f[NQ], const double u[3], double s[NQ]) {
+  double px[3][3], py[3][3], pz[3][3];
+  psi_central(u[0], px);
+  psi_central(u[1], py);
+  psi_central(u[2], pz);
+  double M200 = central_moment(f, u, 2, 0, 0), M020 = central_moment(f, u, 0, 2, 0), M002 = central_moment(f, u, 0, 0, 2);
+  double M110 = central_moment(f, u, 1, 1, 0), M101 = central_moment(f, u, 1, 0, 1), M011 = central_moment(f, u, 0, 1, 1);
+  double T = M200 + M020 + M002;
+  double D200 = M200 - T / 3.0, D020 = M020 - T / 3.0, D002 = M002 - T / 3.0;
+  for (int i = 0; i < NQ; ++i) {
+    const int x = cxi(i) + 1, y = cyi(i) + 1, z = czi(i) + 1;
+    s[i] = D200 * px[2][x] * py[0][y] * pz[0][z] + D020 * px[0][x] * py[2][y] * pz[0][z] +
+           D002 * px[0][x] * py[0][y] * pz[2][z] + M110 * px[1][x] * py[1][y] * pz[0][z] +
+           M101 * px[1][x] * py[0][y] * pz[1][z] + M011 * px[0][x] * py[1][y] * pz[1][z];
+  }
+}
+
 static void kinematic_part(const double f[NQ], double k[NQ]) {
   double M000 = moment(f, 0, 0, 0), M100 = moment(f, 1, 0, 0), M010 = moment(f, 0, 1, 0),
          M001 = moment(f, 0, 0, 1);
@@ -139,15 +187,30 @@ static double esp(const double X[NQ], const double Y[NQ], const double feq[NQ]) 
  * difference shift f' += feq(rho, u + F/rho) - feq(rho, u).  Pass F = NULL for
  * none.  gamma_fixed > 0 replaces the stabiliser by that constant (tests).
  * Returns gamma; *guard is set to 1 when the <dh|dh> rule was used. */
+static double collide_basis(double f[NQ], double beta, const double *F, double gamma_fixed, int *guard, int central);
 double or_collide_ex(double f[NQ], double beta, const double *F, double gamma_fixed, int *guard) {
+  return collide_basis(f, beta, F, gamma_fixed, guard, 0);
+}
+
+/* The same collision with the central-moment s of or_shear_part_central (central = 1). */
+double or_collide_central(double f[NQ], double beta, const double *F, double gamma_fixed, int *guard) {
+  return collide_basis(f, beta, F, gamma_fixed, guard, 1);
+}
+
+static double collide_basis(double f[NQ], double beta, const double *F, double gamma_fixed, int *guard, int central) {
   double rho = moment(f, 0, 0, 0);
   double u[3] = {moment(f, 1, 0, 0) / rho, moment(f, 0, 1, 0) / rho, moment(f, 0, 0, 1) / rho};
   double feq[NQ], k[NQ], s[NQ], h[NQ], seq[NQ], heq[NQ], keq[NQ], ds[NQ], dh[NQ];
   or_feq(rho, u, feq);
   kinematic_part(f, k);
-  or_shear_part(f, s);
   kinematic_part(feq, keq);
-  or_shear_part(feq, seq);
+  if (central) {
+    or_shear_part_central(f, u, s);
+    or_shear_part_central(feq, u, seq);
+  } else {
+    or_shear_part(f, s);
+    or_shear_part(feq, seq);
+  }
   for (int i = 0; i < NQ; ++i) {
     h[i] = f[i] - k[i] - s[i];
     heq[i] = feq[i] - keq[i] - seq[i];
@@ -283,6 +346,7 @@ typedef struct {
   int32_t stabiliser;  /* 0: the analytic gamma of Sec. II; 1: the exact root of eq. gamma_min
                           (or_gamma_exact; the analytic one where no root is bracketed);
                           2: gamma = 2 (LBGK) */
+  int32_t central;     /* 1: central-moment s (or_shear_part_central), with stabiliser 0 */
 } or_grid;
 
 typedef struct {
@@ -928,7 +992,8 @@ int or_step(const or_grid *g, const or_body *bodies, int nb, double t, const dou
             if (isfinite(ge) && ge > 0.0) gfix = ge;
             else cnt[4 * z + 2]++;
           }
-          gam = or_collide_ex(f, beta, F ? Fn : 0, gfix, &guard);
+          gam = g->central ? or_collide_central(f, beta, F ? Fn : 0, gfix, &guard)
+                           : or_collide_ex(f, beta, F ? Fn : 0, gfix, &guard);
         }
         cnt[4 * z + 3] += guard;
         if (gam < gmin[z]) gmin[z] = gam;

@@ -251,9 +251,23 @@ __device__ inline float kbc_collide_lanes(int lane, float d, float beta, float i
   const float e_ = ex[cx(i) + 1];
   const float P = e_ + pyz + e_ * pyz;
   const float fdev = wf(i) * (dr + rho * P);
+  constexpr bool CENTRAL = (STAB & STAB_CENTRAL) != 0;
   float ds = 0.f;
-  if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
-  else if (nnz(i) == 2) ds = cz(i) == 0 ? c0 * c1 * sxy : (cy(i) == 0 ? c0 * c2 * sxz : c1 * c2 * syz);
+  if (CENTRAL) {
+    // shear part through the dual basis of the shifted velocities, as in kbc_collide
+    float cbx[3][3], cby[3][3], cbz[3][3];
+    central_basis(ux, cbx);
+    central_basis(uy, cby);
+    central_basis(uz, cbz);
+    const int x = cx(i) + 1, y = cy(i) + 1, z = cz(i) + 1;
+    ds = (2.f * sfx) * cbx[2][x] * cby[0][y] * cbz[0][z] + (2.f * sfy) * cbx[0][x] * cby[2][y] * cbz[0][z] +
+         (2.f * sfz) * cbx[0][x] * cby[0][y] * cbz[2][z] + (4.f * sxy) * cbx[1][x] * cby[1][y] * cbz[0][z] +
+         (4.f * sxz) * cbx[1][x] * cby[0][y] * cbz[1][z] + (4.f * syz) * cbx[0][x] * cby[1][y] * cbz[1][z];
+  } else if (nnz(i) == 1) {
+    ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
+  } else if (nnz(i) == 2) {
+    ds = cz(i) == 0 ? c0 * c1 * sxy : (cy(i) == 0 ? c0 * c2 * sxz : c1 * c2 * syz);
+  }
   if (!own) ds = 0.f;
   float h = own ? (d - fdev) - ds : 0.f;
   // remove the rounding residue of the mass and momentum of dh (rest and face populations)
@@ -271,8 +285,8 @@ __device__ inline float kbc_collide_lanes(int lane, float d, float beta, float i
   const float th = h * ife;
   const float b = gsum(th * h), a = gsum(th * ds);
   float gamma = (b > 1e-30f) ? inv_beta - (2.f - inv_beta) * a / b : 2.f;
-  if (STAB == STAB_LBGK) gamma = 2.f;
-  if (STAB == STAB_EXACT && b > 1e-30f) {
+  if ((STAB & 3) == STAB_LBGK) gamma = 2.f;
+  if ((STAB & 3) == STAB_EXACT && b > 1e-30f) {
     // bracketed Newton on eq. gamma_min, as in kbc_collide (sums and extrema over the group)
     float clo = -1e6f, chi = 1e6f;
     if (own) {
@@ -308,7 +322,8 @@ __device__ inline float kbc_collide_lanes(int lane, float d, float beta, float i
       if (g > 0.f) gamma = g;
     }
   }
-  const float s2 = (27.f * (sfx * sfx + sfy * sfy + sfz * sfz) + 216.f * (sxy * sxy + sxz * sxz + syz * syz)) * rinv;
+  const float s2 = CENTRAL ? gsum(ds * ds * ife)
+                           : (27.f * (sfx * sfx + sfy * sfy + sfz * sfz) + 216.f * (sxy * sxy + sxz * sxz + syz * syz)) * rinv;
   float out = d - (2.f * beta) * ds - (beta * gamma) * h;
   if (FORCE) {
     const double rr = (double)rho;

@@ -68,6 +68,9 @@ int validate(const elbm_params* p, char* err) {
     return snprintf(err, 256, "ELBM_FLAG_EXACT_GAMMA and ELBM_FLAG_LBGK exclude each other"), ELBM_EINVAL;
   if ((p->flags & ELBM_FLAG_EXACT_GAMMA) && (p->flags & ELBM_FLAG_ADJOINT))
     return snprintf(err, 256, "the adjoint differentiates the analytic stabiliser only"), ELBM_EINVAL;
+  if ((p->flags & ELBM_FLAG_CENTRAL) && (p->flags & (ELBM_FLAG_EXACT_GAMMA | ELBM_FLAG_LBGK | ELBM_FLAG_ADJOINT)))
+    return snprintf(err, 256, "ELBM_FLAG_CENTRAL goes with the analytic stabiliser and without the adjoint"),
+           ELBM_EINVAL;
   if (p->max_mesh_vertices < 0 || p->max_mesh_triangles < 0 || p->max_mesh_triangles > (1 << 24) ||
       p->max_mesh_vertices > (1 << 24))
     return snprintf(err, 256, "bad mesh capacity"), ELBM_EINVAL;
@@ -244,6 +247,7 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->beta = 1.0 / (6.0 * p->nu + 1.0);
   c->fp64_thr = p->fp64_threshold > 0.0 ? p->fp64_threshold : 1e-12;
   c->stab = (p->flags & ELBM_FLAG_EXACT_GAMMA) ? STAB_EXACT : ((p->flags & ELBM_FLAG_LBGK) ? STAB_LBGK : STAB_KBC);
+  if (p->flags & ELBM_FLAG_CENTRAL) c->stab |= STAB_CENTRAL;
   c->pop[0] = c->ws + L.pop[0];
   c->pop[1] = c->ws + L.pop[1];
   c->cur = 0;
@@ -768,10 +772,13 @@ int elbm_collide_nodes(const float* f_in_dev, float* f_out_dev, float* gamma_dev
                        double nu, double fp64_threshold, uint32_t flags, void* stream) {
   if (!f_in_dev || !f_out_dev || n < 0 || !(nu > 0.0)) return fail(nullptr, ELBM_EINVAL, "bad arguments");
   if ((flags & ELBM_FLAG_EXACT_GAMMA) && (flags & ELBM_FLAG_LBGK)) return fail(nullptr, ELBM_EINVAL, "bad flags");
+  if ((flags & ELBM_FLAG_CENTRAL) && (flags & (ELBM_FLAG_EXACT_GAMMA | ELBM_FLAG_LBGK)))
+    return fail(nullptr, ELBM_EINVAL, "ELBM_FLAG_CENTRAL goes with the analytic stabiliser");
   if (n == 0) return ELBM_OK;
   const double beta = 1.0 / (6.0 * nu + 1.0);
   const double thr = fp64_threshold < 0.0 ? -1.0 : (fp64_threshold == 0.0 ? 1e-12 : fp64_threshold);
-  const int stab = (flags & ELBM_FLAG_EXACT_GAMMA) ? STAB_EXACT : ((flags & ELBM_FLAG_LBGK) ? STAB_LBGK : STAB_KBC);
+  int stab = (flags & ELBM_FLAG_EXACT_GAMMA) ? STAB_EXACT : ((flags & ELBM_FLAG_LBGK) ? STAB_LBGK : STAB_KBC);
+  if (flags & ELBM_FLAG_CENTRAL) stab |= STAB_CENTRAL;
   hipError_t e = launch_collide_nodes(f_in_dev, f_out_dev, gamma_dev, F_dev, n, beta, thr, stab, (hipStream_t)stream);
   if (e != hipSuccess) return fail(nullptr, ELBM_EDEVICE, "collide: %s", hipGetErrorString(e));
   return ELBM_OK;

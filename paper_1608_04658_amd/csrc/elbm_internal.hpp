@@ -114,6 +114,24 @@ __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
 // Stabiliser of the collision: the paper's analytic approximation (default), the exact root of
 // eq. gamma_min, or gamma = 2 (LBGK, for comparisons).
 constexpr int STAB_KBC = 0, STAB_EXACT = 1, STAB_LBGK = 2;
+// bit added to the stabiliser code: the shear part from central moments (with STAB_KBC only)
+constexpr int STAB_CENTRAL = 4;
+
+// Dual basis of the shifted velocities c - u, c in {-1, 0, 1}, for moments taken in the frame
+// moving with u: cb[p][c + 1] = coefficient of xi^p in the Lagrange polynomial of the points
+// {-1 - u, -u, 1 - u} that is 1 at c - u (at u = 0: 1 - c^2, c/2, 3c^2/2 - 1).
+template <typename T>
+__device__ __forceinline__ void central_basis(T u, T (&cb)[3][3]) {
+  cb[0][0] = T(0.5) * u * (u - T(1));
+  cb[1][0] = u - T(0.5);
+  cb[2][0] = T(0.5);
+  cb[0][1] = T(1) - u * u;
+  cb[1][1] = T(-2) * u;
+  cb[2][1] = T(-1);
+  cb[0][2] = T(0.5) * u * (u + T(1));
+  cb[1][2] = u + T(0.5);
+  cb[2][2] = T(0.5);
+}
 
 // Term of direction i in the root condition of eq. gamma_min,
 //   G(g) = sum_i dh_i ln(1 + ((1 - beta g) dh_i - (2 beta - 1) ds_i) / feq_i) = 0,
@@ -202,7 +220,9 @@ __device__ __forceinline__ bool needs_fp64(const KbcOut<T>& r, T thr) {
 //   - gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh>, <X|Y> = sum X Y / feq; gamma = 2 when
 //     <dh|dh> <= 1e-30 (then dh is zero to round-off and f' does not depend on it).  STAB selects
 //     this analytic stabiliser (the paper's choice), the exact root of eq. gamma_min (Newton from
-//     the analytic value), or gamma = 2 (LBGK).
+//     the analytic value), or gamma = 2 (LBGK); with the STAB_CENTRAL bit, ds is rebuilt from the
+//     same deviatoric moments (central ones equal the raw ones for df, which carries no mass or
+//     momentum) through the dual basis of the shifted velocities c - u (central_basis).
 // Working in deviations keeps every difference between O(1) numbers out of the FP32 arithmetic.
 // FORCE adds the exact-difference body-force increment feq(rho, u + F/rho) - feq(rho, u),
 // evaluated in FP64 to avoid cancellation.
@@ -263,6 +283,32 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
   const T tr3 = (dM200 + dM020 + dM002) * third;
   const T sfx = T(0.5) * (dM200 - tr3), sfy = T(0.5) * (dM020 - tr3), sfz = T(0.5) * (dM002 - tr3);
   const T sxy = T(0.25) * (Q110 - jx * uy), sxz = T(0.25) * (Q101 - jx * uz), syz = T(0.25) * (Q011 - jy * uz);
+  constexpr bool CENTRAL = (STAB & STAB_CENTRAL) != 0;
+  T cbx[3][3], cby[3][3], cbz[3][3];
+  if (CENTRAL) {
+    central_basis(ux, cbx);
+    central_basis(uy, cby);
+    central_basis(uz, cbz);
+  }
+  // shear part of direction i: raw basis (faces D_aa/2, edges c_a c_b P_ab/4), or central
+  auto ds_of = [&](int i) -> T {
+    if (CENTRAL) {
+      const int x = cx(i) + 1, y = cy(i) + 1, z = cz(i) + 1;
+      const T dx = T(2) * sfx, dy = T(2) * sfy, dz = T(2) * sfz;
+      const T pxy = T(4) * sxy, pxz = T(4) * sxz, pyz = T(4) * syz;
+      return dx * cbx[2][x] * cby[0][y] * cbz[0][z] + dy * cbx[0][x] * cby[2][y] * cbz[0][z] +
+             dz * cbx[0][x] * cby[0][y] * cbz[2][z] + pxy * cbx[1][x] * cby[1][y] * cbz[0][z] +
+             pxz * cbx[1][x] * cby[0][y] * cbz[1][z] + pyz * cbx[0][x] * cby[1][y] * cbz[1][z];
+    }
+    T ds = T(0);
+    if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
+    if (nnz(i) == 2) {
+      if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
+      else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
+      else ds = T(cy(i) * cz(i)) * syz;
+    }
+    return ds;
+  };
 
   T dh[27];
   T hm = T(0), hx = T(0), hy = T(0), hz = T(0);
@@ -274,13 +320,7 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
     const T e_ = ex[cx(i) + 1];
     const T P = e_ + pyz + e_ * pyz;
     const T fdev = T(wd(i)) * (dr + rho * P);
-    T ds = T(0);
-    if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
-    if (nnz(i) == 2) {
-      if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
-      else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
-      else ds = T(cy(i) * cz(i)) * syz;
-    }
+    const T ds = ds_of(i);
     const T h = (d[i] - fdev) - ds;
     hm += h;
     if (cx(i)) hx += T(cx(i)) * h;
@@ -298,24 +338,19 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
   dh[10] += T(0.5) * hy;
   dh[22] -= T(0.5) * hz;
   dh[4] += T(0.5) * hz;
-  T a = T(0), b = T(0);
+  T a = T(0), b = T(0), s2c = T(0);
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const T ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
-    T ds = T(0);
-    if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
-    if (nnz(i) == 2) {
-      if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
-      else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
-      else ds = T(cy(i) * cz(i)) * syz;
-    }
+    const T ds = ds_of(i);
     const T th = dh[i] * ife;
     b += th * dh[i];
-    if (nnz(i) == 1 || nnz(i) == 2) a += th * ds;
+    if (CENTRAL || nnz(i) == 1 || nnz(i) == 2) a += th * ds;
+    if (CENTRAL) s2c += ds * ds * ife;
   }
   T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * a / b : T(2);
-  if (STAB == STAB_LBGK) gamma = T(2);
-  if (STAB == STAB_EXACT && b > T(1e-30)) {
+  if ((STAB & 3) == STAB_LBGK) gamma = T(2);
+  if ((STAB & 3) == STAB_EXACT && b > T(1e-30)) {
     // Root of eq. gamma_min inside the admissible interval (lo, hi), where every argument of the
     // logarithm, p0_i + p1_i g, is positive. G falls from +inf at lo to -inf at hi, so the root is
     // unique. Newton from the analytic value (its first-order approximation) inside a bracket that
@@ -325,13 +360,7 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
       const T ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
-      T ds = T(0);
-      if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
-      if (nnz(i) == 2) {
-        if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
-        else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
-        else ds = T(cy(i) * cz(i)) * syz;
-      }
+      const T ds = ds_of(i);
       const T p0 = T(1) + (dh[i] - (T(2) * beta - T(1)) * ds) * ife, p1 = -beta * dh[i] * ife;
       if (p1 > T(0)) lo = fmax(lo, -p0 / p1);
       else if (p1 < T(0)) hi = fmin(hi, -p0 / p1);
@@ -345,13 +374,7 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
           const T ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
-          T ds = T(0);
-          if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
-          if (nnz(i) == 2) {
-            if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
-            else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
-            else ds = T(cy(i) * cz(i)) * syz;
-          }
+          const T ds = ds_of(i);
           ok = gamma_term(g, beta, dh[i], ds, ife, G, dG, Ga) && ok;
         }
         // G at its rounding level: g is the root as far as the arithmetic can tell
@@ -376,17 +399,12 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
     }
   }
   // faces: W = 2/27 (2 per axis), edges: W = 1/54 (4 per plane)
-  const T s2 = (T(27) * (sfx * sfx + sfy * sfy + sfz * sfz) + T(216) * (sxy * sxy + sxz * sxz + syz * syz)) * rinv;
+  const T s2 = CENTRAL ? s2c
+                       : (T(27) * (sfx * sfx + sfy * sfy + sfz * sfz) + T(216) * (sxy * sxy + sxz * sxz + syz * syz)) * rinv;
   const T bg = beta * gamma, b2 = T(2) * beta;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    T ds = T(0);
-    if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
-    if (nnz(i) == 2) {
-      if (cz(i) == 0) ds = T(cx(i) * cy(i)) * sxy;
-      else if (cy(i) == 0) ds = T(cx(i) * cz(i)) * sxz;
-      else ds = T(cy(i) * cz(i)) * syz;
-    }
+    const T ds = ds_of(i);
     d[i] = d[i] - b2 * ds - bg * dh[i];
   }
   if (FORCE) {

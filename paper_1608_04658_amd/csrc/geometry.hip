@@ -832,6 +832,7 @@ static void boundary_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd) {
   switch (c->stab) {
     case STAB_EXACT: boundary_launch_st<S, STAB_EXACT>(c, a, bd); break;
     case STAB_LBGK: boundary_launch_st<S, STAB_LBGK>(c, a, bd); break;
+    case STAB_KBC | STAB_CENTRAL: boundary_launch_st<S, STAB_KBC | STAB_CENTRAL>(c, a, bd); break;
     default: boundary_launch_st<S, STAB_KBC>(c, a, bd);
   }
 }

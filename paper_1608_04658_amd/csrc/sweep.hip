@@ -241,6 +241,7 @@ static hipError_t sweep_s(elbm_ctx* c, const SweepArgs& a, dim3 g, dim3 b) {
   switch (c->stab) {
     case STAB_EXACT: return sweep_st<S, STAB_EXACT>(c, a, g, b);
     case STAB_LBGK: return sweep_st<S, STAB_LBGK>(c, a, g, b);
+    case STAB_KBC | STAB_CENTRAL: return sweep_st<S, STAB_KBC | STAB_CENTRAL>(c, a, g, b);
     default: return sweep_st<S, STAB_KBC>(c, a, g, b);
   }
 }
@@ -270,6 +271,7 @@ static hipError_t fixup_s(elbm_ctx* c, const SweepArgs& a) {
   switch (c->stab) {
     case STAB_EXACT: return fixup_st<S, STAB_EXACT>(c, a);
     case STAB_LBGK: return fixup_st<S, STAB_LBGK>(c, a);
+    case STAB_KBC | STAB_CENTRAL: return fixup_st<S, STAB_KBC | STAB_CENTRAL>(c, a);
     default: return fixup_st<S, STAB_KBC>(c, a);
   }
 }
@@ -427,6 +429,9 @@ hipError_t launch_collide_nodes(const float* fin, float* fout, float* gam, const
     hipLaunchKernelGGL(k_collide_nodes<STAB_EXACT>, grid_1d(n), dim3(256), 0, s, fin, fout, gam, F, n, b, ib, th);
   else if (stab == STAB_LBGK)
     hipLaunchKernelGGL(k_collide_nodes<STAB_LBGK>, grid_1d(n), dim3(256), 0, s, fin, fout, gam, F, n, b, ib, th);
+  else if (stab == (STAB_KBC | STAB_CENTRAL))
+    hipLaunchKernelGGL(k_collide_nodes<STAB_KBC | STAB_CENTRAL>, grid_1d(n), dim3(256), 0, s, fin, fout, gam, F, n, b,
+                       ib, th);
   else
     hipLaunchKernelGGL(k_collide_nodes<STAB_KBC>, grid_1d(n), dim3(256), 0, s, fin, fout, gam, F, n, b, ib, th);
   return hipGetLastError();

@@ -23,7 +23,8 @@ BC_PERIODIC, BC_CHANNEL = 0, 1
 BODY_SPHERE, BODY_PLANE, BODY_MESH = 0, 1, 2
 MOTION_PRESCRIBED, MOTION_FREE, MOTION_FREE_ROTATING = 0, 1, 2
 MAX_BODIES = 8
-FLAG_BODY_FORCE, FLAG_STREAM_ONLY, FLAG_NO_FP64, FLAG_ADJOINT, FLAG_EXACT_GAMMA, FLAG_LBGK = 1, 2, 4, 8, 16, 32
+FLAG_BODY_FORCE, FLAG_STREAM_ONLY, FLAG_NO_FP64, FLAG_ADJOINT, FLAG_EXACT_GAMMA, FLAG_LBGK, FLAG_CENTRAL = \
+    1, 2, 4, 8, 16, 32, 64
 
 
 class ElbmError(RuntimeError):

@@ -64,6 +64,10 @@ def test_workspace_size_counts_two_population_arrays():
     (dict(shape=(2, 4, 4), channel=True), "channel"),
     (dict(shape=(4, 4, 4), max_bodies=9), "max_bodies"),
     (dict(shape=(4, 4, 4), storage=7), "storage"),
+    (dict(shape=(4, 4, 4), flags=64 | 16), "CENTRAL"),
+    (dict(shape=(4, 4, 4), flags=64 | 8), "CENTRAL"),
+    (dict(shape=(4, 4, 4), flags=16 | 32), "EXACT_GAMMA"),
+    (dict(shape=(4, 4, 4), max_bodies=1, max_mesh_vertices=10), "mesh capacity"),
 ])
 def test_bad_parameters_are_rejected(kw, msg):
     shape = kw.pop("shape")

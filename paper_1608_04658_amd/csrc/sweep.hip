@@ -206,9 +206,11 @@ static SweepArgs sweep_args(elbm_ctx* c) {
 
 // Launch shape: 256-thread workgroups, x-extent the widest power of two <= 256 (<= 128 for rows
 // longer than 256) that divides nx (at least 32), the rest along y.  Tile order (FP32): the
-// XCD-contiguous order of k_sweep measured faster only where a row is 4 tiles of 128 (512^3: 5.58
-// TB/s against 5.30 in dispatch order); plain dispatch order measured faster at nx = 384 (5.40
-// against 5.14 TB/s) and nx = 1600 (+2 %); 2-byte storage is faster in plain dispatch order.
+// XCD-contiguous order of k_sweep where a row is four 128-wide tiles (512^3: 5.33-5.58 TB/s against
+// 5.30 in dispatch order and 4.86 with full-row workgroups of 512 threads); plain dispatch order
+// elsewhere (nx = 384: 5.42 TB/s against 5.14 remapped and 5.34 with full rows; nx = 1600: 5.26
+// against 5.04-5.14 for 800-, 400- and 320-wide rows); 2-byte storage in dispatch order.  The
+// 1-D tile grid also serves shapes beyond the 65535 limit of the y and z grid extents.
 static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   int bx = nx > 256 ? 128 : 256;
@@ -219,7 +221,6 @@ static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
   a.gx = (nx + bx - 1) / bx;
   a.gy = (ny + by - 1) / by;
   a.tiles = a.gx * a.gy * nz;
-  // (the 1-D tile grid also serves shapes beyond the 65535 limit of the y and z grid extents)
   const bool remap = (storage == ELBM_STORAGE_F32 && bx == 128 && nx == 4 * bx) || a.gy > 65535 || nz > 65535;
   a.remap = remap ? 1 : 0;
   grid = remap ? dim3(a.tiles, 1, 1) : dim3(a.gx, a.gy, nz);

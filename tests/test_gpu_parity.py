@@ -77,11 +77,11 @@ def test_streaming_is_bit_exact(E, O, shape):
             assert np.array_equal(got, s.A)
 
 
-@pytest.mark.parametrize("shape", [(320, 4, 3), (512, 3, 2)])
+@pytest.mark.parametrize("shape", [(320, 4, 3), (512, 3, 2), (1024, 2, 2), (96, 5, 3)])
 def test_long_rows_parity(E, O, shape):
-    """Rows longer than 256 nodes take the XCD-contiguous tile order of the FP32 sweep (128- and
-    64-wide tiles here): stream-only bit-exact, and 20 full steps of a random near-equilibrium
-    state within 1e-6 of the oracle."""
+    """The launch shapes of the sweep: 64-wide tiles (320), full-row workgroups of 512 and 1024
+    threads, 32-wide tiles with a y-extent of 8 (96, ragged in y): stream-only bit-exact, and 20
+    full steps of a random near-equilibrium state within 1e-6 of the oracle."""
     nx, ny, nz = shape
     rng = np.random.default_rng(17)
     w = O.lattice()[1][:, None, None, None]

@@ -22,7 +22,9 @@
  *    (or elbm_set_stream()).  Calls return without waiting for the GPU unless
  *    stated ("synchronises").
  *  - Layout: N = nx*ny*nz nodes, node n = (z*ny + y)*nx + x (x fastest).
- *    Population arrays are structure-of-arrays [27][N]; velocity i has
+ *    Population arrays exchanged through the ABI (FP64 reads and writes,
+ *    adjoint fields) are structure-of-arrays [27][N]; the storage arrays
+ *    inside the workspace follow elbm_info.layout.  Velocity i has
  *    c_i = (i%3 - 1, (i/3)%3 - 1, i/9 - 1), so the opposite of i is 26 - i.
  *    Vector fields are [3][N].
  *  - One context per host thread at a time; contexts are independent.
@@ -48,6 +50,11 @@ extern "C" {
 #define ELBM_STORAGE_F32 0   /* d_i = f_i - W_i as binary32 */
 #define ELBM_STORAGE_F16 1   /* d_i = f_i - W_i as binary16 (round to nearest even) */
 #define ELBM_STORAGE_BF16 2  /* d_i = f_i - W_i as bfloat16 (round to nearest even) */
+
+/* placement of the 27 N elements of a population array in the workspace (elbm_info.layout; chosen
+ * by the library from the storage format, the same for both time levels and for elbm_save_state) */
+#define ELBM_LAYOUT_SOA 0    /* [27][nz][ny][nx] */
+#define ELBM_LAYOUT_ROWS 1   /* [nz][ny][27][nx]: the 27 directions of each lattice row together */
 
 /* x-direction boundary (y and z are always periodic) */
 #define ELBM_BC_PERIODIC 0
@@ -149,6 +156,8 @@ typedef struct elbm_info {
   int32_t nbodies;
   int64_t boundary_nodes; /* boundary + refill nodes of the last step (synchronises) */
   int64_t fp64_nodes;     /* nodes recomputed in FP64 during the last step (synchronises) */
+  int32_t layout;         /* ELBM_LAYOUT_* of the population arrays */
+  int32_t pad;
 } elbm_info;
 
 /* Bytes of device workspace a context with these parameters needs. */
@@ -249,8 +258,8 @@ int elbm_read_flags(struct elbm_ctx* ctx, uint8_t* out_dev);
 /* Context information (synchronises for the per-step counters). */
 int elbm_get_info(struct elbm_ctx* ctx, elbm_info* out);
 
-/* Copy the current populations, in the context's storage format ([27][N] elements of 4 or 2
- * bytes), to pop_dev (dev).  Used for checkpoints. */
+/* Copy the current populations, in the context's storage format and layout (27 N elements of 4
+ * or 2 bytes, placed as elbm_info.layout says), to pop_dev (dev).  Used for checkpoints. */
 int elbm_save_state(struct elbm_ctx* ctx, void* pop_dev);
 
 /* Replace the current populations by pop_dev (dev, storage format, as written by
@@ -264,7 +273,8 @@ int elbm_load_state(struct elbm_ctx* ctx, const void* pop_dev, int64_t t);
  * of that step (w_force: host double[nbodies][3], NULL for none).  Also accumulates
  *   gF_dev += dL/dF (dev [3][N] FP32, body-force field; NULL to skip)
  * and, inside the context, dL/d(amp) of every body (elbm_adjoint_param_grad).
- * pop_t_dev: dev, the populations A^t in the storage format (e.g. recomputed from a checkpoint); the
+ * pop_t_dev: dev, the populations A^t in the storage format and layout (as elbm_save_state writes
+ * them, e.g. recomputed from a checkpoint); the
  * entries of nodes uncovered by the step are overwritten with their refill values, as the forward
  * step does with its own buffer;
  * lam_in_dev, lam_out_dev: dev [27][N] FP32, distinct.  The solid masks of the step are those of

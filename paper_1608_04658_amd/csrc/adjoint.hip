@@ -226,10 +226,10 @@ __device__ inline long pull_source(const BArgs& a, int i, int x, int y, int z) {
 }
 
 // Pull sources of a node, computed once: the 3 source x (clamped to the outlet in channel mode)
-// and the 9 source-row offsets (periodic in y and z).  The transpose of the pull writes to the
+// and the 9 source rows (periodic in y and z).  The transpose of the pull writes to the
 // same entries, except beyond the inlet (nothing) and beyond the outlet (the side buffer).
 struct PullIdx {
-  long row[9];  // row[3 (cz+1) + (cy+1)] = ((z - cz) ny + (y - cy)) nx
+  long row[9];  // row[3 (cz+1) + (cy+1)] = (z - cz) ny + (y - cy), the source lattice row
   int xs[3];    // xs[cx+1] = source x
   bool in_lo;   // channel: x - 1 < 0 (cx = +1 comes through the inlet)
   bool out_hi;  // channel: x + 1 >= nx (cx = -1 comes from beyond the outlet, copied)
@@ -252,11 +252,15 @@ __device__ inline void pull_idx(const BArgs& a, int x, int y, int z, PullIdx& P)
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj) P.row[3 * k + jj] = ((long)zs[k] * a.ny + ys[jj]) * a.nx;
+    for (int jj = 0; jj < 3; ++jj) P.row[3 * k + jj] = (long)zs[k] * a.ny + ys[jj];
 }
 
-__device__ __forceinline__ long pull_src_idx(const PullIdx& P, int i) {
-  return P.row[3 * (cz(i) + 1) + cy(i) + 1] + P.xs[cx(i) + 1];
+// Node pulled into direction i, and the element of its population i in A^t.
+__device__ __forceinline__ long pull_src_idx(const BArgs& a, const PullIdx& P, int i) {
+  return P.row[3 * (cz(i) + 1) + cy(i) + 1] * a.nx + P.xs[cx(i) + 1];
+}
+__device__ __forceinline__ int64_t pull_src_pop(const BArgs& a, const PullIdx& P, int i) {
+  return P.row[3 * (cz(i) + 1) + cy(i) + 1] * a.lay.rs + i * a.lay.si + P.xs[cx(i) + 1];
 }
 
 // Transpose of the pull for direction i of node (y, z): entry (x - c_i, i) of dL/dA^t receives v.
@@ -267,7 +271,7 @@ __device__ __forceinline__ void push_idx(const BArgs& a, const AdjArgs& j, const
     j.side[(size_t)(i / 3) * a.ny * a.nz + (size_t)z * a.ny + y] = v;
     return;
   }
-  j.lam_out[(size_t)i * a.N + pull_src_idx(P, i)] = v;
+  j.lam_out[(size_t)i * a.N + pull_src_idx(a, P, i)] = v;
 }
 
 template <int S, bool FLAGS, bool FORCE>
@@ -292,7 +296,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
   double f[27], gp[27], g[27], gF[3];
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    f[i] = (double)C::load_dev(A + i * a.N + pull_src_idx(P, i)) + wd(i);  // exact widening
+    f[i] = (double)C::load_dev(A + pull_src_pop(a, P, i)) + wd(i);  // exact widening
     gp[i] = (double)j.lam_in[i * a.N + n];
   }
   double Fx = 0.0, Fy = 0.0, Fz = 0.0;
@@ -686,8 +690,8 @@ __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, con
     j.gUR[a.N + n] = 0.0;
     j.gUR[2 * a.N + n] = 0.0;
     j.gUR[3 * a.N + n] = 0.0;
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
     if (a.flags[n] & FL_SOLID_PREV) {
-      const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
       int kb = first_body(bd, false, x, y, z);
       if (kb < 0) kb = 0;
       atomicAdd(&p.gamp[kb], gU0 * p.dU0[kb][0] + gU1 * p.dU0[kb][1] + gU2 * p.dU0[kb][2]);
@@ -696,7 +700,7 @@ __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, con
     float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;  // as the forward: from the stored deviations
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-      const float v = C::load_dev(A + i * a.N + n);
+      const float v = C::load_dev(A + pop_off(a.lay, i, x, y, z));
       dr += v;
       jx += cx(i) * v;
       jy += cy(i) * v;
@@ -743,6 +747,7 @@ static BArgs bargs(elbm_ctx* c, const void* A) {
   a.ny = c->p.ny;
   a.nz = c->p.nz;
   a.N = c->N;
+  a.lay = c->lay;
   a.channel = c->p.bc_x == ELBM_BC_CHANNEL;
   a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64);
   a.stream_only = 0;

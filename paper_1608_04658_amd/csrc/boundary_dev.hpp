@@ -62,6 +62,7 @@ struct BArgs {
   int32_t moving;
   int32_t nx, ny, nz;
   int64_t N;
+  PopLayout lay;  // placement of the populations in A and B
   int32_t channel;
   int32_t fp64;
   int32_t stream_only;
@@ -127,11 +128,13 @@ __device__ __forceinline__ long far_node(const BArgs& a, int x, int y, int z, in
   const int b = k >> 1, s = (k & 1) ? -2 : 2;
   return neighbour(a, x, y, z, b == 0 ? s : 0, b == 1 ? s : 0, b == 2 ? s : 0);
 }
-__device__ __forceinline__ long pull_node(const BArgs& a, int x, int y, int z, int i) {
+// Element of direction i pulled into node (x, y, z): the population at x - c_i (x clamped to the
+// lattice in channel mode).
+__device__ __forceinline__ int64_t pull_pop(const BArgs& a, int x, int y, int z, int i) {
   int sx = x - cx(i);
   if (a.channel) sx = sx >= a.nx ? a.nx - 1 : (sx < 0 ? 0 : sx);
   else sx = wrap(sx, a.nx);
-  return node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
+  return pop_off(a.lay, i, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
 }
 
 // This lane's view of a listed node's neighbourhood; the masks are the same on every lane.
@@ -178,8 +181,8 @@ __device__ inline void lane_gather(const BArgs& a, const typename Codec<S>::E* A
   h.f = 0.f;
   h.fo = 0.f;
   if (POPS && own) {
-    h.fo = C::load_dev(A + (long)i * a.N + n);
-    if (!miss) h.f = C::load_dev(A + (long)i * a.N + pull_node(a, x, y, z, i));
+    h.fo = C::load_dev(A + pop_off(a.lay, i, x, y, z));
+    if (!miss) h.f = C::load_dev(A + pull_pop(a, x, y, z, i));
   }
   const bool uf = own && ((h.fluid >> i) & 1u);
 #pragma unroll

@@ -57,6 +57,8 @@ int validate(const elbm_params* p, char* err) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return snprintf(err, 256, "lattice size must be >= 1"), ELBM_EINVAL;
   const double N = (double)p->nx * p->ny * p->nz;
   if (N >= 2147483648.0) return snprintf(err, 256, "more than 2^31-1 nodes"), ELBM_EINVAL;
+  if (27.0 * 4.0 * p->nx * p->ny >= 4294967296.0)
+    return snprintf(err, 256, "a z plane of the populations exceeds 4 GiB (nx ny too large)"), ELBM_EINVAL;
   if (p->storage < 0 || p->storage > 2) return snprintf(err, 256, "bad storage %d", p->storage), ELBM_EINVAL;
   if (p->bc_x != ELBM_BC_PERIODIC && p->bc_x != ELBM_BC_CHANNEL) return snprintf(err, 256, "bad bc_x"), ELBM_EINVAL;
   if (p->bc_x == ELBM_BC_CHANNEL && p->nx < 4) return snprintf(err, 256, "channel needs nx >= 4"), ELBM_EINVAL;
@@ -251,6 +253,7 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->pop[0] = c->ws + L.pop[0];
   c->pop[1] = c->ws + L.pop[1];
   c->cur = 0;
+  c->lay = pop_layout(c->p);
   c->cnt = (DevCounters*)(c->ws + L.cnt);
   c->scratch64 = (double*)(c->ws + L.scratch);
   c->fix_list = (int32_t*)(c->ws + L.fix_list);
@@ -685,6 +688,7 @@ int elbm_get_info(elbm_ctx* c, elbm_info* out) {
   out->pop_offset = (size_t)((char*)c->pop[c->cur] - c->ws);
   out->flags_offset = c->flags ? (size_t)((char*)c->flags - c->ws) : 0;
   out->storage = c->p.storage;
+  out->layout = c->lay.interleaved ? ELBM_LAYOUT_ROWS : ELBM_LAYOUT_SOA;
   out->nbodies = c->nb;
   HIP_OK(c, hipStreamSynchronize(c->stream));
   DevCounters h;

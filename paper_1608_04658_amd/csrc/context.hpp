@@ -18,6 +18,7 @@ struct elbm_ctx {
   // carved fields (device)
   void* pop[2];
   int cur;                 // pop[cur] holds A^t
+  elbm::PopLayout lay;     // placement of the populations in pop[0], pop[1] (pop_layout)
   uint8_t* flags;          // N (geometry only)
   float* macro;            // 4 N: U (3 N) then R (N) (geometry only)
   int32_t* blist;          // boundary list (geometry only)
@@ -91,6 +92,7 @@ struct elbm_ctx {
 
 namespace elbm {
 // kernel launchers (defined in sweep.hip / geometry.hip)
+PopLayout pop_layout(const elbm_params& p);
 hipError_t launch_sweep(elbm_ctx* c);
 hipError_t launch_fixup(elbm_ctx* c);
 hipError_t launch_init_eq(elbm_ctx* c, const double* rho, const double* u);

@@ -37,6 +37,31 @@ constexpr uint8_t FL_SPECIAL = 4;     // handled by the boundary kernel (missing
 constexpr uint32_t FIX_PRE = 0x80000000u;
 
 // ---------------------------------------------------------------------------------------------
+// Placement of the populations in a population array.  Direction i of the node in column x of
+// lattice row r = z ny + y sits at element r rs + i si + x:
+//   structure of arrays [27][nz][ny][nx]:  rs = nx,     si = N;
+//   rows interleaved    [nz][ny][27][nx]:  rs = 27 nx,  si = nx.
+// Both keep x fastest, so a wavefront's access to one direction is one contiguous run either way.
+// The interleaved form puts the 27 streams of a row next to each other: the 27 x 9 rows a workgroup
+// gathers lie in 9 runs of 27 nx elements instead of 243 places up to 27 N apart.
+struct PopLayout {
+  int64_t si;  // stride between directions
+  int64_t rs;  // stride between lattice rows
+  int32_t nx, ny;
+  int32_t interleaved;
+  int32_t pad;
+};
+__host__ __device__ __forceinline__ int64_t pop_off(const PopLayout& L, int i, int x, int y, int z) {
+  return ((int64_t)z * L.ny + y) * L.rs + (int64_t)i * L.si + x;
+}
+// Offset of direction 0 of node n = (z ny + y) nx + x (n < 2^31); direction i adds i si.
+__device__ __forceinline__ int64_t pop_base_n(const PopLayout& L, int64_t n) {
+  const uint32_t r = (uint32_t)n / (uint32_t)L.nx;
+  const int x = (int)((uint32_t)n - r * (uint32_t)L.nx);
+  return (int64_t)r * L.rs + x;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Population storage: every format stores the deviation d = f - W_i from the lattice weight (FP32,
 // or FP16 / BF16 rounded to nearest even); arithmetic is FP32 (FP64 on the recomputation path).
 // load/store take absolute populations, load_dev/store_dev deviations.

@@ -293,8 +293,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_emit(GeoArgs g, int skip_in
 // Previous-step macroscopic field U^t, R^t on a box: moments of A^t with U = (j - F/2)/rho at
 // nodes fluid at t; rigid-body velocity (R = rho0) at nodes solid at t.
 template <int S, bool MESH>
-__global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, float* macro, const float* F, Box box,
-                        int32_t nx, int32_t ny, int64_t N, double rho0, Bodies bd) {
+__global__ void k_macro(const typename Codec<S>::E* A, PopLayout lay, const uint8_t* flags, float* macro, const float* F,
+                        Box box, int32_t nx, int32_t ny, int64_t N, double rho0, Bodies bd) {
   using C = Codec<S>;
   const long total = box.count();
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
@@ -320,7 +320,7 @@ __global__ void k_macro(const typename Codec<S>::E* A, const uint8_t* flags, flo
       float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;  // from the stored deviations f - W
 #pragma unroll
       for (int i = 0; i < 27; ++i) {
-        const float v = C::load_dev(A + i * N + n);
+        const float v = C::load_dev(A + pop_off(lay, i, x, y, z));
         dr += v;
         jx += cx(i) * v;
         jy += cy(i) * v;
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(64) void k_refill(const BArgs a, const Bodies bd, v
     float G[9], Pi[6];
     grad_u_grp(h, G);
     pressure_tensor(ravg, uw, G, a.beta, Pi);
-    if (lane < 27) C::store(A + (long)lane * a.N + n, grad_pop(lane, ravg, uw, Pi), wf(lane));
+    if (lane < 27) C::store(A + pop_off(a.lay, lane, h.x, h.y, h.z), grad_pop(lane, ravg, uw, Pi), wf(lane));
   }
 }
 
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
       for (int j = lane; j < nb * 6; j += GROUP) rec[j] = 0.0;
     }
     if (a.stream_only) {
-      if (active && lane < 27) C::store_dev(B + (long)lane * a.N + n, fi);
+      if (active && lane < 27) C::store_dev(B + pop_off(a.lay, lane, h.x, h.y, h.z), fi);
       continue;
     }
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
     // <dh|dh> at the FP32 noise floor (equal on all lanes of the group): store the pre-collision
     // deviations and queue the node for the FP64 collision of k_fixup
     const bool fp64 = a.fp64 && needs_fp64(r, a.thr);
-    if (active && lane < 27) C::store_dev(B + (long)lane * a.N + n, fp64 ? fi : fpost);
+    if (active && lane < 27) C::store_dev(B + pop_off(a.lay, lane, h.x, h.y, h.z), fp64 ? fi : fpost);
     if (fp64 && active && lane == 0) a.fix_list[atomicAdd(a.fix_count, 1u)] = (uint32_t)n | FIX_PRE;
     // inlet slab: U, R of the new state, summed in direction order on the group's first lane
     sh[g][lane] = fpost;
@@ -658,11 +658,11 @@ template <int S>
 static void macro_launch(elbm_ctx* c, const void* A, const Box& box, const Bodies& bd) {
   if (bd.mesh >= 0)
     hipLaunchKernelGGL((k_macro<S, true>), grid_for(box.count()), dim3(256), 0, c->stream,
-                       (const typename Codec<S>::E*)A, (const uint8_t*)c->flags, c->macro, c->bodyforce, box, c->p.nx,
+                       (const typename Codec<S>::E*)A, c->lay, (const uint8_t*)c->flags, c->macro, c->bodyforce, box, c->p.nx,
                        c->p.ny, (int64_t)c->N, c->p.rho0, bd);
   else
     hipLaunchKernelGGL((k_macro<S, false>), grid_for(box.count()), dim3(256), 0, c->stream,
-                       (const typename Codec<S>::E*)A, (const uint8_t*)c->flags, c->macro, c->bodyforce, box, c->p.nx,
+                       (const typename Codec<S>::E*)A, c->lay, (const uint8_t*)c->flags, c->macro, c->bodyforce, box, c->p.nx,
                        c->p.ny, (int64_t)c->N, c->p.rho0, bd);
 }
 
@@ -860,6 +860,7 @@ BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
   a.ny = c->p.ny;
   a.nz = c->p.nz;
   a.N = c->N;
+  a.lay = c->lay;
   a.channel = channel ? 1 : 0;
   a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64);
   a.stream_only = (c->p.flags & ELBM_FLAG_STREAM_ONLY) != 0;

@@ -4,8 +4,9 @@
 //
 // One thread per node, x fastest inside a wavefront: every load and store of a population
 // array is a contiguous 64-lane access (the +-x shifted loads straddle one extra cache line,
-// which the neighbouring lanes of the same workgroup bring into L2).  Population arrays are
-// structure-of-arrays, so each direction streams through HBM exactly once per step.
+// which the neighbouring lanes of the same workgroup bring into L2).  Each direction of each
+// lattice row is one contiguous run in either population layout (PopLayout), so every population
+// streams through HBM exactly once per step.
 #include "context.hpp"
 
 namespace elbm {
@@ -19,6 +20,7 @@ struct SweepArgs {
   uint32_t* fix_count;  // this step's FP64 queue length
   uint32_t* fix_clear;  // the other parity's, cleared by the fix-up kernel for the next step
   float* slab_next;  // [4][nz][ny][3] staging of U, R for x < 3 (written when slab is set)
+  PopLayout lay;
   int32_t nx, ny, nz;
   uint32_t N;
   float beta, inv_beta, thr;
@@ -31,27 +33,43 @@ struct SweepArgs {
   int32_t tiles;   // gx * gy * nz
 };
 
-// Source coordinates of the pull for each velocity component: xs[cx+1] = x - cx and the 9 row
-// offsets rs[3 (cz+1) + (cy+1)] = ((z - cz) ny + (y - cy)) nx, periodic in y and z; periodic in x
-// or, in channel mode, clamped (the outlet copy; x = 0 is never gathered by the bulk path).
-__device__ __forceinline__ void gather_offsets(int x, int y, int z, const SweepArgs& a, uint32_t (&xs)[3],
-                                               uint32_t (&rs)[9]) {
+// Source coordinates of the pull for each velocity component, split for the addressing: the
+// element offset zb[cz+1] of the first row of source plane z - cz (uniform over a workgroup of the
+// bulk sweep, so the per-direction bases stay scalar) and the in-plane offsets
+// lo[3 (cy+1) + (cx+1)] = (y - cy) rs + (x - cx) (elements, < 2^32 / 4 by the plane-size limit of
+// the context); periodic in y and z; periodic in x or, in channel mode, clamped (the outlet copy;
+// x = 0 is never gathered by the bulk path).
+__device__ __forceinline__ void gather_offsets(int x, int y, int z, const SweepArgs& a, int64_t (&zb)[3],
+                                               uint32_t (&lo)[9]) {
+  int xs[3];
   if (a.channel) {
-    xs[0] = (uint32_t)min(x + 1, a.nx - 1);
-    xs[2] = (uint32_t)max(x - 1, 0);
+    xs[0] = min(x + 1, a.nx - 1);
+    xs[2] = max(x - 1, 0);
   } else {
-    xs[0] = (uint32_t)(x + 1 == a.nx ? 0 : x + 1);
-    xs[2] = (uint32_t)(x == 0 ? a.nx - 1 : x - 1);
+    xs[0] = x + 1 == a.nx ? 0 : x + 1;
+    xs[2] = x == 0 ? a.nx - 1 : x - 1;
   }
-  xs[1] = (uint32_t)x;
+  xs[1] = x;
   const int ym = (y + 1 == a.ny) ? 0 : y + 1, yp = (y == 0) ? a.ny - 1 : y - 1;
   const int zm = (z + 1 == a.nz) ? 0 : z + 1, zp = (z == 0) ? a.nz - 1 : z - 1;
   const int ys[3] = {ym, y, yp};  // source y for cy = -1, 0, +1
   const int zs[3] = {zm, z, zp};
+  const uint32_t rs = (uint32_t)a.lay.rs;
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < 3; ++k) zb[k] = (int64_t)zs[k] * a.ny * a.lay.rs;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) rs[3 * k + j] = (uint32_t)((zs[k] * a.ny + ys[j]) * a.nx);
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lo[3 * j + k] = (uint32_t)ys[j] * rs + (uint32_t)xs[k];
+}
+
+// Element i of the pull: base of direction i in source plane z - cz_i, plus the in-plane byte
+// offset in 32 bits.
+template <typename E>
+__device__ __forceinline__ const E* pull_ptr(const E* A, const SweepArgs& a, const int64_t (&zb)[3],
+                                             const uint32_t (&lo)[9], int i) {
+  const E* base = A + (zb[cz(i) + 1] + (int64_t)i * a.lay.si);
+  return (const E*)((const char*)base + lo[3 * (cy(i) + 1) + cx(i) + 1] * (uint32_t)sizeof(E));
 }
 
 template <int S, bool FLAGS, bool FORCE, int STAB>
@@ -76,12 +94,13 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
   // the flag byte is loaded together with the 27 gathers (all sources are in range for every
   // node), so that waiting for it does not delay them; solid and listed nodes then leave
   const bool skip = FLAGS && (a.flags[n] & (FL_SOLID | FL_SPECIAL));
-  uint32_t xs[3], rs[9];
-  gather_offsets(x, y, z, a, xs, rs);
+  int64_t zb[3];
+  uint32_t lo[9];
+  gather_offsets(x, y, z, a, zb, lo);
   const E* __restrict__ A = (const E*)a.A;
   float f[27];  // deviations f - W
 #pragma unroll
-  for (int i = 0; i < 27; ++i) f[i] = C::load_dev(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]));
+  for (int i = 0; i < 27; ++i) f[i] = C::load_dev(pull_ptr(A, a, zb, lo, i));
   if (FLAGS) {
     // compiler-only barrier: keeps the gathers issued above the branch (no machine instruction)
     __asm__ volatile("" ::: "memory");
@@ -115,11 +134,12 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
   // buffer only after the whole sweep, so keeping the write stream out of the caches wins; measured
   // for FP32 and for 2-byte storage alike)
   E* __restrict__ B = (E*)a.B;
+  const uint32_t off = ((uint32_t)y * (uint32_t)a.lay.rs + (uint32_t)x) * (uint32_t)sizeof(E);
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     E v;
     C::store_dev(&v, f[i]);
-    E* p = (E*)((char*)(B + (size_t)i * a.N) + n * (uint32_t)sizeof(E));
+    E* p = (E*)((char*)(B + (zb[1] + (int64_t)i * a.lay.si)) + off);
     __builtin_nontemporal_store(v, p);
   }
 }
@@ -141,19 +161,19 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
     const uint32_t n = e & ~FIX_PRE;
     if (n >= a.N) continue;  // never written so; guards the accesses below
     double f[27];  // deviations f - W
+    const int x = (int)(n % (uint32_t)a.nx);
+    const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
+    const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
     if (e & FIX_PRE) {
       // wall node: its reconstructed pre-collision deviations were left in B
 #pragma unroll
-      for (int i = 0; i < 27; ++i) f[i] = (double)C::load_dev(B + (size_t)i * a.N + n);
+      for (int i = 0; i < 27; ++i) f[i] = (double)C::load_dev(B + pop_off(a.lay, i, x, y, z));
     } else {
-      const int x = (int)(n % (uint32_t)a.nx);
-      const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
-      const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
-      uint32_t xs[3], rs[9];
-      gather_offsets(x, y, z, a, xs, rs);
+      int64_t zb[3];
+      uint32_t lo[9];
+      gather_offsets(x, y, z, a, zb, lo);
 #pragma unroll
-      for (int i = 0; i < 27; ++i)
-        f[i] = (double)C::load_dev(A + (size_t)i * a.N + (rs[3 * (cz(i) + 1) + cy(i) + 1] + xs[cx(i) + 1]));
+      for (int i = 0; i < 27; ++i) f[i] = (double)C::load_dev(pull_ptr(A, a, zb, lo, i));
     }
     double Fx = 0, Fy = 0, Fz = 0;
     if (FORCE) {
@@ -167,15 +187,27 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
       out[i] = (float)f[i];
-      C::store_dev(B + (size_t)i * a.N + n, out[i]);
+      C::store_dev(B + pop_off(a.lay, i, x, y, z), out[i]);
     }
-    const int xn = (int)(n % (uint32_t)a.nx);
-    if (a.slab && xn < 3) {
-      const int yn = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny), zn = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
+    if (a.slab && x < 3)
       macro_from_post<S, FORCE>(out, (float)Fx, (float)Fy, (float)Fz, a.slab_next, (size_t)3 * a.ny * a.nz,
-                                slab_index(xn, yn, zn, a.ny));
-    }
+                                slab_index(x, y, z, a.ny));
   }
+}
+
+// Population layout per storage format: rows interleaved for FP32, where it measured faster on
+// long rows (a 512^3 sweep: 5.67-5.72 TB/s against 5.35-5.36 in structure of arrays; equal at
+// 256^3); structure of arrays for the 2-byte formats.
+PopLayout pop_layout(const elbm_params& p) {
+  PopLayout L;
+  L.nx = p.nx;
+  L.ny = p.ny;
+  L.pad = 0;
+  L.interleaved = p.storage == ELBM_STORAGE_F32 ? 1 : 0;
+  const int64_t N = (int64_t)p.nx * p.ny * p.nz;
+  L.rs = L.interleaved ? 27 * (int64_t)p.nx : p.nx;
+  L.si = L.interleaved ? p.nx : N;
+  return L;
 }
 
 static SweepArgs sweep_args(elbm_ctx* c) {
@@ -198,6 +230,7 @@ static SweepArgs sweep_args(elbm_ctx* c) {
   a.fp64 = !(c->p.flags & ELBM_FLAG_NO_FP64) && !(c->p.flags & ELBM_FLAG_STREAM_ONLY);
   a.stream_only = (c->p.flags & ELBM_FLAG_STREAM_ONLY) != 0;
   a.slab_next = c->slab_next;
+  a.lay = c->lay;
   a.slab = (c->flags != nullptr && a.channel && !a.stream_only && c->slab_next) ? 1 : 0;
   a.remap = 0;
   a.gx = a.gy = a.tiles = 0;
@@ -311,28 +344,32 @@ template <> __device__ __forceinline__ double load_d<ELBM_STORAGE_BF16>(const ui
 }
 
 template <int S>
-__global__ __launch_bounds__(256) void k_init_eq(typename Codec<S>::E* A, const double* rho, const double* u, int64_t N) {
+__global__ __launch_bounds__(256) void k_init_eq(typename Codec<S>::E* A, PopLayout L, const double* rho,
+                                                 const double* u, int64_t N) {
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
     double fe[27];
     feq_all(rho ? rho[n] : 1.0, u[n], u[N + n], u[2 * N + n], fe);
+    const int64_t b = pop_base_n(L, n);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) store_d<S>(A + i * N + n, fe[i], i);
+    for (int i = 0; i < 27; ++i) store_d<S>(A + b + i * L.si, fe[i], i);
   }
 }
 
 template <int S>
-__global__ __launch_bounds__(256) void k_write_pop(typename Codec<S>::E* A, const double* src, int64_t N) {
+__global__ __launch_bounds__(256) void k_write_pop(typename Codec<S>::E* A, PopLayout L, const double* src, int64_t N) {
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = pop_base_n(L, n);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) store_d<S>(A + i * N + n, src[i * N + n], i);
+    for (int i = 0; i < 27; ++i) store_d<S>(A + b + i * L.si, src[i * N + n], i);
   }
 }
 
 template <int S>
-__global__ __launch_bounds__(256) void k_read_pop(const typename Codec<S>::E* A, double* dst, int64_t N) {
+__global__ __launch_bounds__(256) void k_read_pop(const typename Codec<S>::E* A, PopLayout L, double* dst, int64_t N) {
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = pop_base_n(L, n);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) dst[i * N + n] = load_d<S>(A + i * N + n, i);
+    for (int i = 0; i < 27; ++i) dst[i * N + n] = load_d<S>(A + b + i * L.si, i);
   }
 }
 
@@ -347,13 +384,13 @@ hipError_t launch_init_eq(elbm_ctx* c, const double* rho, const double* u) {
   void* A = c->pop[c->cur];
   switch (c->p.storage) {
     case ELBM_STORAGE_F32:
-      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F32>, grid_1d(c->N), dim3(256), 0, c->stream, (float*)A, rho, u, c->N);
+      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F32>, grid_1d(c->N), dim3(256), 0, c->stream, (float*)A, c->lay, rho, u, c->N);
       break;
     case ELBM_STORAGE_F16:
-      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F16>, grid_1d(c->N), dim3(256), 0, c->stream, (_Float16*)A, rho, u, c->N);
+      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_F16>, grid_1d(c->N), dim3(256), 0, c->stream, (_Float16*)A, c->lay, rho, u, c->N);
       break;
     default:
-      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_BF16>, grid_1d(c->N), dim3(256), 0, c->stream, (uint16_t*)A, rho, u, c->N);
+      hipLaunchKernelGGL(k_init_eq<ELBM_STORAGE_BF16>, grid_1d(c->N), dim3(256), 0, c->stream, (uint16_t*)A, c->lay, rho, u, c->N);
   }
   return hipGetLastError();
 }
@@ -362,13 +399,13 @@ hipError_t launch_write_pop(elbm_ctx* c, const double* src) {
   void* A = c->pop[c->cur];
   switch (c->p.storage) {
     case ELBM_STORAGE_F32:
-      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F32>, grid_1d(c->N), dim3(256), 0, c->stream, (float*)A, src, c->N);
+      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F32>, grid_1d(c->N), dim3(256), 0, c->stream, (float*)A, c->lay, src, c->N);
       break;
     case ELBM_STORAGE_F16:
-      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F16>, grid_1d(c->N), dim3(256), 0, c->stream, (_Float16*)A, src, c->N);
+      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_F16>, grid_1d(c->N), dim3(256), 0, c->stream, (_Float16*)A, c->lay, src, c->N);
       break;
     default:
-      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_BF16>, grid_1d(c->N), dim3(256), 0, c->stream, (uint16_t*)A, src, c->N);
+      hipLaunchKernelGGL(k_write_pop<ELBM_STORAGE_BF16>, grid_1d(c->N), dim3(256), 0, c->stream, (uint16_t*)A, c->lay, src, c->N);
   }
   return hipGetLastError();
 }
@@ -377,15 +414,15 @@ hipError_t launch_read_pop(elbm_ctx* c, double* dst) {
   const void* A = c->pop[c->cur];
   switch (c->p.storage) {
     case ELBM_STORAGE_F32:
-      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F32>, grid_1d(c->N), dim3(256), 0, c->stream, (const float*)A, dst, c->N);
+      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F32>, grid_1d(c->N), dim3(256), 0, c->stream, (const float*)A, c->lay, dst, c->N);
       break;
     case ELBM_STORAGE_F16:
-      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F16>, grid_1d(c->N), dim3(256), 0, c->stream, (const _Float16*)A, dst,
-                         c->N);
+      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_F16>, grid_1d(c->N), dim3(256), 0, c->stream, (const _Float16*)A, c->lay,
+                         dst, c->N);
       break;
     default:
-      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_BF16>, grid_1d(c->N), dim3(256), 0, c->stream, (const uint16_t*)A, dst,
-                         c->N);
+      hipLaunchKernelGGL(k_read_pop<ELBM_STORAGE_BF16>, grid_1d(c->N), dim3(256), 0, c->stream, (const uint16_t*)A, c->lay,
+                         dst, c->N);
   }
   return hipGetLastError();
 }

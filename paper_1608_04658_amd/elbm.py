@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libelbm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "elbm.h")
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+LAYOUT_SOA, LAYOUT_ROWS = 0, 1  # storage arrays [27][nz][ny][nx] or [nz][ny][27][nx]
 BC_PERIODIC, BC_CHANNEL = 0, 1
 BODY_SPHERE, BODY_PLANE, BODY_MESH = 0, 1, 2
 MOTION_PRESCRIBED, MOTION_FREE, MOTION_FREE_ROTATING = 0, 1, 2
@@ -52,7 +53,7 @@ class Info(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int64), ("nodes", ctypes.c_int64), ("beta", ctypes.c_double),
                 ("pop_bytes", ctypes.c_size_t), ("pop_offset", ctypes.c_size_t), ("flags_offset", ctypes.c_size_t),
                 ("storage", ctypes.c_int32), ("nbodies", ctypes.c_int32), ("boundary_nodes", ctypes.c_int64),
-                ("fp64_nodes", ctypes.c_int64)]
+                ("fp64_nodes", ctypes.c_int64), ("layout", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -457,24 +458,30 @@ class Lattice:
         return elbm_get_info(self.ctx)
 
     def state_tensor(self):
-        """A new device tensor holding a copy of the current populations in storage format."""
+        """A new device tensor holding a copy of the current populations in storage format and
+        layout (flat, 27 N elements; `storage_shape` gives their arrangement)."""
         torch = self.torch
         dt = {0: torch.float32, 1: torch.float16, 2: torch.int16}[self.params.storage]
-        nx, ny, nz = self.shape
-        out = torch.empty((27, nz, ny, nx), dtype=dt, device="cuda")
+        out = torch.empty(27 * self.N, dtype=dt, device="cuda")
         elbm_save_state(self.ctx, out)
         return out
 
     def load_state(self, state, t):
         elbm_load_state(self.ctx, state, t)
 
+    def storage_shape(self):
+        """Shape of the storage arrays in memory order: (27, nz, ny, nx) or (nz, ny, 27, nx)."""
+        nx, ny, nz = self.shape
+        return (27, nz, ny, nx) if self.info().layout == LAYOUT_SOA else (nz, ny, 27, nx)
+
     def population_view(self):
-        """Zero-copy view of the current population storage (27, nz, ny, nx) in the workspace."""
+        """Zero-copy view of the current population storage in the workspace, indexed
+        [i, z, y, x] whatever the layout (a permuted view for the row-interleaved one)."""
         torch = self.torch
         info = self.info()
-        nx, ny, nz = self.shape
         dt = {0: torch.float32, 1: torch.float16, 2: torch.int16}[info.storage]
         es = 4 if info.storage == 0 else 2
         start = self._off + info.pop_offset
-        raw = self._ws[start:start + 27 * self.N * es]
-        return raw.view(dt).view(27, nz, ny, nx)
+        raw = self._ws[start:start + 27 * self.N * es].view(dt)
+        v = raw.view(self.storage_shape())
+        return v if info.layout == LAYOUT_SOA else v.permute(2, 0, 1, 3)

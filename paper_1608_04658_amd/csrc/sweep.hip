@@ -195,18 +195,18 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
   }
 }
 
-// Population layout per storage format: rows interleaved for FP32, where it measured faster on
-// long rows (a 512^3 sweep: 5.67-5.72 TB/s against 5.35-5.36 in structure of arrays; equal at
-// 256^3); structure of arrays for the 2-byte formats.
+// Population layout: rows interleaved for every storage format.  Measured on the bulk sweep against
+// structure of arrays (same kernel, only the strides differ): 512^3 FP32 6.04-6.07 TB/s against
+// 5.36-5.53, FP16 5.05-5.07 against 4.79-4.81 (with the tile shapes below), BF16 4.87-4.91 against
+// 4.74-4.76; 384-wide channels +3-5 %; 256^3 equal within noise.
 PopLayout pop_layout(const elbm_params& p) {
   PopLayout L;
   L.nx = p.nx;
   L.ny = p.ny;
   L.pad = 0;
-  L.interleaved = p.storage == ELBM_STORAGE_F32 ? 1 : 0;
-  const int64_t N = (int64_t)p.nx * p.ny * p.nz;
-  L.rs = L.interleaved ? 27 * (int64_t)p.nx : p.nx;
-  L.si = L.interleaved ? p.nx : N;
+  L.interleaved = 1;
+  L.rs = 27 * (int64_t)p.nx;
+  L.si = p.nx;
   return L;
 }
 
@@ -237,24 +237,36 @@ static SweepArgs sweep_args(elbm_ctx* c) {
   return a;
 }
 
-// Launch shape: 256-thread workgroups, x-extent the widest power of two <= 256 (<= 128 for rows
-// longer than 256) that divides nx (at least 32), the rest along y.  Tile order (FP32): the
-// XCD-contiguous order of k_sweep where a row is four 128-wide tiles (512^3: 5.33-5.58 TB/s against
-// 5.30 in dispatch order and 4.86 with full-row workgroups of 512 threads); plain dispatch order
-// elsewhere (nx = 384: 5.42 TB/s against 5.14 remapped and 5.34 with full rows; nx = 1600: 5.26
-// against 5.04-5.14 for 800-, 400- and 320-wide rows); 2-byte storage in dispatch order.  The
-// 1-D tile grid also serves shapes beyond the 65535 limit of the y and z grid extents.
+// Launch shape: 256-thread workgroups, x-extent bx, the rest along y.  Rows up to 256 wide: the
+// widest power of two <= 256 dividing nx (at least 32).  Longer rows, measured with the interleaved
+// layout: bx = 128 where it divides nx and 256 does not (384: 6.03-6.06 TB/s against 4.74-4.79 with
+// a ragged 256-wide tile), bx = 256 where it divides nx (512^3 FP16 5.05-5.07 against 4.86-4.98 with
+// 128), except 512-wide FP32 rows, which keep 128 with an XCD-contiguous tile order (5.72-5.73 TB/s
+// against 5.27-5.28 in dispatch order; 256-wide tiles 5.68-6.05, not distinguishable in the noise);
+// bx = 256 with a ragged last tile otherwise (1600-wide channel: 5.42-5.50 TB/s against 4.86-4.95
+// with 128 and 4.90-4.95 with 64).  The XCD-contiguous order: workgroups are dispatched round-robin
+// over the 8 XCDs and k_sweep remaps the 1-D grid so that each XCD takes a contiguous range of
+// tiles.  The 1-D tile grid also serves shapes beyond the 65535 limit of the y and z grid extents.
 static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  int bx = nx > 256 ? 128 : 256;
-  while (bx > 32 && (nx % bx) != 0) bx >>= 1;
-  if (nx < bx) bx = 32;
+  int bx;
+  if (nx <= 256) {
+    bx = 256;
+    while (bx > 32 && (nx % bx) != 0) bx >>= 1;
+    if (nx < bx) bx = 32;
+  } else if (nx % 256 == 0) {
+    bx = (storage == ELBM_STORAGE_F32 && nx == 512) ? 128 : 256;
+  } else if (nx % 128 == 0 && nx <= 512) {
+    bx = 128;
+  } else {
+    bx = 256;
+  }
   const int by = 256 / bx;
   block = dim3(bx, by, 1);
   a.gx = (nx + bx - 1) / bx;
   a.gy = (ny + by - 1) / by;
   a.tiles = a.gx * a.gy * nz;
-  const bool remap = (storage == ELBM_STORAGE_F32 && bx == 128 && nx == 4 * bx) || a.gy > 65535 || nz > 65535;
+  const bool remap = (storage == ELBM_STORAGE_F32 && bx == 128 && nx == 512) || a.gy > 65535 || nz > 65535;
   a.remap = remap ? 1 : 0;
   grid = remap ? dim3(a.tiles, 1, 1) : dim3(a.gx, a.gy, nz);
 }

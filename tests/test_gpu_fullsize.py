@@ -145,9 +145,9 @@ def test_turb512_reduced_storage_sampled(E, O, torch_cuda):
         lat = E.Lattice(w["shape"], w["nu"], storage=storage)
         E.elbm_init_equilibrium(lat.ctx, r5, u5)
         lat.step(1)
-        view = lat.population_view().reshape(27, -1)
-        idx = torch.tensor([(z * 512 + y) * 512 + x for z, y, x in nodes], device="cuda")
-        raw = view[:, idx]
+        view = lat.population_view()  # [i, z, y, x] over the storage layout, no copy
+        zt, yt, xt = (torch.tensor(c, device="cuda") for c in zip(*nodes))
+        raw = view[:, zt, yt, xt]
         if storage == "f16":
             d = raw.float()
         else:

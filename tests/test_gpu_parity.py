@@ -77,11 +77,12 @@ def test_streaming_is_bit_exact(E, O, shape):
             assert np.array_equal(got, s.A)
 
 
-@pytest.mark.parametrize("shape", [(320, 4, 3), (512, 3, 2), (1024, 2, 2), (96, 5, 3)])
+@pytest.mark.parametrize("shape", [(320, 4, 3), (384, 3, 2), (512, 3, 2), (1024, 2, 2), (1600, 2, 2), (96, 5, 3)])
 def test_long_rows_parity(E, O, shape):
-    """The launch shapes of the sweep: 64-wide tiles (320), full-row workgroups of 512 and 1024
-    threads, 32-wide tiles with a y-extent of 8 (96, ragged in y): stream-only bit-exact, and 20
-    full steps of a random near-equilibrium state within 1e-6 of the oracle."""
+    """The launch shapes of the FP32 sweep: 256-wide tiles with a ragged last tile (320, 1600),
+    128-wide tiles (384), 128-wide tiles in the XCD-contiguous order (512), 256-wide tiles (1024),
+    32-wide tiles with a y-extent of 8 (96, ragged in y): stream-only bit-exact, and 20 full steps
+    of a random near-equilibrium state within 1e-6 of the oracle."""
     nx, ny, nz = shape
     rng = np.random.default_rng(17)
     w = O.lattice()[1][:, None, None, None]
@@ -105,6 +106,24 @@ def test_long_rows_parity(E, O, shape):
     err = np.max(np.abs(lat.populations().cpu().numpy() - ref))
     _say(f"long rows {shape} max|df| = {err:.3e}")
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("shape", [(512, 3, 2), (1600, 2, 2), (384, 2, 3)])
+def test_long_rows_two_byte_streaming(E, O, shape, storage):
+    """The 2-byte launch shapes (256-wide tiles at 512, ragged at 1600, 128-wide at 384): deviations
+    on a grid of 1/128 (exact in FP16 and BF16) stream bit for bit."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(23)
+    w = O.lattice()[1][:, None, None, None]
+    A0 = w + rng.integers(0, 128, size=(27, nz, ny, nx)).astype(np.float64) / 128.0
+    _say(f"case: two-byte streaming {shape} {storage}")
+    lat = E.Lattice(shape, 0.1, flags=E.FLAG_STREAM_ONLY, storage=storage)
+    lat.write_populations(A0, 0)
+    assert np.array_equal(lat.populations().cpu().numpy(), A0)
+    lat.step(3)
+    s = O.Simulation(shape, 0.1, A0=A0, stream_only=True).step(3)
+    assert np.array_equal(lat.populations().cpu().numpy(), s.A)
 
 
 def test_collision_alone_matches_oracle(E, O, torch_cuda):

@@ -476,8 +476,9 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
 // Adjoint of the boundary rules of Secs. III / IV.A at the listed nodes, in the lane-parallel
 // form of the forward wall kernel: one node per group of 32 lanes, lane i < 27 owning direction
 // i.  The forward reconstruction is recomputed (same helper as the forward kernel); the FP64
-// collision VJP and the reverse of the reconstruction run per lane with butterfly sums.  Listed nodes without missing populations (inlet and outlet
-// rows, refill nodes) take the plain collision VJP, since the bulk kernel skips FL_SPECIAL nodes.
+// collision VJP and the reverse of the reconstruction run per lane with butterfly sums.  Listed nodes
+// without missing populations (inlet and outlet rows, refill nodes) take the plain collision VJP here:
+// their forward values are the wall kernel's, and the adjoint bulk kernel skips FL_SPECIAL nodes.
 template <int S, bool FORCE>
 __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies bd, const AdjArgs j,
                                                      const AdjBodyArgs p) {

@@ -51,8 +51,9 @@ extern "C" {
 #define ELBM_STORAGE_F16 1   /* d_i = f_i - W_i as binary16 (round to nearest even) */
 #define ELBM_STORAGE_BF16 2  /* d_i = f_i - W_i as bfloat16 (round to nearest even) */
 
-/* placement of the 27 N elements of a population array in the workspace (elbm_info.layout; chosen
- * by the library from the storage format, the same for both time levels and for elbm_save_state) */
+/* placement of the 27 N elements of a population array in the workspace (elbm_info.layout; the
+ * same for both time levels and for elbm_save_state).  This version stores every format as
+ * ELBM_LAYOUT_ROWS; ELBM_LAYOUT_SOA names the plain form for readers of raw checkpoints. */
 #define ELBM_LAYOUT_SOA 0    /* [27][nz][ny][nx] */
 #define ELBM_LAYOUT_ROWS 1   /* [nz][ny][27][nx]: the 27 directions of each lattice row together */
 

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "elbm_internal.hpp"
+#include "lanes_dev.hpp"
 #include "mesh_dev.hpp"
 
 namespace elbm {
@@ -91,37 +92,10 @@ __device__ __forceinline__ long neighbour(const BArgs& a, int x, int y, int z, i
 __host__ __device__ constexpr int dir_index(int dx, int dy, int dz) { return 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1); }
 
 // ---------------------------------------------------------------------------------------------
-// Lane-parallel form: one listed node per group of 32 lanes (two per wavefront), lane i < 27 owns
-// direction i, lanes 27..31 (and lane 13 for a sixth) fetch the nodes two steps away along the
-// axes.  Per-direction work runs side by side across the lanes instead of as 27 unrolled copies
-// in one thread; sums over directions are butterfly reductions inside the group (fixed order).
-// (GROUP = 32 is defined with the shared declarations.)
-
-__device__ __forceinline__ float gsum(float v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GROUP);
-  return v;
-}
-__device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GROUP);
-  return v;
-}
-__device__ __forceinline__ float gmax(float v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, GROUP));
-  return v;
-}
-__device__ __forceinline__ float gmin(float v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, GROUP));
-  return v;
-}
-// Bit l = predicate of lane l of the calling group.
-__device__ __forceinline__ uint32_t gballot(bool p) {
-  const unsigned long long b = __ballot(p);
-  return (uint32_t)(b >> (threadIdx.x & 32u));
-}
+// Lane-parallel form of the wall kernels (lanes_dev.hpp): one listed node per group of 32 lanes,
+// lane i < 27 owns direction i, lanes 27..31 (and lane 13 for a sixth) fetch the nodes two steps
+// away along the axes.  Per-direction work runs side by side across the lanes instead of as 27
+// unrolled copies in one thread.
 __host__ __device__ constexpr int far_lane(int k) { return k < 5 ? 27 + k : 13; }
 
 __device__ __forceinline__ long far_node(const BArgs& a, int x, int y, int z, int k) {
@@ -217,132 +191,6 @@ __device__ inline void grad_u_grp(const LaneNb& h, float (&G)[9]) {
       G[3 * c + b] = d;
     }
   }
-}
-
-// The KBC collision (Sec. II) in the lane-parallel form of the wall kernels: lane i < 27 holds
-// d_i = f_i - W_i and receives the post-collision deviation; lanes >= 27 pass zeros.  Same
-// arithmetic as kbc_collide<float>, with every sum over directions a butterfly reduction inside the
-// group.  r receives gamma, <dh|dh>, rho and the shear estimate for the FP64 rule (equal on all
-// lanes of the group).
-template <bool FORCE, int STAB = STAB_KBC>
-__device__ inline float kbc_collide_lanes(int lane, float d, float beta, float inv_beta, float Fx, float Fy, float Fz,
-                                          KbcOut<float>& r) {
-  const bool own = lane < 27;
-  const int i = own ? lane : 13;
-  if (!own) d = 0.f;
-  const float c0 = (float)cx(i), c1 = (float)cy(i), c2 = (float)cz(i);
-  const float dr = gsum(d), jx = gsum(c0 * d), jy = gsum(c1 * d), jz = gsum(c2 * d);
-  const float Q200 = gsum(c0 * c0 * d), Q020 = gsum(c1 * c1 * d), Q002 = gsum(c2 * c2 * d);
-  const float Q110 = gsum(c0 * c1 * d), Q101 = gsum(c0 * c2 * d), Q011 = gsum(c1 * c2 * d);
-  const float rho = 1.f + dr;
-  const float rinv = rcp_(rho);
-  const float ux = jx * rinv, uy = jy * rinv, uz = jz * rinv;
-  float ex[3], ey[3], ez[3], psx[3], psy[3], psz[3], sx, sy, sz;
-  axis_dev(ux, ex, psx, sx);
-  axis_dev(uy, ey, psy, sy);
-  axis_dev(uz, ez, psz, sz);
-  const float third = 1.f / 3.f;
-  const float dM200 = Q200 - (dr * (1.f + 2.f * sx) + 2.f * sx) * third;
-  const float dM020 = Q020 - (dr * (1.f + 2.f * sy) + 2.f * sy) * third;
-  const float dM002 = Q002 - (dr * (1.f + 2.f * sz) + 2.f * sz) * third;
-  const float tr3 = (dM200 + dM020 + dM002) * third;
-  const float sfx = 0.5f * (dM200 - tr3), sfy = 0.5f * (dM020 - tr3), sfz = 0.5f * (dM002 - tr3);
-  const float sxy = 0.25f * (Q110 - jx * uy), sxz = 0.25f * (Q101 - jx * uz), syz = 0.25f * (Q011 - jy * uz);
-  // feq_i - W_i = W_i (dr + rho P_i)
-  const float a_ = ey[cy(i) + 1], b_ = ez[cz(i) + 1];
-  const float pyz = a_ + b_ + a_ * b_;
-  const float e_ = ex[cx(i) + 1];
-  const float P = e_ + pyz + e_ * pyz;
-  const float fdev = wf(i) * (dr + rho * P);
-  constexpr bool CENTRAL = (STAB & STAB_CENTRAL) != 0;
-  float ds = 0.f;
-  if (CENTRAL) {
-    // shear part through the dual basis of the shifted velocities, as in kbc_collide
-    float cbx[3][3], cby[3][3], cbz[3][3];
-    central_basis(ux, cbx);
-    central_basis(uy, cby);
-    central_basis(uz, cbz);
-    const int x = cx(i) + 1, y = cy(i) + 1, z = cz(i) + 1;
-    ds = (2.f * sfx) * cbx[2][x] * cby[0][y] * cbz[0][z] + (2.f * sfy) * cbx[0][x] * cby[2][y] * cbz[0][z] +
-         (2.f * sfz) * cbx[0][x] * cby[0][y] * cbz[2][z] + (4.f * sxy) * cbx[1][x] * cby[1][y] * cbz[0][z] +
-         (4.f * sxz) * cbx[1][x] * cby[0][y] * cbz[1][z] + (4.f * syz) * cbx[0][x] * cby[1][y] * cbz[1][z];
-  } else if (nnz(i) == 1) {
-    ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
-  } else if (nnz(i) == 2) {
-    ds = cz(i) == 0 ? c0 * c1 * sxy : (cy(i) == 0 ? c0 * c2 * sxz : c1 * c2 * syz);
-  }
-  if (!own) ds = 0.f;
-  float h = own ? (d - fdev) - ds : 0.f;
-  // remove the rounding residue of the mass and momentum of dh (rest and face populations)
-  const float hm = gsum(h), hx = gsum(c0 * h), hy = gsum(c1 * h), hz = gsum(c2 * h);
-  if (own) {
-    if (i == 13) h -= hm;
-    else if (i == 14) h -= 0.5f * hx;
-    else if (i == 12) h += 0.5f * hx;
-    else if (i == 16) h -= 0.5f * hy;
-    else if (i == 10) h += 0.5f * hy;
-    else if (i == 22) h -= 0.5f * hz;
-    else if (i == 4) h += 0.5f * hz;
-  }
-  const float ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
-  const float th = h * ife;
-  const float b = gsum(th * h), a = gsum(th * ds);
-  float gamma = (b > 1e-30f) ? inv_beta - (2.f - inv_beta) * a / b : 2.f;
-  if ((STAB & 3) == STAB_LBGK) gamma = 2.f;
-  if ((STAB & 3) == STAB_EXACT && b > 1e-30f) {
-    // bracketed Newton on eq. gamma_min, as in kbc_collide (sums and extrema over the group)
-    float clo = -1e6f, chi = 1e6f;
-    if (own) {
-      // argument of the logarithm = p0 + p1 g
-      const float p0 = 1.f + (h - (2.f * beta - 1.f) * ds) * ife, p1 = -beta * h * ife;
-      if (p1 > 0.f) clo = -p0 / p1;
-      else if (p1 < 0.f) chi = -p0 / p1;
-    }
-    float lo = fmaxf(gmax(clo), -1e6f), hi = fminf(gmin(chi), 1e6f);
-    if (lo < hi) {
-      float g = (gamma > lo && gamma < hi) ? gamma : 0.5f * (lo + hi);
-      for (int it = 0; it < 64; ++it) {
-        float Gl = 0.f, dGl = 0.f, Gal = 0.f;
-        const bool okl = own ? gamma_term(g, beta, h, ds, ife, Gl, dGl, Gal) : true;
-        const float G = gsum(Gl), dG = gsum(dGl), Ga = gsum(Gal);
-        const bool bad = gballot(!okl) != 0u;
-        if (!bad && fabsf(G) <= 64.f * eps_of<float>() * Ga) break;
-        float gn;
-        if (bad || !(dG < 0.f)) {
-          if (g < 0.5f * (lo + hi)) lo = g;
-          else hi = g;
-          gn = 0.5f * (lo + hi);
-        } else {
-          if (G > 0.f) lo = g;
-          else hi = g;
-          gn = g - G / dG;
-          if (!(gn > lo && gn < hi)) gn = 0.5f * (lo + hi);
-        }
-        const bool done = !(fabsf(gn - g) > 1e-6f * fabsf(gn));
-        g = gn;
-        if (done) break;
-      }
-      if (g > 0.f) gamma = g;
-    }
-  }
-  const float s2 = CENTRAL ? gsum(ds * ds * ife)
-                           : (27.f * (sfx * sfx + sfy * sfy + sfz * sfz) + 216.f * (sxy * sxy + sxz * sxz + syz * syz)) * rinv;
-  float out = d - (2.f * beta) * ds - (beta * gamma) * h;
-  if (FORCE) {
-    const double rr = (double)rho;
-    double p0[3], q0[3], w0[3], p1[3], q1[3], w1[3];
-    axis_phi((double)ux, p0);
-    axis_phi((double)uy, q0);
-    axis_phi((double)uz, w0);
-    axis_phi((double)ux + (double)Fx / rr, p1);
-    axis_phi((double)uy + (double)Fy / rr, q1);
-    axis_phi((double)uz + (double)Fz / rr, w1);
-    const double e0 = rr * p0[cx(i) + 1] * q0[cy(i) + 1] * w0[cz(i) + 1];
-    const double e1 = rr * p1[cx(i) + 1] * q1[cy(i) + 1] * w1[cz(i) + 1];
-    out = (float)((double)out + (e1 - e0));
-  }
-  r = KbcOut<float>{gamma, b, rho, s2};
-  return own ? out : 0.f;
 }
 
 // Geometry of boundary link i (i in Dbar) at node (x,y,z): link fraction q, wall velocity u_w and

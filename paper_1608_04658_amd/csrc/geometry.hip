@@ -484,7 +484,7 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
       Fz = a.F[2 * a.N + n];
     }
     KbcOut<float> r;
-    const float fpost = kbc_collide_lanes<FORCE, STAB>(lane, fi, a.beta, a.inv_beta, Fx, Fy, Fz, r);
+    const float fpost = kbc_collide_lanes<float, FORCE, STAB>(lane, fi, a.beta, a.inv_beta, Fx, Fy, Fz, r);
     // <dh|dh> at the FP32 noise floor (equal on all lanes of the group): store the pre-collision
     // deviations and queue the node for the FP64 collision of k_fixup
     const bool fp64 = a.fp64 && needs_fp64(r, a.thr);

@@ -8,6 +8,7 @@
 // lattice row is one contiguous run in either population layout (PopLayout), so every population
 // streams through HBM exactly once per step.
 #include "context.hpp"
+#include "lanes_dev.hpp"
 
 namespace elbm {
 
@@ -152,9 +153,19 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
 }
 
 // FP64 recomputation of the nodes whose <dh|dh> fell below the FP32 threshold: the same gather
-// and the same collision in double precision, rounded once on store.  The queue length of the
-// other parity is cleared here for the next step, so the kernel is launched every step without a
-// host round trip.
+// and the same collision in double precision, rounded once on store.  Two forms, chosen on the
+// device from the queue length (uniform over the grid):
+//  - a short queue (a few thousand nodes, as around a moving body in a stream) is bound by the
+//    chain of dependent FP64 operations of one node: one node per group of 32 lanes, lane i < 27
+//    owning direction i (kbc_collide_lanes, sums as butterfly reductions in the group); sphere384,
+//    ~2.7 k nodes: 8.6 us against 17.4 us with one thread per node;
+//  - a long queue (a fluid largely at rest, ~10^5 nodes) is bound by FP64 throughput, where the
+//    shuffles of the lane form cost more than they save: one node per thread (the settling sphere:
+//    30 us against 191 us in the lane form).
+// The queue length of the other parity is cleared here for the next step, so the kernel is
+// launched every step without a host round trip.
+constexpr uint32_t FIX_LANES_MAX = 8192;  // queue lengths served by the lane form
+
 template <int S, bool FORCE, int STAB>
 __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
   using C = Codec<S>;
@@ -163,16 +174,65 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.fix_clear = 0u;
   const E* __restrict__ A = (const E*)a.A;
   E* __restrict__ B = (E*)a.B;
+  const double beta = (double)a.beta;
+  if (count <= FIX_LANES_MAX) {
+    const int lane = threadIdx.x & (GROUP - 1);
+    const bool own = lane < 27;
+    const int i = own ? lane : 13;
+    const uint32_t per_block = blockDim.x / GROUP;
+    for (uint32_t k = blockIdx.x * per_block + threadIdx.x / GROUP; k < count; k += gridDim.x * per_block) {
+      const uint32_t e = a.fix_list[k];
+      const uint32_t n = e & ~FIX_PRE;
+      if (n >= a.N) continue;  // never written so; guards the accesses below (uniform over the group)
+      const int x = (int)(n % (uint32_t)a.nx);
+      const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
+      const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
+      double d = 0.0;  // deviation f_i - W_i of this lane's direction
+      if (own) {
+        if (e & FIX_PRE) {
+          // wall node: its reconstructed pre-collision deviations were left in B
+          d = (double)C::load_dev(B + pop_off(a.lay, i, x, y, z));
+        } else {
+          // the pull of the bulk sweep: x - c_i, periodic in y and z, in x periodic or clamped
+          int sx = x - cx(i), sy = y - cy(i), sz = z - cz(i);
+          if (a.channel) sx = min(max(sx, 0), a.nx - 1);
+          else sx = sx < 0 ? sx + a.nx : (sx >= a.nx ? sx - a.nx : sx);
+          sy = sy < 0 ? sy + a.ny : (sy >= a.ny ? sy - a.ny : sy);
+          sz = sz < 0 ? sz + a.nz : (sz >= a.nz ? sz - a.nz : sz);
+          d = (double)C::load_dev(A + pop_off(a.lay, i, sx, sy, sz));
+        }
+      }
+      double Fx = 0, Fy = 0, Fz = 0;
+      if (FORCE) {
+        Fx = a.F[n];
+        Fy = a.F[a.N + n];
+        Fz = a.F[2 * (size_t)a.N + n];
+      }
+      KbcOut<double> r;
+      const double post = kbc_collide_lanes<double, FORCE, STAB>(lane, d, beta, 1.0 / beta, Fx, Fy, Fz, r);
+      const float out = (float)post;
+      if (own) C::store_dev(B + pop_off(a.lay, i, x, y, z), out);
+      if (a.slab && x < 3) {
+        // U, R of the stored state for the inlet slab, summed in direction order on the first lane
+        float o[27];
+#pragma unroll
+        for (int j = 0; j < 27; ++j) o[j] = __shfl(out, j, GROUP);
+        if (lane == 0)
+          macro_from_post<S, FORCE>(o, (float)Fx, (float)Fy, (float)Fz, a.slab_next, (size_t)3 * a.ny * a.nz,
+                                    slab_index(x, y, z, a.ny));
+      }
+    }
+    return;
+  }
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
     const uint32_t e = a.fix_list[k];
     const uint32_t n = e & ~FIX_PRE;
     if (n >= a.N) continue;  // never written so; guards the accesses below
-    double f[27];  // deviations f - W
     const int x = (int)(n % (uint32_t)a.nx);
     const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
     const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
+    double f[27];  // deviations f - W
     if (e & FIX_PRE) {
-      // wall node: its reconstructed pre-collision deviations were left in B
 #pragma unroll
       for (int i = 0; i < 27; ++i) f[i] = (double)C::load_dev(B + pop_off(a.lay, i, x, y, z));
     } else {
@@ -188,7 +248,6 @@ __global__ __launch_bounds__(256) void k_fixup(const SweepArgs a) {
       Fy = a.F[a.N + n];
       Fz = a.F[2 * (size_t)a.N + n];
     }
-    const double beta = (double)a.beta;
     kbc_collide<double, FORCE, STAB>(f, beta, 1.0 / beta, Fx, Fy, Fz);
     float out[27];
 #pragma unroll

@@ -80,11 +80,15 @@ template <> struct Codec<ELBM_STORAGE_F16> {
   static __device__ __forceinline__ float load_dev(const E* p) { return (float)(*p); }
   static __device__ __forceinline__ void store_dev(E* p, float d) { *p = (_Float16)d; }
 };
+// binary32 -> bfloat16, round to nearest even: gfx950's conversion instruction (v_cvt_pk_bf16_f32,
+// one VALU operation where the integer form takes five per value; NaN stays a quiet NaN).  The empty
+// asm statement (no instruction) makes v an opaque binary32 value: without it the compiler fuses a
+// preceding (float) of a double into one double -> bfloat16 rounding, which differs from rounding
+// the binary32 value at ties, and the stored populations would no longer be the rounding of the
+// binary32 deviations that the inlet-slab staging and the tests assume.
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  __asm__("" : "+v"(v));
+  return __builtin_bit_cast(uint16_t, (__bf16)v);
 }
 template <> struct Codec<ELBM_STORAGE_BF16> {
   using E = uint16_t;

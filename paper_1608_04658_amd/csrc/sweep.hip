@@ -405,7 +405,9 @@ template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_F32>(float* p, 
   *p = (float)(v - wd(i));
 }
 template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_F16>(_Float16* p, double v, int i) {
-  *p = (_Float16)(float)(v - wd(i));
+  float d = (float)(v - wd(i));
+  __asm__("" : "+v"(d));  // round the binary32 deviation, as every other store does (see f32_to_bf16_rne)
+  *p = (_Float16)d;
 }
 template <> __device__ __forceinline__ void store_d<ELBM_STORAGE_BF16>(uint16_t* p, double v, int i) {
   *p = f32_to_bf16_rne((float)(v - wd(i)));

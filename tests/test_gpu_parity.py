@@ -126,6 +126,40 @@ def test_long_rows_two_byte_streaming(E, O, shape, storage):
     assert np.array_equal(lat.populations().cpu().numpy(), s.A)
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_two_byte_storage_rounds_to_nearest_even(E, O, storage):
+    """The 2-byte stores (gfx950's conversion instructions) against round to nearest even of the
+    binary32 deviation (bit-pattern definition for BF16, numpy's conversion for FP16), at ties
+    (dropped bits exactly half an ulp, with even and odd kept parts) and next to them, for
+    deviations of both signs between 2^-14 and 2^-4, written through elbm_write_populations."""
+    shape = (8, 8, 8)
+    n = 27 * 8 * 8 * 8
+    drop = 16 if storage == "bf16" else 13  # binary32 mantissa bits the format drops
+    rng = np.random.default_rng(29)
+    sign = rng.integers(0, 2, n).astype(np.uint32) << 31
+    expo = rng.integers(127 - 14, 127 - 4, n).astype(np.uint32) << 23
+    kept = rng.integers(0, 1 << (23 - drop), n).astype(np.uint32) << drop
+    half = 1 << (drop - 1)
+    low = np.array([0, half - 1, half, half + 1, (1 << drop) - 1], dtype=np.uint32)
+    lows = np.where(rng.random(n) < 0.8, low[rng.integers(0, 5, n)],
+                    rng.integers(0, 1 << drop, n).astype(np.uint32))
+    bits = sign | expo | kept | lows
+    d32 = bits.view(np.float32)
+    if storage == "bf16":
+        want = (((bits + (half - 1) + ((bits >> drop) & 1)) >> drop) << drop).astype(np.uint32).view(np.float32)
+    else:
+        want = d32.astype(np.float16).astype(np.float32)
+    w = O.lattice()[1][:, None, None, None]
+    _say(f"case: {storage} rounding")
+    lat = E.Lattice(shape, 0.1, storage=storage)
+    lat.write_populations(w + d32.astype(np.float64).reshape(27, 8, 8, 8), 0)
+    got = (lat.populations().cpu().numpy() - w).astype(np.float32).ravel()
+    ties = lows == half
+    _say(f"{storage} rounding: {int((got != want).sum())} of {n} differ, {int(ties.sum())} ties")
+    assert ties.sum() > 100
+    assert np.array_equal(got, want)
+
+
 def test_collision_alone_matches_oracle(E, O, torch_cuda):
     """Random near-equilibrium states (and exact equilibria, which take the FP64 path)."""
     torch = torch_cuda

@@ -108,6 +108,33 @@ def test_long_rows_parity(E, O, shape):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 4, 3), (2, 1, 3), (3, 2, 1), (2, 2, 2)])
+def test_degenerate_extents_parity(E, O, shape):
+    """Lattices one or two nodes thick, where every periodic neighbour wraps onto the node itself or
+    its single neighbour: stream-only bit-exact, and 10 full steps of a random near-equilibrium state
+    (including nodes the FP64 rule may pick) within 1e-6 of the oracle."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(41)
+    w = O.lattice()[1][:, None, None, None]
+    A0 = w + rng.integers(0, 4096, size=(27, nz, ny, nx)).astype(np.float64) / 1024.0
+    _say(f"case: degenerate {shape} stream-only")
+    lat = E.Lattice(shape, 0.1, flags=E.FLAG_STREAM_ONLY)
+    lat.write_populations(A0, 0)
+    lat.step(3)
+    s = O.Simulation(shape, 0.1, A0=A0, stream_only=True).step(3)
+    assert np.array_equal(lat.populations().cpu().numpy(), s.A)
+    _say(f"case: degenerate {shape} 10 steps")
+    u = 0.03 * rng.uniform(-1, 1, (3, nz, ny, nx))
+    rho = 1.0 + 0.01 * rng.uniform(-1, 1, (nz, ny, nx))
+    lat = E.Lattice(shape, 0.01)
+    lat.init_equilibrium(rho, u)
+    lat.step(10)
+    ref = O.Simulation(shape, 0.01, rho, u).step(10).A
+    err = np.max(np.abs(lat.populations().cpu().numpy() - ref))
+    _say(f"degenerate {shape} max|df| = {err:.3e}")
+    assert err <= 1e-6
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("shape", [(512, 3, 2), (1600, 2, 2), (384, 2, 3)])
 def test_long_rows_two_byte_streaming(E, O, shape, storage):

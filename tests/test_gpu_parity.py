@@ -135,6 +135,26 @@ def test_degenerate_extents_parity(E, O, shape):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("shape", [(4, 1, 1), (5, 1, 3), (6, 2, 1)])
+def test_degenerate_channel_parity(E, O, shape):
+    """Channels one or two nodes thick in y or z (the inlet face, its velocity-gradient stencil and
+    the far nodes of the wall kernel wrap onto the node itself): 10 steps of a random state in a
+    0.03 stream within 1e-6 of the oracle."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(43)
+    u = 0.02 * rng.uniform(-1, 1, (3, nz, ny, nx))
+    u[0] += 0.03
+    rho = 1.0 + 0.01 * rng.uniform(-1, 1, (nz, ny, nx))
+    _say(f"case: degenerate channel {shape}")
+    lat = E.Lattice(shape, 0.02, channel=True, u_inlet=(0.03, 0.0, 0.0))
+    lat.init_equilibrium(rho, u)
+    lat.step(10)
+    ref = O.Simulation(shape, 0.02, rho, u, channel=True, u_in=(0.03, 0.0, 0.0)).step(10).A
+    err = np.max(np.abs(lat.populations().cpu().numpy() - ref))
+    _say(f"degenerate channel {shape} max|df| = {err:.3e}")
+    assert err <= 1e-6
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("shape", [(512, 3, 2), (1600, 2, 2), (384, 2, 3)])
 def test_long_rows_two_byte_streaming(E, O, shape, storage):

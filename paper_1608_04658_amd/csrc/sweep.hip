@@ -307,12 +307,16 @@ static SweepArgs sweep_args(elbm_ctx* c) {
 // widest power of two <= 256 dividing nx (at least 32).  Longer rows, measured with the interleaved
 // layout: bx = 128 where it divides nx and 256 does not (384: 6.03-6.06 TB/s against 4.74-4.79 with
 // a ragged 256-wide tile), bx = 256 where it divides nx (512^3 FP16 5.05-5.07 against 4.86-4.98 with
-// 128), except 512-wide FP32 rows, which keep 128 with an XCD-contiguous tile order (5.72-5.73 TB/s
-// against 5.27-5.28 in dispatch order; 256-wide tiles 5.68-6.05, not distinguishable in the noise);
-// bx = 256 with a ragged last tile otherwise (1600-wide channel: 5.42-5.50 TB/s against 4.86-4.95
-// with 128 and 4.90-4.95 with 64).  The XCD-contiguous order: workgroups are dispatched round-robin
-// over the 8 XCDs and k_sweep remaps the 1-D grid so that each XCD takes a contiguous range of
-// tiles.  The 1-D tile grid also serves shapes beyond the 65535 limit of the y and z grid extents.
+// 128), except 512-wide FP32 rows, which keep 128 (256-wide tiles 5.68-6.05 TB/s, not distinguishable
+// in the noise); bx = 256 with a ragged last tile otherwise (1600-wide channel: 5.42-5.50 TB/s against
+// 4.86-4.95 with 128 and 4.90-4.95 with 64).
+// Tile order: FP32 rows of four or more tiles run in an XCD-contiguous order, so that the tiles of a
+// row, which share the cache lines at their edges, sit on one XCD's L2 (512^3: 5.72-5.73 TB/s
+// against 5.27-5.28 in dispatch order, reads 1.0003x the algorithmic bytes; 1600-wide channel:
+// 9.66-9.67 ms against 9.83-10.18); fewer tiles per row (384: 533-539 us against 558 us remapped)
+// and the 2-byte forms (4.67 against 5.20 TB/s) keep the dispatch order.  Workgroups are dispatched
+// round-robin over the 8 XCDs; k_sweep remaps the 1-D grid so that each XCD takes a contiguous range
+// of tiles.  The 1-D tile grid also serves shapes beyond the 65535 limit of the y and z grid extents.
 static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   int bx;
@@ -332,7 +336,7 @@ static void sweep_shape(SweepArgs& a, int storage, dim3& grid, dim3& block) {
   a.gx = (nx + bx - 1) / bx;
   a.gy = (ny + by - 1) / by;
   a.tiles = a.gx * a.gy * nz;
-  const bool remap = (storage == ELBM_STORAGE_F32 && bx == 128 && nx == 512) || a.gy > 65535 || nz > 65535;
+  const bool remap = (storage == ELBM_STORAGE_F32 && a.gx >= 4) || a.gy > 65535 || nz > 65535;
   a.remap = remap ? 1 : 0;
   grid = remap ? dim3(a.tiles, 1, 1) : dim3(a.gx, a.gy, nz);
 }

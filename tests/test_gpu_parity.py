@@ -79,10 +79,11 @@ def test_streaming_is_bit_exact(E, O, shape):
 
 @pytest.mark.parametrize("shape", [(320, 4, 3), (384, 3, 2), (512, 3, 2), (1024, 2, 2), (1600, 2, 2), (96, 5, 3)])
 def test_long_rows_parity(E, O, shape):
-    """The launch shapes of the FP32 sweep: 256-wide tiles with a ragged last tile (320, 1600),
-    128-wide tiles (384), 128-wide tiles in the XCD-contiguous order (512), 256-wide tiles (1024),
-    32-wide tiles with a y-extent of 8 (96, ragged in y): stream-only bit-exact, and 20 full steps
-    of a random near-equilibrium state within 1e-6 of the oracle."""
+    """The launch shapes of the FP32 sweep: 256-wide tiles with a ragged last tile (320; 1600 in the
+    XCD-contiguous order), 128-wide tiles (384), 128-wide tiles in the XCD-contiguous order (512),
+    256-wide tiles in that order (1024), 32-wide tiles with a y-extent of 8 (96, ragged in y):
+    stream-only bit-exact, and 20 full steps of a random near-equilibrium state within 1e-6 of the
+    oracle."""
     nx, ny, nz = shape
     rng = np.random.default_rng(17)
     w = O.lattice()[1][:, None, None, None]

@@ -172,8 +172,9 @@ def _rollout_case(O, E, torch, cfg, steps, window, K, seed, h_amp=1e-5, h_F=1e-3
     Lp, _ = run(amp0 + h_amp, Fh, masks)
     Lm, _ = run(amp0 - h_amp, Fh, masks)
     fdA = (Lp - Lm) / (2 * h_amp)
-    res = dict(Lg=float(Lg), L0=L0, gA=gA, fdA=fdA)
-    _say(f"L gpu {float(Lg):.8e} oracle {L0:.8e}; dL/dA adjoint {gA:.8e} FD {fdA:.8e} "
+    Lg = float(Lg.detach())
+    res = dict(Lg=Lg, L0=L0, gA=gA, fdA=fdA)
+    _say(f"L gpu {Lg:.8e} oracle {L0:.8e}; dL/dA adjoint {gA:.8e} FD {fdA:.8e} "
          f"rel {abs(gA - fdA) / abs(fdA):.2e}")
     for name, v in dirs.items():
         Lp, _ = run(amp0, Fh + h_F * v, masks)

@@ -340,7 +340,6 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
   };
 
   T dh[27];
-  T hm = T(0), hx = T(0), hy = T(0), hz = T(0);
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     // feq_i - W_i = W_i (dr + rho P_i),  P_i = prod (1 + e) - 1 expanded without cancellation
@@ -349,13 +348,29 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
     const T e_ = ex[cx(i) + 1];
     const T P = e_ + pyz + e_ * pyz;
     const T fdev = T(wd(i)) * (dr + rho * P);
-    const T ds = ds_of(i);
-    const T h = (d[i] - fdev) - ds;
-    hm += h;
-    if (cx(i)) hx += T(cx(i)) * h;
-    if (cy(i)) hy += T(cy(i)) * h;
-    if (cz(i)) hz += T(cz(i)) * h;
-    dh[i] = h;
+    dh[i] = (d[i] - fdev) - ds_of(i);
+  }
+  // mass and momentum of dh by the separable transform used for the moments of d
+  T hm, hx, hy, hz;
+  {
+    T r0[9], r1[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const T a = dh[3 * r], b = dh[3 * r + 1], c = dh[3 * r + 2];
+      r0[r] = (a + c) + b;
+      r1[r] = c - a;
+    }
+    T q00[3], q01[3], q10[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      q00[k] = (r0[3 * k] + r0[3 * k + 2]) + r0[3 * k + 1];
+      q01[k] = r0[3 * k + 2] - r0[3 * k];
+      q10[k] = (r1[3 * k] + r1[3 * k + 2]) + r1[3 * k + 1];
+    }
+    hm = (q00[0] + q00[2]) + q00[1];
+    hz = q00[2] - q00[0];
+    hy = (q01[0] + q01[2]) + q01[1];
+    hx = (q10[0] + q10[2]) + q10[1];
   }
   // dh has zero mass and momentum in exact arithmetic; remove the rounding residue (its kinematic
   // part in the dual basis: mass on the rest population, momentum on the face pairs) so that the

@@ -73,6 +73,12 @@ __device__ __forceinline__ const E* pull_ptr(const E* A, const SweepArgs& a, con
   return (const E*)((const char*)base + lo[3 * (cy(i) + 1) + cx(i) + 1] * (uint32_t)sizeof(E));
 }
 
+// Raw buffer resources on gfx950 (CDNA): fourth descriptor word of an untyped 32-bit buffer, and the
+// cache-policy operand of a non-temporal access.
+constexpr int BUF_WORD3 = 0x00020000;
+constexpr int BUF_NT = 2;
+constexpr int BUF_ALL = (int)0xFFFFFFFFu;  // record count: no range check on the 32-bit offsets
+
 template <int S, bool FLAGS, bool FORCE, int STAB>
 __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
   using C = Codec<S>;
@@ -138,17 +144,21 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
     if (FLAGS && a.slab && x < 3 && !listed)
       macro_from_post<S, FORCE>(f, Fx, Fy, Fz, a.slab_next, (size_t)3 * a.ny * a.nz, slab_index(x, y, z, a.ny));
   }
-  // 32-bit byte offsets on per-direction bases and non-temporal stores (the next step reads this
-  // buffer only after the whole sweep, so keeping the write stream out of the caches wins; measured
-  // for FP32 and for 2-byte storage alike)
+  // Non-temporal stores (the next step reads this buffer only after the whole sweep, so keeping the
+  // write stream out of the caches wins; measured for FP32 and for 2-byte storage alike), each
+  // through a buffer resource on its direction's base in this plane (scalar registers) with the
+  // lane's 32-bit in-plane byte offset: no per-store 64-bit address arithmetic on the vector ALU,
+  // which the ALU-bound 2-byte sweeps feel.
   E* __restrict__ B = (E*)a.B;
   const uint32_t off = ((uint32_t)y * (uint32_t)a.lay.rs + (uint32_t)x) * (uint32_t)sizeof(E);
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     E v;
     C::store_dev(&v, f[i]);
-    E* p = (E*)((char*)(B + (zb[1] + (int64_t)i * a.lay.si)) + off);
-    __builtin_nontemporal_store(v, p);
+    const __amdgpu_buffer_rsrc_t dst =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(B + (zb[1] + (int64_t)i * a.lay.si)), (short)0, BUF_ALL, BUF_WORD3);
+    if constexpr (sizeof(E) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), dst, off, 0, BUF_NT);
+    else __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), dst, off, 0, BUF_NT);
   }
 }
 

@@ -68,6 +68,8 @@ def test_workspace_size_counts_two_population_arrays():
     (dict(shape=(4, 4, 4), flags=64 | 8), "CENTRAL"),
     (dict(shape=(4, 4, 4), flags=16 | 32), "EXACT_GAMMA"),
     (dict(shape=(4, 4, 4), max_bodies=1, max_mesh_vertices=10), "mesh capacity"),
+    (dict(shape=(2048, 1024, 1025)), "2\\^31"),
+    (dict(shape=(8192, 8192, 1)), "z plane"),
 ])
 def test_bad_parameters_are_rejected(kw, msg):
     shape = kw.pop("shape")

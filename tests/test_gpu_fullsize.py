@@ -159,3 +159,30 @@ def test_turb512_reduced_storage_sampled(E, O, torch_cuda):
         assert err < tol
         del view, raw, lat
         torch.cuda.empty_cache()
+
+
+def test_sphere384_full_size_steps(E, O, torch_cuda):
+    """The moving-sphere channel at its full size (384x192x192, sphere R = 12 oscillating with
+    amplitude 8), in the benchmark's launch configuration: 12 steps from the impulsive start against
+    the oracle, every fluid population within 2e-5 and drag and lift within 1e-3 of the largest."""
+    w = WL.WORKLOADS["sphere384"]
+    steps = 12
+    rho, u = WL.initial_field("sphere384")
+    _say("case: sphere384 full size")
+    lat = E.Lattice(w["shape"], w["nu"], channel=True, u_inlet=w["u_in"], max_bodies=1)
+    lat.init_equilibrium(rho, u)
+    lat.set_bodies(w["bodies"])
+    lat.step(steps)
+    got = lat.populations().cpu().numpy()
+    F = lat.force_history(0, 1, steps)
+    del lat
+    torch_cuda.cuda.empty_cache()
+    s = O.Simulation(w["shape"], w["nu"], rho, u, bodies=w["bodies"], channel=True, u_in=w["u_in"]).step(steps)
+    fluid = s.solid == 0
+    err = max(float(np.max(np.abs(got[i][fluid] - s.A[i][fluid]))) for i in range(27))
+    Fo = np.array([f[0] for f in s.forces])
+    ef = np.max(np.abs(F[:, :3] - Fo[:, :3])) / np.max(np.abs(Fo[:, :3]))
+    _say(f"sphere384 full size, {steps} steps: max|df| {err:.3e}, force rel {ef:.2e}, "
+         f"refills {sum(st['refill_nodes'] for st in s.stats)}")
+    assert err <= 2e-5
+    assert ef <= 1e-3

@@ -691,7 +691,8 @@ __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, con
     j.gUR[a.N + n] = 0.0;
     j.gUR[2 * a.N + n] = 0.0;
     j.gUR[3 * a.N + n] = 0.0;
-    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    int x, y, z;
+    node_xyz(a, n, x, y, z);
     if (a.flags[n] & FL_SOLID_PREV) {
       int kb = first_body(bd, false, x, y, z);
       if (kb < 0) kb = 0;

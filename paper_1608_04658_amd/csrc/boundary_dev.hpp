@@ -16,10 +16,14 @@ struct GeoArgs {
   Box box;
 };
 
+// Node of linear index idx in a box (x fastest).  A box lies inside the lattice (< 2^31 nodes), so
+// 32-bit divisions suffice (a 64-bit one is a long software sequence on the GPU).
 __device__ __forceinline__ void box_node(const Box& b, long idx, int& x, int& y, int& z) {
-  x = b.lo[0] + (int)(idx % b.n[0]);
-  y = b.lo[1] + (int)((idx / b.n[0]) % b.n[1]);
-  z = b.lo[2] + (int)(idx / ((long)b.n[0] * b.n[1]));
+  const uint32_t i = (uint32_t)idx, nx = (uint32_t)b.n[0], ny = (uint32_t)b.n[1];
+  const uint32_t q = i / nx;
+  x = b.lo[0] + (int)(i - q * nx);
+  y = b.lo[1] + (int)(q % ny);
+  z = b.lo[2] + (int)(q / ny);
 }
 
 __device__ __forceinline__ int first_body(const Bodies& bd, bool at_t1, double x, double y, double z) {
@@ -76,6 +80,14 @@ struct BArgs {
 __device__ __forceinline__ long node_at(const BArgs& a, int x, int y, int z) {
   return ((long)z * a.ny + y) * a.nx + x;
 }
+// Coordinates of node n (n < 2^31: 32-bit divisions).
+__device__ __forceinline__ void node_xyz(const BArgs& a, long n, int& x, int& y, int& z) {
+  const uint32_t m = (uint32_t)n, nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
+  const uint32_t r = m / nx;
+  x = (int)(m - r * nx);
+  y = (int)(r % ny);
+  z = (int)(r / ny);
+}
 
 // Node x + d, or -1 when it does not exist (outside [0, nx) in channel mode).
 __device__ __forceinline__ long neighbour(const BArgs& a, int x, int y, int z, int dx, int dy, int dz) {
@@ -130,7 +142,8 @@ template <int S, bool POPS, bool RHO>
 __device__ inline void lane_gather(const BArgs& a, const typename Codec<S>::E* A, long n, int lane, LaneNb& h) {
   using C = Codec<S>;
   h.n = n;
-  const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+  int x, y, z;
+  node_xyz(a, n, x, y, z);
   h.x = x;
   h.y = y;
   h.z = z;

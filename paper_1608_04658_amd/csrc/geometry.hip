@@ -354,7 +354,8 @@ __global__ __launch_bounds__(64) void k_mesh_uncovered(const BArgs a, const Bodi
     const long n = a.list[k];
     const uint8_t fl = a.flags[n];
     if (!(fl & FL_SOLID_PREV) || (fl & FL_SOLID)) continue;  // uniform over the group
-    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    int x, y, z;
+    node_xyz(a, n, x, y, z);
     if (owner_body(bd, false, x, y, z) != bd.mesh) continue;
     const double p[3] = {(double)x, (double)y, (double)z};
     double v[3];

@@ -60,17 +60,28 @@ __global__ void k_mesh_count(MeshDev m, const double* X, int32_t* cnt, uint32_t*
 __global__ __launch_bounds__(1024) void k_mesh_scan(int32_t* cnt, int32_t* start, int32_t ncell, int64_t cap,
                                                     uint32_t* overflow) {
   __shared__ int32_t wsum[16];
+  // The loads of eight consecutive 1024-cell chunks are issued together, so the chunk scans wait
+  // for memory once per 8192 cells.
+  constexpr int CHUNKS = 8;
   int32_t running = 0;
-  for (int base = 0; base < ncell; base += 1024) {
-    const int i = base + threadIdx.x;
-    const int32_t v = i < ncell ? cnt[i] : 0;
-    int32_t total;
-    const int32_t incl = scan1024_inclusive(v, wsum, total);
-    if (i < ncell) {
-      start[i] = running + incl - v;
-      cnt[i] = 0;
+  for (int64_t base = 0; base < ncell; base += 1024 * CHUNKS) {
+    int32_t v[CHUNKS];
+#pragma unroll
+    for (int k = 0; k < CHUNKS; ++k) {
+      const int64_t i = base + k * 1024 + threadIdx.x;
+      v[k] = i < ncell ? cnt[i] : 0;
     }
-    running += total;
+#pragma unroll
+    for (int k = 0; k < CHUNKS; ++k) {
+      const int64_t i = base + k * 1024 + threadIdx.x;
+      int32_t total;
+      const int32_t incl = scan1024_inclusive(v[k], wsum, total);
+      if (i < ncell) {
+        start[i] = running + incl - v[k];
+        cnt[i] = 0;
+      }
+      running += total;
+    }
   }
   if (threadIdx.x == 0) {
     start[ncell] = running;

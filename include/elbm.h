@@ -306,6 +306,23 @@ const char* elbm_last_error(const struct elbm_ctx* ctx);
 int elbm_collide_nodes(const float* f_in_dev, float* f_out_dev, float* gamma_dev, const float* F_dev,
                        int64_t n, double nu, double fp64_threshold, uint32_t flags, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): one time step of a periodic box without bodies, the
+ * work of elbm_step on such a context (pull streaming, KBC collision, FP64 recomputation of the
+ * nodes the threshold selects), with no context and no workspace.  p: the parameters of such a
+ * context (bc_x = ELBM_BC_PERIODIC, max_bodies = 0; flags only ELBM_FLAG_NO_FP64,
+ * ELBM_FLAG_EXACT_GAMMA, ELBM_FLAG_LBGK, ELBM_FLAG_CENTRAL, ELBM_FLAG_STREAM_ONLY; the other
+ * fields as elbm_create reads them).  pop_in_dev: dev, A^t, 27 N elements in the storage format
+ * and layout that elbm_save_state writes (ELBM_LAYOUT_ROWS); pop_out_dev: dev, receives A^{t+1} in
+ * the same form; the two must not overlap; both stay the caller's.  stream: a hipStream_t of the
+ * current device.  Returns ELBM_EINVAL (elbm_last_error(NULL) says why) for other parameters, for
+ * N > 8 388 608 nodes, or for overlapping arrays; ELBM_EDEVICE if a HIP call fails.
+ * The library allocates nothing here: the FP64 queue and its counters live in a static device array
+ * of 32 MiB + 256 bytes that each GPU the library runs on holds until the process ends.  Every call
+ * on one GPU shares that array: calls that overlap in time on one GPU (several streams or host
+ * threads) race and must be ordered by the caller. */
+int elbm_step_periodic_noalloc(const elbm_params* p, const void* pop_in_dev, void* pop_out_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "context.hpp"
@@ -788,4 +789,101 @@ int elbm_collide_nodes(const float* f_in_dev, float* f_out_dev, float* gamma_dev
   return ELBM_OK;
 }
 
+
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// elbm_step_periodic_noalloc: one step of a periodic box without bodies for callers that cannot
+// allocate device memory.  elbm_step keeps the FP64 recomputation queue (one entry per node) and
+// its counters in the caller's workspace; here they live in the file-scope device array below,
+// one copy per GPU, held from the library's first load on that GPU until the process ends.  Its
+// device address is taken once per device with hipGetSymbolAddress; host code passes only that
+// address to kernels (the array's own name is a host-side stand-in, not a device address).
+namespace {
+constexpr size_t NOALLOC_COUNTER_BYTES = 256;
+constexpr int64_t NOALLOC_MAX_NODES = (int64_t)1 << 23;  // 8 388 608 nodes, e.g. 256 x 256 x 128
+constexpr size_t NOALLOC_BYTES = NOALLOC_COUNTER_BYTES + sizeof(uint32_t) * (size_t)NOALLOC_MAX_NODES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static_assert(sizeof(DevCounters) <= NOALLOC_COUNTER_BYTES, "counters must fit their slot");
+}  // namespace
+
+// [counters: NOALLOC_COUNTER_BYTES][FP64 queue: one uint32 per node, NOALLOC_MAX_NODES entries]
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[NOALLOC_MAX_DEVICES];  // device address of `scratch` on each device, or null
+
+// The per-call counters must start at zero: a kernel clears them (no memset node, so the call
+// can be captured into a graph).
+__global__ void k_noalloc_clear(uint32_t* counters, int n) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) counters[k] = 0u;
+}
+
+// Address of the scratch array on the current device (taken on the first call there).
+hipError_t noalloc_scratch(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[dev] = (char*)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" int elbm_step_periodic_noalloc(const elbm_params* p, const void* pop_in_dev, void* pop_out_dev,
+                                          void* stream) {
+  const int rc = validate(p, g_create_err);
+  if (rc) return rc;
+  if (!pop_in_dev || !pop_out_dev) return fail(nullptr, ELBM_EINVAL, "pop_in_dev and pop_out_dev must be set");
+  if (p->bc_x != ELBM_BC_PERIODIC || p->max_bodies != 0)
+    return fail(nullptr, ELBM_EINVAL, "the allocation-free step serves a periodic box without bodies");
+  const uint32_t allowed = ELBM_FLAG_NO_FP64 | ELBM_FLAG_EXACT_GAMMA | ELBM_FLAG_LBGK | ELBM_FLAG_CENTRAL |
+                           ELBM_FLAG_STREAM_ONLY;
+  if (p->flags & ~allowed)
+    return fail(nullptr, ELBM_EINVAL, "flags 0x%x: no body force or adjoint in the allocation-free step",
+                p->flags & ~allowed);
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  if (N > NOALLOC_MAX_NODES)
+    return fail(nullptr, ELBM_EINVAL, "%lld nodes exceed the %lld of the allocation-free step's scratch",
+                (long long)N, (long long)NOALLOC_MAX_NODES);
+  const size_t bytes = 27 * (size_t)N * storage_bytes(p->storage);
+  const char* a0 = (const char*)pop_in_dev;
+  const char* b0 = (const char*)pop_out_dev;
+  if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(nullptr, ELBM_EINVAL, "pop_in_dev and pop_out_dev overlap");
+  char* scr = nullptr;
+  hipError_t e = noalloc_scratch(&scr);
+  if (e != hipSuccess) return fail(nullptr, ELBM_EDEVICE, "scratch address: %s", hipGetErrorString(e));
+  // a context on the host stack: the same sweep and FP64 kernels as elbm_step, their queue and
+  // counters in the scratch array, the populations the caller's
+  elbm_ctx c{};
+  c.p = *p;
+  c.stream = (hipStream_t)stream;
+  c.N = N;
+  c.beta = 1.0 / (6.0 * p->nu + 1.0);
+  c.fp64_thr = p->fp64_threshold > 0.0 ? p->fp64_threshold : 1e-12;
+  c.stab = (p->flags & ELBM_FLAG_EXACT_GAMMA) ? STAB_EXACT : ((p->flags & ELBM_FLAG_LBGK) ? STAB_LBGK : STAB_KBC);
+  if (p->flags & ELBM_FLAG_CENTRAL) c.stab |= STAB_CENTRAL;
+  c.pop[0] = const_cast<void*>(pop_in_dev);
+  c.pop[1] = pop_out_dev;
+  c.cur = 0;
+  c.lay = pop_layout(c.p);
+  c.cnt = (DevCounters*)scr;
+  c.fix_list = (int32_t*)(scr + NOALLOC_COUNTER_BYTES);
+  c.fix_par = 0;
+  hipLaunchKernelGGL(k_noalloc_clear, dim3(1), dim3(64), 0, c.stream, (uint32_t*)scr,
+                     (int)(NOALLOC_COUNTER_BYTES / sizeof(uint32_t)));
+  e = hipGetLastError();
+  if (e == hipSuccess) e = launch_sweep(&c);
+  if (e == hipSuccess) e = launch_fixup(&c);
+  if (e != hipSuccess) return fail(nullptr, ELBM_EDEVICE, "allocation-free step: %s", hipGetErrorString(e));
+  return ELBM_OK;
+}

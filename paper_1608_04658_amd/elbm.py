@@ -97,6 +97,7 @@ def load():
         "elbm_adjoint_param_grad": [_VP, P(ctypes.c_double), ctypes.c_int32],
         "elbm_set_timing": [_VP, ctypes.c_int32],
         "elbm_get_timing": [_VP, P(ctypes.c_double), P(ctypes.c_int64)],
+        "elbm_step_periodic_noalloc": [P(Params), _VP, _VP, _VP],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -134,6 +135,8 @@ def _ptr(t) -> int | None:
 
 
 def _stream_handle(stream=None) -> int:
+    if isinstance(stream, int):
+        return stream
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
@@ -316,6 +319,11 @@ def elbm_collide_nodes(f_in, f_out, gamma, F, n: int, nu: float, fp64_threshold:
                        stream=None):
     _check(load().elbm_collide_nodes(_ptr(f_in), _ptr(f_out), _ptr(gamma), _ptr(F), int(n), float(nu),
                                      float(fp64_threshold), int(flags), _stream_handle(stream)))
+
+
+def elbm_step_periodic_noalloc(params: Params, pop_in, pop_out, stream=None):
+    _check(load().elbm_step_periodic_noalloc(ctypes.byref(params), _ptr(pop_in), _ptr(pop_out),
+                                             _stream_handle(stream)))
 
 
 # ----------------------------------------------------------------------------- convenience owner

@@ -87,3 +87,24 @@ def test_create_rejects_small_or_misaligned_workspace(lib):
     assert "needs" in elbm.elbm_last_error(None)
     assert lib.elbm_create(ctypes.byref(p), None, ctypes.c_void_p(257), n, ctypes.byref(ctx)) == -1
     assert lib.elbm_create(ctypes.byref(p), None, None, n, ctypes.byref(ctx)) == -1
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(shape=(256, 256, 129)), "exceed"),
+    (dict(shape=(16, 16, 16), channel=True), "periodic box without bodies"),
+    (dict(shape=(16, 16, 16), max_bodies=1), "periodic box without bodies"),
+    (dict(shape=(16, 16, 16), flags=1), "no body force"),
+    (dict(shape=(16, 16, 16), flags=8), "no body force"),
+])
+def test_noalloc_step_rejects_what_it_does_not_serve(lib, kw, msg):
+    # rejected on the host before any device call: no GPU needed
+    shape = kw.pop("shape")
+    p = elbm.make_params(shape, 0.1, **kw)
+    with pytest.raises(elbm.ElbmError, match=msg):
+        elbm.elbm_step_periodic_noalloc(p, 256, 1 << 40, stream=0)
+
+
+def test_noalloc_step_rejects_overlap(lib):
+    p = elbm.make_params((8, 8, 8), 0.1)
+    with pytest.raises(elbm.ElbmError, match="overlap"):
+        elbm.elbm_step_periodic_noalloc(p, 4096, 4096 + 64, stream=0)

@@ -7,6 +7,11 @@ shares no code with the GPU path: its C source (``elbm_oracle.c``) carries its
 own lattice tables and follows the paper's equations with one scalar loop per
 node in FP64.
 
+A second library, ``elbm_oracle_adjoint.cpp`` (C++, FP64), is the adjoint of one step: it
+restates the step on a generic scalar type and takes exact local Jacobians with forward-mode dual
+numbers (``Simulation.adjoint_step``).  It does not call the forward oracle, so the tests check the
+two against each other.
+
 This module is a ctypes wrapper (argument marshalling plus the time loop).
 Population arrays are float64 numpy arrays of shape (27, nz, ny, nx); the
 velocity order is i = 9 (cz+1) + 3 (cy+1) + (cx+1).
@@ -22,19 +27,28 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "elbm_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libelbm_oracle.so")
+_ADJ_SRC = os.path.join(_HERE, "elbm_oracle_adjoint.cpp")
+_ADJ_LIB_PATH = os.path.join(_HERE, "libelbm_oracle_adjoint.so")
 _lib = None
+_adj_lib = None
 
 NQ = 27
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, OpenMP, no FP contraction)."""
+    """Compile the oracle (gcc) and its adjoint (g++): FP64, OpenMP, no FP contraction."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
                "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
+    if force or not os.path.exists(_ADJ_LIB_PATH):
+        tmp = _ADJ_LIB_PATH + ".tmp"
+        cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall",
+               "-o", tmp, _ADJ_SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _ADJ_LIB_PATH)
     return _LIB_PATH
 
 
@@ -119,6 +133,25 @@ def lib():
     return _lib
 
 
+def adj_lib():
+    """The FP64 adjoint of the oracle step (elbm_oracle_adjoint.cpp)."""
+    global _adj_lib
+    if _adj_lib is None:
+        if not os.path.exists(_ADJ_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_ADJ_LIB_PATH)
+        L.oa_collide.argtypes = [_D, ctypes.c_double, _D, ctypes.c_int]
+        L.oa_collide_vjp.argtypes = [_D, ctypes.c_double, _D, ctypes.c_int, _D, _D, _D]
+        L.oa_grad_pressure_vjp.argtypes = [ctypes.c_double, _D, _D, ctypes.c_double, _D, _D, _D, _D, _D]
+        L.oa_link_fraction.argtypes = [ctypes.POINTER(Body), _D, _D, ctypes.c_int, _D]
+        L.oa_link_fraction.restype = ctypes.c_double
+        L.oa_adjoint_step.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Body), ctypes.c_int, ctypes.c_double,
+                                      _D, _U8, _U8, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.oa_adjoint_step.restype = ctypes.c_int
+        _adj_lib = L
+    return _adj_lib
+
+
 def _dp(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(_D)
@@ -197,6 +230,42 @@ def pressure(rho: float, u, G, beta: float) -> np.ndarray:
     lib().or_pressure(rho, _dp(np.ascontiguousarray(u, dtype=np.float64)),
                       _dp(np.ascontiguousarray(np.asarray(G, dtype=np.float64).reshape(9))), beta, _dp(out))
     return out.reshape(3, 3)
+
+
+def collide_adjoint(f, beta: float, gout, F=None, lbgk: bool = False):
+    """(df'/df)^T gout and (df'/dF)^T gout of one node's collision, from the adjoint library."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    g = np.ascontiguousarray(gout, dtype=np.float64)
+    gf, gF = np.zeros(27), np.zeros(3)
+    Fp = _dp(np.ascontiguousarray(F, dtype=np.float64)) if F is not None else None
+    adj_lib().oa_collide_vjp(_dp(f), beta, Fp, 1 if lbgk else 0, _dp(g), _dp(gf), _dp(gF))
+    return gf, gF
+
+
+def collide_restated(f, beta: float, F=None, lbgk: bool = False):
+    """The adjoint library's own restatement of one node's collision (values)."""
+    f = np.array(f, dtype=np.float64)
+    Fp = _dp(np.ascontiguousarray(F, dtype=np.float64)) if F is not None else None
+    adj_lib().oa_collide(_dp(f), beta, Fp, 1 if lbgk else 0)
+    return f
+
+
+def grad_pressure_adjoint(rho: float, u, G, beta: float, gout):
+    """Grad's distribution at (rho, u, Pi(rho, u, G)) and its transposed derivative (g_rho, g_u, g_G)."""
+    out, gu, gG, gr = np.zeros(27), np.zeros(3), np.zeros(9), np.zeros(1)
+    adj_lib().oa_grad_pressure_vjp(rho, _dp(np.ascontiguousarray(u, dtype=np.float64)),
+                                   _dp(np.ascontiguousarray(np.asarray(G, dtype=np.float64).reshape(9))), beta,
+                                   _dp(np.ascontiguousarray(gout, dtype=np.float64)), _dp(out), _dp(gr), _dp(gu),
+                                   _dp(gG))
+    return out, float(gr[0]), gu, gG.reshape(3, 3)
+
+
+def link_fraction_adjoint(body, c, xb, i: int):
+    """(q, dq/dc) of a link of a sphere or plane with centre c, from the adjoint library."""
+    g = np.zeros(3)
+    q = adj_lib().oa_link_fraction(ctypes.byref(body), _dp(np.asarray(c, dtype=np.float64)),
+                                   _dp(np.asarray(xb, dtype=np.float64)), int(i), _dp(g))
+    return q, g
 
 
 # ----------------------------------------------------------------------------- bodies
@@ -443,6 +512,34 @@ class Simulation:
                 fb["F"] = self.forces[-1][k, :3].copy()
                 fb["M"] = self.forces[-1][k, 3:].copy()
         return self
+
+    def adjoint_step(self, lam, w_force=None, solid_t1=None):
+        """FP64 adjoint of the step t -> t+1 from the current state (oracle adjoint; masks frozen at
+        the current mask and at solid_t1, default the frozen or computed mask of t+1):
+        for L = <lam, A^{t+1}> + sum_k w_k . F_k(t+1) returns (dL/dA^t, dL/dF or None, dL/d(amp_k),
+        A^{t+1}, forces) -- the last two the adjoint library's own forward values.  The state is
+        left unchanged."""
+        nx, ny, nz = self.shape
+        if solid_t1 is None:
+            solid_t1 = self.frozen_masks[self.t + 1] if self.frozen_masks is not None else self.mask(self.t + 1)
+        s1 = np.ascontiguousarray(solid_t1, dtype=np.uint8)
+        self._set_tracks()
+        lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(27, nz, ny, nx)
+        out = np.zeros_like(self.A)
+        A1 = np.zeros_like(self.A)
+        gF = np.zeros((3, nz, ny, nx)) if self.F is not None else None
+        gamp = np.zeros(max(1, self.nb))
+        forces = np.zeros(max(1, self.nb) * 3)
+        w = None
+        if w_force is not None:
+            w = np.ascontiguousarray(np.asarray(w_force, dtype=np.float64).reshape(-1))
+        rc = adj_lib().oa_adjoint_step(ctypes.byref(self.grid), self.bodies, self.nb, float(self.t), _dp(self.A),
+                                       _u8(self.solid), _u8(s1), _dp(self.F) if self.F is not None else None,
+                                       _dp(lam), _dp(w) if w is not None else None, _dp(out),
+                                       _dp(gF) if gF is not None else None, _dp(gamp), _dp(A1), _dp(forces))
+        if rc != 0:
+            raise RuntimeError(f"oa_adjoint_step failed: {rc}")
+        return out, gF, gamp[: self.nb], A1, forces[: 3 * self.nb].reshape(self.nb, 3)
 
     def moments(self):
         rho = np.zeros(self.N)

@@ -582,5 +582,59 @@ class Simulation:
         return G.reshape(3, 3)
 
 
+def force_rollout_adjoint(shape, nu, bodies, steps: int, weights, rho=None, u=None, F=None, channel=False,
+                          u_in=(0.0, 0.0, 0.0), checkpoint: int = 10, masks=None):
+    """FP64 gradient of L = sum_t w_t . F_0(t+1) (the momentum-exchange force on body 0 after the step
+    t -> t+1, t = 0..steps-1) over a rollout from the equilibrium of (rho, u), by the oracle adjoint:
+    the forward run keeps a checkpoint every `checkpoint` steps (and records the solid masks, or takes
+    the given ones, frozen); the reverse sweep recomputes each segment's states and applies
+    Simulation.adjoint_step backwards.  Returns (L, dL/dF or None, dL/d(amp_k), masks)."""
+    wts = np.asarray(weights, dtype=np.float64).reshape(steps, 3)
+
+    def fresh(A0=None):
+        sim = Simulation(shape, nu, rho, u, bodies=bodies, channel=channel, u_in=u_in, F=F, A0=A0)
+        if masks is not None:
+            sim.frozen_masks = masks
+            sim.solid = masks[0].copy()
+        return sim
+
+    sim = fresh()
+    rec = []
+    ckpt = {0: sim.A.copy()}
+    for t in range(steps):
+        sim.step(1, record_masks=rec if masks is None else None)
+        if (t + 1) % checkpoint == 0 and t + 1 < steps:
+            ckpt[t + 1] = sim.A.copy()
+    mk = masks if masks is not None else {k: m for k, m in enumerate(rec)}
+    L = float(sum(wts[t] @ sim.forces[t][0, :3] for t in range(steps)))
+    nb = len(bodies)
+    w_all = np.zeros((steps, max(1, nb), 3))
+    w_all[:, 0, :] = wts
+    nx, ny, nz = shape
+    lam = np.zeros((27, nz, ny, nx))
+    gF = np.zeros((3, nz, ny, nx)) if F is not None else None
+    gamp = np.zeros(nb)
+    for s0 in sorted(ckpt, reverse=True):
+        s1 = min(s0 + checkpoint, steps)
+        seg = Simulation(shape, nu, bodies=bodies, channel=channel, u_in=u_in, F=F, A0=ckpt[s0])
+        seg.t = s0
+        seg.frozen_masks = mk
+        seg.solid = mk[s0].copy()
+        states = [seg.A.copy()]
+        for _ in range(s0, s1 - 1):
+            seg.step(1)
+            states.append(seg.A.copy())
+        for t in reversed(range(s0, s1)):
+            back = Simulation(shape, nu, bodies=bodies, channel=channel, u_in=u_in, F=F, A0=states[t - s0])
+            back.t = t
+            back.frozen_masks = mk
+            back.solid = mk[t].copy()
+            lam, g, ga, _, _ = back.adjoint_step(lam, w_all[t, :nb])
+            if gF is not None:
+                gF += g
+            gamp += ga
+    return L, gF, gamp, mk
+
+
 def max_threads() -> int:
     return lib().or_max_threads()

@@ -190,6 +190,9 @@ struct AdjArgs {
   float* side;
   float* gF;
   double* gUR;
+  const double* m64;  // U^t, R^t in FP64 (4 N) around the bodies and on the inlet slab
+  double* r64;        // FP64 refill populations of the uncovered nodes, [list slot][27]
+  int32_t* slot;      // list slot of each uncovered node
 };
 
 struct AdjBodyArgs {
@@ -299,13 +302,23 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
     f[i] = (double)C::load_dev(A + pull_src_pop(a, P, i)) + wd(i);  // exact widening
     gp[i] = (double)j.lam_in[i * a.N + n];
   }
+  if (FLAGS && (fl & FL_NEAR_REFILL)) {
+    // a source uncovered in this step: its refill value unrounded (the stored one is rounded)
+    for (int i = 0; i < 27; ++i) {
+      const long s = pull_src_idx(a, P, i);
+      if ((a.flags[s] & (FL_SOLID_PREV | FL_SOLID)) == FL_SOLID_PREV) {
+        const uint32_t sl = (uint32_t)j.slot[s];
+        if (sl < (uint32_t)a.cap) f[i] = j.r64[(size_t)sl * 27 + i];
+      }
+    }
+  }
   double Fx = 0.0, Fy = 0.0, Fz = 0.0;
   if (FORCE) {
     Fx = a.F[n];
     Fy = a.F[a.N + n];
     Fz = a.F[2 * a.N + n];
   }
-  kbc_vjp<double, FORCE>(f, gp, (double)a.beta, Fx, Fy, Fz, g, gF, a.stab == STAB_LBGK);
+  kbc_vjp<double, FORCE>(f, gp, a.beta64, Fx, Fy, Fz, g, gF, a.stab == STAB_LBGK);
 #pragma unroll
   for (int i = 0; i < 27; ++i) push_idx(a, j, P, i, y, z, (float)g[i]);
   if (FORCE && j.gF) {
@@ -316,51 +329,53 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
 }
 
 // Adjoint of Grad's distribution f*_i(rho, u, Pi) (eq. grad), accumulated over directions.
-__device__ inline void grad_pop_vjp(int i, float gfs, float rho, const float (&u)[3], float& gr, float (&gu)[3],
-                                    float (&gP)[6]) {
-  const float W = wf(i);
-  const float c[3] = {(float)cx(i), (float)cy(i), (float)cz(i)};
-  const float cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
-  const float c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-  gr += gfs * W * (1.f + 3.f * cu - 1.5f * (c2 - 1.f));
-  gu[0] += gfs * 3.f * rho * W * c[0];
-  gu[1] += gfs * 3.f * rho * W * c[1];
-  gu[2] += gfs * 3.f * rho * W * c[2];
-  const float t = 1.f / 3.f;
-  gP[0] += gfs * 4.5f * W * (c[0] * c[0] - t);
-  gP[1] += gfs * 4.5f * W * (c[1] * c[1] - t);
-  gP[2] += gfs * 4.5f * W * (c[2] * c[2] - t);
-  gP[3] += gfs * 9.f * W * c[0] * c[1];
-  gP[4] += gfs * 9.f * W * c[0] * c[2];
-  gP[5] += gfs * 9.f * W * c[1] * c[2];
+template <typename T>
+__device__ inline void grad_pop_vjp(int i, T gfs, T rho, const T (&u)[3], T& gr, T (&gu)[3], T (&gP)[6]) {
+  const T W = T(wd(i));
+  const T c[3] = {T(cx(i)), T(cy(i)), T(cz(i))};
+  const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+  const T c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+  gr += gfs * W * (T(1) + T(3) * cu - T(1.5) * (c2 - T(1)));
+  gu[0] += gfs * T(3) * rho * W * c[0];
+  gu[1] += gfs * T(3) * rho * W * c[1];
+  gu[2] += gfs * T(3) * rho * W * c[2];
+  const T t = T(1.0 / 3.0);
+  gP[0] += gfs * T(4.5) * W * (c[0] * c[0] - t);
+  gP[1] += gfs * T(4.5) * W * (c[1] * c[1] - t);
+  gP[2] += gfs * T(4.5) * W * (c[2] * c[2] - t);
+  gP[3] += gfs * T(9) * W * c[0] * c[1];
+  gP[4] += gfs * T(9) * W * c[0] * c[2];
+  gP[5] += gfs * T(9) * W * c[1] * c[2];
 }
 
 // Adjoint of the pressure tensor (eqs. pressure, pressure2) in the packed order xx,yy,zz,xy,xz,yz.
-__device__ inline void pressure_vjp(float rho, const float (&u)[3], const float (&G)[9], float beta,
-                                    const float (&gP)[6], float& gr, float (&gu)[3], float (&gG)[9]) {
-  const float k = rho / (6.f * beta), kr = 1.f / (6.f * beta);
-  gr += gP[0] * (1.f / 3.f + u[0] * u[0] - 2.f * kr * G[0]) + gP[1] * (1.f / 3.f + u[1] * u[1] - 2.f * kr * G[4]) +
-        gP[2] * (1.f / 3.f + u[2] * u[2] - 2.f * kr * G[8]) + gP[3] * (u[0] * u[1] - kr * (G[1] + G[3])) +
+template <typename T>
+__device__ inline void pressure_vjp(T rho, const T (&u)[3], const T (&G)[9], T beta, const T (&gP)[6], T& gr,
+                                    T (&gu)[3], T (&gG)[9]) {
+  const T k = rho / (T(6) * beta), kr = T(1) / (T(6) * beta);
+  const T t = T(1.0 / 3.0);
+  gr += gP[0] * (t + u[0] * u[0] - T(2) * kr * G[0]) + gP[1] * (t + u[1] * u[1] - T(2) * kr * G[4]) +
+        gP[2] * (t + u[2] * u[2] - T(2) * kr * G[8]) + gP[3] * (u[0] * u[1] - kr * (G[1] + G[3])) +
         gP[4] * (u[0] * u[2] - kr * (G[2] + G[6])) + gP[5] * (u[1] * u[2] - kr * (G[5] + G[7]));
-  gu[0] += 2.f * rho * u[0] * gP[0] + rho * u[1] * gP[3] + rho * u[2] * gP[4];
-  gu[1] += 2.f * rho * u[1] * gP[1] + rho * u[0] * gP[3] + rho * u[2] * gP[5];
-  gu[2] += 2.f * rho * u[2] * gP[2] + rho * u[0] * gP[4] + rho * u[1] * gP[5];
-  gG[0] = -2.f * k * gP[0];
-  gG[4] = -2.f * k * gP[1];
-  gG[8] = -2.f * k * gP[2];
+  gu[0] += T(2) * rho * u[0] * gP[0] + rho * u[1] * gP[3] + rho * u[2] * gP[4];
+  gu[1] += T(2) * rho * u[1] * gP[1] + rho * u[0] * gP[3] + rho * u[2] * gP[5];
+  gu[2] += T(2) * rho * u[2] * gP[2] + rho * u[0] * gP[4] + rho * u[1] * gP[5];
+  gG[0] = -T(2) * k * gP[0];
+  gG[4] = -T(2) * k * gP[1];
+  gG[8] = -T(2) * k * gP[2];
   gG[1] = gG[3] = -k * gP[3];
   gG[2] = gG[6] = -k * gP[4];
   gG[5] = gG[7] = -k * gP[5];
 }
 
-__device__ inline void addU(const BArgs& a, const AdjArgs& j, int comp, long node, float v) {
-  if (v != 0.f) atomicAdd(&j.gUR[comp * a.N + node], (double)v);
+__device__ inline void addU(const BArgs& a, const AdjArgs& j, int comp, long node, double v) {
+  if (v != 0.0) atomicAdd(&j.gUR[comp * a.N + node], v);
 }
 
 // Transpose of the finite-difference stencil of grad_u for one (axis b, component c) pair:
 // g = dL/dG[3c+b] -> dL/dU^t at the stencil nodes (FP64 accumulators).
-__device__ inline void grad_u_vjp_one(const BArgs& a, const AdjArgs& j, const LaneNb& h, int b, int c, float g) {
-  if (g == 0.f) return;
+__device__ inline void grad_u_vjp_one(const BArgs& a, const AdjArgs& j, const LaneNb& h, int b, int c, double g) {
+  if (g == 0.0) return;
   const int ip = dir_index(b == 0, b == 1, b == 2), im = dir_index(-(b == 0), -(b == 1), -(b == 2));
   const bool op1 = (h.fluid >> ip) & 1u, om1 = (h.fluid >> im) & 1u;
   const bool op2 = (h.far >> (2 * b)) & 1u, om2 = (h.far >> (2 * b + 1)) & 1u;
@@ -369,16 +384,16 @@ __device__ inline void grad_u_vjp_one(const BArgs& a, const AdjArgs& j, const La
   const long m1 = neighbour(a, h.x, h.y, h.z, cx(im), cy(im), cz(im));
   const long p2 = far_node(a, h.x, h.y, h.z, 2 * b), m2 = far_node(a, h.x, h.y, h.z, 2 * b + 1);
   if (op1 && om1) {
-    addU(a, j, c, p1, 0.5f * g);
-    addU(a, j, c, m1, -0.5f * g);
+    addU(a, j, c, p1, 0.5 * g);
+    addU(a, j, c, m1, -0.5 * g);
   } else if (op1 && op2) {
-    addU(a, j, c, n0, -1.5f * g);
-    addU(a, j, c, p1, 2.f * g);
-    addU(a, j, c, p2, -0.5f * g);
+    addU(a, j, c, n0, -1.5 * g);
+    addU(a, j, c, p1, 2.0 * g);
+    addU(a, j, c, p2, -0.5 * g);
   } else if (om1 && om2) {
-    addU(a, j, c, n0, 1.5f * g);
-    addU(a, j, c, m1, -2.f * g);
-    addU(a, j, c, m2, 0.5f * g);
+    addU(a, j, c, n0, 1.5 * g);
+    addU(a, j, c, m1, -2.0 * g);
+    addU(a, j, c, m2, 0.5 * g);
   } else if (op1) {
     addU(a, j, c, p1, g);
     addU(a, j, c, n0, -g);
@@ -473,12 +488,164 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
   return gp + g_dh + e + g_rho + ci[0] * gjx + ci[1] * gjy + ci[2] * gjz;
 }
 
+// ---------------------------------------------------------------------------------------------
+// The point of linearisation.  The stabiliser's derivative changes fast with the state (its
+// curvature goes with 1/<dh|dh>), so a reverse step evaluated at populations rounded to FP32
+// differs from the derivative at the exact state by far more than FP32 rounding: at inlet nodes
+// of a state with relative noise 1e-3, FP32 Grad populations moved dL/dA^t by up to 1e-4 of its
+// size.  The reverse step therefore rebuilds its forward quantities in FP64 from the stored state:
+// U^t and R^t (k_macro64), the wall targets and Grad populations (wall_targets64), the refill
+// values (k_adj_refill); only the adjoint fields themselves are stored in FP32.
+
+// U^t, R^t in FP64 on a box: the rule of k_macro (moments of A^t with U = (j - F/2)/rho at nodes
+// fluid at t, the rigid-body velocity and rho0 at nodes solid at t) from the exactly widened
+// stored deviations.
+template <int S>
+__global__ void k_macro64(const typename Codec<S>::E* A, PopLayout lay, const uint8_t* flags, double* m64,
+                          const float* F, Box box, int32_t nx, int32_t ny, int64_t N, double rho0, Bodies bd) {
+  using C = Codec<S>;
+  const long total = box.count();
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    box_node(box, idx, x, y, z);
+    const long n = ((long)z * ny + y) * nx + x;
+    double U[3], R;
+    if (flags[n] & FL_SOLID_PREV) {
+      const BodyDev& b = bd.b[max(first_body(bd, false, x, y, z), 0)];
+      const double r[3] = {x - b.c0[0], y - b.c0[1], z - b.c0[2]};
+      U[0] = b.U0[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]);
+      U[1] = b.U0[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]);
+      U[2] = b.U0[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]);
+      R = rho0;
+    } else {
+      double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        const double v = (double)C::load_dev(A + pop_off(lay, i, x, y, z));
+        dr += v;
+        jx += cx(i) * v;
+        jy += cy(i) * v;
+        jz += cz(i) * v;
+      }
+      const double rho = 1.0 + dr;
+      if (F) {
+        jx -= 0.5 * (double)F[n];
+        jy -= 0.5 * (double)F[N + n];
+        jz -= 0.5 * (double)F[2 * N + n];
+      }
+      U[0] = jx / rho;
+      U[1] = jy / rho;
+      U[2] = jz / rho;
+      R = rho;
+    }
+    m64[n] = U[0];
+    m64[N + n] = U[1];
+    m64[2 * N + n] = U[2];
+    m64[3 * N + n] = R;
+  }
+}
+
+// This lane's FP64 U^t, R^t of the stencil gathered by lane_gather (same masks).
+struct LaneU64 {
+  double U[3];  // U^t at x + c_lane where fluid at t+1
+  double V[3];  // U^t at the far node of this lane where fluid at t+1
+  double R;     // R^t at x + c_lane where fluid at t and t+1
+};
+
+__device__ inline void lane_u64(const BArgs& a, const double* m64, const LaneNb& h, int lane, LaneU64& u) {
+  const bool own = lane < 27;
+  const int i = own ? lane : 13;
+  const long m = neighbour(a, h.x, h.y, h.z, cx(i), cy(i), cz(i));
+  const int fk = lane >= 27 ? lane - 27 : (lane == 13 ? 5 : -1);
+  const bool uf = own && ((h.fluid >> i) & 1u);
+  const bool vf = fk >= 0 && ((h.far >> fk) & 1u);
+  const long mf = vf ? far_node(a, h.x, h.y, h.z, fk) : -1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    u.U[c] = uf ? m64[c * a.N + m] : 0.0;
+    u.V[c] = vf ? m64[c * a.N + mf] : 0.0;
+  }
+  u.R = (own && ((h.fluid0 >> i) & 1u)) ? m64[3 * a.N + m] : 0.0;
+}
+
+// grad_u_grp on the FP64 stencil.
+__device__ inline void grad_u_grp64(const LaneNb& h, const LaneU64& u, double (&G)[9]) {
+  double u0[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u0[c] = __shfl(u.U[c], 13, GROUP);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int ip = dir_index(b == 0, b == 1, b == 2), im = dir_index(-(b == 0), -(b == 1), -(b == 2));
+    const bool op1 = (h.fluid >> ip) & 1u, om1 = (h.fluid >> im) & 1u;
+    const bool op2 = (h.far >> (2 * b)) & 1u, om2 = (h.far >> (2 * b + 1)) & 1u;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double up1 = __shfl(u.U[c], ip, GROUP), um1 = __shfl(u.U[c], im, GROUP);
+      const double up2 = __shfl(u.V[c], far_lane(2 * b), GROUP), um2 = __shfl(u.V[c], far_lane(2 * b + 1), GROUP);
+      double d;
+      if (op1 && om1) d = 0.5 * (up1 - um1);
+      else if (op1 && op2) d = 0.5 * (-3.0 * u0[c] + 4.0 * up1 - up2);
+      else if (om1 && om2) d = 0.5 * (3.0 * u0[c] - 4.0 * um1 + um2);
+      else if (op1) d = up1 - u0[c];
+      else if (om1) d = u0[c] - um1;
+      else d = 0.0;
+      G[3 * c + b] = d;
+    }
+  }
+}
+
+// wall_targets in FP64: this lane's link, the group's targets, the gradient of U^t, the pressure
+// tensor and this lane's Grad population (absolute), from the FP64 U^t and the exactly widened
+// stored deviations.
+struct WallLane64 {
+  bool mine;
+  double q, uw[3];
+  int kb;
+  double fb;  // bounce-back value: deviation of A^t_{opp(lane)}(x)
+  double fs;  // f*_lane (absolute; mine)
+  double rt, ut[3], G[9], Pi[6];
+  int nD;
+};
+
+// fdev: this lane's pulled deviation (0 where missing), fodev: the node's own deviation of this
+// lane's direction, both in FP64.
+__device__ inline void wall_targets64(const BArgs& a, const Bodies& bd, const LaneNb& h, const LaneU64& u, int lane,
+                                      double fdev, double fodev, WallLane64& w) {
+  const int i = lane < 27 ? lane : 13;
+  w.mine = lane < 27 && ((h.dbar >> lane) & 1u);
+  w.q = 0.0;
+  w.uw[0] = w.uw[1] = w.uw[2] = 0.0;
+  w.kb = -1;
+  if (w.mine) link_geometry<false>(a, bd, i, h.x, h.y, h.z, w.q, w.uw, w.kb);
+  w.fb = __shfl(fodev, opp(i), GROUP);
+  double tu[3] = {0.0, 0.0, 0.0}, trs = 0.0, trd = 0.0;
+  if (w.mine) {
+    const bool fluid = (h.fluid >> lane) & 1u;
+    const double inv = 1.0 / (1.0 + w.q);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tu[c] = (w.q * (fluid ? u.U[c] : w.uw[c]) + w.uw[c]) * inv;
+    trs = w.fb;
+    trd = 6.0 * wd(i) * a.rho0 * (cx(i) * w.uw[0] + cy(i) * w.uw[1] + cz(i) * w.uw[2]);
+  } else if (lane < 27) {
+    trs = fdev;
+  }
+  const double rstat = gsum(trs), rdyn = gsum(trd);  // rstat: sum of deviations (weights add to 1)
+  w.nD = __popc(h.dbar);
+  const double invn = 1.0 / (double)w.nD;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w.ut[c] = gsum(tu[c]) * invn;
+  w.rt = 1.0 + rstat + rdyn;
+  grad_u_grp64(h, u, w.G);
+  pressure_tensor(w.rt, w.ut, w.G, a.beta64, w.Pi);
+  w.fs = w.mine ? grad_pop(i, w.rt, w.ut, w.Pi) : 0.0;
+}
+
 // Adjoint of the boundary rules of Secs. III / IV.A at the listed nodes, in the lane-parallel
 // form of the forward wall kernel: one node per group of 32 lanes, lane i < 27 owning direction
-// i.  The forward reconstruction is recomputed (same helper as the forward kernel); the FP64
-// collision VJP and the reverse of the reconstruction run per lane with butterfly sums.  Listed nodes
-// without missing populations (inlet and outlet rows, refill nodes) take the plain collision VJP here:
-// their forward values are the wall kernel's, and the adjoint bulk kernel skips FL_SPECIAL nodes.
+// i.  The reconstruction is rebuilt in FP64 (wall_targets64); the FP64 collision VJP and the
+// reverse of the reconstruction run per lane with butterfly sums.  Listed nodes without missing
+// populations (inlet and outlet rows, refill nodes) take the plain collision VJP here: their
+// forward values are the wall kernel's, and the adjoint bulk kernel skips FL_SPECIAL nodes.
 template <int S, bool FORCE>
 __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies bd, const AdjArgs j,
                                                      const AdjBodyArgs p) {
@@ -496,13 +663,36 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
     const long n = a.list[active ? k : base];
     LaneNb h;
     lane_gather<S, true, false>(a, A, n, lane, h);
-    const float gpi = lane < 27 ? j.lam_in[(long)i * a.N + n] : 0.f;
+    const double gpi = lane < 27 ? (double)j.lam_in[(long)i * a.N + n] : 0.0;
     const uint32_t dmask = h.dbar;
-    WallLane w;
+    // FP64 deviations: the stored ones widened exactly, except at nodes uncovered in this step,
+    // whose refill values are taken unrounded -- the node's own (a refill node) and pulled ones
+    double fdev = (double)h.f, fodev = (double)h.fo;
+    if (lane < 27) {
+      if ((a.flags[n] & (FL_SOLID_PREV | FL_SOLID)) == FL_SOLID_PREV) {
+        const uint32_t sl = (uint32_t)j.slot[n];
+        if (sl < (uint32_t)a.cap) fodev = j.r64[(size_t)sl * 27 + i] - wd(i);
+      }
+      if (!((dmask >> lane) & 1u)) {
+        int sx = h.x - cx(i);
+        if (a.channel) sx = sx >= a.nx ? a.nx - 1 : sx;
+        else sx = wrap(sx, a.nx);
+        const long s = node_at(a, sx, wrap(h.y - cy(i), a.ny), wrap(h.z - cz(i), a.nz));
+        if ((a.flags[s] & (FL_SOLID_PREV | FL_SOLID)) == FL_SOLID_PREV) {
+          const uint32_t sl = (uint32_t)j.slot[s];
+          if (sl < (uint32_t)a.cap) fdev = j.r64[(size_t)sl * 27 + i] - wd(i);
+        }
+      }
+    }
+    WallLane64 w;
     w.mine = false;
-    if (dmask) wall_targets<false>(a, bd, h, lane, w);
-    // collision input: f*_i (absolute) where missing, else the pulled deviation widened exactly
-    const double fdi = lane < 27 ? (((dmask >> lane) & 1u) ? (double)w.fs : wd(i) + (double)h.f) : 0.0;
+    if (dmask) {
+      LaneU64 u;
+      lane_u64(a, j.m64, h, lane, u);
+      wall_targets64(a, bd, h, u, lane, fdev, fodev, w);
+    }
+    // collision input: f*_i (absolute) where missing, else the pulled value in FP64
+    const double fdi = lane < 27 ? (((dmask >> lane) & 1u) ? w.fs : wd(i) + fdev) : 0.0;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
     if (FORCE) {
       Fx = a.F[n];
@@ -510,49 +700,46 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
       Fz = a.F[2 * a.N + n];
     }
     double gFn[3];
-    const float gi =
-        (float)kbc_vjp_lanes<FORCE>(lane, fdi, (double)gpi, (double)a.beta, Fx, Fy, Fz, gFn, a.stab == STAB_LBGK);
+    const double gi = kbc_vjp_lanes<FORCE>(lane, fdi, gpi, a.beta64, Fx, Fy, Fz, gFn, a.stab == STAB_LBGK);
     if (FORCE && j.gF && active && lane == 0) {
       j.gF[n] += (float)gFn[0];
       j.gF[a.N + n] += (float)gFn[1];
       j.gF[2 * a.N + n] += (float)gFn[2];
     }
     if (!dmask) {
-      if (active && lane < 27) adj_push(a, j, i, h.x, h.y, h.z, gi);
+      if (active && lane < 27) adj_push(a, j, i, h.x, h.y, h.z, (float)gi);
     } else {
-      float grl = 0.f, gul[3] = {0.f, 0.f, 0.f}, gPl[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      double grl = 0.0, gul[3] = {0.0, 0.0, 0.0}, gPl[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       if (w.mine) {
-        float gfs = gi;
+        double gfs = gi;
         if (p.loss && w.kb >= 0)
-          gfs -= (float)(p.w[w.kb][0] * (cx(i) - w.uw[0]) + p.w[w.kb][1] * (cy(i) - w.uw[1]) +
-                         p.w[w.kb][2] * (cz(i) - w.uw[2]));
+          gfs -= p.w[w.kb][0] * (cx(i) - w.uw[0]) + p.w[w.kb][1] * (cy(i) - w.uw[1]) + p.w[w.kb][2] * (cz(i) - w.uw[2]);
         grad_pop_vjp(i, gfs, w.rt, w.ut, grl, gul, gPl);
       }
-      float gr = gsum(grl), gu[3], gP[6], gG[9];
+      double gr = gsum(grl), gu[3], gP[6], gG[9];
 #pragma unroll
       for (int c = 0; c < 3; ++c) gu[c] = gsum(gul[c]);
 #pragma unroll
       for (int c = 0; c < 6; ++c) gP[c] = gsum(gPl[c]);
-      pressure_vjp(w.rt, w.ut, w.G, a.beta, gP, gr, gu, gG);
+      pressure_vjp(w.rt, w.ut, w.G, a.beta64, gP, gr, gu, gG);
       if (active && lane < 27) {
         if (!w.mine) {
-          adj_push(a, j, i, h.x, h.y, h.z, gi + gr);
+          adj_push(a, j, i, h.x, h.y, h.z, (float)(gi + gr));
         } else {
-          float vbb = gr;
+          double vbb = gr;
           double guw[3];
           const double qd = w.q, inv = 1.0 / (w.nD * (1.0 + qd));
           const double cv[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
 #pragma unroll
-          for (int c = 0; c < 3; ++c) guw[c] = (double)gr * 6.0 * wd(i) * a.rho0 * cv[c] + gu[c] * inv;
+          for (int c = 0; c < 3; ++c) guw[c] = gr * 6.0 * wd(i) * a.rho0 * cv[c] + gu[c] * inv;
           if (p.loss && w.kb >= 0) {
-            const double fbd = wd(opp(i)) + (double)w.fb;
-            const double fs = (double)w.fs;
-            vbb += (float)(p.w[w.kb][0] * (-cv[0] - w.uw[0]) + p.w[w.kb][1] * (-cv[1] - w.uw[1]) +
-                           p.w[w.kb][2] * (-cv[2] - w.uw[2]));
+            const double fbd = wd(opp(i)) + w.fb;
+            vbb += p.w[w.kb][0] * (-cv[0] - w.uw[0]) + p.w[w.kb][1] * (-cv[1] - w.uw[1]) +
+                   p.w[w.kb][2] * (-cv[2] - w.uw[2]);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) guw[c] += p.w[w.kb][c] * (fs - fbd);
+            for (int c = 0; c < 3; ++c) guw[c] += p.w[w.kb][c] * (w.fs - fbd);
           }
-          j.lam_out[(long)opp(i) * a.N + n] += vbb;
+          j.lam_out[(long)opp(i) * a.N + n] += (float)vbb;
           if (!(a.channel && h.x - cx(i) < 0)) adj_push(a, j, i, h.x, h.y, h.z, 0.f);
           // u_f and q
           double uf[3];
@@ -560,8 +747,8 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
             const long nf = neighbour(a, h.x, h.y, h.z, cx(i), cy(i), cz(i));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              uf[c] = h.U[c];
-              addU(a, j, c, nf, (float)(gu[c] * qd * inv));
+              uf[c] = j.m64[c * a.N + nf];
+              addU(a, j, c, nf, gu[c] * qd * inv);
             }
           } else {
 #pragma unroll
@@ -598,10 +785,56 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
   }
 }
 
+// Flag bit FL_NEAR_REFILL of the nodes next to an uncovered node (set = true, or cleared); 32-bit
+// atomics on the word holding the flag byte (the flag array is padded to 256 bytes).
+__device__ inline void mark_near(uint8_t* flags, long m, bool set) {
+  uint32_t* word = (uint32_t*)(flags + (m & ~3L));
+  const uint32_t bit = (uint32_t)FL_NEAR_REFILL << (8 * (m & 3));
+  if (set) atomicOr(word, bit);
+  else atomicAnd(word, ~bit);
+}
+
+// The refill of the step in FP64 (k_refill's rule, from the FP64 U^t and R^t): the populations of
+// each uncovered node go to its list slot of the table r64, the slot to the node's entry of slot[],
+// and the node's neighbours that are fluid at t+1 get FL_NEAR_REFILL, so that the reverse kernels
+// read the unrounded values where they pull from it.
+__global__ __launch_bounds__(64) void k_adj_refill64(const BArgs a, const Bodies bd, const AdjArgs j) {
+  int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
+  if (count > a.cap) count = a.cap;
+  const int lane = threadIdx.x & (GROUP - 1), g = threadIdx.x / GROUP;
+  for (int64_t k = a.n_static + 2 * (int64_t)blockIdx.x + g; k < count; k += 2 * (int64_t)gridDim.x) {
+    const long n = a.list[k];
+    if (!(a.flags[n] & FL_SOLID_PREV)) continue;  // uniform over the group
+    LaneNb h;
+    lane_gather<ELBM_STORAGE_F32, false, false>(a, nullptr, n, lane, h);
+    LaneU64 u;
+    lane_u64(a, j.m64, h, lane, u);
+    int kb = first_body(bd, false, h.x, h.y, h.z);
+    if (kb < 0) kb = 0;
+    const BodyDev& b = bd.b[kb];
+    const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
+    double uw[3];
+    uw[0] = b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]);
+    uw[1] = b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]);
+    uw[2] = b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]);
+    const uint32_t nbm = h.fluid0 & ~(1u << 13);
+    const double rs = gsum(lane != 13 ? u.R : 0.0);
+    const int m = __popc(nbm);
+    const double ravg = m ? rs / (double)m : a.rho0;
+    double G[9], Pi[6];
+    grad_u_grp64(h, u, G);
+    pressure_tensor(ravg, uw, G, a.beta64, Pi);
+    if (lane < 27) j.r64[(size_t)k * 27 + lane] = grad_pop(lane, ravg, uw, Pi);
+    if (lane == 0) j.slot[n] = (int32_t)k;
+    if (lane < 27 && lane != 13 && ((h.fluid >> lane) & 1u))
+      mark_near(const_cast<uint8_t*>(a.flags), neighbour(a, h.x, h.y, h.z, cx(lane), cy(lane), cz(lane)), true);
+  }
+}
+
 // Adjoint of the refill (which writes Grad's distribution into A^t at the nodes uncovered by the
 // step): the completed dL/dA^t of a refill node goes through Grad's distribution to R^t of its
 // neighbours, U^t of its stencil and the body's amplitude; the node's own entries are then zero
-// (its stored A^t is overwritten and influences nothing).
+// (its stored A^t is overwritten and influences nothing).  FP64, from the FP64 U^t and R^t.
 __global__ __launch_bounds__(64) void k_adj_refill(const BArgs a, const Bodies bd, const AdjArgs j,
                                                    const AdjBodyArgs p) {
   int64_t count = a.n_static + (a.moving ? (int64_t)*a.dyn_count : 0);
@@ -611,42 +844,46 @@ __global__ __launch_bounds__(64) void k_adj_refill(const BArgs a, const Bodies b
     const long n = a.list[k];
     if (!(a.flags[n] & FL_SOLID_PREV)) continue;  // uniform over the group
     LaneNb h;
-    lane_gather<ELBM_STORAGE_F32, false, true>(a, nullptr, n, lane, h);
+    lane_gather<ELBM_STORAGE_F32, false, false>(a, nullptr, n, lane, h);
+    LaneU64 u;
+    lane_u64(a, j.m64, h, lane, u);
     // forward recomputation, as k_refill
     int kb = first_body(bd, false, h.x, h.y, h.z);
     if (kb < 0) kb = 0;
     const BodyDev& b = bd.b[kb];
     const double r[3] = {h.x - b.c1[0], h.y - b.c1[1], h.z - b.c1[2]};
-    float uw[3];
-    uw[0] = (float)(b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]));
-    uw[1] = (float)(b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]));
-    uw[2] = (float)(b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]));
+    double uw[3];
+    uw[0] = b.U1[0] + (b.omega[1] * r[2] - b.omega[2] * r[1]);
+    uw[1] = b.U1[1] + (b.omega[2] * r[0] - b.omega[0] * r[2]);
+    uw[2] = b.U1[2] + (b.omega[0] * r[1] - b.omega[1] * r[0]);
     const uint32_t nbm = h.fluid0 & ~(1u << 13);
-    const float rs = gsum(lane != 13 ? h.R : 0.f);
+    const double rs = gsum(lane != 13 ? u.R : 0.0);
     const int m = __popc(nbm);
-    const float ravg = m ? rs / (float)m : (float)a.rho0;
-    float G[9], Pi[6];
-    grad_u_grp(h, G);
-    pressure_tensor(ravg, uw, G, a.beta, Pi);
+    const double ravg = m ? rs / (double)m : a.rho0;
+    double G[9], Pi[6];
+    grad_u_grp64(h, u, G);
+    pressure_tensor(ravg, uw, G, a.beta64, Pi);
     // reverse: the completed dL/dA^t of the refilled entries goes through Grad's distribution;
     // the entries themselves were overwritten, so their adjoint restarts at zero
-    float grl = 0.f, gul[3] = {0.f, 0.f, 0.f}, gPl[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    double grl = 0.0, gul[3] = {0.0, 0.0, 0.0}, gPl[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (lane < 27) {
-      const float gi = j.lam_out[(long)lane * a.N + n];
+      const double gi = (double)j.lam_out[(long)lane * a.N + n];
       j.lam_out[(long)lane * a.N + n] = 0.f;
       grad_pop_vjp(lane, gi, ravg, uw, grl, gul, gPl);
     }
-    float gr = gsum(grl), gu[3], gP[6], gG[9];
+    double gr = gsum(grl), gu[3], gP[6], gG[9];
 #pragma unroll
     for (int c = 0; c < 3; ++c) gu[c] = gsum(gul[c]);
 #pragma unroll
     for (int c = 0; c < 6; ++c) gP[c] = gsum(gPl[c]);
-    pressure_vjp(ravg, uw, G, a.beta, gP, gr, gu, gG);
+    pressure_vjp(ravg, uw, G, a.beta64, gP, gr, gu, gG);
     if (m && lane < 27 && ((nbm >> lane) & 1u))
-      atomicAdd(&j.gUR[3 * a.N + neighbour(a, h.x, h.y, h.z, cx(lane), cy(lane), cz(lane))], (double)(gr / (float)m));
-    if (lane == 0)
-      atomicAdd(&p.gamp[kb], (double)gu[0] * p.dU1[kb][0] + (double)gu[1] * p.dU1[kb][1] + (double)gu[2] * p.dU1[kb][2]);
+      atomicAdd(&j.gUR[3 * a.N + neighbour(a, h.x, h.y, h.z, cx(lane), cy(lane), cz(lane))], gr / (double)m);
+    if (lane == 0) atomicAdd(&p.gamp[kb], gu[0] * p.dU1[kb][0] + gu[1] * p.dU1[kb][1] + gu[2] * p.dU1[kb][2]);
     if (lane < 9) grad_u_vjp_one(a, j, h, lane / 3, lane % 3, gG[3 * (lane % 3) + lane / 3]);
+    // every reader of the marks (bulk and wall kernels) has run: clear them
+    if (lane < 27 && lane != 13 && ((h.fluid >> lane) & 1u))
+      mark_near(const_cast<uint8_t*>(a.flags), neighbour(a, h.x, h.y, h.z, cx(lane), cy(lane), cz(lane)), false);
   }
 }
 
@@ -699,30 +936,30 @@ __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, con
       atomicAdd(&p.gamp[kb], gU0 * p.dU0[kb][0] + gU1 * p.dU0[kb][1] + gU2 * p.dU0[kb][2]);
       continue;
     }
-    float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;  // as the forward: from the stored deviations
+    // U, R of the node from the exactly widened stored deviations (as k_macro64)
+    double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-      const float v = C::load_dev(A + pop_off(a.lay, i, x, y, z));
+      const double v = (double)C::load_dev(A + pop_off(a.lay, i, x, y, z));
       dr += v;
       jx += cx(i) * v;
       jy += cy(i) * v;
       jz += cz(i) * v;
     }
-    const float rho = 1.f + dr;
+    const double rho = 1.0 + dr;
     if (a.F) {
-      jx -= 0.5f * a.F[n];
-      jy -= 0.5f * a.F[a.N + n];
-      jz -= 0.5f * a.F[2 * a.N + n];
+      jx -= 0.5 * (double)a.F[n];
+      jy -= 0.5 * (double)a.F[a.N + n];
+      jz -= 0.5 * (double)a.F[2 * a.N + n];
     }
-    const float U[3] = {jx / rho, jy / rho, jz / rho};
-    const float g0 = (float)gU0, g1 = (float)gU1, g2 = (float)gU2, gr = (float)gR;
+    const double U[3] = {jx / rho, jy / rho, jz / rho};
 #pragma unroll
     for (int i = 0; i < 27; ++i)
-      j.lam_out[i * a.N + n] += gr + (g0 * (cx(i) - U[0]) + g1 * (cy(i) - U[1]) + g2 * (cz(i) - U[2])) / rho;
+      j.lam_out[i * a.N + n] += (float)(gR + (gU0 * (cx(i) - U[0]) + gU1 * (cy(i) - U[1]) + gU2 * (cz(i) - U[2])) / rho);
     if (a.F && j.gF) {
-      j.gF[n] -= g0 / (2.f * rho);
-      j.gF[a.N + n] -= g1 / (2.f * rho);
-      j.gF[2 * a.N + n] -= g2 / (2.f * rho);
+      j.gF[n] -= (float)(gU0 / (2.0 * rho));
+      j.gF[a.N + n] -= (float)(gU1 / (2.0 * rho));
+      j.gF[2 * a.N + n] -= (float)(gU2 / (2.0 * rho));
     }
   }
 }
@@ -756,6 +993,7 @@ static BArgs bargs(elbm_ctx* c, const void* A) {
   a.stab = c->stab;
   a.beta = (float)c->beta;
   a.inv_beta = (float)(1.0 / c->beta);
+  a.beta64 = c->beta;
   a.thr = (float)c->fp64_thr;
   a.rho0 = c->p.rho0;
   for (int e = 0; e < 3; ++e) a.u_in[e] = c->p.u_inlet[e];
@@ -777,6 +1015,24 @@ static void amp_derivatives(const elbm_body& b, double t, double dc[3], double d
 }
 
 template <int S>
+static void macro64_box(elbm_ctx* c, const void* A, const Box& box, const Bodies& bd) {
+  hipLaunchKernelGGL((k_macro64<S>), grid_for(box.count()), dim3(256), 0, c->stream, (const typename Codec<S>::E*)A,
+                     c->lay, (const uint8_t*)c->flags, c->adj_macro64, c->bodyforce, box, c->p.nx, c->p.ny,
+                     (int64_t)c->N, c->p.rho0, bd);
+}
+
+// FP64 U^t, R^t on the boxes where the wall rules read them: around the bodies and the inlet slab.
+template <int S>
+static void macro64_fields(elbm_ctx* c, const void* A, const Bodies& bd) {
+  if (c->nb > 0) macro64_box<S>(c, A, union_box(c, bd), bd);
+  if (c->p.bc_x == ELBM_BC_CHANNEL) {
+    Box slab = full_box(c);
+    slab.n[0] = c->p.nx < 3 ? c->p.nx : 3;
+    macro64_box<S>(c, A, slab, bd);
+  }
+}
+
+template <int S>
 static void adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, const AdjArgs& j, const AdjBodyArgs& p) {
   int bx = 256;
   while (bx > 32 && (c->p.nx % bx) != 0) bx >>= 1;
@@ -784,6 +1040,11 @@ static void adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, const AdjA
   const dim3 blk(bx, 256 / bx, 1);
   const dim3 grd((c->p.nx + bx - 1) / bx, (c->p.ny + blk.y - 1) / blk.y, c->p.nz);
   const bool geo = c->flags != nullptr, force = c->bodyforce != nullptr;
+  if (geo) macro64_fields<S>(c, a.A, bd);
+  if (geo && c->moving) {
+    const dim3 gr((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap - a.n_static + 1) / 2, 1), 4096));
+    hipLaunchKernelGGL(k_adj_refill64, gr, dim3(64), 0, c->stream, a, bd, j);
+  }
   if (geo && force) hipLaunchKernelGGL((k_adj_bulk<S, true, true>), grd, blk, 0, c->stream, a, j);
   else if (geo) hipLaunchKernelGGL((k_adj_bulk<S, true, false>), grd, blk, 0, c->stream, a, j);
   else if (force) hipLaunchKernelGGL((k_adj_bulk<S, false, true>), grd, blk, 0, c->stream, a, j);
@@ -822,6 +1083,9 @@ hipError_t launch_adjoint(elbm_ctx* c, int64_t t, const void* A, const float* la
   j.side = c->adj_side;
   j.gF = gF;
   j.gUR = c->adj_gUR;
+  j.m64 = c->adj_macro64;
+  j.r64 = c->adj_refill64;
+  j.slot = c->adj_slot;
   AdjBodyArgs p{};
   p.gamp = c->adj_gamp;
   p.loss = w_force != nullptr;

@@ -73,6 +73,7 @@ struct BArgs {
   int32_t stream_only;
   int32_t stab;  // STAB_* of the context
   float beta, inv_beta, thr;
+  double beta64;  // beta in FP64 (the reverse step's arithmetic)
   double rho0;
   double u_in[3];
 };

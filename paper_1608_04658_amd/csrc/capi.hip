@@ -38,7 +38,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t pop[2], cnt, fix_list, flags, macro, slab, blist, brec, ring, force_partial, scratch, scan_tmp, adj_gUR, adj_side,
-      adj_gamp, mesh_tri, mesh_X[2], mesh_V[2], mesh_start[2], mesh_items[2], mesh_cursor, free_hist, free_U1, total;
+      adj_gamp, adj_macro64, adj_refill64, adj_slot, mesh_tri, mesh_X[2], mesh_V[2], mesh_start[2], mesh_items[2], mesh_cursor, free_hist, free_U1, total;
   int64_t mesh_cap;
   int64_t scan_blocks;
   int64_t cap;
@@ -123,6 +123,9 @@ Layout layout(const elbm_params* p) {
     L.adj_gUR = take(sizeof(double) * 4 * N);
     L.adj_side = take(sizeof(float) * 9 * (size_t)p->ny * p->nz);
     L.adj_gamp = take(sizeof(double) * ELBM_MAX_BODIES);
+    L.adj_macro64 = take(sizeof(double) * 4 * N);
+    L.adj_refill64 = take(sizeof(double) * 27 * (size_t)(L.cap > 0 ? L.cap : 1));
+    L.adj_slot = take(sizeof(int32_t) * N);
   }
   if (p->max_mesh_triangles > 0) {
     const size_t nv = (size_t)p->max_mesh_vertices, nt = (size_t)p->max_mesh_triangles;
@@ -270,6 +273,9 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->adj_gUR = adj ? (double*)(c->ws + L.adj_gUR) : nullptr;
   c->adj_side = adj ? (float*)(c->ws + L.adj_side) : nullptr;
   c->adj_gamp = adj ? (double*)(c->ws + L.adj_gamp) : nullptr;
+  c->adj_macro64 = adj ? (double*)(c->ws + L.adj_macro64) : nullptr;
+  c->adj_refill64 = adj ? (double*)(c->ws + L.adj_refill64) : nullptr;
+  c->adj_slot = adj ? (int32_t*)(c->ws + L.adj_slot) : nullptr;
   const bool mesh = p->max_mesh_triangles > 0;
   c->mesh_body = -1;
   c->mesh_set = false;
@@ -313,6 +319,8 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_gUR, 0, sizeof(double) * 4 * (size_t)c->N, c->stream);
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_side, 0, sizeof(float) * 9 * (size_t)p->ny * p->nz, c->stream);
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_gamp, 0, sizeof(double) * ELBM_MAX_BODIES, c->stream);
+  if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_macro64, 0, sizeof(double) * 4 * (size_t)c->N, c->stream);
+  if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_slot, 0xFF, sizeof(int32_t) * (size_t)c->N, c->stream);
   if (e == hipSuccess && L.geometry) e = hipMemsetAsync(c->free_U1, 0, sizeof(double) * 6 * ELBM_MAX_BODIES, c->stream);
   if (e == hipSuccess && L.geometry) e = hipStreamCreate(&c->aux);  // default priority
   for (int k = 0; k < FREE_HIST && e == hipSuccess && L.geometry; ++k)

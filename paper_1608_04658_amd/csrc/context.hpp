@@ -84,6 +84,10 @@ struct elbm_ctx {
   double* adj_gUR;         // 4 N: dL/dU^t (3 N) and dL/dR^t (N), FP64 scatter targets
   float* adj_side;         // 9 ny nz: outlet-copy adjoint contributions
   double* adj_gamp;        // [MAX_BODIES] dL/d(amplitude)
+  double* adj_macro64;     // 4 N: U^t (3 N), R^t (N) in FP64 around the bodies and on the inlet slab,
+                           // the point at which the reverse step linearises the wall rules
+  double* adj_refill64;    // [blist_cap][27]: FP64 refill populations of the uncovered nodes, by list slot
+  int32_t* adj_slot;       // N: list slot of an uncovered node (read only where the flags say refill)
   // sweep timing (HIP events around each bulk-sweep launch)
   bool timing;
   hipEvent_t* ev;

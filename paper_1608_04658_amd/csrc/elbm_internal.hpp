@@ -31,6 +31,7 @@ __host__ __device__ constexpr int nnz(int i) { return (cx(i) != 0) + (cy(i) != 0
 constexpr uint8_t FL_SOLID = 1;       // solid at the time level being produced (t+1)
 constexpr uint8_t FL_SOLID_PREV = 2;  // solid at the previous time level (t)
 constexpr uint8_t FL_SPECIAL = 4;     // handled by the boundary kernel (missing populations or refill)
+constexpr uint8_t FL_NEAR_REFILL = 8; // reverse step only: pulls from a node uncovered in the step
 
 // FP64 fix-up queue entries: node index, with this bit set when the node's pre-collision
 // deviations already sit in the output buffer (wall nodes) instead of being pulled from A^t.

@@ -868,6 +868,7 @@ BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
   a.stab = c->stab;
   a.beta = (float)c->beta;
   a.inv_beta = (float)(1.0 / c->beta);
+  a.beta64 = c->beta;
   a.thr = (float)c->fp64_thr;
   a.rho0 = c->p.rho0;
   for (int e = 0; e < 3; ++e) a.u_in[e] = c->p.u_inlet[e];

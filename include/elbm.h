@@ -44,7 +44,9 @@ extern "C" {
 #define ELBM_ENOSPACE (-2)   /* workspace too small, or a device list overflowed */
 #define ELBM_EDEVICE (-3)    /* a HIP call failed */
 #define ELBM_ESTATE (-4)     /* call not valid in the context's current state */
-#define ELBM_ENONFINITE (-5) /* non-finite or non-positive population found */
+#define ELBM_ENONFINITE (-5) /* a collided node had a non-finite state, or one where the entropic
+                                equilibrium is not positive (rho <= 0 or some |u_a| >= 1, where an
+                                feq_i <= 0 and the entropic scalar product is undefined) */
 
 /* storage of the populations in HBM */
 #define ELBM_STORAGE_F32 0   /* d_i = f_i - W_i as binary32 */
@@ -159,6 +161,11 @@ typedef struct elbm_info {
   int64_t fp64_nodes;     /* nodes recomputed in FP64 during the last step (synchronises) */
   int32_t layout;         /* ELBM_LAYOUT_* of the population arrays */
   int32_t pad;
+  double gamma_min;       /* with elbm_set_diagnostics(ctx, 1): smallest and largest stabiliser gamma */
+  double gamma_max;       /* of the nodes collided since the last elbm_get_info (0 if none) */
+  int32_t nonfinite;      /* nonzero once a step met a state that ELBM_ENONFINITE describes (bit 0 in
+                             the bulk sweep, bit 1 at a wall node); cleared when populations are set */
+  int32_t gamma_stats;    /* 1 while the gamma range is recorded */
 } elbm_info;
 
 /* Bytes of device workspace a context with these parameters needs. */
@@ -192,7 +199,7 @@ int elbm_read_populations(struct elbm_ctx* ctx, double* pop_dev);
  * must stay at least 6 nodes away from the inlet and outlet faces. */
 int elbm_set_geometry(struct elbm_ctx* ctx, const elbm_body* bodies, int32_t nb);
 
-/* Triangulated body (the deforming geometries of Sec. IV.B: a closed triangulated surface whose
+/* Triangulated body (the deforming geometries of Sec. IV.C: a closed triangulated surface whose
  * wall velocity at each link intersection is the barycentric interpolation of its vertex
  * velocities).  Sets the surface at the current time level: tris_dev dev [nt][3] int32 vertex
  * indices; verts_dev, vels_dev dev [nv][3] FP64 positions and velocities (vels_dev NULL = at rest);
@@ -246,7 +253,8 @@ int elbm_step(struct elbm_ctx* ctx, int32_t nsteps);
 /* Force and torque on body `body` from the step that produced time level
  * `step` (1 <= step <= t, within the last force_ring steps): momentum exchange
  * of Sec. IV.A, torque about the body centre.  F, M: host double[3].
- * Synchronises. */
+ * Synchronises.  Returns ELBM_ENOSPACE after a list overflow and ELBM_ENONFINITE once a step met
+ * a failed state (see elbm_set_diagnostics). */
 int elbm_force(struct elbm_ctx* ctx, int32_t body, int64_t step, double F[3], double M[3]);
 
 /* Forces of `count` consecutive steps starting at time level `first`:
@@ -256,8 +264,19 @@ int elbm_force_history(struct elbm_ctx* ctx, int32_t body, int64_t first, int32_
 /* Node flags at the current time level: out_dev (dev [N] uint8), bit 0 = solid. */
 int elbm_read_flags(struct elbm_ctx* ctx, uint8_t* out_dev);
 
-/* Context information (synchronises for the per-step counters). */
+/* Context information (synchronises for the per-step counters).  Fills *out, then returns
+ * ELBM_ENOSPACE if the boundary list has overflowed its capacity (the steps since are wrong at the
+ * nodes that did not fit), else ELBM_OK.  A failed state is reported in out->nonfinite (and by
+ * elbm_force, which returns ELBM_ENONFINITE); the gamma range restarts after each call. */
 int elbm_get_info(struct elbm_ctx* ctx, elbm_info* out);
+
+/* Failure detection is always on: every collided node tests that its state is finite and inside the
+ * domain of the entropic equilibrium (Sec. II, eq. feq_min: rho > 0 and |u_a| < 1 for all a, so
+ * that every feq_i > 0 and the entropic scalar product is defined), one vote per wavefront.
+ * gamma_stats = 1 also records the range of the stabiliser gamma of the collided nodes (a
+ * wavefront-wide min/max and one pair of atomics per wavefront in the bulk sweep; FP32 gamma for
+ * nodes recomputed in FP64), reported and restarted by elbm_get_info; 0 stops it. */
+int elbm_set_diagnostics(struct elbm_ctx* ctx, int32_t gamma_stats);
 
 /* Copy the current populations, in the context's storage format and layout (27 N elements of 4
  * or 2 bytes, placed as elbm_info.layout says), to pop_dev (dev).  Used for checkpoints. */

@@ -400,7 +400,7 @@ class Simulation:
                                     u=np.asarray(spec.get("vel", (0, 0, 0)), float).copy(), F=np.zeros(3),
                                     w=np.asarray(spec.get("omega", (0, 0, 0)) if rot else (0, 0, 0), float).copy(),
                                     M=np.zeros(3))
-        # triangulated bodies (Sec. IV.B): vertex positions and velocities of the current time level
+        # triangulated bodies (Sec. IV.C): vertex positions and velocities of the current time level
         # and, when mesh_next() was called, of the next one (else the mesh holds still)
         self.meshes = {}
         for k, spec in enumerate(bodies):

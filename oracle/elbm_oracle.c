@@ -351,7 +351,7 @@ typedef struct {
 
 typedef struct {
   int32_t kind;      /* 0: sphere, 1: half-space bounded by a plane, 2: closed triangulated
-                        surface (the deforming bodies of Sec. IV.B) */
+                        surface (the deforming bodies of Sec. IV.C) */
   int32_t tracked;   /* 1: centre and velocity come from the track below (a freely moving body
                         whose motion the caller integrates), not from the prescribed motion */
   double p0[3];      /* sphere centre, or a point of the plane, at t = 0 */
@@ -442,7 +442,7 @@ static void body_velocity(const or_body *b, const double c[3], const double U[3]
 
 
 /* ------------------------------------------------------------------------ */
-/* Triangulated bodies (Sec. IV.B: the swimmer is a triangulated surface; the wall velocity at
+/* Triangulated bodies (Sec. IV.C: the swimmer is a triangulated surface; the wall velocity at
  * the link intersections is the barycentric interpolation of the vertex velocities).
  * Readings (the paper gives no algorithm for these):
  *  - inside: a node is solid iff a ray from it along +x crosses the surface an odd number of

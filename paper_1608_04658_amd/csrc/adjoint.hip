@@ -977,6 +977,8 @@ static BArgs bargs(elbm_ctx* c, const void* A) {
   a.brec = c->brec;
   a.fix_list = nullptr;  // the adjoint kernels queue nothing
   a.fix_count = nullptr;
+  a.diag = c->cnt;
+  a.stats = 0;
   a.n_static = c->n_static;
   a.lo = 0;
   a.hi = -1;

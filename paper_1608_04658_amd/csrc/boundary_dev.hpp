@@ -61,6 +61,8 @@ struct BArgs {
   double* brec;
   uint32_t* fix_list;   // FP64 fix-up queue (wall nodes enter it tagged FIX_PRE)
   uint32_t* fix_count;  // its length for this step
+  DevCounters* diag;    // failure flag and gamma range (k_boundary)
+  int32_t stats;        // 1: record the gamma range
   int64_t n_static;
   int64_t lo, hi;  // k_boundary: list entries [lo, min(hi, count)) (hi < 0: to the end)
   int64_t cap;

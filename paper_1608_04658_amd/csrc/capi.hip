@@ -64,7 +64,8 @@ int validate(const elbm_params* p, char* err) {
   if (p->bc_x != ELBM_BC_PERIODIC && p->bc_x != ELBM_BC_CHANNEL) return snprintf(err, 256, "bad bc_x"), ELBM_EINVAL;
   if (p->bc_x == ELBM_BC_CHANNEL && p->nx < 4) return snprintf(err, 256, "channel needs nx >= 4"), ELBM_EINVAL;
   if (p->max_bodies < 0 || p->max_bodies > ELBM_MAX_BODIES) return snprintf(err, 256, "bad max_bodies"), ELBM_EINVAL;
-  if (p->max_bodies > 0 && p->force_ring < 1) return snprintf(err, 256, "force_ring must be >= 1"), ELBM_EINVAL;
+  if (p->force_ring < 0 || (p->max_bodies > 0 && p->force_ring < 1))
+    return snprintf(err, 256, "force_ring must be >= 1 (>= 0 without bodies)"), ELBM_EINVAL;
   if (!(p->nu > 0.0) || !isfinite(p->nu)) return snprintf(err, 256, "nu must be positive"), ELBM_EINVAL;
   if (p->max_boundary < 0) return snprintf(err, 256, "bad max_boundary"), ELBM_EINVAL;
   if ((p->flags & ELBM_FLAG_EXACT_GAMMA) && (p->flags & ELBM_FLAG_LBGK))
@@ -220,7 +221,25 @@ hipError_t free_reanchor(elbm_ctx* c, int64_t t) {
   return free_init(c);
 }
 
+// Failure flag cleared (with_flag) and the gamma range emptied (lo = all ones, hi = 0).
+hipError_t diag_reset(elbm_ctx* c, bool with_flag) {
+  hipError_t e = hipSuccess;
+  if (with_flag) e = hipMemsetAsync(&c->cnt->nonfinite, 0, sizeof(uint32_t), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(&c->cnt->gamma_lo, 0xFF, sizeof(uint32_t), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(&c->cnt->gamma_hi, 0, sizeof(uint32_t), c->stream);
+  return e;
+}
+
 }  // namespace
+
+// geometry_init, and the static part of the boundary list checked against its capacity.
+static int geo_init(elbm_ctx* c) {
+  HIP_OK(c, geometry_init(c));
+  if (c->n_static > c->blist_cap)
+    return fail(c, ELBM_ENOSPACE, "the static boundary list needs %lld entries, max_boundary allows %lld",
+                (long long)c->n_static, (long long)c->blist_cap);
+  return ELBM_OK;
+}
 
 extern "C" {
 
@@ -313,8 +332,10 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   c->ev_cap = c->ev_used = 0;
   hipError_t e = hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), c->stream);
   if (e == hipSuccess && L.geometry) e = hipMemsetAsync(c->flags, 0, (size_t)c->N, c->stream);
-  if (e == hipSuccess && L.geometry)
-    e = hipMemsetAsync(c->ring, 0, sizeof(double) * 6 * ELBM_MAX_BODIES * c->p.force_ring, c->stream);
+  if (e == hipSuccess && L.geometry)  // the ring as layout() sized it
+    e = hipMemsetAsync(c->ring, 0, sizeof(double) * 6 * ELBM_MAX_BODIES * (size_t)(p->force_ring > 0 ? p->force_ring : 1),
+                       c->stream);
+  if (e == hipSuccess) e = diag_reset(c, true);
   if (e == hipSuccess && L.geometry) e = hipMemsetAsync(c->macro, 0, 16 * (size_t)c->N, c->stream);
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_gUR, 0, sizeof(double) * 4 * (size_t)c->N, c->stream);
   if (e == hipSuccess && adj) e = hipMemsetAsync(c->adj_side, 0, sizeof(float) * 9 * (size_t)p->ny * p->nz, c->stream);
@@ -335,8 +356,15 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   if (L.geometry) {
     // channel without bodies: the inlet face is the static boundary list
     const int g = geometry_init(c);
-    if (g != hipSuccess) {
+    const bool over = g == hipSuccess && c->n_static > c->blist_cap;
+    if (g != hipSuccess || over) {
+      for (int k = 0; k < FREE_HIST; ++k)
+        if (c->free_ev[k]) (void)hipEventDestroy(c->free_ev[k]);
+      if (c->aux) (void)hipStreamDestroy(c->aux);
+      const long long ns = (long long)c->n_static, cap = (long long)c->blist_cap;
       delete c;
+      if (over)
+        return fail(nullptr, ELBM_ENOSPACE, "the static boundary list needs %lld entries, max_boundary allows %lld", ns, cap);
       return fail(nullptr, ELBM_EDEVICE, "geometry set-up failed");
     }
   }
@@ -380,7 +408,8 @@ int elbm_init_equilibrium(elbm_ctx* c, const double* rho_dev, const double* u_de
   c->cur = 0;
   c->t = 0;
   HIP_OK(c, launch_init_eq(c, rho_dev, u_dev));
-  if (c->flags) HIP_OK(c, geometry_init(c));
+  HIP_OK(c, diag_reset(c, true));
+  if (c->flags) return geo_init(c);
   return ELBM_OK;
 }
 
@@ -390,7 +419,8 @@ int elbm_write_populations(elbm_ctx* c, const double* pop_dev, int64_t t) {
   HIP_OK(c, free_reanchor(c, t));
   c->t = t;
   HIP_OK(c, launch_write_pop(c, pop_dev));
-  if (c->flags) HIP_OK(c, geometry_init(c));
+  HIP_OK(c, diag_reset(c, true));
+  if (c->flags) return geo_init(c);
   return ELBM_OK;
 }
 
@@ -479,8 +509,7 @@ int elbm_set_geometry(elbm_ctx* c, const elbm_body* bodies, int32_t nb) {
     if (nb > 0) return fail(c, ELBM_ESTATE, "context created with max_bodies = 0");
     return ELBM_OK;
   }
-  HIP_OK(c, geometry_init(c));
-  return ELBM_OK;
+  return geo_init(c);
 }
 
 int elbm_set_mesh(elbm_ctx* c, const int32_t* tris_dev, int32_t nt, const double* verts_dev, const double* vels_dev,
@@ -656,6 +685,11 @@ int elbm_force_history(elbm_ctx* c, int32_t body, int64_t first, int32_t count, 
   if (ov & 2u) return fail(c, ELBM_ENOSPACE, "a mesh vertex left the declared box, or the mesh grid is full");
   if (ov & 4u) return fail(c, ELBM_ENOSPACE, "a lattice row crosses the mesh more than 32 times");
   if (ov & 8u) return fail(c, ELBM_EINVAL, "a mesh triangle has a vertex index outside [0, nv)");
+  uint32_t nf = 0;
+  HIP_OK(c, hipMemcpy(&nf, &c->cnt->nonfinite, sizeof nf, hipMemcpyDeviceToHost));
+  if (nf)
+    return fail(c, ELBM_ENONFINITE, "a node had a non-finite state or one where the entropic equilibrium is not "
+                "positive (rho <= 0 or |u_a| >= 1) in the %s", (nf & 1u) ? "bulk sweep" : "wall kernel");
   for (int32_t k = 0; k < count; ++k) {
     const int64_t step = first + k;
     const int slot = (int)(step % ring);
@@ -704,6 +738,21 @@ int elbm_get_info(elbm_ctx* c, elbm_info* out) {
   HIP_OK(c, hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
   out->boundary_nodes = c->flags ? c->n_static + (c->moving ? (int64_t)h.dyn_count : 0) : 0;
   out->fp64_nodes = h.fix_count[c->fix_par ^ 1];
+  out->nonfinite = (int32_t)h.nonfinite;
+  out->gamma_stats = c->gamma_stats ? 1 : 0;
+  const bool seen = c->gamma_stats && h.gamma_lo != 0xFFFFFFFFu;
+  out->gamma_min = seen ? (double)f32_unkey(h.gamma_lo) : 0.0;
+  out->gamma_max = seen ? (double)f32_unkey(h.gamma_hi) : 0.0;
+  if (c->gamma_stats) HIP_OK(c, diag_reset(c, false));  // the range restarts with the next step
+  if (h.overflow & 1u)
+    return fail(c, ELBM_ENOSPACE, "boundary list overflowed its capacity (%lld)", (long long)c->blist_cap);
+  return ELBM_OK;
+}
+
+int elbm_set_diagnostics(elbm_ctx* c, int32_t gamma_stats) {
+  if (!c) return ELBM_EINVAL;
+  c->gamma_stats = gamma_stats != 0;
+  HIP_OK(c, diag_reset(c, false));
   return ELBM_OK;
 }
 
@@ -722,7 +771,8 @@ int elbm_load_state(elbm_ctx* c, const void* pop_dev, int64_t t) {
   HIP_OK(c, hipMemcpyAsync(c->pop[c->cur], pop_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, free_reanchor(c, t));
   c->t = t;
-  if (c->flags) HIP_OK(c, geometry_init(c));
+  HIP_OK(c, diag_reset(c, true));
+  if (c->flags) return geo_init(c);
   return ELBM_OK;
 }
 

@@ -33,6 +33,7 @@ struct elbm_ctx {
   elbm::DevCounters* cnt;
   int fix_par;             // parity of the FP64 queue counter of the next step (DevCounters::fix_count)
   double* scratch64;       // small FP64 scratch (force sums)
+  bool gamma_stats;        // record the range of gamma (elbm_set_diagnostics)
   const float* bodyforce;
   // geometry state
   int32_t nb;

@@ -226,7 +226,24 @@ template <typename T> struct KbcOut {
   T b;    // <dh|dh>
   T rho;
   T s2;   // <ds|ds> estimated with feq ~ rho W (used only to decide on the FP64 path)
+  bool dom;  // 0 < rho < inf and every |u_a| < 1: the entropic equilibrium is positive (a NaN or an
+             // infinite population fails this test through rho or u)
 };
+
+// Largest finite binary32 value (the upper end of the density test).
+constexpr float FLT_BIG = 3.4028234663852886e38f;
+
+// Order-preserving map of binary32 values to uint32 (for atomic min/max of gamma).
+__device__ __forceinline__ uint32_t f32_key(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ inline float f32_unkey(uint32_t k) {
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  float v;
+  __builtin_memcpy(&v, &b, 4);
+  return v;
+}
 
 // FP64 recomputation rule: <dh|dh> is at the FP32 noise floor (the ratio <ds|dh>/<dh|dh> is then
 // ill-conditioned) while the shear part is not (otherwise gamma dh, bounded by the shear part, is
@@ -460,7 +477,8 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
 #pragma unroll
     for (int i = 0; i < 27; ++i) d[i] = (T)((double)d[i] + (e1[i] - e0[i]));
   }
-  return KbcOut<T>{gamma, b, rho, s2};
+  const bool dom = rho > T(0) && rho < T(FLT_BIG) && fabs(ux) < T(1) && fabs(uy) < T(1) && fabs(uz) < T(1);
+  return KbcOut<T>{gamma, b, rho, s2, dom};
 }
 
 // Grad's distribution (eq. grad) with c_s^2 = 1/3:
@@ -610,7 +628,10 @@ struct DevCounters {
   uint32_t overflow;      // sticky: 1 boundary list, 2 mesh vertex outside its box or grid full,
                           // 4 more crossings on a lattice row than the mask kernel holds,
                           // 8 mesh vertex index out of range
-  uint32_t pad[4];
+  uint32_t nonfinite;     // sticky: a collided node had a non-finite state or one outside the
+                          // domain of the entropic equilibrium (1 bulk sweep, 2 wall kernel)
+  uint32_t gamma_lo, gamma_hi;  // f32_key of the smallest and largest gamma since the last read
+  uint32_t pad;
 };
 
 // Lanes per node in the lane-parallel boundary kernels (two nodes per wavefront of 64).

@@ -489,6 +489,14 @@ __global__ __launch_bounds__(64) void k_boundary(const BArgs a, const Bodies bd)
     // <dh|dh> at the FP32 noise floor (equal on all lanes of the group): store the pre-collision
     // deviations and queue the node for the FP64 collision of k_fixup
     const bool fp64 = a.fp64 && needs_fp64(r, a.thr);
+    if (active && lane == 0) {
+      // failure detection and the gamma range (r is equal on all lanes of the group)
+      if (!r.dom) atomicOr(&a.diag->nonfinite, 2u);
+      if (a.stats) {
+        atomicMin(&a.diag->gamma_lo, f32_key(r.gamma));
+        atomicMax(&a.diag->gamma_hi, f32_key(r.gamma));
+      }
+    }
     if (active && lane < 27) C::store_dev(B + pop_off(a.lay, lane, h.x, h.y, h.z), fp64 ? fi : fpost);
     if (fp64 && active && lane == 0) a.fix_list[atomicAdd(a.fix_count, 1u)] = (uint32_t)n | FIX_PRE;
     // inlet slab: U, R of the new state, summed in direction order on the group's first lane
@@ -851,6 +859,8 @@ BArgs boundary_args(elbm_ctx* c, const void* A, void* B) {
   a.brec = c->brec;
   a.fix_list = (uint32_t*)c->fix_list;
   a.fix_count = &c->cnt->fix_count[c->fix_par];
+  a.diag = c->cnt;
+  a.stats = c->gamma_stats ? 1 : 0;
   a.slab_next = (channel && !(c->p.flags & ELBM_FLAG_STREAM_ONLY)) ? c->slab_next : nullptr;
   a.n_static = c->n_static;
   a.lo = 0;

@@ -168,7 +168,8 @@ __device__ inline T kbc_collide_lanes(int lane, T d, T beta, T inv_beta, T Fx, T
     const double e1 = rr * p1[cx(i) + 1] * q1[cy(i) + 1] * w1[cz(i) + 1];
     out = (T)((double)out + (e1 - e0));
   }
-  r = KbcOut<T>{gamma, b, rho, s2};
+  const bool dom = rho > T(0) && rho < T(FLT_BIG) && fabs(ux) < T(1) && fabs(uy) < T(1) && fabs(uz) < T(1);
+  r = KbcOut<T>{gamma, b, rho, s2, dom};
   return own ? out : T(0);
 }
 

@@ -1,4 +1,4 @@
-// mesh.hip -- the triangulated body (the deforming geometries of Sec. IV.B): upload of a time
+// mesh.hip -- the triangulated body (the deforming geometries of Sec. IV.C): upload of a time
 // level of vertex positions and velocities, binning of the triangles into a uniform grid on the
 // device (count, scan, fill; no host round trip), and the solid mask by crossing parity, one
 // lattice row per thread.

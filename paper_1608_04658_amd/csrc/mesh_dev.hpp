@@ -1,4 +1,4 @@
-// mesh_dev.hpp -- device geometry of the triangulated body (the deforming bodies of Sec. IV.B):
+// mesh_dev.hpp -- device geometry of the triangulated body (the deforming bodies of Sec. IV.C):
 // crossing of a +x ray with a triangle (inside test by crossing parity), ray-triangle link
 // fractions with the barycentric wall velocity, and the velocity of the closest surface point.
 // Every predicate and intersection is FP64 with the operations in the order written and no

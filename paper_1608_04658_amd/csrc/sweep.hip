@@ -20,6 +20,8 @@ struct SweepArgs {
   uint32_t* fix_list;
   uint32_t* fix_count;  // this step's FP64 queue length
   uint32_t* fix_clear;  // the other parity's, cleared by the fix-up kernel for the next step
+  DevCounters* diag;    // failure flag and gamma range
+  int32_t stats;        // 1: record the gamma range (listed nodes excluded: the wall kernel's)
   float* slab_next;  // [4][nz][ny][3] staging of U, R for x < 3 (written when slab is set)
   PopLayout lay;
   int32_t nx, ny, nz;
@@ -128,6 +130,21 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
       Fz = a.F[2 * (size_t)a.N + n];
     }
     const KbcOut<float> r = kbc_collide<float, FORCE, STAB>(f, a.beta, a.inv_beta, Fx, Fy, Fz);
+    // failure detection: a non-finite state, or one where the entropic equilibrium is not positive
+    // (the tests of r.dom); one ballot per wavefront, an atomic only where a node fails.  Listed
+    // nodes pulled from solid nodes here and are checked by the wall kernel.
+    const uint64_t bad = __ballot(!r.dom && !listed);
+    if (bad && __lane_id() == (uint32_t)(__ffsll((unsigned long long)bad) - 1)) atomicOr(&a.diag->nonfinite, 1u);
+    if (a.stats) {
+      // gamma range over the wavefront's active lanes (exec-aware reduction), one atomic pair
+      const unsigned long long act = __ballot(1);
+      const uint32_t lo = __reduce_min_sync(act, listed ? 0xFFFFFFFFu : f32_key(r.gamma));
+      const uint32_t hi = __reduce_max_sync(act, listed ? 0u : f32_key(r.gamma));
+      if (__lane_id() == (uint32_t)(__ffsll(act) - 1)) {
+        atomicMin(&a.diag->gamma_lo, lo);
+        atomicMax(&a.diag->gamma_hi, hi);
+      }
+    }
     if (a.fp64) {
       // one queue reservation per wavefront for all of its nodes that need the FP64 collision
       const bool q = needs_fp64(r, a.thr) && !listed;
@@ -295,6 +312,8 @@ static SweepArgs sweep_args(elbm_ctx* c) {
   a.fix_list = (uint32_t*)c->fix_list;
   a.fix_count = &c->cnt->fix_count[c->fix_par];
   a.fix_clear = &c->cnt->fix_count[c->fix_par ^ 1];
+  a.diag = c->cnt;
+  a.stats = c->gamma_stats ? 1 : 0;
   a.nx = c->p.nx;
   a.ny = c->p.ny;
   a.nz = c->p.nz;

@@ -53,7 +53,9 @@ class Info(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int64), ("nodes", ctypes.c_int64), ("beta", ctypes.c_double),
                 ("pop_bytes", ctypes.c_size_t), ("pop_offset", ctypes.c_size_t), ("flags_offset", ctypes.c_size_t),
                 ("storage", ctypes.c_int32), ("nbodies", ctypes.c_int32), ("boundary_nodes", ctypes.c_int64),
-                ("fp64_nodes", ctypes.c_int64), ("layout", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("fp64_nodes", ctypes.c_int64), ("layout", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("gamma_min", ctypes.c_double), ("gamma_max", ctypes.c_double), ("nonfinite", ctypes.c_int32),
+                ("gamma_stats", ctypes.c_int32)]
 
 
 _lib = None
@@ -98,6 +100,7 @@ def load():
         "elbm_set_timing": [_VP, ctypes.c_int32],
         "elbm_get_timing": [_VP, P(ctypes.c_double), P(ctypes.c_int64)],
         "elbm_step_periodic_noalloc": [P(Params), _VP, _VP, _VP],
+        "elbm_set_diagnostics": [_VP, ctypes.c_int32],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -274,6 +277,10 @@ def elbm_get_info(ctx) -> Info:
     info = Info()
     _check(load().elbm_get_info(ctx, ctypes.byref(info)), ctx)
     return info
+
+
+def elbm_set_diagnostics(ctx, gamma_stats: bool):
+    _check(load().elbm_set_diagnostics(ctx, 1 if gamma_stats else 0), ctx)
 
 
 def elbm_save_state(ctx, pop_dev):

@@ -1,4 +1,4 @@
-"""Triangulated bodies on the GPU against the oracle (the deforming geometries of Sec. IV.B):
+"""Triangulated bodies on the GPU against the oracle (the deforming geometries of Sec. IV.C):
 solid masks bit for bit (including rays through triangle edges and vertices), then whole steps of a
 resting box in a channel, a rigidly oscillating sphere mesh and the deforming swimmer: populations
 of fluid nodes within 2e-5, forces within 1e-3 of the largest."""
@@ -120,7 +120,7 @@ def test_oscillating_sphere_mesh(E, oracle_mod):
 
 
 def test_deforming_swimmer(E, oracle_mod):
-    """The swimmer of Sec. IV.B (L = 32, undulation period 400, started at full amplitude) held in
+    """The swimmer of Sec. IV.C (L = 32, undulation period 400, started at full amplitude) held in
     place in a channel, deforming every step."""
     O = oracle_mod
     shape, nu, u_in, steps = (56, 24, 24), 0.01, (0.02, 0.0, 0.0), 30

@@ -1,6 +1,6 @@
 """Pins of the oracle's freely rotating sphere (two-way coupling with the torque: I dw/dt = M,
 explicit Euler with unit step, I = (2/5) m R^2; Sec. IV.A's Newton equations with the rotational
-one the swimmer case of Sec. IV.B also integrates).  Pinned by what mechanics fixes: the state
+one the swimmer case of Sec. IV.C also integrates).  Pinned by what mechanics fixes: the state
 follows the Euler recurrence with the torques the steps report (the first update keeps the initial
 spin, no torque yet); a sphere spinning about an axis through the centre of a box symmetric about
 it feels no net force and stays put; and its spin decays at the rate the Stokes torque -8 pi rho nu

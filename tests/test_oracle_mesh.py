@@ -1,4 +1,4 @@
-"""Pins of the oracle's triangulated bodies (the deforming geometries of Sec. IV.B: a triangulated
+"""Pins of the oracle's triangulated bodies (the deforming geometries of Sec. IV.C: a triangulated
 surface; wall velocity at the link intersections by barycentric interpolation of the vertex
 velocities).  Pinned by closed forms and by the analytic bodies:
   * inside test: a box with faces between lattice planes gives exactly the box's node set; a box

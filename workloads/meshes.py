@@ -9,7 +9,7 @@ the GPU library and the oracle receive the same arrays.
 * ``octahedron_mesh`` -- |x-c|_1 = r, 8 triangles (integer vertices put rays through edges and
                          vertices: the tie cases of the inside test).
 * ``icosphere_mesh``  -- sphere of radius r from a subdivided icosahedron (vertices on the sphere).
-* ``swimmer_mesh``    -- the anguilliform swimmer of Sec. IV.B: elliptical cross sections with
+* ``swimmer_mesh``    -- the anguilliform swimmer of Sec. IV.C: elliptical cross sections with
                          the half axes w(s), h(s) of the paper along a centre line that undulates
                          laterally as y(s, t) = 0.125 beta(t) L (s/L + 0.03125)/1.03125
                          sin(2 pi (s/L - t/T)) with the ramp beta(t) of eq. fish_ramping;
@@ -78,7 +78,7 @@ def icosphere_mesh(center, r, level: int):
     return verts, np.array(f, dtype=np.int32)
 
 
-# ----------------------------------------------------------------------------- swimmer (Sec. IV.B)
+# ----------------------------------------------------------------------------- swimmer (Sec. IV.C)
 def swimmer_halfwidth(s, L):
     """w(s): half width of the cross section at arc length s (w_h = s_b = 0.04 L, s_t = 0.95 L,
     w_t = 0.01 L)."""

@@ -3,20 +3,24 @@
 
 A step is one pass of the whole path (geometry, pull streaming, moments, entropic equilibrium,
 KBC collision with the per-node stabiliser, wall reconstruction and forces where the workload has
-walls, store) over the workload's lattice.  The headline workload is ``turb256``: 256^3 periodic
-box, seeded divergence-free turbulence (E(k) ~ k^4 exp(-2 (k/k0)^2), k0 = 4, rms 0.04), FP32
-populations.  ``value`` is whole-job MLUPS (lattice-node updates per second / 1e6) with the
-populations already resident in HBM.
+walls, store) over the workload's lattice.  The headline workload is ``turb512``: the 512^3
+periodic box of seeded divergence-free turbulence (E(k) ~ k^4 exp(-2 (k/k0)^2), k0 = 8, rms 0.04,
+Re_lambda ~ 100), FP32 populations -- the box the 70 % roofline target is stated on.  ``value`` is
+whole-job MLUPS (lattice-node updates per second / 1e6) with the populations already resident in HBM.
 
 Also reported on the same JSON line:
-  roofline      -- the bulk sweep kernel's algorithmic HBM bytes per launch / its average launch
-                   duration (HIP events recorded around each launch on the library's stream),
-                   against the MI355X HBM peak of 8 TB/s; ``traffic`` comes from the committed
-                   rocprofv3 counter summary when it was taken on the current kernel source.
-  cpu_baseline  -- the FP64 CPU oracle, as it stands, on a bounded sample of the same workload.
-  forms         -- the other forms at their workloads: FP32 / FP16 / BF16 storage on 512^3, the
-                   moving-sphere channel (384x192x192), and a plain copy kernel as the measured
-                   achievable HBM bandwidth.
+  roofline      -- the bulk sweep kernel's algorithmic HBM bytes per launch (216 per node) / its
+                   average launch duration (HIP events recorded around each launch on the library's
+                   stream), against the MI355X HBM peak of 8 TB/s; ``traffic`` comes from the
+                   committed rocprofv3 counter summary when it was taken on the current kernel
+                   source at this size.
+  cpu_baseline  -- the FP64 CPU oracle, as it stands, on the headline recipe at 64^3 (the rerun the
+                   reduced-storage error is stated on; per-node cost does not depend on the box
+                   size): all host threads over the rerun's full 500 steps, one thread on a sample of
+                   it, and the full 32^3 Taylor-Green workload.
+  forms         -- the other forms: FP16 / BF16 storage on 512^3, FP32 on 256^3, the stabiliser
+                   variants, the moving-sphere channel (384x192x192), the settling sphere, the
+                   deforming swimmer, the adjoint rollout, and a plain copy kernel.
 Progress goes to stderr; stdout carries the one JSON line.
 """
 from __future__ import annotations
@@ -36,7 +40,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_NODE = {"f32": 216, "f16": 108, "bf16": 108}
 SWEEP_SOURCES = ["paper_1608_04658_amd/csrc/sweep.hip", "paper_1608_04658_amd/csrc/elbm_internal.hpp"]
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_f32_turb256_traffic.md")
+TRAFFIC_PROFILES = {"turb512": os.path.join(ROOT, "profiles", "sweep_turb512_traffic.md"),
+                    "turb256": os.path.join(ROOT, "profiles", "sweep_f32_turb256_traffic.md")}
 
 
 def log(msg: str):
@@ -51,12 +56,13 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(nodes: int):
+def traffic_from_profile(workload: str, nodes: int):
     """HBM bytes per sweep launch from the committed counter summary, or None when the summary is
     missing, for another size, or was taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILES.get(workload)
+    if path is None or not os.path.exists(path):
         return None
-    text = open(TRAFFIC_PROFILE).read()
+    text = open(path).read()
     m_hash = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
     m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     m_nodes = re.search(r"nodes:\s*(\d+)", text)
@@ -167,7 +173,7 @@ def settle_form(elbm, torch, WL, steps: int = 500):
 
 
 def swimmer_form(elbm, torch, steps: int = 20, warmup: int = 3, L: int = 200):
-    """Deforming triangulated body (Sec. IV.B): the anguilliform swimmer of length L = 200 in the
+    """Deforming triangulated body (Sec. IV.C): the anguilliform swimmer of length L = 200 in the
     paper's 8L x 4L x L domain (1600 x 800 x 200, 256 M nodes, FP32), undulation period T = 10^4,
     Re = (L^2/T)/nu = 7142, held in place in a channel stream at its swimming speed 0.415 L/T, at full
     amplitude.  The surface (150 segments x 16 points) of every step is generated beforehand and
@@ -219,28 +225,69 @@ def swimmer_form(elbm, torch, steps: int = 20, warmup: int = 3, L: int = 200):
     return out
 
 
-def cpu_baseline(workload: str, budget_s: float = 15.0):
-    """The FP64 oracle, unmodified, stepping the workload's own lattice on the host cores for a
-    bounded number of steps (at least 2, until ~budget_s seconds of stepping)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_run(workload: str, n: int, steps: int, budget_s: float | None):
+    """Step the FP64 oracle on `workload`'s recipe at n^3 (the workload's own size if n = 0) from its
+    initial field: `steps` steps, or fewer if budget_s seconds of stepping are reached first (at
+    least 2).  Returns (nodes, steps done, seconds, threads)."""
     import oracle
     import workloads as WL
     w = WL.WORKLOADS[workload]
-    rho, u = WL.initial_field(workload)
-    sim = oracle.Simulation(w["shape"], w["nu"], rho, u)
-    del rho, u
-    steps = 0
+    shape = w["shape"] if n == 0 else (n, n, n)
+    rho, u = WL.initial_field(workload, shape)
+    sim = oracle.Simulation(shape, w["nu"], rho, u)
+    done = 0
     t0 = time.perf_counter()
-    while True:
+    while done < steps:
         sim.step(1)
-        steps += 1
+        done += 1
         el = time.perf_counter() - t0
-        log(f"cpu_baseline: oracle step {steps} at {el:.1f}s")
-        if steps >= 2 and el >= budget_s:
+        if done % 50 == 0 or done <= 2:
+            log(f"cpu_baseline: {workload} at {shape[0]}^3, oracle step {done} at {el:.1f}s "
+                f"({oracle.max_threads()} threads)")
+        if budget_s is not None and done >= 2 and el >= budget_s:
             break
-    n = sim.N
-    return {"value": n * steps / el / 1e6, "unit": "MLUPS", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{workload} ({w['shape'][0]}x{w['shape'][1]}x{w['shape'][2]}, FP64 C oracle): "
-                      f"{steps} of its {w['steps']} steps, {el:.1f} s"}
+    return sim.N, done, time.perf_counter() - t0, oracle.max_threads()
+
+
+def cpu_baseline(workload: str, budget_s: float = 10.0):
+    """The FP64 oracle, unmodified, on the host cores.  The headline recipe is run as the 64^3 rerun
+    (the turbulence recipe of the headline box at 64^3, its 500 steps in full): the oracle's cost per
+    node does not depend on the box size, and the 512^3 box would need about 90 GB of host memory
+    and 16 s per step.  Also: one host thread on a bounded sample of the same rerun (a child process
+    with OMP_NUM_THREADS=1), and the 32^3 Taylor-Green workload in full."""
+    import subprocess
+    import workloads as WL
+    w = WL.WORKLOADS[workload]
+    n_rerun = 64 if w["shape"][0] > 64 else 0
+    nodes, steps, el, threads = oracle_run(workload, n_rerun, w["steps"], None)
+    value = nodes * steps / el / 1e6
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-sample", workload, str(n_rerun),
+                          str(w["steps"]), str(budget_s)], env=env, capture_output=True, text=True, timeout=600)
+    if one.returncode != 0:
+        raise RuntimeError(f"one-thread oracle run failed: {one.stderr[-500:]}")
+    n1, s1, e1, t1 = json.loads(one.stdout.strip().splitlines()[-1])
+    tg_nodes, tg_steps, tg_s, _ = oracle_run("tg32", 0, WL.WORKLOADS["tg32"]["steps"], None)
+    side = w["shape"][0] if n_rerun == 0 else n_rerun
+    return {"value": round(value, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{workload} recipe at {side}^3 (FP64 C oracle): all {steps} steps in {el:.1f} s "
+                      f"on {threads} threads; MLUPS per node does not depend on the box size",
+            "cpu_model": cpu_model(), "host_threads_available": len(os.sched_getaffinity(0)),
+            "one_thread": {"value": round(n1 * s1 / e1 / 1e6, 4), "unit": "MLUPS",
+                           "sample": f"{s1} steps of the same {side}^3 rerun, {e1:.1f} s, {t1} thread"},
+            "tg32_full": {"steps": tg_steps, "seconds": round(tg_s, 2), "MLUPS": round(tg_nodes * tg_steps / tg_s / 1e6, 3)},
+            "rerun_full": {"steps": steps, "seconds": round(el, 2)}}
 
 
 def main():
@@ -248,16 +295,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's step count)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="turb256")
+    ap.add_argument("--workload", default="turb512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--form-steps", type=int, default=100)
-    ap.add_argument("--forms", default="copy,stabilisers,turb512,sphere384,settle,swimmer,adj128",
+    ap.add_argument("--forms", default="copy,turb512_2byte,turb256,stabilisers,sphere384,settle,swimmer,adj128",
                     help="comma-separated subset of the extra forms to run")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="after the headline run, copy a buffer of this many MiB 5 times (a plain copy kernel "
                          "of known size, used to scale the HBM byte counters of a rocprofv3 --pmc run)")
+    ap.add_argument("--oracle-sample", nargs=4, metavar=("WORKLOAD", "N", "STEPS", "BUDGET_S"),
+                    help="internal: time the FP64 oracle only (no GPU) and print [nodes, steps, s, threads]")
     args = ap.parse_args()
+
+    if args.oracle_sample:
+        wl, n, st, bud = args.oracle_sample
+        print(json.dumps(list(oracle_run(wl, int(n), int(st), float(bud)))), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -265,7 +319,7 @@ def main():
               f"{args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
     import workloads as WL
     from paper_1608_04658_amd import elbm
@@ -276,31 +330,45 @@ def main():
     torch.cuda.set_device(0)
     elbm.load()
 
+    def make_init(workload):
+        """Initial equilibrium of a workload's field: the 512^3 turbulence drawn on the device (the
+        host FFT at that size is slow), the others from the host recipe."""
+        wl = WL.WORKLOADS[workload]
+        if workload == "turb512":
+            log("turb512: generating the initial field on the device")
+            r_, u_ = WL.turbulence_device(512, wl["k0"], wl["urms"], wl["seed"])
+
+            def init_dev(lat):
+                elbm.elbm_init_equilibrium(lat.ctx, r_, u_)
+                torch.cuda.synchronize()
+            return init_dev, (r_, u_)
+        log(f"{workload}: generating the initial field")
+        r_, u_ = WL.initial_field(workload)
+
+        def init_host(lat):
+            lat.init_equilibrium(r_, u_)
+        return init_host, (r_, u_)
+
     w = WL.WORKLOADS[args.workload]
     steps = args.steps if args.steps is not None else w["steps"]
     shape = w["shape"]
-    log(f"workload {args.workload} {shape}, generating the initial field")
-    rho, u = WL.initial_field(args.workload)
-
-    def init(lat):
-        lat.init_equilibrium(rho, u)
-
-    log(f"timing {steps} steps after {args.warmup} warm-up steps")
+    init, keep = make_init(args.workload)
+    log(f"workload {args.workload} {shape}: timing {steps} steps after {args.warmup} warm-up steps")
     mlups, ms_step, gbps, sweep_ms, info, lat = run_form(elbm, torch, shape, w["nu"], "f32", steps, args.warmup,
                                                          init, bodies=w.get("bodies"), channel=w.get("channel", False),
                                                          u_in=w.get("u_in", (0, 0, 0)))
-    pops = lat.populations()
-    finite = bool(torch.isfinite(pops).all().item())
-    mass = float(pops.sum().item()) / lat.N
-    del pops, lat
+    # the stored FP32 deviations, checked in place (an FP64 copy of 512^3 would take 29 GB)
+    finite = bool(torch.isfinite(lat.population_view()).all().item())
+    healthy = info.nonfinite == 0
+    del lat
     torch.cuda.empty_cache()
     log(f"{args.workload}: {mlups:.0f} MLUPS, sweep {gbps:.0f} GB/s, {ms_step:.3f} ms/step, finite={finite}, "
-        f"mean rho={mass:.6f}, fp64 nodes last step={info.fp64_nodes}")
+        f"no failed state={healthy}, fp64 nodes last step={info.fp64_nodes}")
     n_nodes = shape[0] * shape[1] * shape[2]
     roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic_from_profile(n_nodes),
+            "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic_from_profile(args.workload, n_nodes),
             "kernel": "k_sweep<f32> (bulk stream-collide)", "bytes_per_launch": BYTES_PER_NODE["f32"] * n_nodes,
-            "avg_launch_ms": round(sweep_ms, 4)}
+            "avg_launch_ms": round(sweep_ms, 4), "sweep_source_sha16": sweep_source_hash()}
 
     if args.probe_copy_mib:
         nb = args.probe_copy_mib << 20
@@ -320,32 +388,50 @@ def main():
             log(f"copy probe {forms['copy_probe_GBps']} GB/s")
             # the library's stream-only mode: the sweep's pull and store, no collision -- the
             # attainable bandwidth of exactly this access pattern
-            _, _, gb, _, _, lat = run_form(elbm, torch, shape, w["nu"], "f32", 100, 5, init,
+            _, _, gb, _, _, lat = run_form(elbm, torch, shape, w["nu"], "f32", args.form_steps, 5, init,
                                            flags=elbm.FLAG_STREAM_ONLY)
             del lat
             torch.cuda.empty_cache()
             forms["pull_copy_GBps"] = round(gb, 1)
             roof["attainable_pull_copy"] = round(gb, 1)
             log(f"stream-only pull copy ({args.workload}) {gb:.0f} GB/s")
-        if "turb512" in which:
+        if "turb512_2byte" in which:
             w5 = WL.WORKLOADS["turb512"]
-            log("turb512: generating the initial field on the device")
-            r5, u5 = WL.turbulence_device(512, w5["k0"], w5["urms"], w5["seed"])
-
-            def init5(lat):
-                elbm.elbm_init_equilibrium(lat.ctx, r5, u5)
-                torch.cuda.synchronize()
-
-            for st in ("f32", "f16", "bf16"):
+            init5, keep5 = (init, keep) if args.workload == "turb512" else make_init("turb512")
+            stores = ("f16", "bf16") if args.workload == "turb512" else ("f32", "f16", "bf16")
+            for st in stores:
                 m, msps, gb, _, inf, lat = run_form(elbm, torch, w5["shape"], w5["nu"], st, args.form_steps, 5, init5)
                 del lat
                 torch.cuda.empty_cache()
                 forms[f"turb512_{st}"] = {"MLUPS": round(m, 1), "ms_per_step": round(msps, 4),
                                           "sweep_GBps": round(gb, 1), "frac": round(gb / HBM_PEAK_GBPS, 4),
+                                          "vs_f32_MLUPS": round(m / mlups, 3) if args.workload == "turb512" else None,
                                           "fp64_nodes_last_step": int(inf.fp64_nodes)}
                 log(f"turb512 {st}: {m:.0f} MLUPS, sweep {gb:.0f} GB/s")
-            del r5, u5
+            del init5, keep5
             torch.cuda.empty_cache()
+        if "turb256" in which and args.workload != "turb256":
+            w1 = WL.WORKLOADS["turb256"]
+            init1, keep1 = make_init("turb256")
+            m, msps, gb, sms, inf, lat = run_form(elbm, torch, w1["shape"], w1["nu"], "f32", 2 * args.form_steps, 5,
+                                                  init1)
+            del lat, init1, keep1
+            torch.cuda.empty_cache()
+            forms["turb256_f32"] = {"MLUPS": round(m, 1), "ms_per_step": round(msps, 4), "sweep_GBps": round(gb, 1),
+                                    "frac": round(gb / HBM_PEAK_GBPS, 4), "avg_launch_ms": round(sms, 4),
+                                    "traffic": traffic_from_profile("turb256", 256 ** 3)}
+            log(f"turb256 f32: {m:.0f} MLUPS, sweep {gb:.0f} GB/s")
+        if "stabilisers" in which:
+            # the headline run with the exact stabiliser, LBGK and the central-moment shear part
+            for name, fl in (("exact_gamma", elbm.FLAG_EXACT_GAMMA), ("lbgk", elbm.FLAG_LBGK),
+                             ("central", elbm.FLAG_CENTRAL)):
+                m, msps, gb, _, _, lat = run_form(elbm, torch, shape, w["nu"], "f32", max(10, args.form_steps // 5), 3,
+                                                  init, flags=fl)
+                del lat
+                torch.cuda.empty_cache()
+                forms[f"{args.workload}_{name}"] = {"MLUPS": round(m, 1), "ms_per_step": round(msps, 4),
+                                                    "sweep_GBps": round(gb, 1)}
+                log(f"{args.workload} {name}: {m:.0f} MLUPS, sweep {gb:.0f} GB/s")
         if "sphere384" in which:
             w2 = WL.WORKLOADS["sphere384"]
             r2, u2 = WL.initial_field("sphere384")
@@ -362,16 +448,6 @@ def main():
                                       "boundary_nodes": int(inf.boundary_nodes), "fp64_nodes_last_step": int(inf.fp64_nodes),
                                       "drag_last_step": F[0]}
             log(f"sphere384: {m:.0f} MLUPS, boundary nodes {inf.boundary_nodes}, drag {F[0]:.4e}")
-        if "stabilisers" in which:
-            # the same turb256 run with the exact stabiliser and with LBGK, for comparison
-            for name, fl in (("exact_gamma", elbm.FLAG_EXACT_GAMMA), ("lbgk", elbm.FLAG_LBGK),
-                             ("central", elbm.FLAG_CENTRAL)):
-                m, msps, gb, _, _, lat = run_form(elbm, torch, shape, w["nu"], "f32", 100, 5, init, flags=fl)
-                del lat
-                torch.cuda.empty_cache()
-                forms[f"{args.workload}_{name}"] = {"MLUPS": round(m, 1), "ms_per_step": round(msps, 4),
-                                                    "sweep_GBps": round(gb, 1)}
-                log(f"{args.workload} {name}: {m:.0f} MLUPS, sweep {gb:.0f} GB/s")
         if "settle" in which:
             forms["settle_f32"] = settle_form(elbm, torch, WL)
             log(f"settling sphere: {forms['settle_f32']}")
@@ -384,12 +460,14 @@ def main():
     except Exception as exc:  # a failing extra form must not hide the headline number
         forms["error"] = repr(exc)
         log(f"forms failed: {exc!r}")
+    del init, keep
+    torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
-        del rho, u
         cpu = cpu_baseline(args.workload)
-        log(f"cpu_baseline {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
+        log(f"cpu_baseline {cpu['value']:.2f} MLUPS on {cpu['cores']} threads, "
+            f"{cpu['one_thread']['value']:.3f} MLUPS on one ({cpu['cpu_model']})")
 
     line = {
         "metric": "MLUPS and % of HBM roofline, FP32 vs reduced-storage vs adjoint, 1 MI355X",
@@ -410,6 +488,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "finite": finite,
+        "failed_state": not healthy,
     }
     print(json.dumps(line), flush=True)
 

@@ -38,13 +38,13 @@ NQ = 27
 def build(force: bool = True) -> str:
     """Compile the oracle (gcc) and its adjoint (g++): FP64, OpenMP, no FP contraction."""
     if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
+        tmp = f"{_LIB_PATH}.{os.getpid()}.tmp"  # per process: concurrent builds do not collide
         cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
                "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     if force or not os.path.exists(_ADJ_LIB_PATH):
-        tmp = _ADJ_LIB_PATH + ".tmp"
+        tmp = f"{_ADJ_LIB_PATH}.{os.getpid()}.tmp"
         cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall",
                "-o", tmp, _ADJ_SRC]
         subprocess.run(cmd, check=True)

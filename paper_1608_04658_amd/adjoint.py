@@ -68,13 +68,17 @@ class ForceRollout:
         gF = torch.zeros((3, nz, ny, nx), dtype=torch.float32, device="cuda")
         elbm.elbm_adjoint_param_grad(lat.ctx, 1, reset=True)
         starts = sorted(self.ckpt)
+        # the recomputed levels of a segment are stepped straight into these buffers (no copies);
+        # they start as copies of a valid state so that nodes a step leaves alone (solid ones) hold
+        # finite values
+        bufs = [self.ckpt[0].clone() for _ in range(min(self.K, self.steps) - 1)]
         for s0 in reversed(starts):
             s1 = min(s0 + self.K, self.steps)
             lat.load_state(self.ckpt[s0], s0)
             states = [self.ckpt[s0]]
             for t in range(s0, s1 - 1):
-                lat.step(1)
-                states.append(lat.state_tensor())
+                elbm.elbm_step_into(lat.ctx, bufs[t - s0])
+                states.append(bufs[t - s0])
             for t in reversed(range(s0, s1)):
                 w = self.weights[t]           # loss weight of time level t+1
                 wf = w if np.any(w != 0.0) else None

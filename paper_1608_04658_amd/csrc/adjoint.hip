@@ -47,6 +47,10 @@ template <typename T> struct VjpOut {
 };
 
 // Vector-Jacobian product of kbc_collide: g = (d f'/d f)^T gp and gF = (d f'/d F)^T gp.
+// The equilibrium and its reciprocal come from per-axis factors (feq_i = rho phi_x phi_y phi_z),
+// so no division runs per direction; the equilibrium's cotangent is folded into the four sums it
+// feeds (d/drho and d/du of feq) as soon as each term is known, so no per-direction array besides
+// gp, the deviations and g stays live.
 template <typename T, bool FORCE>
 __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T beta, const T Fx, const T Fy,
                                     const T Fz, T (&g)[27], T (&gF)[3], bool lbgk = false) {
@@ -58,17 +62,35 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
     jy += T(cy(i)) * f[i];
     jz += T(cz(i)) * f[i];
   }
-  const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
-  T px[3], py[3], pz[3];
+  const T irho = T(1) / rho;
+  const T ux = jx * irho, uy = jy * irho, uz = jz * irho;
+  T px[3], py[3], pz[3], ipz[3], pxy[9], ipxy[9];
   axis_phi(ux, px);
   axis_phi(uy, py);
   axis_phi(uz, pz);
-  T feq[27], dh[27];
+  {
+    T ipx[3], ipy[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ipx[k] = T(1) / px[k];
+      ipy[k] = T(1) / py[k];
+      ipz[k] = T(1) / pz[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        pxy[3 * l + k] = rho * px[k] * py[l];
+        ipxy[3 * l + k] = irho * ipx[k] * ipy[l];
+      }
+  }
+  auto FE = [&](int i) -> T { return pxy[3 * (cy(i) + 1) + cx(i) + 1] * pz[cz(i) + 1]; };
+  auto IFE = [&](int i) -> T { return ipxy[3 * (cy(i) + 1) + cx(i) + 1] * ipz[cz(i) + 1]; };
+  T dh[27];
   T M200 = 0, M020 = 0, M002 = 0, M110 = 0, M101 = 0, M011 = 0;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    feq[i] = rho * px[cx(i) + 1] * py[cy(i) + 1] * pz[cz(i) + 1];
-    const T d = f[i] - feq[i];
+    const T d = f[i] - FE(i);
     dh[i] = d;
     M200 += T(cx(i) * cx(i)) * d;
     M020 += T(cy(i) * cy(i)) * d;
@@ -89,32 +111,40 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
     }
     return T(0);
   };
-  T a = T(0), b = T(0);
+  T a = T(0), b = T(0), g_gam = T(0);
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     dh[i] -= DS(i);
-    const T th = dh[i] / feq[i];
+    const T th = dh[i] * IFE(i);
     b += th * dh[i];
     a += th * DS(i);
+    g_gam += gp[i] * dh[i];
   }
   const bool guard = lbgk || !(b > T(1e-30));  // gamma fixed at 2: no derivative through it
   const T ib = T(1) / beta;
-  const T gam = guard ? T(2) : ib - (T(2) - ib) * a / b;
+  const T inv_b = guard ? T(0) : T(1) / b;
+  const T gam = guard ? T(2) : ib - (T(2) - ib) * a * inv_b;
   // reverse
-  T g_gam = T(0);
-#pragma unroll
-  for (int i = 0; i < 27; ++i) g_gam += gp[i] * dh[i];
   g_gam *= -beta;
-  const T g_a = guard ? T(0) : -(T(2) - ib) / b * g_gam;
-  const T g_b = guard ? T(0) : (T(2) - ib) * a / (b * b) * g_gam;
+  const T g_a = -(T(2) - ib) * inv_b * g_gam;
+  const T g_b = (T(2) - ib) * a * inv_b * inv_b * g_gam;
+  const T Dx[3] = {dlnphi(-1, ux), dlnphi(0, ux), dlnphi(1, ux)};
+  const T Dy[3] = {dlnphi(-1, uy), dlnphi(0, uy), dlnphi(1, uy)};
+  const T Dz[3] = {dlnphi(-1, uz), dlnphi(0, uz), dlnphi(1, uz)};
+  // S0, Sx, Sy, Sz: sums of (dL/dfeq_i) feq_i times 1 and d ln feq_i / du
+  T S0 = T(0), Sx = T(0), Sy = T(0), Sz = T(0);
   T gDx = 0, gDy = 0, gDz = 0, gPxy = 0, gPxz = 0, gPyz = 0;
-  T g_feq[27];
+  const T bg = beta * gam;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    const T ds = DS(i), fe = feq[i], h = dh[i];
-    const T g_dh = -beta * gam * gp[i] + (g_a * ds + T(2) * g_b * h) / fe;
-    const T g_ds = -T(2) * beta * gp[i] + g_a * h / fe - g_dh;
-    g_feq[i] = -(g_a * ds * h + g_b * h * h) / (fe * fe) - g_dh;
+    const T ds = DS(i), h = dh[i], ife = IFE(i);
+    const T g_dh = -bg * gp[i] + (g_a * ds + T(2) * g_b * h) * ife;
+    const T g_ds = -T(2) * beta * gp[i] + g_a * h * ife - g_dh;
+    const T ge = -(g_a * ds + g_b * h) * h * ife - g_dh * FE(i);
+    S0 += ge;
+    Sx += ge * Dx[cx(i) + 1];
+    Sy += ge * Dy[cy(i) + 1];
+    Sz += ge * Dz[cz(i) + 1];
     g[i] = gp[i] + g_dh;
     if (nnz(i) == 1) {
       if (cx(i)) gDx += T(0.5) * g_ds;
@@ -128,57 +158,60 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
   }
   const T gm = (gDx + gDy + gDz) * T(1.0 / 3.0);
   const T gM200 = gDx - gm, gM020 = gDy - gm, gM002 = gDz - gm;
+  T g_rho = T(0), gux = T(0), guy = T(0), guz = T(0);
+  gF[0] = gF[1] = gF[2] = T(0);
+  T qx[3], qy[3], qz[3], D1x[3], D1y[3], D1z[3], u1x = T(0), u1y = T(0), u1z = T(0);
+  T gr1 = T(0), g1x = T(0), g1y = T(0), g1z = T(0);
+  if (FORCE) {
+    // f' += feq(rho, u + F/rho) - feq(rho, u)
+    u1x = ux + Fx * irho;
+    u1y = uy + Fy * irho;
+    u1z = uz + Fz * irho;
+    axis_phi(u1x, qx);
+    axis_phi(u1y, qy);
+    axis_phi(u1z, qz);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      D1x[k] = dlnphi(k - 1, u1x);
+      D1y[k] = dlnphi(k - 1, u1y);
+      D1z[k] = dlnphi(k - 1, u1z);
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const T e = gM200 * T(cx(i) * cx(i)) + gM020 * T(cy(i) * cy(i)) + gM002 * T(cz(i) * cz(i)) +
                 gPxy * T(cx(i) * cy(i)) + gPxz * T(cx(i) * cz(i)) + gPyz * T(cy(i) * cz(i));
     g[i] += e;
-    g_feq[i] -= e;
-  }
-  T g_rho = T(0), gux = T(0), guy = T(0), guz = T(0);
-  gF[0] = gF[1] = gF[2] = T(0);
-  if (FORCE) {
-    // f' += feq(rho, u + F/rho) - feq(rho, u)
-    const T u1x = ux + Fx / rho, u1y = uy + Fy / rho, u1z = uz + Fz / rho;
-    T qx[3], qy[3], qz[3];
-    axis_phi(u1x, qx);
-    axis_phi(u1y, qy);
-    axis_phi(u1z, qz);
-    const T D1x[3] = {dlnphi(-1, u1x), dlnphi(0, u1x), dlnphi(1, u1x)};
-    const T D1y[3] = {dlnphi(-1, u1y), dlnphi(0, u1y), dlnphi(1, u1y)};
-    const T D1z[3] = {dlnphi(-1, u1z), dlnphi(0, u1z), dlnphi(1, u1z)};
-    T g1x = 0, g1y = 0, g1z = 0, gr1 = 0;
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      const T e1 = rho * qx[cx(i) + 1] * qy[cy(i) + 1] * qz[cz(i) + 1];
-      const T ge = gp[i] * e1;
-      gr1 += ge;
-      g1x += ge * D1x[cx(i) + 1];
-      g1y += ge * D1y[cy(i) + 1];
-      g1z += ge * D1z[cz(i) + 1];
-      g_feq[i] -= gp[i];
+    T ge = -e;
+    if (FORCE) {
+      const T g1 = gp[i] * rho * qx[cx(i) + 1] * qy[cy(i) + 1] * qz[cz(i) + 1];
+      gr1 += g1;
+      g1x += g1 * D1x[cx(i) + 1];
+      g1y += g1 * D1y[cy(i) + 1];
+      g1z += g1 * D1z[cz(i) + 1];
+      ge -= gp[i];
     }
-    g_rho += gr1 / rho - (g1x * Fx + g1y * Fy + g1z * Fz) / (rho * rho);
+    ge *= FE(i);
+    S0 += ge;
+    Sx += ge * Dx[cx(i) + 1];
+    Sy += ge * Dy[cy(i) + 1];
+    Sz += ge * Dz[cz(i) + 1];
+  }
+  if (FORCE) {
+    g_rho += gr1 * irho - (g1x * Fx + g1y * Fy + g1z * Fz) * irho * irho;
     gux += g1x;
     guy += g1y;
     guz += g1z;
-    gF[0] = g1x / rho;
-    gF[1] = g1y / rho;
-    gF[2] = g1z / rho;
+    gF[0] = g1x * irho;
+    gF[1] = g1y * irho;
+    gF[2] = g1z * irho;
   }
-  const T Dx[3] = {dlnphi(-1, ux), dlnphi(0, ux), dlnphi(1, ux)};
-  const T Dy[3] = {dlnphi(-1, uy), dlnphi(0, uy), dlnphi(1, uy)};
-  const T Dz[3] = {dlnphi(-1, uz), dlnphi(0, uz), dlnphi(1, uz)};
-#pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    const T ge = g_feq[i] * feq[i];
-    g_rho += ge / rho;
-    gux += ge * Dx[cx(i) + 1];
-    guy += ge * Dy[cy(i) + 1];
-    guz += ge * Dz[cz(i) + 1];
-  }
-  const T gjx = gux / rho, gjy = guy / rho, gjz = guz / rho;
-  g_rho -= (gux * ux + guy * uy + guz * uz) / rho;
+  g_rho += S0 * irho;
+  gux += Sx;
+  guy += Sy;
+  guz += Sz;
+  const T gjx = gux * irho, gjy = guy * irho, gjz = guz * irho;
+  g_rho -= (gux * ux + guy * uy + guz * uz) * irho;
 #pragma unroll
   for (int i = 0; i < 27; ++i) g[i] += g_rho + T(cx(i)) * gjx + T(cy(i)) * gjy + T(cz(i)) * gjz;
   return VjpOut<T>{b, rho};
@@ -291,8 +324,13 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
   PullIdx P;
   pull_idx(a, x, y, z, P);
   if (fl & FL_SOLID) {
+    // a source fluid at t+1 is a wall node whose missing population this one is: the wall kernel
+    // writes the entry (the bounce-back term), so it is left alone here
 #pragma unroll
-    for (int i = 0; i < 27; ++i) push_idx(a, j, P, i, y, z, 0.f);
+    for (int i = 0; i < 27; ++i) {
+      const bool beyond = (cx(i) == 1 && P.in_lo) || (cx(i) == -1 && P.out_hi);
+      if (beyond || (a.flags[pull_src_idx(a, P, i)] & FL_SOLID)) push_idx(a, j, P, i, y, z, 0.f);
+    }
     return;
   }
   const E* __restrict__ A = (const E*)a.A;
@@ -497,17 +535,29 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
 // U^t and R^t (k_macro64), the wall targets and Grad populations (wall_targets64), the refill
 // values (k_adj_refill); only the adjoint fields themselves are stored in FP32.
 
+// Two disjoint boxes walked by one launch (the body box and the inlet slab): index idx < count of
+// the first lies in it, the rest in the second.
+struct Box2 {
+  Box b[2];
+  __host__ __device__ long count() const { return b[0].count() + b[1].count(); }
+};
+__device__ __forceinline__ void box2_node(const Box2& bb, long idx, int& x, int& y, int& z) {
+  const long c0 = bb.b[0].count();
+  if (idx < c0) box_node(bb.b[0], idx, x, y, z);
+  else box_node(bb.b[1], idx - c0, x, y, z);
+}
+
 // U^t, R^t in FP64 on a box: the rule of k_macro (moments of A^t with U = (j - F/2)/rho at nodes
 // fluid at t, the rigid-body velocity and rho0 at nodes solid at t) from the exactly widened
 // stored deviations.
 template <int S>
 __global__ void k_macro64(const typename Codec<S>::E* A, PopLayout lay, const uint8_t* flags, double* m64,
-                          const float* F, Box box, int32_t nx, int32_t ny, int64_t N, double rho0, Bodies bd) {
+                          const float* F, Box2 box, int32_t nx, int32_t ny, int64_t N, double rho0, Bodies bd) {
   using C = Codec<S>;
   const long total = box.count();
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
     int x, y, z;
-    box_node(box, idx, x, y, z);
+    box2_node(box, idx, x, y, z);
     const long n = ((long)z * ny + y) * nx + x;
     double U[3], R;
     if (flags[n] & FL_SOLID_PREV) {
@@ -533,9 +583,10 @@ __global__ void k_macro64(const typename Codec<S>::E* A, PopLayout lay, const ui
         jy -= 0.5 * (double)F[N + n];
         jz -= 0.5 * (double)F[2 * N + n];
       }
-      U[0] = jx / rho;
-      U[1] = jy / rho;
-      U[2] = jz / rho;
+      const double irho = 1.0 / rho;
+      U[0] = jx * irho;
+      U[1] = jy * irho;
+      U[2] = jz * irho;
       R = rho;
     }
     m64[n] = U[0];
@@ -659,10 +710,12 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
   for (int64_t base = 2 * (int64_t)blockIdx.x; base < count; base += 2 * (int64_t)gridDim.x) {
     // a group past the end repeats the block's first node and writes nothing
     const int64_t k = base + g;
-    const bool active = k < count;
-    const long n = a.list[active ? k : base];
+    const long n = a.list[k < count ? k : base];
+    // the plain inlet nodes are k_adj_inlet's: decided from flags alone, before the gather
+    // (uniform over the group: every lane tests one source, the group's ballot decides)
     LaneNb h;
     lane_gather<S, true, false>(a, A, n, lane, h);
+    const bool active = k < count;
     const double gpi = lane < 27 ? (double)j.lam_in[(long)i * a.N + n] : 0.0;
     const uint32_t dmask = h.dbar;
     // FP64 deviations: the stored ones widened exactly, except at nodes uncovered in this step,
@@ -709,7 +762,7 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
     if (!dmask) {
       if (active && lane < 27) adj_push(a, j, i, h.x, h.y, h.z, (float)gi);
     } else {
-      double grl = 0.0, gul[3] = {0.0, 0.0, 0.0}, gPl[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      double grl = 0.0, gul[3] = {0.0, 0.0, 0.0}, gPl[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, ga = 0.0;
       if (w.mine) {
         double gfs = gi;
         if (p.loss && w.kb >= 0)
@@ -739,7 +792,8 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
 #pragma unroll
             for (int c = 0; c < 3; ++c) guw[c] += p.w[w.kb][c] * (w.fs - fbd);
           }
-          j.lam_out[(long)opp(i) * a.N + n] += (float)vbb;
+          // the only writer of this entry: its puller, the solid node, leaves it to this kernel
+          j.lam_out[(long)opp(i) * a.N + n] = (float)vbb;
           if (!(a.channel && h.x - cx(i) < 0)) adj_push(a, j, i, h.x, h.y, h.z, 0.f);
           // u_f and q
           double uf[3];
@@ -772,12 +826,16 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
 #pragma unroll
               for (int c = 0; c < 3; ++c) dqdc[c] = -b.n[c] / nv;
             }
-            double ga = 0.0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) ga += guw[c] * p.dU1[w.kb][c] + gq * dqdc[c] * p.dc1[w.kb][c];
-            atomicAdd(&p.gamp[w.kb], ga);
           }
         }
+      }
+      // dL/d(amp) of the group's links, summed over the group first: one atomic per node and body
+      // (per-link atomics on the one address serialise)
+      for (int kb = 0; kb < bd.nb; ++kb) {
+        const double sg = gsum(w.mine && w.kb == kb ? ga : 0.0);
+        if (active && lane == 0 && sg != 0.0) atomicAdd(&p.gamp[kb], sg);
       }
       // transpose of the gradient stencil: lanes 0..8 take one (axis, component) pair each
       if (active && lane < 9) grad_u_vjp_one(a, j, h, lane / 3, lane % 3, gG[3 * (lane % 3) + lane / 3]);
@@ -889,39 +947,49 @@ __global__ __launch_bounds__(64) void k_adj_refill(const BArgs a, const Bodies b
 
 // Channel faces, before the boundary adjoint: entries that no node pulls -- x = 0 moving in -x and
 // x = nx-1 moving in +x -- start at zero (the wall rule then adds the bounce-back terms at x = 0).
+// One thread per (direction pair k, y, z).
 __global__ void k_adj_faces_zero(const BArgs a, const AdjArgs j) {
-  const long total = (long)a.ny * a.nz;
+  const long face = (long)a.ny * a.nz, total = 9 * face;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-    const int y = (int)(idx % a.ny), z = (int)(idx / a.ny);
-    const long n0 = node_at(a, 0, y, z), n1 = node_at(a, a.nx - 1, y, z);
-    for (int k = 0; k < 9; ++k) {
-      j.lam_out[(3 * k) * a.N + n0] = 0.f;
-      j.lam_out[(3 * k + 2) * a.N + n1] = 0.f;
-    }
+    const int k = (int)(idx / face);
+    const long r = idx - k * face;
+    const int y = (int)(r % a.ny), z = (int)(r / a.ny);
+    j.lam_out[(3 * k) * a.N + node_at(a, 0, y, z)] = 0.f;
+    j.lam_out[(3 * k + 2) * a.N + node_at(a, a.nx - 1, y, z)] = 0.f;
   }
 }
 
 // Channel faces, after the boundary adjoint: add the outlet-copy contributions of the side buffer.
+// One thread per (direction k with c_x = -1, y, z); for each k the targets are distinct.
 __global__ void k_adj_outlet(const BArgs a, const AdjArgs j) {
-  const long total = (long)a.ny * a.nz;
+  const long face = (long)a.ny * a.nz, total = 9 * face;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-    const int y = (int)(idx % a.ny), z = (int)(idx / a.ny);
-    for (int k = 0; k < 9; ++k) {
-      const int i = 3 * k;
-      const long tgt = node_at(a, a.nx - 1, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
-      j.lam_out[i * a.N + tgt] += j.side[(size_t)k * a.ny * a.nz + (size_t)z * a.ny + y];
-    }
+    const int k = (int)(idx / face);
+    const long r = idx - k * face;
+    const int y = (int)(r % a.ny), z = (int)(r / a.ny);
+    const int i = 3 * k;
+    const long tgt = node_at(a, a.nx - 1, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
+    j.lam_out[i * a.N + tgt] += j.side[(size_t)k * face + (size_t)z * a.ny + y];
   }
 }
 
 // dL/dU^t, dL/dR^t -> dL/dA^t at nodes fluid at t (U = (j - F/2)/rho, R = rho), or dL/d(amp) at
 // nodes solid at t (U = rigid-body velocity at t).  Clears the accumulators it consumes.
+// Launched on the boxes where the wall rules read U^t and R^t (around the bodies, the inlet slab),
+// which hold every accumulated entry.
 template <int S>
-__global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, const AdjBodyArgs p) {
+__global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, const AdjBodyArgs p, const Box2 box) {
   using C = Codec<S>;
   using E = typename C::E;
   const E* __restrict__ A = (const E*)a.A;
-  for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < a.N; n += (long)gridDim.x * blockDim.x) {
+  const long total = box.count();
+  double acc[ELBM_MAX_BODIES];  // this thread's dL/d(amp) per body, summed over the wave at the end
+#pragma unroll
+  for (int q = 0; q < ELBM_MAX_BODIES; ++q) acc[q] = 0.0;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    int bx, by, bz;
+    box2_node(box, idx, bx, by, bz);
+    const long n = node_at(a, bx, by, bz);
     const double gU0 = j.gUR[n], gU1 = j.gUR[a.N + n], gU2 = j.gUR[2 * a.N + n], gR = j.gUR[3 * a.N + n];
     if (gU0 == 0.0 && gU1 == 0.0 && gU2 == 0.0 && gR == 0.0) continue;
     j.gUR[n] = 0.0;
@@ -933,7 +1001,9 @@ __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, con
     if (a.flags[n] & FL_SOLID_PREV) {
       int kb = first_body(bd, false, x, y, z);
       if (kb < 0) kb = 0;
-      atomicAdd(&p.gamp[kb], gU0 * p.dU0[kb][0] + gU1 * p.dU0[kb][1] + gU2 * p.dU0[kb][2]);
+      const double v = gU0 * p.dU0[kb][0] + gU1 * p.dU0[kb][1] + gU2 * p.dU0[kb][2];
+#pragma unroll
+      for (int q = 0; q < ELBM_MAX_BODIES; ++q) acc[q] += q == kb ? v : 0.0;
       continue;
     }
     // U, R of the node from the exactly widened stored deviations (as k_macro64)
@@ -952,15 +1022,24 @@ __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, con
       jy -= 0.5 * (double)a.F[a.N + n];
       jz -= 0.5 * (double)a.F[2 * a.N + n];
     }
-    const double U[3] = {jx / rho, jy / rho, jz / rho};
+    const double irho = 1.0 / rho;
+    const double U[3] = {jx * irho, jy * irho, jz * irho};
+    const double h0 = gU0 * irho, h1 = gU1 * irho, h2 = gU2 * irho;
+    const double base = gR - (h0 * U[0] + h1 * U[1] + h2 * U[2]);
 #pragma unroll
-    for (int i = 0; i < 27; ++i)
-      j.lam_out[i * a.N + n] += (float)(gR + (gU0 * (cx(i) - U[0]) + gU1 * (cy(i) - U[1]) + gU2 * (cz(i) - U[2])) / rho);
+    for (int i = 0; i < 27; ++i) j.lam_out[i * a.N + n] += (float)(base + h0 * cx(i) + h1 * cy(i) + h2 * cz(i));
     if (a.F && j.gF) {
-      j.gF[n] -= (float)(gU0 / (2.0 * rho));
-      j.gF[a.N + n] -= (float)(gU1 / (2.0 * rho));
-      j.gF[2 * a.N + n] -= (float)(gU2 / (2.0 * rho));
+      j.gF[n] -= (float)(0.5 * h0);
+      j.gF[a.N + n] -= (float)(0.5 * h1);
+      j.gF[2 * a.N + n] -= (float)(0.5 * h2);
     }
+  }
+  // one atomic per wave and body (every lane of the launch reaches this point)
+  for (int q = 0; q < bd.nb; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v != 0.0) atomicAdd(&p.gamp[q], v);
   }
 }
 
@@ -1016,26 +1095,40 @@ static void amp_derivatives(const elbm_body& b, double t, double dc[3], double d
   }
 }
 
+// The boxes where the wall rules read U^t and R^t: around the bodies and, in channel mode, the inlet
+// slab x < 3 (the body box without the slab, so the two are disjoint).
+static Box2 adj_boxes(const elbm_ctx* c, const Bodies& bd) {
+  Box2 bb;
+  Box slab = full_box(c);
+  slab.n[0] = 0;
+  if (c->p.bc_x == ELBM_BC_CHANNEL) slab.n[0] = c->p.nx < 3 ? c->p.nx : 3;
+  Box ub = full_box(c);
+  ub.n[0] = 0;
+  if (c->nb > 0) {
+    ub = union_box(c, bd);
+    const int cut = slab.n[0] - ub.lo[0];  // columns of the body box inside the slab
+    if (cut > 0) {
+      ub.lo[0] += cut;
+      ub.n[0] = ub.n[0] > cut ? ub.n[0] - cut : 0;
+    }
+  }
+  bb.b[0] = ub;
+  bb.b[1] = slab;
+  return bb;
+}
+
+// FP64 U^t, R^t on the boxes where the wall rules read them.
 template <int S>
-static void macro64_box(elbm_ctx* c, const void* A, const Box& box, const Bodies& bd) {
-  hipLaunchKernelGGL((k_macro64<S>), grid_for(box.count()), dim3(256), 0, c->stream, (const typename Codec<S>::E*)A,
-                     c->lay, (const uint8_t*)c->flags, c->adj_macro64, c->bodyforce, box, c->p.nx, c->p.ny,
+static void macro64_fields(elbm_ctx* c, const void* A, const Bodies& bd) {
+  const Box2 bb = adj_boxes(c, bd);
+  if (bb.count() == 0) return;
+  hipLaunchKernelGGL((k_macro64<S>), grid_for(bb.count()), dim3(256), 0, c->stream, (const typename Codec<S>::E*)A,
+                     c->lay, (const uint8_t*)c->flags, c->adj_macro64, c->bodyforce, bb, c->p.nx, c->p.ny,
                      (int64_t)c->N, c->p.rho0, bd);
 }
 
-// FP64 U^t, R^t on the boxes where the wall rules read them: around the bodies and the inlet slab.
 template <int S>
-static void macro64_fields(elbm_ctx* c, const void* A, const Bodies& bd) {
-  if (c->nb > 0) macro64_box<S>(c, A, union_box(c, bd), bd);
-  if (c->p.bc_x == ELBM_BC_CHANNEL) {
-    Box slab = full_box(c);
-    slab.n[0] = c->p.nx < 3 ? c->p.nx : 3;
-    macro64_box<S>(c, A, slab, bd);
-  }
-}
-
-template <int S>
-static void adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, const AdjArgs& j, const AdjBodyArgs& p) {
+static hipError_t adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, const AdjArgs& j, const AdjBodyArgs& p) {
   int bx = 256;
   while (bx > 32 && (c->p.nx % bx) != 0) bx >>= 1;
   if (c->p.nx < bx) bx = 32;
@@ -1044,26 +1137,31 @@ static void adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, const AdjA
   const bool geo = c->flags != nullptr, force = c->bodyforce != nullptr;
   if (geo) macro64_fields<S>(c, a.A, bd);
   if (geo && c->moving) {
-    const dim3 gr((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap - a.n_static + 1) / 2, 1), 4096));
+    const dim3 gr((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap - a.n_static + 1) / 2, 1), 1024));
     hipLaunchKernelGGL(k_adj_refill64, gr, dim3(64), 0, c->stream, a, bd, j);
   }
+  const dim3 gf = grid_for(9L * c->p.ny * c->p.nz);
+  // entries no node pulls start at zero; the wall kernels write the inlet's bounce-back terms
+  if (geo && a.channel) hipLaunchKernelGGL(k_adj_faces_zero, gf, dim3(256), 0, c->stream, a, j);
   if (geo && force) hipLaunchKernelGGL((k_adj_bulk<S, true, true>), grd, blk, 0, c->stream, a, j);
   else if (geo) hipLaunchKernelGGL((k_adj_bulk<S, true, false>), grd, blk, 0, c->stream, a, j);
   else if (force) hipLaunchKernelGGL((k_adj_bulk<S, false, true>), grd, blk, 0, c->stream, a, j);
   else hipLaunchKernelGGL((k_adj_bulk<S, false, false>), grd, blk, 0, c->stream, a, j);
   if (geo) {
-    const dim3 gf = grid_for((long)c->p.ny * c->p.nz);
-    if (a.channel) hipLaunchKernelGGL(k_adj_faces_zero, gf, dim3(256), 0, c->stream, a, j);
-    const dim3 gb((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap + 1) / 2, 1), 16384));
+    // a grid-stride loop over the list: about two groups per SIMD (the list length is on the device)
+    const dim3 gb((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap + 1) / 2, 1), 2048));
     if (force) hipLaunchKernelGGL((k_adj_boundary<S, true>), gb, dim3(64), 0, c->stream, a, bd, j, p);
     else hipLaunchKernelGGL((k_adj_boundary<S, false>), gb, dim3(64), 0, c->stream, a, bd, j, p);
     if (a.channel) hipLaunchKernelGGL(k_adj_outlet, gf, dim3(256), 0, c->stream, a, j);
     if (c->moving) {
-      const dim3 gr((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap - a.n_static + 1) / 2, 1), 4096));
+      const dim3 gr((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap - a.n_static + 1) / 2, 1), 1024));
       hipLaunchKernelGGL(k_adj_refill, gr, dim3(64), 0, c->stream, a, bd, j, p);
     }
-    hipLaunchKernelGGL(k_adj_macro<S>, grid_for(c->N), dim3(256), 0, c->stream, a, bd, j, p);
+    const Box2 bb = adj_boxes(c, bd);
+    if (bb.count() > 0)
+      hipLaunchKernelGGL(k_adj_macro<S>, grid_for(bb.count()), dim3(256), 0, c->stream, a, bd, j, p, bb);
   }
+  return hipGetLastError();
 }
 
 hipError_t launch_adjoint(elbm_ctx* c, int64_t t, const void* A, const float* lam_in, float* lam_out,
@@ -1098,11 +1196,10 @@ hipError_t launch_adjoint(elbm_ctx* c, int64_t t, const void* A, const float* la
     for (int e = 0; e < 3; ++e) p.w[k][e] = w_force ? w_force[3 * k + e] : 0.0;
   }
   switch (c->p.storage) {
-    case ELBM_STORAGE_F32: adj_launch<ELBM_STORAGE_F32>(c, a, bd, j, p); break;
-    case ELBM_STORAGE_F16: adj_launch<ELBM_STORAGE_F16>(c, a, bd, j, p); break;
-    default: adj_launch<ELBM_STORAGE_BF16>(c, a, bd, j, p);
+    case ELBM_STORAGE_F32: return adj_launch<ELBM_STORAGE_F32>(c, a, bd, j, p);
+    case ELBM_STORAGE_F16: return adj_launch<ELBM_STORAGE_F16>(c, a, bd, j, p);
+    default: return adj_launch<ELBM_STORAGE_BF16>(c, a, bd, j, p);
   }
-  return hipGetLastError();
 }
 
 }  // namespace elbm

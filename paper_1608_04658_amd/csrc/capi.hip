@@ -251,6 +251,13 @@ int elbm_workspace_bytes(const elbm_params* p, size_t* bytes) {
   return ELBM_OK;
 }
 
+// The context's own streams and events (those that exist).
+static void release_streams(elbm_ctx* c) {
+  for (int k = 0; k < FREE_HIST; ++k)
+    if (c->free_ev[k]) (void)hipEventDestroy(c->free_ev[k]);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
+}
+
 int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_bytes, elbm_ctx** out) {
   const int rc = validate(p, g_create_err);
   if (rc) return rc;
@@ -275,6 +282,8 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   if (p->flags & ELBM_FLAG_CENTRAL) c->stab |= STAB_CENTRAL;
   c->pop[0] = c->ws + L.pop[0];
   c->pop[1] = c->ws + L.pop[1];
+  c->own[0] = c->pop[0];
+  c->own[1] = c->pop[1];
   c->cur = 0;
   c->lay = pop_layout(c->p);
   c->cnt = (DevCounters*)(c->ws + L.cnt);
@@ -347,9 +356,7 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
   for (int k = 0; k < FREE_HIST && e == hipSuccess && L.geometry; ++k)
     e = hipEventCreateWithFlags(&c->free_ev[k], hipEventDisableTiming);
   if (e != hipSuccess) {
-    for (int k = 0; k < FREE_HIST; ++k)
-      if (c->free_ev[k]) (void)hipEventDestroy(c->free_ev[k]);
-    if (c->aux) (void)hipStreamDestroy(c->aux);
+    release_streams(c);
     delete c;
     return fail(nullptr, ELBM_EDEVICE, "context set-up: %s", hipGetErrorString(e));
   }
@@ -358,9 +365,7 @@ int elbm_create(const elbm_params* p, void* stream, void* workspace, size_t ws_b
     const int g = geometry_init(c);
     const bool over = g == hipSuccess && c->n_static > c->blist_cap;
     if (g != hipSuccess || over) {
-      for (int k = 0; k < FREE_HIST; ++k)
-        if (c->free_ev[k]) (void)hipEventDestroy(c->free_ev[k]);
-      if (c->aux) (void)hipStreamDestroy(c->aux);
+      release_streams(c);
       const long long ns = (long long)c->n_static, cap = (long long)c->blist_cap;
       delete c;
       if (over)
@@ -385,9 +390,7 @@ static void free_events(elbm_ctx* c) {
 int elbm_destroy(elbm_ctx* c) {
   if (!c) return ELBM_EINVAL;
   free_events(c);
-  for (int k = 0; k < FREE_HIST; ++k)
-    if (c->free_ev[k]) (void)hipEventDestroy(c->free_ev[k]);
-  if (c->aux) (void)hipStreamDestroy(c->aux);
+  release_streams(c);
   delete c;
   return ELBM_OK;
 }
@@ -403,6 +406,8 @@ int elbm_init_equilibrium(elbm_ctx* c, const double* rho_dev, const double* u_de
   if (!u_dev) return fail(c, ELBM_EINVAL, "u_dev is NULL");
   // both buffers: nodes that stay solid are never written by a step
   HIP_OK(c, free_reanchor(c, 0));
+  c->pop[0] = c->own[0];
+  c->pop[1] = c->own[1];
   c->cur = 1;
   HIP_OK(c, launch_init_eq(c, rho_dev, u_dev));
   c->cur = 0;
@@ -418,6 +423,8 @@ int elbm_write_populations(elbm_ctx* c, const double* pop_dev, int64_t t) {
   if (!pop_dev || t < 0) return fail(c, ELBM_EINVAL, "bad arguments");
   HIP_OK(c, free_reanchor(c, t));
   c->t = t;
+  c->pop[0] = c->own[0];
+  c->pop[1] = c->own[1];
   HIP_OK(c, launch_write_pop(c, pop_dev));
   HIP_OK(c, diag_reset(c, true));
   if (c->flags) return geo_init(c);
@@ -621,11 +628,11 @@ int elbm_set_body_force(elbm_ctx* c, const float* F_dev) {
   return ELBM_OK;
 }
 
-int elbm_step(elbm_ctx* c, int32_t nsteps) {
-  if (!c) return ELBM_EINVAL;
-  if (nsteps < 0) return fail(c, ELBM_EINVAL, "nsteps < 0");
+// One step t -> t+1 writing A^{t+1} into dst (NULL: the workspace buffer of the other slot).
+static int one_step(elbm_ctx* c, void* dst) {
   const bool geo = c->flags != nullptr;
-  for (int32_t s = 0; s < nsteps; ++s) {
+  c->pop[c->cur ^ 1] = dst ? dst : c->own[c->cur ^ 1];
+  {
     if (c->n_free) {
       // positions at t and t+1 from the state of level t or t-1 (the latter read one step behind
       // the device: the step before is still running meanwhile)
@@ -668,6 +675,27 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
     c->slab_valid = c->slab_next != nullptr && !(c->p.flags & ELBM_FLAG_STREAM_ONLY);
   }
   return ELBM_OK;
+}
+
+int elbm_step(elbm_ctx* c, int32_t nsteps) {
+  if (!c) return ELBM_EINVAL;
+  if (nsteps < 0) return fail(c, ELBM_EINVAL, "nsteps < 0");
+  for (int32_t s = 0; s < nsteps; ++s) {
+    const int rc = one_step(c, nullptr);
+    if (rc) return rc;
+  }
+  return ELBM_OK;
+}
+
+int elbm_step_into(elbm_ctx* c, void* pop_next_dev) {
+  if (!c) return ELBM_EINVAL;
+  if (!pop_next_dev) return fail(c, ELBM_EINVAL, "pop_next_dev is NULL");
+  const size_t bytes = 27 * (size_t)c->N * storage_bytes(c->p.storage);
+  const char* a0 = (const char*)c->pop[c->cur];
+  const char* b0 = (const char*)pop_next_dev;
+  if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(c, ELBM_EINVAL, "pop_next_dev overlaps the current populations");
+  if (((uintptr_t)pop_next_dev) % 16) return fail(c, ELBM_EINVAL, "pop_next_dev must be 16-byte aligned");
+  return one_step(c, pop_next_dev);
 }
 
 int elbm_force_history(elbm_ctx* c, int32_t body, int64_t first, int32_t count, double* out_host) {
@@ -728,7 +756,7 @@ int elbm_get_info(elbm_ctx* c, elbm_info* out) {
   out->nodes = c->N;
   out->beta = c->beta;
   out->pop_bytes = 27 * (size_t)c->N * storage_bytes(c->p.storage);
-  out->pop_offset = (size_t)((char*)c->pop[c->cur] - c->ws);
+  out->pop_offset = c->pop[c->cur] == c->own[c->cur] ? (size_t)((char*)c->pop[c->cur] - c->ws) : (size_t)-1;
   out->flags_offset = c->flags ? (size_t)((char*)c->flags - c->ws) : 0;
   out->storage = c->p.storage;
   out->layout = c->lay.interleaved ? ELBM_LAYOUT_ROWS : ELBM_LAYOUT_SOA;
@@ -768,6 +796,8 @@ int elbm_load_state(elbm_ctx* c, const void* pop_dev, int64_t t) {
   if (!c) return ELBM_EINVAL;
   if (!pop_dev || t < 0) return fail(c, ELBM_EINVAL, "bad arguments");
   const size_t bytes = 27 * (size_t)c->N * storage_bytes(c->p.storage);
+  c->pop[0] = c->own[0];
+  c->pop[1] = c->own[1];
   HIP_OK(c, hipMemcpyAsync(c->pop[c->cur], pop_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, free_reanchor(c, t));
   c->t = t;

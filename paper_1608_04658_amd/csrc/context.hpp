@@ -18,6 +18,8 @@ struct elbm_ctx {
   // carved fields (device)
   void* pop[2];
   int cur;                 // pop[cur] holds A^t
+  void* own[2];            // the workspace's two population buffers (pop[] may point to a caller's
+                           // buffer after elbm_step_into; a step always writes into own[] otherwise)
   elbm::PopLayout lay;     // placement of the populations in pop[0], pop[1] (pop_layout)
   uint8_t* flags;          // N (geometry only)
   float* macro;            // 4 N: U (3 N) then R (N) (geometry only)

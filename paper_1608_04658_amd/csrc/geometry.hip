@@ -266,7 +266,7 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(const uint32_t* block_cou
   }
   if (threadIdx.x == 0) {
     *count_out = running;
-    if (base + (int64_t)running > cap) *overflow = 1u;
+    if (base + (int64_t)running > cap) atomicOr(overflow, 1u);
   }
 }
 

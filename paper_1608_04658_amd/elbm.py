@@ -87,6 +87,7 @@ def load():
         "elbm_body_spin": [_VP, ctypes.c_int32, P(ctypes.c_double)],
         "elbm_set_body_force": [_VP, _VP],
         "elbm_step": [_VP, ctypes.c_int32],
+        "elbm_step_into": [_VP, _VP],
         "elbm_force": [_VP, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double), P(ctypes.c_double)],
         "elbm_force_history": [_VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ctypes.c_double)],
         "elbm_read_flags": [_VP, _VP],
@@ -253,6 +254,12 @@ def elbm_set_body_force(ctx, F_dev):
 
 def elbm_step(ctx, nsteps: int = 1):
     _check(load().elbm_step(ctx, int(nsteps)), ctx)
+
+
+def elbm_step_into(ctx, pop_next):
+    """One step whose new populations go to the device tensor `pop_next` (27 N elements of the
+    storage type), which becomes the current population buffer."""
+    _check(load().elbm_step_into(ctx, _ptr(pop_next)), ctx)
 
 
 def elbm_force(ctx, body: int, step: int):
@@ -496,6 +503,8 @@ class Lattice:
         info = self.info()
         dt = {0: torch.float32, 1: torch.float16, 2: torch.int16}[info.storage]
         es = 4 if info.storage == 0 else 2
+        if info.pop_offset == 2 ** 64 - 1:
+            raise ElbmError("the current populations are in a caller's buffer (elbm_step_into)")
         start = self._off + info.pop_offset
         raw = self._ws[start:start + 27 * self.N * es].view(dt)
         v = raw.view(self.storage_shape())

@@ -107,8 +107,11 @@ def test_turb256_properties_after_many_steps(E, torch_cuda):
 
 
 def test_turb512_reduced_storage_sampled(E, O, torch_cuda):
-    """512^3 (the reduced-storage workload) with FP16 deviations: one step at 300 sampled nodes
-    against the oracle fed with the same (device-generated) initial field."""
+    """512^3 turbulence (the headline box) with FP32, FP16 and BF16 deviations, in the benchmark's
+    launch configuration (for FP32 the 128-wide tiles in the XCD-remapped grid): one step at 300
+    sampled nodes against the oracle fed with the same (device-generated) initial field.  Bounds:
+    FP32 1e-6 (the FP32 collision's rounding, a few 1e-8), FP16 6e-5 and BF16 5e-4 (half an ulp of
+    the stored deviation, 2^-11 and 2^-8 times |f - W| <~ 0.05, plus the FP32 arithmetic)."""
     torch = torch_cuda
     w = WL.WORKLOADS["turb512"]
     r5, u5 = WL.turbulence_device(512, w["k0"], w["urms"], w["seed"])
@@ -140,7 +143,7 @@ def test_turb512_reduced_storage_sampled(E, O, torch_cuda):
             key = ((z - c[i, 2]) % 512, (y - c[i, 1]) % 512, (x - c[i, 0]) % 512)
             f[i] = O.feq(r_h[key], u_h[key])[i]
         ref[k] = O.collide(f, beta)[0]
-    for storage, tol in (("f16", 6e-5), ("bf16", 5e-4)):
+    for storage, tol in (("f32", 1e-6), ("f16", 6e-5), ("bf16", 5e-4)):
         _say(f"case: turb512 {storage}")
         lat = E.Lattice(w["shape"], w["nu"], storage=storage)
         E.elbm_init_equilibrium(lat.ctx, r5, u5)
@@ -148,7 +151,7 @@ def test_turb512_reduced_storage_sampled(E, O, torch_cuda):
         view = lat.population_view()  # [i, z, y, x] over the storage layout, no copy
         zt, yt, xt = (torch.tensor(c, device="cuda") for c in zip(*nodes))
         raw = view[:, zt, yt, xt]
-        if storage == "f16":
+        if storage in ("f32", "f16"):
             d = raw.float()
         else:
             d = (raw.to(torch.int32) << 16).view(torch.float32)
@@ -164,7 +167,8 @@ def test_turb512_reduced_storage_sampled(E, O, torch_cuda):
 def test_sphere384_full_size_steps(E, O, torch_cuda):
     """The moving-sphere channel at its full size (384x192x192, sphere R = 12 oscillating with
     amplitude 8), in the benchmark's launch configuration: 12 steps from the impulsive start against
-    the oracle, every fluid population within 2e-5 and drag and lift within 1e-3 of the largest."""
+    the oracle.  Measured 4.7e-8 on the fluid populations and 1.3e-7 on drag and lift relative to the
+    largest; bounds 1e-6 and 2e-6."""
     w = WL.WORKLOADS["sphere384"]
     steps = 12
     rho, u = WL.initial_field("sphere384")
@@ -184,5 +188,5 @@ def test_sphere384_full_size_steps(E, O, torch_cuda):
     ef = np.max(np.abs(F[:, :3] - Fo[:, :3])) / np.max(np.abs(Fo[:, :3]))
     _say(f"sphere384 full size, {steps} steps: max|df| {err:.3e}, force rel {ef:.2e}, "
          f"refills {sum(st['refill_nodes'] for st in s.stats)}")
-    assert err <= 2e-5
-    assert ef <= 1e-3
+    assert err <= 1e-6
+    assert ef <= 2e-6

@@ -1,7 +1,8 @@
 """Triangulated bodies on the GPU against the oracle (the deforming geometries of Sec. IV.C):
 solid masks bit for bit (including rays through triangle edges and vertices), then whole steps of a
-resting box in a channel, a rigidly oscillating sphere mesh and the deforming swimmer: populations
-of fluid nodes within 2e-5, forces within 1e-3 of the largest."""
+resting box in a channel, a rigidly oscillating sphere mesh and the deforming swimmer.  Measured up to
+5.9e-8 on the fluid populations, 6.1e-7 on the force and 3.0e-6 on the torque (relative to the largest
+component); bounds 1e-6, 1e-5 and 3e-5."""
 import numpy as np
 import pytest
 
@@ -67,9 +68,9 @@ def _compare(E, lat, s, label, steps):
     em = np.max(np.abs(F[:, 3:] - Fo[:, 3:])) / max(np.max(np.abs(Fo[:, 3:])), 1e-12)
     _say(f"{label}: max|df| = {err:.3e}, force rel {ef:.2e}, torque rel {em:.2e}, "
          f"refills {sum(st['refill_nodes'] for st in s.stats)}")
-    assert err <= 2e-5
-    assert ef <= 1e-3
-    assert em <= 1e-3
+    assert err <= 1e-6
+    assert ef <= 1e-5
+    assert em <= 3e-5
 
 
 def test_resting_box_in_channel(E, oracle_mod):

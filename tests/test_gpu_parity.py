@@ -275,7 +275,8 @@ def test_couette_gpu_matches_oracle(E, O):
 def test_moving_sphere_channel_parity(E, O):
     """Scaled copy of the oscillating-sphere channel (96x48x48, R = 3, amplitude 2, inlet 0.03; period
     400 so that the wall moves by more than a cell in 60 steps): moving-wall reconstruction, refill
-    and momentum exchange."""
+    and momentum exchange.  Measured 4.0e-8 on the populations and 7.8e-7 on the force history
+    (relative to its largest component); bounds 1e-6 and 1e-5."""
     shape = (96, 48, 48)
     nu = 0.0072
     steps = 60
@@ -294,17 +295,19 @@ def test_moving_sphere_channel_parity(E, O):
     err = np.max(np.abs(got[:, fluid] - s.A[:, fluid]))
     _say(f"sphere channel max|df| = {err:.3e}; refill nodes seen by oracle: "
          f"{sum(st['refill_nodes'] for st in s.stats)}")
-    assert err < 2e-5
+    assert err < 1e-6
     hist = lat.force_history(0, 1, steps)
     ref = np.array([f[0] for f in s.forces])
     ferr = np.max(np.abs(hist - ref)) / np.max(np.abs(ref[:, :3]))
     _say(f"force rel err = {ferr:.3e}")
-    assert ferr < 1e-3
+    assert ferr < 1e-5
 
 
 def test_rotating_sphere_force_and_torque_parity(E, O):
     """Prescribed rotation and oscillation (wall velocity U + Omega x r): populations, force and torque
-    against the oracle over 80 steps in a periodic box."""
+    against the oracle over 80 steps in a periodic box.  Measured 2.7e-8 on the populations, 6.5e-8 on
+    the force and 3.3e-7 on the torque (relative to their largest components); bounds 1e-6, 1e-6 and
+    3e-6."""
     shape = (48, 32, 32)
     body = WL.sphere((23.3, 15.6, 15.4), 5.0, amp=1.0, period=100.0, direction=(0.0, 1.0, 0.0),
                      omega=(0.002, -0.003, 0.004))
@@ -323,6 +326,6 @@ def test_rotating_sphere_force_and_torque_parity(E, O):
     ef = np.max(np.abs(got[:, :3] - ref[:, :3])) / np.max(np.abs(ref[:, :3]))
     em = np.max(np.abs(got[:, 3:] - ref[:, 3:])) / np.max(np.abs(ref[:, 3:]))
     _say(f"rotating sphere max|df| = {err:.3e}, force rel {ef:.2e}, torque rel {em:.2e}")
-    assert err <= 2e-5
-    assert ef <= 1e-3
-    assert em <= 1e-3
+    assert err <= 1e-6
+    assert ef <= 1e-6
+    assert em <= 3e-6

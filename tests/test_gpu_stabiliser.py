@@ -92,7 +92,8 @@ def test_taylor_green_variants(E, oracle_mod, mode):
 
 @pytest.mark.parametrize("mode", ["exact", "lbgk", "central"])
 def test_moving_wall_variants(E, oracle_mod, mode):
-    """Wall kernel path: an oscillating sphere in a small channel, 30 steps."""
+    """Wall kernel path: an oscillating sphere in a small channel, 30 steps.  Measured up to 7.5e-8 on
+    the populations and 9e-8 on the force; bounds 1e-6 and 1e-5."""
     O = oracle_mod
     shape, nu = (40, 20, 20), 0.01
     body = WL.sphere((15.3, 10.2, 9.8), 4.0, amp=1.5, period=40.0, direction=(0.0, 1.0, 0.0))
@@ -109,5 +110,5 @@ def test_moving_wall_variants(E, oracle_mod, mode):
     Fo = np.array([f[0, :3] for f in s.forces])
     ef = np.max(np.abs(F - Fo)) / np.max(np.abs(Fo))
     _say(f"moving wall {mode}: max|df| = {err:.3e}, force rel {ef:.2e}")
-    assert err <= 2e-5
-    assert ef <= 1e-3
+    assert err <= 1e-6
+    assert ef <= 1e-5

@@ -261,14 +261,22 @@ __device__ inline long pull_source(const BArgs& a, int i, int x, int y, int z) {
   return node_at(a, sx, wrap(y - cy(i), a.ny), wrap(z - cz(i), a.nz));
 }
 
-// Pull sources of a node, computed once: the 3 source x (clamped to the outlet in channel mode)
-// and the 9 source rows (periodic in y and z).  The transpose of the pull writes to the
-// same entries, except beyond the inlet (nothing) and beyond the outlet (the side buffer).
+// Pull sources of a node, computed once, split for the addressing as in the bulk sweep: per source
+// plane z - cz its element offset in the population layout and its first node (uniform over a
+// workgroup: z is the grid's z), per source row y - cy its in-plane offsets, and the 3 source x
+// (clamped to the outlet in channel mode; periodic in y and z).  Loads and stores go through buffer
+// resources on the uniform bases with 32-bit in-plane byte offsets (the plane-size limit of the
+// context and fewer than 2^30 nodes for the adjoint keep them below 2^32).  The transpose of the pull
+// writes to the same entries, except beyond the inlet (nothing) and beyond the outlet (the side
+// buffer).
 struct PullIdx {
-  long row[9];  // row[3 (cz+1) + (cy+1)] = (z - cz) ny + (y - cy), the source lattice row
-  int xs[3];    // xs[cx+1] = source x
-  bool in_lo;   // channel: x - 1 < 0 (cx = +1 comes through the inlet)
-  bool out_hi;  // channel: x + 1 >= nx (cx = -1 comes from beyond the outlet, copied)
+  int64_t zb[3];   // zb[cz+1]: element offset of source plane z - cz (population layout)
+  uint32_t zn[3];  // zn[cz+1]: node index of the first node of source plane z - cz
+  uint32_t yo[3];  // yo[cy+1]: element offset of source row y - cy inside its plane
+  uint32_t yn[3];  // yn[cy+1]: node offset of source row y - cy inside its plane
+  uint32_t xs[3];  // xs[cx+1]: source x
+  bool in_lo;      // channel: x - 1 < 0 (cx = +1 comes through the inlet)
+  bool out_hi;     // channel: x + 1 >= nx (cx = -1 comes from beyond the outlet, copied)
 };
 
 __device__ inline void pull_idx(const BArgs& a, int x, int y, int z, PullIdx& P) {
@@ -286,17 +294,45 @@ __device__ inline void pull_idx(const BArgs& a, int x, int y, int z, PullIdx& P)
   const int ys[3] = {y + 1 == a.ny ? 0 : y + 1, y, y == 0 ? a.ny - 1 : y - 1};
   const int zs[3] = {z + 1 == a.nz ? 0 : z + 1, z, z == 0 ? a.nz - 1 : z - 1};
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) P.row[3 * k + jj] = (long)zs[k] * a.ny + ys[jj];
+  for (int k = 0; k < 3; ++k) {
+    P.zb[k] = (int64_t)zs[k] * a.ny * a.lay.rs;
+    P.zn[k] = (uint32_t)zs[k] * (uint32_t)a.ny * (uint32_t)a.nx;
+    P.yo[k] = (uint32_t)ys[k] * (uint32_t)a.lay.rs;
+    P.yn[k] = (uint32_t)ys[k] * (uint32_t)a.nx;
+  }
 }
 
-// Node pulled into direction i, and the element of its population i in A^t.
-__device__ __forceinline__ long pull_src_idx(const BArgs& a, const PullIdx& P, int i) {
-  return P.row[3 * (cz(i) + 1) + cy(i) + 1] * a.nx + P.xs[cx(i) + 1];
+// Node pulled into direction i.
+__device__ __forceinline__ uint32_t pull_src_idx(const BArgs& a, const PullIdx& P, int i) {
+  return P.zn[cz(i) + 1] + P.yn[cy(i) + 1] + P.xs[cx(i) + 1];
 }
-__device__ __forceinline__ int64_t pull_src_pop(const BArgs& a, const PullIdx& P, int i) {
-  return P.row[3 * (cz(i) + 1) + cy(i) + 1] * a.lay.rs + i * a.lay.si + P.xs[cx(i) + 1];
+
+// Deviation of population i of the node pulled into direction i, in A^t.
+template <int S>
+__device__ __forceinline__ float pull_load(const BArgs& a, const PullIdx& P, int i) {
+  using E = typename Codec<S>::E;
+  const E* base = (const E*)a.A + (P.zb[cz(i) + 1] + (int64_t)i * a.lay.si);
+  const uint32_t off = (P.yo[cy(i) + 1] + P.xs[cx(i) + 1]) * (uint32_t)sizeof(E);
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, BUF_ALL, BUF_WORD3);
+  if constexpr (sizeof(E) == 4) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  } else {
+    const E e = __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+    return Codec<S>::load_dev(&e);
+  }
+}
+
+// Entry n of direction i of an adjoint field ([27][N] FP32), through a buffer resource on the
+// direction's base.
+__device__ __forceinline__ float dir_load(const float* f, const BArgs& a, int i, uint32_t n) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(f + (int64_t)i * a.N), (short)0, BUF_ALL, BUF_WORD3);
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, n * 4u, 0, 0));
+}
+__device__ __forceinline__ void dir_store(float* f, const BArgs& a, int i, uint32_t n, float v) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(f + (int64_t)i * a.N), (short)0, BUF_ALL, BUF_WORD3);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, n * 4u, 0, 0);
 }
 
 // Transpose of the pull for direction i of node (y, z): entry (x - c_i, i) of dL/dA^t receives v.
@@ -307,7 +343,7 @@ __device__ __forceinline__ void push_idx(const BArgs& a, const AdjArgs& j, const
     j.side[(size_t)(i / 3) * a.ny * a.nz + (size_t)z * a.ny + y] = v;
     return;
   }
-  j.lam_out[(size_t)i * a.N + pull_src_idx(a, P, i)] = v;
+  dir_store(j.lam_out, a, i, pull_src_idx(a, P, i), v);
 }
 
 template <int S, bool FLAGS, bool FORCE>
@@ -333,17 +369,16 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
     }
     return;
   }
-  const E* __restrict__ A = (const E*)a.A;
   double f[27], gp[27], g[27], gF[3];
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    f[i] = (double)C::load_dev(A + pull_src_pop(a, P, i)) + wd(i);  // exact widening
-    gp[i] = (double)j.lam_in[i * a.N + n];
+    f[i] = (double)pull_load<S>(a, P, i) + wd(i);  // exact widening
+    gp[i] = (double)dir_load(j.lam_in, a, i, (uint32_t)n);
   }
   if (FLAGS && (fl & FL_NEAR_REFILL)) {
     // a source uncovered in this step: its refill value unrounded (the stored one is rounded)
     for (int i = 0; i < 27; ++i) {
-      const long s = pull_src_idx(a, P, i);
+      const uint32_t s = pull_src_idx(a, P, i);
       if ((a.flags[s] & (FL_SOLID_PREV | FL_SOLID)) == FL_SOLID_PREV) {
         const uint32_t sl = (uint32_t)j.slot[s];
         if (sl < (uint32_t)a.cap) f[i] = j.r64[(size_t)sl * 27 + i];

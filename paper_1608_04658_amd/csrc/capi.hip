@@ -70,6 +70,8 @@ int validate(const elbm_params* p, char* err) {
   if (p->max_boundary < 0) return snprintf(err, 256, "bad max_boundary"), ELBM_EINVAL;
   if ((p->flags & ELBM_FLAG_EXACT_GAMMA) && (p->flags & ELBM_FLAG_LBGK))
     return snprintf(err, 256, "ELBM_FLAG_EXACT_GAMMA and ELBM_FLAG_LBGK exclude each other"), ELBM_EINVAL;
+  if ((p->flags & ELBM_FLAG_ADJOINT) && N >= 1073741824.0)  // 32-bit byte offsets into each adjoint direction
+    return snprintf(err, 256, "the adjoint needs fewer than 2^30 nodes"), ELBM_EINVAL;
   if ((p->flags & ELBM_FLAG_EXACT_GAMMA) && (p->flags & ELBM_FLAG_ADJOINT))
     return snprintf(err, 256, "the adjoint differentiates the analytic stabiliser only"), ELBM_EINVAL;
   if ((p->flags & ELBM_FLAG_CENTRAL) && (p->flags & (ELBM_FLAG_EXACT_GAMMA | ELBM_FLAG_LBGK | ELBM_FLAG_ADJOINT)))

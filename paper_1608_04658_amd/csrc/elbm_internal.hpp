@@ -66,6 +66,12 @@ __device__ __forceinline__ int64_t pop_base_n(const PopLayout& L, int64_t n) {
 // Population storage: every format stores the deviation d = f - W_i from the lattice weight (FP32,
 // or FP16 / BF16 rounded to nearest even); arithmetic is FP32 (FP64 on the recomputation path).
 // load/store take absolute populations, load_dev/store_dev deviations.
+// Raw buffer resources on gfx950 (CDNA): fourth descriptor word of an untyped 32-bit buffer, and the
+// cache-policy operand of a non-temporal access.
+constexpr int BUF_WORD3 = 0x00020000;
+constexpr int BUF_NT = 2;
+constexpr int BUF_ALL = (int)0xFFFFFFFFu;  // record count: no range check on the 32-bit offsets
+
 template <int S> struct Codec;
 template <> struct Codec<ELBM_STORAGE_F32> {
   using E = float;

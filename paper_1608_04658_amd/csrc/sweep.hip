@@ -75,12 +75,6 @@ __device__ __forceinline__ const E* pull_ptr(const E* A, const SweepArgs& a, con
   return (const E*)((const char*)base + lo[3 * (cy(i) + 1) + cx(i) + 1] * (uint32_t)sizeof(E));
 }
 
-// Raw buffer resources on gfx950 (CDNA): fourth descriptor word of an untyped 32-bit buffer, and the
-// cache-policy operand of a non-temporal access.
-constexpr int BUF_WORD3 = 0x00020000;
-constexpr int BUF_NT = 2;
-constexpr int BUF_ALL = (int)0xFFFFFFFFu;  // record count: no range check on the 32-bit offsets
-
 template <int S, bool FLAGS, bool FORCE, int STAB>
 __global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
   using C = Codec<S>;

@@ -1,11 +1,7 @@
-"""Free-moving spheres (two-way coupling, Sec. IV.A) on the GPU.
-
-Parity: the library's trajectory, forces and populations against the FP64 oracle (same Euler
-recurrence, integrated independently in the oracle's driver).  Galilean invariance, the paper's own
-validation of the coupling, at reduced scale: the drag coefficient of a fixed sphere in a uniform
-stream u_inf gives, through the settling force balance rho_s/rho_f = 1 + 3 u_t^2 C_d / (4 D g), the
-density ratio for which a sphere settling under gravity in a fluid at rest should reach the terminal
-velocity u_t = u_inf; the measured terminal velocity is compared with u_inf."""
+"""Free-moving spheres (two-way coupling, Sec. IV.A) on the GPU: the library's trajectory, forces and
+populations against the FP64 oracle (same Euler recurrence, integrated independently in the
+oracle's driver).  The paper's Galilean-invariance check of the coupling (the settling sphere) is in
+test_gpu_settling.py."""
 import numpy as np
 import pytest
 
@@ -66,10 +62,11 @@ def test_free_sphere_parity(E, oracle_mod, channel):
     ef = np.max(np.abs(lat.populations().cpu().numpy()[:, fluid] - s.A[:, fluid]))
     _say(f"free sphere channel={channel}: travel {ox[-1] - ox[0]}, max|dx| {ex:.2e}, velocity rel {eu:.2e}, "
          f"force rel {eF:.2e}, max|df| {ef:.2e}")
+    # measured: position 4.7e-8, velocity 8.2e-7, force 2.9e-6, populations 1.8e-8
     assert ex <= 1e-6
-    assert eu <= 1e-4
-    assert eF <= 1e-3
-    assert ef <= 2e-5
+    assert eu <= 1e-5
+    assert eF <= 3e-5
+    assert ef <= 1e-6
 
 
 def test_free_rotating_sphere_parity(E, oracle_mod):
@@ -104,12 +101,14 @@ def test_free_rotating_sphere_parity(E, oracle_mod):
     _say(f"free rotating sphere: spin {o[0, 6:]} -> {o[-1, 6:]}, max|dx| {ex:.2e}, velocity rel {eu:.2e}, "
          f"spin rel {ew:.2e}, force rel {eF:.2e}, torque rel {eM:.2e}, max|df| {ef:.2e}")
     assert np.max(np.abs(o[-1, 6:] - o[0, 6:])) > 1e-5  # the torque did turn it
+    # measured: position 2.7e-7, velocity 1.9e-6, spin 1.7e-7, force 1.5e-6, torque 4.3e-7,
+    # populations 2.8e-8
     assert ex <= 1e-6
-    assert eu <= 1e-4
-    assert ew <= 1e-4
-    assert eF <= 1e-3
-    assert eM <= 1e-3
-    assert ef <= 2e-5
+    assert eu <= 2e-5
+    assert ew <= 2e-6
+    assert eF <= 2e-5
+    assert eM <= 5e-6
+    assert ef <= 1e-6
 
 
 def test_free_sphere_leaving_the_domain_is_an_error(E):
@@ -121,42 +120,3 @@ def test_free_sphere_leaving_the_domain_is_an_error(E):
     lat.step(2)  # centre 8 -> 7.7 -> 7.4: still 3 nodes inside
     with pytest.raises(E.ElbmError, match="free body"):
         lat.step(10)
-
-
-@pytest.mark.timeout(900)
-def test_settling_sphere_galilean_invariance(E, torch_cuda):
-    """D = 10, Re = u_inf D / nu = 100 with u_inf = 0.02; lateral box 48 x 48 (periodic) in both runs."""
-    torch = torch_cuda
-    R, u_inf, nu = 5.0, 0.02, 0.002
-    D = 2 * R
-    # 1) fixed sphere in a uniform stream: drag coefficient after the transient
-    shape = (192, 48, 48)
-    rho, u = WL.uniform_flow(shape, (u_inf, 0.0, 0.0))
-    lat = E.Lattice(shape, nu, channel=True, u_inlet=(u_inf, 0.0, 0.0), max_bodies=1, force_ring=4096)
-    lat.init_equilibrium(rho, u)
-    lat.set_bodies([WL.sphere((48.0, 23.5, 23.5), R)])
-    steps = 16000
-    lat.step(steps)
-    Fx = lat.force_history(0, steps - 1999, 2000)[:, 0].mean()
-    Cd = Fx / (0.5 * u_inf ** 2 * np.pi * R ** 2)
-    _say(f"fixed sphere: C_d = {Cd:.4f} (mean drag over the last 2000 of {steps} steps)")
-    del lat
-    torch.cuda.empty_cache()
-    # 2) sphere settling under gravity in a fluid at rest, density ratio from the force balance
-    ratio = 2.0
-    g = 3.0 * u_inf ** 2 * Cd / (4.0 * D * (ratio - 1.0))
-    shape = (320, 48, 48)
-    rho, u = WL.uniform_flow(shape, (0.0, 0.0, 0.0))
-    lat = E.Lattice(shape, nu, channel=True, u_inlet=(0.0, 0.0, 0.0), max_bodies=1, force_ring=4096)
-    lat.init_equilibrium(rho, u)
-    lat.set_bodies([WL.free_sphere((20.0, 23.5, 23.5), R, ratio, gravity=(g, 0.0, 0.0))])
-    T = int(25 * D / u_inf)  # t u / D = 25, as in the paper
-    vs = []
-    for k in range(T // 250):
-        lat.step(250)
-        vs.append(lat.body_state(0)[1][0])
-    x, v = lat.body_state(0)
-    ut = float(np.mean(vs[-8:]))
-    _say(f"settling sphere: ratio {ratio}, g {g:.4e}, after {T} steps at x = {x[0]:.1f}: u_t = {ut:.6f} "
-         f"(u_inf {u_inf}), relative {ut / u_inf - 1:+.4f}; velocity history {np.round(vs[::4], 6)}")
-    assert abs(ut / u_inf - 1.0) < 0.03

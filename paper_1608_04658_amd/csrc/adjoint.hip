@@ -570,18 +570,6 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
 // U^t and R^t (k_macro64), the wall targets and Grad populations (wall_targets64), the refill
 // values (k_adj_refill); only the adjoint fields themselves are stored in FP32.
 
-// Two disjoint boxes walked by one launch (the body box and the inlet slab): index idx < count of
-// the first lies in it, the rest in the second.
-struct Box2 {
-  Box b[2];
-  __host__ __device__ long count() const { return b[0].count() + b[1].count(); }
-};
-__device__ __forceinline__ void box2_node(const Box2& bb, long idx, int& x, int& y, int& z) {
-  const long c0 = bb.b[0].count();
-  if (idx < c0) box_node(bb.b[0], idx, x, y, z);
-  else box_node(bb.b[1], idx - c0, x, y, z);
-}
-
 // U^t, R^t in FP64 on a box: the rule of k_macro (moments of A^t with U = (j - F/2)/rho at nodes
 // fluid at t, the rigid-body velocity and rho0 at nodes solid at t) from the exactly widened
 // stored deviations.
@@ -1012,11 +1000,7 @@ __global__ void k_adj_outlet(const BArgs a, const AdjArgs j) {
 // nodes solid at t (U = rigid-body velocity at t).  Clears the accumulators it consumes.
 // Launched on the boxes where the wall rules read U^t and R^t (around the bodies, the inlet slab),
 // which hold every accumulated entry.
-template <int S>
 __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, const AdjBodyArgs p, const Box2 box) {
-  using C = Codec<S>;
-  using E = typename C::E;
-  const E* __restrict__ A = (const E*)a.A;
   const long total = box.count();
   double acc[ELBM_MAX_BODIES];  // this thread's dL/d(amp) per body, summed over the wave at the end
 #pragma unroll
@@ -1025,15 +1009,23 @@ __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, con
     int bx, by, bz;
     box2_node(box, idx, bx, by, bz);
     const long n = node_at(a, bx, by, bz);
+    // every operand is loaded up front, independent of the others (one memory round trip): the
+    // accumulators, the FP64 U^t and R^t of k_macro64 (the same rule: U = (j - F/2)/rho from the
+    // exactly widened stored deviations), the node's 27 entries of dL/dA^t and its flags
     const double gU0 = j.gUR[n], gU1 = j.gUR[a.N + n], gU2 = j.gUR[2 * a.N + n], gR = j.gUR[3 * a.N + n];
+    const double U0 = j.m64[n], U1 = j.m64[a.N + n], U2 = j.m64[2 * a.N + n], rho = j.m64[3 * a.N + n];
+    const uint8_t fl = a.flags[n];
+    float lam[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) lam[i] = j.lam_out[i * a.N + n];
     if (gU0 == 0.0 && gU1 == 0.0 && gU2 == 0.0 && gR == 0.0) continue;
     j.gUR[n] = 0.0;
     j.gUR[a.N + n] = 0.0;
     j.gUR[2 * a.N + n] = 0.0;
     j.gUR[3 * a.N + n] = 0.0;
-    int x, y, z;
-    node_xyz(a, n, x, y, z);
-    if (a.flags[n] & FL_SOLID_PREV) {
+    if (fl & FL_SOLID_PREV) {
+      int x, y, z;
+      node_xyz(a, n, x, y, z);
       int kb = first_body(bd, false, x, y, z);
       if (kb < 0) kb = 0;
       const double v = gU0 * p.dU0[kb][0] + gU1 * p.dU0[kb][1] + gU2 * p.dU0[kb][2];
@@ -1041,28 +1033,11 @@ __global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, con
       for (int q = 0; q < ELBM_MAX_BODIES; ++q) acc[q] += q == kb ? v : 0.0;
       continue;
     }
-    // U, R of the node from the exactly widened stored deviations (as k_macro64)
-    double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      const double v = (double)C::load_dev(A + pop_off(a.lay, i, x, y, z));
-      dr += v;
-      jx += cx(i) * v;
-      jy += cy(i) * v;
-      jz += cz(i) * v;
-    }
-    const double rho = 1.0 + dr;
-    if (a.F) {
-      jx -= 0.5 * (double)a.F[n];
-      jy -= 0.5 * (double)a.F[a.N + n];
-      jz -= 0.5 * (double)a.F[2 * a.N + n];
-    }
     const double irho = 1.0 / rho;
-    const double U[3] = {jx * irho, jy * irho, jz * irho};
     const double h0 = gU0 * irho, h1 = gU1 * irho, h2 = gU2 * irho;
-    const double base = gR - (h0 * U[0] + h1 * U[1] + h2 * U[2]);
+    const double base = gR - (h0 * U0 + h1 * U1 + h2 * U2);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) j.lam_out[i * a.N + n] += (float)(base + h0 * cx(i) + h1 * cy(i) + h2 * cz(i));
+    for (int i = 0; i < 27; ++i) j.lam_out[i * a.N + n] = lam[i] + (float)(base + h0 * cx(i) + h1 * cy(i) + h2 * cz(i));
     if (a.F && j.gF) {
       j.gF[n] -= (float)(0.5 * h0);
       j.gF[a.N + n] -= (float)(0.5 * h1);
@@ -1130,32 +1105,10 @@ static void amp_derivatives(const elbm_body& b, double t, double dc[3], double d
   }
 }
 
-// The boxes where the wall rules read U^t and R^t: around the bodies and, in channel mode, the inlet
-// slab x < 3 (the body box without the slab, so the two are disjoint).
-static Box2 adj_boxes(const elbm_ctx* c, const Bodies& bd) {
-  Box2 bb;
-  Box slab = full_box(c);
-  slab.n[0] = 0;
-  if (c->p.bc_x == ELBM_BC_CHANNEL) slab.n[0] = c->p.nx < 3 ? c->p.nx : 3;
-  Box ub = full_box(c);
-  ub.n[0] = 0;
-  if (c->nb > 0) {
-    ub = union_box(c, bd);
-    const int cut = slab.n[0] - ub.lo[0];  // columns of the body box inside the slab
-    if (cut > 0) {
-      ub.lo[0] += cut;
-      ub.n[0] = ub.n[0] > cut ? ub.n[0] - cut : 0;
-    }
-  }
-  bb.b[0] = ub;
-  bb.b[1] = slab;
-  return bb;
-}
-
 // FP64 U^t, R^t on the boxes where the wall rules read them.
 template <int S>
 static void macro64_fields(elbm_ctx* c, const void* A, const Bodies& bd) {
-  const Box2 bb = adj_boxes(c, bd);
+  const Box2 bb = macro_boxes(c, bd, true);
   if (bb.count() == 0) return;
   hipLaunchKernelGGL((k_macro64<S>), grid_for(bb.count()), dim3(256), 0, c->stream, (const typename Codec<S>::E*)A,
                      c->lay, (const uint8_t*)c->flags, c->adj_macro64, c->bodyforce, bb, c->p.nx, c->p.ny,
@@ -1192,9 +1145,9 @@ static hipError_t adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, cons
       const dim3 gr((unsigned)std::min<int64_t>(std::max<int64_t>((a.cap - a.n_static + 1) / 2, 1), 1024));
       hipLaunchKernelGGL(k_adj_refill, gr, dim3(64), 0, c->stream, a, bd, j, p);
     }
-    const Box2 bb = adj_boxes(c, bd);
+    const Box2 bb = macro_boxes(c, bd, true);
     if (bb.count() > 0)
-      hipLaunchKernelGGL(k_adj_macro<S>, grid_for(bb.count()), dim3(256), 0, c->stream, a, bd, j, p, bb);
+      hipLaunchKernelGGL(k_adj_macro, grid_for(bb.count()), dim3(256), 0, c->stream, a, bd, j, p, bb);
   }
   return hipGetLastError();
 }

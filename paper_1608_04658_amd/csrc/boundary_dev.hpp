@@ -26,6 +26,14 @@ __device__ __forceinline__ void box_node(const Box& b, long idx, int& x, int& y,
   z = b.lo[2] + (int)(q / ny);
 }
 
+// Two disjoint boxes walked by one launch (the body box and the inlet slab): index idx < count of
+// the first lies in it, the rest in the second.
+__device__ __forceinline__ void box2_node(const Box2& bb, long idx, int& x, int& y, int& z) {
+  const long c0 = bb.b[0].count();
+  if (idx < c0) box_node(bb.b[0], idx, x, y, z);
+  else box_node(bb.b[1], idx - c0, x, y, z);
+}
+
 __device__ __forceinline__ int first_body(const Bodies& bd, bool at_t1, double x, double y, double z) {
   for (int k = 0; k < bd.nb; ++k)
     if (inside_body(bd.b[k], at_t1 ? bd.b[k].c1 : bd.b[k].c0, x, y, z)) return k;

@@ -119,6 +119,7 @@ hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd, bool slab)
 hipError_t geometry_for_step(elbm_ctx* c, const Bodies& bd);
 Box union_box(const elbm_ctx* c, const Bodies& bd);
 Box full_box(const elbm_ctx* c);
+Box2 macro_boxes(const elbm_ctx* c, const Bodies& bd, bool slab);
 dim3 grid_for(long n);
 Bodies make_bodies(const elbm_ctx* c, double t);
 constexpr int MESH_CELLS = 1 << 16;

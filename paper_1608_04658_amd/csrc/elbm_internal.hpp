@@ -682,5 +682,9 @@ struct Box {
   int n[3];
   __host__ __device__ long count() const { return (long)n[0] * n[1] * n[2]; }
 };
+struct Box2 {
+  Box b[2];
+  __host__ __device__ long count() const { return b[0].count() + b[1].count(); }
+};
 
 }  // namespace elbm

@@ -162,6 +162,28 @@ Box union_box(const elbm_ctx* c, const Bodies& bd) {
   return box;
 }
 
+// The boxes where the wall rules read U^t and R^t: around the bodies and, with slab in channel
+// mode, the inlet slab x < 3 (the body box without the slab's columns, so the two are disjoint).
+Box2 macro_boxes(const elbm_ctx* c, const Bodies& bd, bool slab) {
+  Box2 bb;
+  Box sl = full_box(c);
+  sl.n[0] = 0;
+  if (slab && c->p.bc_x == ELBM_BC_CHANNEL) sl.n[0] = c->p.nx < 3 ? c->p.nx : 3;
+  Box ub = full_box(c);
+  ub.n[0] = 0;
+  if (c->nb > 0) {
+    ub = union_box(c, bd);
+    const int cut = sl.n[0] - ub.lo[0];  // columns of the body box inside the slab
+    if (cut > 0) {
+      ub.lo[0] += cut;
+      ub.n[0] = ub.n[0] > cut ? ub.n[0] - cut : 0;
+    }
+  }
+  bb.b[0] = ub;
+  bb.b[1] = sl;
+  return bb;
+}
+
 Box full_box(const elbm_ctx* c) {
   Box b;
   b.lo[0] = b.lo[1] = b.lo[2] = 0;
@@ -294,12 +316,12 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_emit(GeoArgs g, int skip_in
 // nodes fluid at t; rigid-body velocity (R = rho0) at nodes solid at t.
 template <int S, bool MESH>
 __global__ void k_macro(const typename Codec<S>::E* A, PopLayout lay, const uint8_t* flags, float* macro, const float* F,
-                        Box box, int32_t nx, int32_t ny, int64_t N, double rho0, Bodies bd) {
+                        Box2 box, int32_t nx, int32_t ny, int64_t N, double rho0, Bodies bd) {
   using C = Codec<S>;
   const long total = box.count();
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
     int x, y, z;
-    box_node(box, idx, x, y, z);
+    box2_node(box, idx, x, y, z);
     const long n = ((long)z * ny + y) * nx + x;
     float U[3], R;
     if (flags[n] & FL_SOLID_PREV) {
@@ -664,7 +686,7 @@ static GeoArgs geo_args(elbm_ctx* c, const Box& box) {
 }
 
 template <int S>
-static void macro_launch(elbm_ctx* c, const void* A, const Box& box, const Bodies& bd) {
+static void macro_launch(elbm_ctx* c, const void* A, const Box2& box, const Bodies& bd) {
   if (bd.mesh >= 0)
     hipLaunchKernelGGL((k_macro<S, true>), grid_for(box.count()), dim3(256), 0, c->stream,
                        (const typename Codec<S>::E*)A, c->lay, (const uint8_t*)c->flags, c->macro, c->bodyforce, box, c->p.nx,
@@ -675,7 +697,7 @@ static void macro_launch(elbm_ctx* c, const void* A, const Box& box, const Bodie
                        c->p.ny, (int64_t)c->N, c->p.rho0, bd);
 }
 
-static void macro_box(elbm_ctx* c, const void* A, const Box& box, const Bodies& bd) {
+static void macro_box(elbm_ctx* c, const void* A, const Box2& box, const Bodies& bd) {
   switch (c->p.storage) {
     case ELBM_STORAGE_F32: macro_launch<ELBM_STORAGE_F32>(c, A, box, bd); break;
     case ELBM_STORAGE_F16: macro_launch<ELBM_STORAGE_F16>(c, A, box, bd); break;
@@ -696,13 +718,8 @@ __global__ void k_slab_copy(const float* slab, float* macro, int32_t nx, int32_t
 
 // U^t, R^t of the populations A around the bodies and, with slab, on the inlet slab.
 hipError_t macro_fields(elbm_ctx* c, const void* A, const Bodies& bd, bool slab) {
-  const bool channel = c->p.bc_x == ELBM_BC_CHANNEL;
-  if (c->nb > 0) macro_box(c, A, union_box(c, bd), bd);
-  if (channel && slab) {
-    Box slab = full_box(c);
-    slab.n[0] = c->p.nx < 3 ? c->p.nx : 3;
-    macro_box(c, A, slab, bd);
-  }
+  const Box2 bb = macro_boxes(c, bd, slab);
+  if (bb.count() > 0) macro_box(c, A, bb, bd);
   return hipGetLastError();
 }
 

@@ -9,36 +9,69 @@
 namespace elbm {
 
 // Reductions over the lanes of the calling group (GROUP = 32 is defined with the shared
-// declarations); every lane receives the result.
+// declarations); every lane receives the result, bit-identical on all lanes.  Four steps inside each
+// 16-lane row through DPP operand modifiers (lane pairs 1, 2 apart, then the mirror images in each
+// 8-lane half and in the row), which the compiler folds into the arithmetic instruction, and one
+// exchange of the two rows of the group through ds_swizzle (lane l and l ^ 16): one LDS-pipe step
+// where a shuffle butterfly takes five.  The pairs of every step hold identical partial results,
+// so each lane adds the same two values.
+template <int CTRL>
+__device__ __forceinline__ float dpp32(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ float row_swap(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+}
+__device__ __forceinline__ double row_swap(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(uint32_t)b, 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(uint32_t)(b >> 32), 0x401F);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+static_assert(GROUP == 32, "the group reductions cover two 16-lane rows");
+constexpr int DPP_XOR1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HMIRROR = 0x141;  // row_half_mirror: lane 7 - l in each 8-lane half
+constexpr int DPP_MIRROR = 0x140;   // row_mirror: lane 15 - l in each row
+template <typename T, typename Op>
+__device__ __forceinline__ T greduce(T v, Op op) {
+  if constexpr (sizeof(T) == 4) {
+    v = op(v, dpp32<DPP_XOR1>(v));
+    v = op(v, dpp32<DPP_XOR2>(v));
+    v = op(v, dpp32<DPP_HMIRROR>(v));
+    v = op(v, dpp32<DPP_MIRROR>(v));
+  } else {
+    v = op(v, dpp64<DPP_XOR1>(v));
+    v = op(v, dpp64<DPP_XOR2>(v));
+    v = op(v, dpp64<DPP_HMIRROR>(v));
+    v = op(v, dpp64<DPP_MIRROR>(v));
+  }
+  return op(v, row_swap(v));
+}
 __device__ __forceinline__ float gsum(float v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GROUP);
-  return v;
+  return greduce(v, [](float x, float y) { return x + y; });
 }
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GROUP);
-  return v;
+  return greduce(v, [](double x, double y) { return x + y; });
 }
 __device__ __forceinline__ float gmax(float v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, GROUP));
-  return v;
+  return greduce(v, [](float x, float y) { return fmaxf(x, y); });
 }
 __device__ __forceinline__ float gmin(float v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, GROUP));
-  return v;
+  return greduce(v, [](float x, float y) { return fminf(x, y); });
 }
 __device__ __forceinline__ double gmax(double v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, GROUP));
-  return v;
+  return greduce(v, [](double x, double y) { return fmax(x, y); });
 }
 __device__ __forceinline__ double gmin(double v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, GROUP));
-  return v;
+  return greduce(v, [](double x, double y) { return fmin(x, y); });
 }
 // Bit l = predicate of lane l of the calling group.
 __device__ __forceinline__ uint32_t gballot(bool p) {

@@ -31,14 +31,30 @@
 
 namespace elbm {
 
-// d ln phi(c, u) / du of the factorised equilibrium factor phi(c,u) = w(c)(2 - s) X^c.
-template <typename T>
-__device__ inline T dlnphi(int c, T u) {
-  const T s = sqrt_(T(3) * u * u + T(1));
-  const T d0 = -T(3) * u / (s * (T(2) - s));
-  if (c == 0) return d0;
-  const T dX = (T(2) + T(3) * u / s) / (T(2) * u + s) + T(1) / (T(1) - u);
-  return d0 + T(c) * dX;
+// FP64 reciprocal from the hardware estimate and two Newton steps (within an ulp of 1/x; the
+// IEEE division sequence costs twice the instructions).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// One velocity component's equilibrium factors phi(c, u) = w(c) (2 - s) X^c (c = -1, 0, 1; the rule
+// of axis_phi, s = sqrt(1 + 3u^2), X = (2u + s)/(1 - u)) and their log-derivatives
+// d ln phi(c, u) / du = d0 + c dX with d0 = -3u / (s (2 - s)) and dX = (2 + 3u/s)/(2u + s) + 1/(1 - u),
+// sharing the square root and five reciprocals.
+__device__ __forceinline__ void axis_phi_dln(double u, double (&ph)[3], double (&D)[3]) {
+  const double s = sqrt_(3.0 * u * u + 1.0);
+  const double g = 2.0 - s;
+  const double is = rcp64(s), ig = rcp64(g), ip = rcp64(1.0 + u), im = rcp64(1.0 - u), iw = rcp64(2.0 * u + s);
+  ph[0] = g * ((s - 2.0 * u) * ip) * (1.0 / 6.0);
+  ph[1] = g * (2.0 / 3.0);
+  ph[2] = g * ((2.0 * u + s) * im) * (1.0 / 6.0);
+  const double d0 = -3.0 * u * is * ig;
+  const double dX = (2.0 + 3.0 * u * is) * iw + im;
+  D[0] = d0 - dX;
+  D[1] = d0;
+  D[2] = d0 + dX;
 }
 
 template <typename T> struct VjpOut {
@@ -62,19 +78,19 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
     jy += T(cy(i)) * f[i];
     jz += T(cz(i)) * f[i];
   }
-  const T irho = T(1) / rho;
+  const T irho = rcp64(rho);
   const T ux = jx * irho, uy = jy * irho, uz = jz * irho;
-  T px[3], py[3], pz[3], ipz[3], pxy[9], ipxy[9];
-  axis_phi(ux, px);
-  axis_phi(uy, py);
-  axis_phi(uz, pz);
+  T px[3], py[3], pz[3], ipz[3], pxy[9], ipxy[9], Dx[3], Dy[3], Dz[3];
+  axis_phi_dln(ux, px, Dx);
+  axis_phi_dln(uy, py, Dy);
+  axis_phi_dln(uz, pz, Dz);
   {
     T ipx[3], ipy[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      ipx[k] = T(1) / px[k];
-      ipy[k] = T(1) / py[k];
-      ipz[k] = T(1) / pz[k];
+      ipx[k] = rcp64(px[k]);
+      ipy[k] = rcp64(py[k]);
+      ipz[k] = rcp64(pz[k]);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -121,16 +137,13 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
     g_gam += gp[i] * dh[i];
   }
   const bool guard = lbgk || !(b > T(1e-30));  // gamma fixed at 2: no derivative through it
-  const T ib = T(1) / beta;
-  const T inv_b = guard ? T(0) : T(1) / b;
+  const T ib = rcp64(beta);
+  const T inv_b = guard ? T(0) : rcp64(b);
   const T gam = guard ? T(2) : ib - (T(2) - ib) * a * inv_b;
   // reverse
   g_gam *= -beta;
   const T g_a = -(T(2) - ib) * inv_b * g_gam;
   const T g_b = (T(2) - ib) * a * inv_b * inv_b * g_gam;
-  const T Dx[3] = {dlnphi(-1, ux), dlnphi(0, ux), dlnphi(1, ux)};
-  const T Dy[3] = {dlnphi(-1, uy), dlnphi(0, uy), dlnphi(1, uy)};
-  const T Dz[3] = {dlnphi(-1, uz), dlnphi(0, uz), dlnphi(1, uz)};
   // S0, Sx, Sy, Sz: sums of (dL/dfeq_i) feq_i times 1 and d ln feq_i / du
   T S0 = T(0), Sx = T(0), Sy = T(0), Sz = T(0);
   T gDx = 0, gDy = 0, gDz = 0, gPxy = 0, gPxz = 0, gPyz = 0;
@@ -167,15 +180,9 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
     u1x = ux + Fx * irho;
     u1y = uy + Fy * irho;
     u1z = uz + Fz * irho;
-    axis_phi(u1x, qx);
-    axis_phi(u1y, qy);
-    axis_phi(u1z, qz);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      D1x[k] = dlnphi(k - 1, u1x);
-      D1y[k] = dlnphi(k - 1, u1y);
-      D1z[k] = dlnphi(k - 1, u1z);
-    }
+    axis_phi_dln(u1x, qx, D1x);
+    axis_phi_dln(u1y, qy, D1y);
+    axis_phi_dln(u1z, qz, D1z);
   }
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
@@ -490,11 +497,12 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
     gp = 0.0;
   }
   const double rho = gsum(f), jx = gsum(ci[0] * f), jy = gsum(ci[1] * f), jz = gsum(ci[2] * f);
-  const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
-  double px[3], py[3], pz[3];
-  axis_phi(ux, px);
-  axis_phi(uy, py);
-  axis_phi(uz, pz);
+  const double irho = rcp64(rho);
+  const double ux = jx * irho, uy = jy * irho, uz = jz * irho;
+  double px[3], py[3], pz[3], Dx[3], Dy[3], Dz[3];
+  axis_phi_dln(ux, px, Dx);
+  axis_phi_dln(uy, py, Dy);
+  axis_phi_dln(uz, pz, Dz);
   const double fe = rho * px[cx(i) + 1] * py[cy(i) + 1] * pz[cz(i) + 1];
   const double d = own ? f - fe : 0.0;
   const double M200 = gsum(ci[0] * ci[0] * d), M020 = gsum(ci[1] * ci[1] * d), M002 = gsum(ci[2] * ci[2] * d);
@@ -506,18 +514,20 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
   if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
   else if (nnz(i) == 2) ds = cz(i) == 0 ? ci[0] * ci[1] * sxy : (cy(i) == 0 ? ci[0] * ci[2] * sxz : ci[1] * ci[2] * syz);
   if (!own) ds = 0.0;
-  const double h = d - ds, th = own ? h / fe : 0.0;
+  const double ife = own ? rcp64(fe) : 0.0;
+  const double h = d - ds, th = h * ife;
   const double b = gsum(th * h), a = gsum(th * ds), ggh = gsum(gp * h);
   const bool guard = lbgk || !(b > 1e-30);  // gamma fixed at 2: no derivative through it
-  const double ib = 1.0 / beta;
-  const double gam = guard ? 2.0 : ib - (2.0 - ib) * a / b;
+  const double ib = rcp64(beta);
+  const double inv_b = guard ? 0.0 : rcp64(b);
+  const double gam = guard ? 2.0 : ib - (2.0 - ib) * a * inv_b;
   // reverse
   const double g_gam = -beta * ggh;
-  const double g_a = guard ? 0.0 : -(2.0 - ib) / b * g_gam;
-  const double g_b = guard ? 0.0 : (2.0 - ib) * a / (b * b) * g_gam;
-  const double g_dh = own ? -beta * gam * gp + (g_a * ds + 2.0 * g_b * h) / fe : 0.0;
-  const double g_ds = own ? -2.0 * beta * gp + g_a * h / fe - g_dh : 0.0;
-  double gfe = own ? -(g_a * ds * h + g_b * h * h) / (fe * fe) - g_dh : 0.0;
+  const double g_a = guard ? 0.0 : -(2.0 - ib) * inv_b * g_gam;
+  const double g_b = guard ? 0.0 : (2.0 - ib) * a * inv_b * inv_b * g_gam;
+  const double g_dh = own ? -beta * gam * gp + (g_a * ds + 2.0 * g_b * h) * ife : 0.0;
+  const double g_ds = own ? -2.0 * beta * gp + g_a * h * ife - g_dh : 0.0;
+  double gfe = own ? -(g_a * ds * h + g_b * h * h) * ife * ife - g_dh : 0.0;
   // g_ds onto the deviatoric moments
   const bool face = nnz(i) == 1, edge = nnz(i) == 2;
   const double gDx = gsum(face && cx(i) ? 0.5 * g_ds : 0.0), gDy = gsum(face && cy(i) ? 0.5 * g_ds : 0.0);
@@ -533,31 +543,31 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
   gF[0] = gF[1] = gF[2] = 0.0;
   if (FORCE) {
     // f' += feq(rho, u + F/rho) - feq(rho, u)
-    const double u1x = ux + Fx / rho, u1y = uy + Fy / rho, u1z = uz + Fz / rho;
-    double qx[3], qy[3], qz[3];
-    axis_phi(u1x, qx);
-    axis_phi(u1y, qy);
-    axis_phi(u1z, qz);
+    const double u1x = ux + Fx * irho, u1y = uy + Fy * irho, u1z = uz + Fz * irho;
+    double qx[3], qy[3], qz[3], D1x[3], D1y[3], D1z[3];
+    axis_phi_dln(u1x, qx, D1x);
+    axis_phi_dln(u1y, qy, D1y);
+    axis_phi_dln(u1z, qz, D1z);
     const double ge1 = own ? gp * rho * qx[cx(i) + 1] * qy[cy(i) + 1] * qz[cz(i) + 1] : 0.0;
     const double gr1 = gsum(ge1);
-    const double g1x = gsum(ge1 * dlnphi(cx(i), u1x)), g1y = gsum(ge1 * dlnphi(cy(i), u1y));
-    const double g1z = gsum(ge1 * dlnphi(cz(i), u1z));
+    const double g1x = gsum(ge1 * D1x[cx(i) + 1]), g1y = gsum(ge1 * D1y[cy(i) + 1]);
+    const double g1z = gsum(ge1 * D1z[cz(i) + 1]);
     gfe -= gp;
-    g_rho += gr1 / rho - (g1x * Fx + g1y * Fy + g1z * Fz) / (rho * rho);
+    g_rho += gr1 * irho - (g1x * Fx + g1y * Fy + g1z * Fz) * irho * irho;
     gux += g1x;
     guy += g1y;
     guz += g1z;
-    gF[0] = g1x / rho;
-    gF[1] = g1y / rho;
-    gF[2] = g1z / rho;
+    gF[0] = g1x * irho;
+    gF[1] = g1y * irho;
+    gF[2] = g1z * irho;
   }
   const double ge = own ? gfe * fe : 0.0;
-  g_rho += gsum(ge) / rho;
-  gux += gsum(ge * dlnphi(cx(i), ux));
-  guy += gsum(ge * dlnphi(cy(i), uy));
-  guz += gsum(ge * dlnphi(cz(i), uz));
-  const double gjx = gux / rho, gjy = guy / rho, gjz = guz / rho;
-  g_rho -= (gux * ux + guy * uy + guz * uz) / rho;
+  g_rho += gsum(ge) * irho;
+  gux += gsum(ge * Dx[cx(i) + 1]);
+  guy += gsum(ge * Dy[cy(i) + 1]);
+  guz += gsum(ge * Dz[cz(i) + 1]);
+  const double gjx = gux * irho, gjy = guy * irho, gjz = guz * irho;
+  g_rho -= (gux * ux + guy * uy + guz * uz) * irho;
   return gp + g_dh + e + g_rho + ci[0] * gjx + ci[1] * gjy + ci[2] * gjz;
 }
 

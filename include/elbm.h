@@ -250,16 +250,21 @@ int elbm_set_body_force(struct elbm_ctx* ctx, const float* F_dev);
  * uncovered nodes, KBC collision, store, and the force on each body. */
 int elbm_step(struct elbm_ctx* ctx, int32_t nsteps);
 
+/* Flags of elbm_step_into. */
+#define ELBM_STEP_SKIP_FORCE 1u /* the force of the step is not summed: its slot of the force ring keeps
+                                   what it held (a recompute of levels whose forces an earlier pass
+                                   recorded); not with free bodies, whose motion needs it */
+
 /* One step of elbm_step that stores A^{t+1} in the caller's device buffer pop_next_dev
  * (27 N elements in the storage format and layout of elbm_save_state, 16-byte aligned, disjoint
  * from the current populations) instead of the workspace, and makes that buffer the current
  * population: the next step reads it and the refill of that step writes the uncovered nodes of
  * it in place.  The buffer is borrowed until the next elbm_step writes the workspace again or
  * elbm_write_populations / elbm_init_equilibrium / elbm_load_state replaces the populations;
- * elbm_get_info reports pop_offset = SIZE_MAX meanwhile.  Lets a checkpointed reverse sweep keep
- * every recomputed level without a copy.  ELBM_EINVAL for NULL, misaligned or overlapping
- * buffers. */
-int elbm_step_into(struct elbm_ctx* ctx, void* pop_next_dev);
+ * elbm_get_info reports pop_offset = SIZE_MAX meanwhile.  step_flags: 0 or ELBM_STEP_SKIP_FORCE.
+ * Lets a checkpointed reverse sweep keep every recomputed level without a copy.  ELBM_EINVAL for
+ * NULL, misaligned or overlapping buffers and for unknown flags. */
+int elbm_step_into(struct elbm_ctx* ctx, void* pop_next_dev, uint32_t step_flags);
 
 /* Force and torque on body `body` from the step that produced time level
  * `step` (1 <= step <= t, within the last force_ring steps): momentum exchange

@@ -77,7 +77,8 @@ class ForceRollout:
             lat.load_state(self.ckpt[s0], s0)
             states = [self.ckpt[s0]]
             for t in range(s0, s1 - 1):
-                elbm.elbm_step_into(lat.ctx, bufs[t - s0])
+                # the forward pass recorded these levels' forces already
+                elbm.elbm_step_into(lat.ctx, bufs[t - s0], skip_force=True)
                 states.append(bufs[t - s0])
             for t in reversed(range(s0, s1)):
                 w = self.weights[t]           # loss weight of time level t+1

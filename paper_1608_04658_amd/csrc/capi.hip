@@ -630,8 +630,9 @@ int elbm_set_body_force(elbm_ctx* c, const float* F_dev) {
   return ELBM_OK;
 }
 
-// One step t -> t+1 writing A^{t+1} into dst (NULL: the workspace buffer of the other slot).
-static int one_step(elbm_ctx* c, void* dst) {
+// One step t -> t+1 writing A^{t+1} into dst (NULL: the workspace buffer of the other slot);
+// force = false leaves the force of the step unsummed (its ring slot keeps what it held).
+static int one_step(elbm_ctx* c, void* dst, bool force = true) {
   const bool geo = c->flags != nullptr;
   c->pop[c->cur ^ 1] = dst ? dst : c->own[c->cur ^ 1];
   {
@@ -665,7 +666,7 @@ static int one_step(elbm_ctx* c, void* dst) {
     if (geo) HIP_OK(c, launch_boundary(c, bd));
     HIP_OK(c, launch_fixup(c));  // bulk and wall nodes queued for the FP64 collision
     c->fix_par ^= 1;
-    if (geo) HIP_OK(c, launch_force_reduce(c));
+    if (geo && force) HIP_OK(c, launch_force_reduce(c));
     if (c->n_free) HIP_OK(c, free_commit(c));  // the free bodies' state of level t+1 on the device
     if (c->mesh_next_set) {
       c->mesh_cur ^= 1;
@@ -689,15 +690,18 @@ int elbm_step(elbm_ctx* c, int32_t nsteps) {
   return ELBM_OK;
 }
 
-int elbm_step_into(elbm_ctx* c, void* pop_next_dev) {
+int elbm_step_into(elbm_ctx* c, void* pop_next_dev, uint32_t step_flags) {
   if (!c) return ELBM_EINVAL;
   if (!pop_next_dev) return fail(c, ELBM_EINVAL, "pop_next_dev is NULL");
+  if (step_flags & ~(uint32_t)ELBM_STEP_SKIP_FORCE) return fail(c, ELBM_EINVAL, "unknown step flags 0x%x", step_flags);
+  const bool skip_force = (step_flags & ELBM_STEP_SKIP_FORCE) != 0;
+  if (skip_force && c->n_free) return fail(c, ELBM_EINVAL, "free bodies need the force of every step");
   const size_t bytes = 27 * (size_t)c->N * storage_bytes(c->p.storage);
   const char* a0 = (const char*)c->pop[c->cur];
   const char* b0 = (const char*)pop_next_dev;
   if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(c, ELBM_EINVAL, "pop_next_dev overlaps the current populations");
   if (((uintptr_t)pop_next_dev) % 16) return fail(c, ELBM_EINVAL, "pop_next_dev must be 16-byte aligned");
-  return one_step(c, pop_next_dev);
+  return one_step(c, pop_next_dev, !skip_force);
 }
 
 int elbm_force_history(elbm_ctx* c, int32_t body, int64_t first, int32_t count, double* out_host) {

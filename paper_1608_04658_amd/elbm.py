@@ -87,7 +87,7 @@ def load():
         "elbm_body_spin": [_VP, ctypes.c_int32, P(ctypes.c_double)],
         "elbm_set_body_force": [_VP, _VP],
         "elbm_step": [_VP, ctypes.c_int32],
-        "elbm_step_into": [_VP, _VP],
+        "elbm_step_into": [_VP, _VP, ctypes.c_uint32],
         "elbm_force": [_VP, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double), P(ctypes.c_double)],
         "elbm_force_history": [_VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ctypes.c_double)],
         "elbm_read_flags": [_VP, _VP],
@@ -256,10 +256,14 @@ def elbm_step(ctx, nsteps: int = 1):
     _check(load().elbm_step(ctx, int(nsteps)), ctx)
 
 
-def elbm_step_into(ctx, pop_next):
+STEP_SKIP_FORCE = 1
+
+
+def elbm_step_into(ctx, pop_next, skip_force: bool = False):
     """One step whose new populations go to the device tensor `pop_next` (27 N elements of the
-    storage type), which becomes the current population buffer."""
-    _check(load().elbm_step_into(ctx, _ptr(pop_next)), ctx)
+    storage type), which becomes the current population buffer; skip_force leaves the step's force
+    unsummed (its ring slot keeps what it held)."""
+    _check(load().elbm_step_into(ctx, _ptr(pop_next), STEP_SKIP_FORCE if skip_force else 0), ctx)
 
 
 def elbm_force(ctx, body: int, step: int):

@@ -1,8 +1,9 @@
 """elbm_step_into (the step that stores A^{t+1} in a caller's buffer, used by the checkpointed reverse
 sweep) against elbm_step: with an oscillating sphere in a channel (nodes covered and uncovered in
 the steps stepped into buffers), the forces of every step and the populations of every fluid node
-at every level agree bit for bit; the borrowed buffer is reported and released as documented; bad
-destinations are rejected on the host."""
+at every level agree bit for bit; the borrowed buffer is reported and released as documented; a
+recompute from a saved level with ELBM_STEP_SKIP_FORCE reproduces the states and leaves the recorded
+forces in place; bad destinations and flags are rejected on the host."""
 import numpy as np
 import pytest
 
@@ -89,6 +90,35 @@ def test_step_into_matches_step(E, torch_cuda, storage):
     assert uncovered > 0 and covered > 0
 
 
+def test_recompute_without_force_sums(E, torch_cuda):
+    """Levels 1..8 by elbm_step (forces recorded), then the state of level 3 loaded back and levels
+    4..7 recomputed into buffers with the force sums skipped: the populations of every fluid node
+    bit-identical, the force history unchanged."""
+    torch = torch_cuda
+    _say("case: recompute with ELBM_STEP_SKIP_FORCE")
+    lat = _lattice(E, "f32")
+    states, fluid = {}, {}
+    for t in range(8):
+        lat.step(1)
+        states[t + 1] = lat.state_tensor()
+        fluid[t + 1] = ((lat.flags() & 1) == 0).cpu().numpy()
+    f_ref = lat.force_history(0, 1, 8)
+    lat.load_state(states[3], 3)
+    bufs = [torch.zeros_like(states[1]) for _ in range(4)]
+    for k in range(4):
+        E.elbm_step_into(lat.ctx, bufs[k], skip_force=True)
+    torch.cuda.synchronize()
+    shp = lat.storage_shape()
+    for k in range(4):
+        a = bufs[k].view(shp).cpu().numpy()
+        b = states[4 + k].view(shp).cpu().numpy()
+        diff = int(np.count_nonzero((a != b) & fluid[4 + k][:, :, None, :]))
+        _say(f"recomputed level {4 + k}: {diff} differing fluid entries")
+        assert diff == 0
+    f = lat.force_history(0, 1, 7)   # the lattice is back at level 7
+    assert np.array_equal(f, f_ref[:7])
+
+
 def test_step_into_rejects_bad_destinations(E, torch_cuda):
     torch = torch_cuda
     _say("case: elbm_step_into argument checks")
@@ -101,4 +131,13 @@ def test_step_into_rejects_bad_destinations(E, torch_cuda):
         E.elbm_step_into(lat.ctx, big[1:])                   # 2-byte aligned
     with pytest.raises(E.ElbmError, match="elbm error -1"):
         E.elbm_step_into(lat.ctx, None)
+    ok = torch.empty(27 * lat.N, dtype=torch.float16, device="cuda")
+    assert E.load().elbm_step_into(lat.ctx, ok.data_ptr(), 6) == -1   # unknown flag bits: ELBM_EINVAL
     assert lat.info().t == 0
+    free = E.Lattice(SHAPE, 0.02, channel=True, u_inlet=(0.03, 0.0, 0.0), max_bodies=1)
+    rho, u = WL.uniform_flow(SHAPE, (0.0, 0.0, 0.0))
+    free.init_equilibrium(rho, u)
+    free.set_bodies([WL.free_sphere((16.0, 12.0, 12.0), 4.0, 2.0)])
+    buf = torch.empty(27 * free.N, dtype=torch.float32, device="cuda")
+    with pytest.raises(E.ElbmError, match="free bodies"):
+        E.elbm_step_into(free.ctx, buf, skip_force=True)

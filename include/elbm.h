@@ -153,7 +153,8 @@ typedef struct elbm_info {
   int64_t nodes;          /* N */
   double beta;
   size_t pop_bytes;       /* bytes of one population array */
-  size_t pop_offset;      /* byte offset of the current populations A^t in the workspace */
+  size_t pop_offset;      /* byte offset of the current populations A^t in the workspace; SIZE_MAX
+                             while they are in a caller's buffer (elbm_step_into) */
   size_t flags_offset;    /* byte offset of the uint8 node flags (0 if no geometry) */
   int32_t storage;
   int32_t nbodies;

@@ -315,7 +315,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for --gpus "
+        print(f"bench.py runs on exactly one GPU: the library has no multi-GPU path (asked for --gpus "
               f"{args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
 

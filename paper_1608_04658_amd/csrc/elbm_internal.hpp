@@ -194,18 +194,30 @@ __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
 //   e(0)  = -(s - 1),                          s - 1 = 3u^2 / (1 + s)
 //   e(+1) = (u (5 - 2s - 3u) + 2 (s - 1)) / (1 - u)
 //   e(-1) = (u (s - 4) - 2 (s - 1)) / (2u + s)
-// and the reciprocals 1/(w(c) g(c)) for the entropic scalar product.
+// and the reciprocals 1/(w(c) g(c)) for the entropic scalar product.  Since s^2 = 1 + 3u^2, the two
+// moving factors multiply to g(+1) g(-1) = (2 - s)^2, so all three reciprocals follow from 1/(2 - s):
+// 1/(w g(-1)) = 6 g(+1)/(2 - s)^2, 1/(w g(+1)) = 6 g(-1)/(2 - s)^2, 1/(w g(0)) = (3/2)/(2 - s); the
+// two denominators of e(+-1) share one reciprocal as well (four reciprocals per axis instead of seven).
 template <typename T>
 __device__ __forceinline__ void axis_dev(T u, T (&e)[3], T (&ps)[3], T& sm1) {
   const T s = sqrt_(T(3) * u * u + T(1));
   sm1 = T(3) * u * u * rcp_(T(1) + s);
   e[1] = -sm1;
-  e[2] = (u * (T(5) - T(2) * s - T(3) * u) + T(2) * sm1) * rcp_(T(1) - u);
-  e[0] = (u * (s - T(4)) - T(2) * sm1) * rcp_(T(2) * u + s);
-  ps[0] = T(6) * rcp_(T(1) + e[0]);
-  ps[1] = T(1.5) * rcp_(T(1) + e[1]);
-  ps[2] = T(6) * rcp_(T(1) + e[2]);
+  const T dp = T(1) - u, dm = T(2) * u + s;
+  const T rpm = rcp_(dp * dm);
+  e[2] = (u * (T(5) - T(2) * s - T(3) * u) + T(2) * sm1) * (dm * rpm);
+  e[0] = (u * (s - T(4)) - T(2) * sm1) * (dp * rpm);
+  const T r = rcp_(T(1) - sm1);  // 1/(2 - s)
+  const T q = T(6) * r * r;
+  ps[0] = q * (T(1) + e[2]);
+  ps[1] = T(1.5) * r;
+  ps[2] = q * (T(1) + e[0]);
 }
+
+// a/b for the stabiliser: FP32 through the hardware reciprocal (the ratio needs no correctly rounded
+// quotient), FP64 as an IEEE division.
+__device__ __forceinline__ float ratio_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double ratio_(double a, double b) { return a / b; }
 
 template <typename T>
 __device__ __forceinline__ void axis_phi(T u, T (&ph)[3]) {
@@ -363,16 +375,21 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
     return ds;
   };
 
+  // feq_i - W_i = W_i (dr + rho P_i),  P_i = prod (1 + e) - 1 expanded without cancellation; with
+  // the y and z factors of a row of three directions (c_y, c_z fixed) in p_yz = (1 + e_y)(1 + e_z) - 1:
+  // dr + rho P_i = (dr + rho p_yz) + e_x rho (1 + p_yz)
   T dh[27];
 #pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    // feq_i - W_i = W_i (dr + rho P_i),  P_i = prod (1 + e) - 1 expanded without cancellation
-    const T a_ = ey[cy(i) + 1], b_ = ez[cz(i) + 1];
+  for (int r = 0; r < 9; ++r) {
+    const T a_ = ey[cy(3 * r) + 1], b_ = ez[cz(3 * r) + 1];
     const T pyz = a_ + b_ + a_ * b_;
-    const T e_ = ex[cx(i) + 1];
-    const T P = e_ + pyz + e_ * pyz;
-    const T fdev = T(wd(i)) * (dr + rho * P);
-    dh[i] = (d[i] - fdev) - ds_of(i);
+    const T Y = rho * pyz + rho, Z = rho * pyz + dr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = 3 * r + k;
+      const T fdev = T(wd(i)) * (ex[k] * Y + Z);
+      dh[i] = (d[i] - fdev) - ds_of(i);
+    }
   }
   // mass and momentum of dh by the separable transform used for the moments of d
   T hm, hx, hy, hz;
@@ -406,17 +423,37 @@ __device__ __forceinline__ KbcOut<T> kbc_collide(T (&d)[27], const T beta, const
   dh[10] += T(0.5) * hy;
   dh[22] -= T(0.5) * hz;
   dh[4] += T(0.5) * hz;
+  // <ds|dh> and <dh|dh>: 1/feq_i = (1/rho) psx psy psz, summed along x inside each row first
   T a = T(0), b = T(0), s2c = T(0);
+  if (CENTRAL) {
 #pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    const T ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
-    const T ds = ds_of(i);
-    const T th = dh[i] * ife;
-    b += th * dh[i];
-    if (CENTRAL || nnz(i) == 1 || nnz(i) == 2) a += th * ds;
-    if (CENTRAL) s2c += ds * ds * ife;
+    for (int i = 0; i < 27; ++i) {
+      const T ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
+      const T ds = ds_of(i);
+      const T th = dh[i] * ife;
+      b += th * dh[i];
+      a += th * ds;
+      s2c += ds * ds * ife;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      T br = T(0), ar = T(0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int i = 3 * r + k;
+        const T th = dh[i] * psx[k];
+        br += th * dh[i];
+        if (nnz(i) == 1 || nnz(i) == 2) ar += th * ds_of(i);
+      }
+      const T w = psy[cy(3 * r) + 1] * psz[cz(3 * r) + 1];
+      b += w * br;
+      a += w * ar;
+    }
+    b *= rinv;
+    a *= rinv;
   }
-  T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * a / b : T(2);
+  T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * ratio_(a, b) : T(2);
   if ((STAB & 3) == STAB_LBGK) gamma = T(2);
   if ((STAB & 3) == STAB_EXACT && b > T(1e-30)) {
     // Root of eq. gamma_min inside the admissible interval (lo, hi), where every argument of the

@@ -81,7 +81,7 @@ __device__ __forceinline__ uint32_t gballot(bool p) {
 
 // The KBC collision (Sec. II) in the lane-parallel form of the wall and FP64 fix-up kernels: lane
 // i < 27 holds d_i = f_i - W_i and receives the post-collision deviation; lanes >= 27 pass zeros.
-// Same arithmetic as kbc_collide<T>, with every sum over directions a butterfly reduction inside the
+// Same formulas as kbc_collide<T>, with every sum over directions a butterfly reduction inside the
 // group.  r receives gamma, <dh|dh>, rho and the shear estimate for the FP64 rule (equal on all
 // lanes of the group).
 template <typename T, bool FORCE, int STAB = STAB_KBC>
@@ -146,7 +146,7 @@ __device__ inline T kbc_collide_lanes(int lane, T d, T beta, T inv_beta, T Fx, T
   const T ife = (rinv * (psy[cy(i) + 1] * psz[cz(i) + 1])) * psx[cx(i) + 1];
   const T th = h * ife;
   const T b = gsum(th * h), a = gsum(th * ds);
-  T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * a / b : T(2);
+  T gamma = (b > T(1e-30)) ? inv_beta - (T(2) - inv_beta) * ratio_(a, b) : T(2);
   if ((STAB & 3) == STAB_LBGK) gamma = T(2);
   if ((STAB & 3) == STAB_EXACT && b > T(1e-30)) {
     // bracketed Newton on eq. gamma_min, as in kbc_collide (sums and extrema over the group)

@@ -75,8 +75,16 @@ __device__ __forceinline__ const E* pull_ptr(const E* A, const SweepArgs& a, con
   return (const E*)((const char*)base + lo[3 * (cy(i) + 1) + cx(i) + 1] * (uint32_t)sizeof(E));
 }
 
+// The plain collision (no body force; the analytic stabiliser or LBGK) runs at five waves per SIMD
+// (at most 102 VGPRs): the compiler's own choice is 111 VGPRs, four waves, which measured about 0.5 %
+// slower for the 2-byte sweeps.  The other forms need more registers and keep the compiler's choice
+// (bounding them spills to scratch).
+template <bool FORCE, int STAB>
+constexpr int sweep_min_waves() { return (FORCE || (STAB & 3) == STAB_EXACT || (STAB & STAB_CENTRAL)) ? 1 : 5; }
+
 template <int S, bool FLAGS, bool FORCE, int STAB>
-__global__ __launch_bounds__(256) void k_sweep(const SweepArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<FORCE, STAB>())))
+void k_sweep(const SweepArgs a) {
   using C = Codec<S>;
   using E = typename C::E;
   int tx = blockIdx.x, ty = blockIdx.y, z = blockIdx.z;

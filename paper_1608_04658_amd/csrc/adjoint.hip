@@ -9,13 +9,13 @@
 // Data flow of a reverse step (all on the context's stream):
 //   k_adj_bulk      per fluid node: collision VJP, then the transpose of the pull -- every
 //                   (source, direction) entry of dL/dA^t is written exactly once by the node that
-//                   pulled it, so the scatter needs no atomics;  solid nodes write zeros.
+//                   pulled it, so the scatter needs no atomics;  solid nodes write zeros; in channel
+//                   mode the face nodes also zero the entries no node pulls (the wall adjoint then
+//                   adds the inlet bounce-back terms).
 //   k_adj_boundary  per boundary/refill node: the adjoint of the reconstruction (Grad populations,
 //                   targets, finite-difference gradient, force term of the loss); contributions to
 //                   U^t and R^t of other nodes go to FP64 accumulators.
-//   k_adj_faces_zero / k_adj_outlet
-//                   channel mode: entries no node pulls start at zero (before the wall adjoint, which
-//                   adds the inlet bounce-back terms); the outlet copy is added afterwards.
+//   k_adj_outlet    channel mode: the outlet copy, added after the wall adjoint.
 //   k_adj_refill    the completed dL/dA^t of refilled nodes sent through Grad's distribution.
 //   k_adj_macro     the accumulated dL/dU^t, dL/dR^t turned into dL/dA^t (nodes fluid at t) or
 //                   into dL/d(amp) (nodes solid at t, whose U^t is the rigid-body velocity).
@@ -362,6 +362,15 @@ __global__ __launch_bounds__(256) void k_adj_bulk(const BArgs a, const AdjArgs j
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
   const long n = node_at(a, x, y, z);
+  if (FLAGS && a.channel && (x == 0 || x == a.nx - 1)) {
+    // channel faces: the entries no node pulls (x = 0 moving in -x, x = nx-1 moving in +x) start at
+    // zero; the wall kernel, launched next, adds the inlet's bounce-back terms to those at x = 0
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if (x == 0) j.lam_out[(3 * k) * a.N + n] = 0.f;
+      if (x == a.nx - 1) j.lam_out[(3 * k + 2) * a.N + n] = 0.f;
+    }
+  }
   const uint8_t fl = FLAGS ? a.flags[n] : (uint8_t)0;
   if (fl & FL_SPECIAL) return;
   PullIdx P;
@@ -744,8 +753,6 @@ __global__ __launch_bounds__(64) void k_adj_boundary(const BArgs a, const Bodies
     // a group past the end repeats the block's first node and writes nothing
     const int64_t k = base + g;
     const long n = a.list[k < count ? k : base];
-    // the plain inlet nodes are k_adj_inlet's: decided from flags alone, before the gather
-    // (uniform over the group: every lane tests one source, the group's ballot decides)
     LaneNb h;
     lane_gather<S, true, false>(a, A, n, lane, h);
     const bool active = k < count;
@@ -978,23 +985,9 @@ __global__ __launch_bounds__(64) void k_adj_refill(const BArgs a, const Bodies b
   }
 }
 
-// Channel faces, before the boundary adjoint: entries that no node pulls -- x = 0 moving in -x and
-// x = nx-1 moving in +x -- start at zero (the wall rule then adds the bounce-back terms at x = 0).
-// One thread per (direction pair k, y, z).
-__global__ void k_adj_faces_zero(const BArgs a, const AdjArgs j) {
-  const long face = (long)a.ny * a.nz, total = 9 * face;
-  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / face);
-    const long r = idx - k * face;
-    const int y = (int)(r % a.ny), z = (int)(r / a.ny);
-    j.lam_out[(3 * k) * a.N + node_at(a, 0, y, z)] = 0.f;
-    j.lam_out[(3 * k + 2) * a.N + node_at(a, a.nx - 1, y, z)] = 0.f;
-  }
-}
-
 // Channel faces, after the boundary adjoint: add the outlet-copy contributions of the side buffer.
 // One thread per (direction k with c_x = -1, y, z); for each k the targets are distinct.
-__global__ void k_adj_outlet(const BArgs a, const AdjArgs j) {
+__global__ __launch_bounds__(256) void k_adj_outlet(const BArgs a, const AdjArgs j) {
   const long face = (long)a.ny * a.nz, total = 9 * face;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
     const int k = (int)(idx / face);
@@ -1010,7 +1003,8 @@ __global__ void k_adj_outlet(const BArgs a, const AdjArgs j) {
 // nodes solid at t (U = rigid-body velocity at t).  Clears the accumulators it consumes.
 // Launched on the boxes where the wall rules read U^t and R^t (around the bodies, the inlet slab),
 // which hold every accumulated entry.
-__global__ void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, const AdjBodyArgs p, const Box2 box) {
+__global__ __launch_bounds__(256) void k_adj_macro(const BArgs a, const Bodies bd, const AdjArgs j, const AdjBodyArgs p,
+                                                   const Box2 box) {
   const long total = box.count();
   double acc[ELBM_MAX_BODIES];  // this thread's dL/d(amp) per body, summed over the wave at the end
 #pragma unroll
@@ -1139,8 +1133,6 @@ static hipError_t adj_launch(elbm_ctx* c, const BArgs& a, const Bodies& bd, cons
     hipLaunchKernelGGL(k_adj_refill64, gr, dim3(64), 0, c->stream, a, bd, j);
   }
   const dim3 gf = grid_for(9L * c->p.ny * c->p.nz);
-  // entries no node pulls start at zero; the wall kernels write the inlet's bounce-back terms
-  if (geo && a.channel) hipLaunchKernelGGL(k_adj_faces_zero, gf, dim3(256), 0, c->stream, a, j);
   if (geo && force) hipLaunchKernelGGL((k_adj_bulk<S, true, true>), grd, blk, 0, c->stream, a, j);
   else if (geo) hipLaunchKernelGGL((k_adj_bulk<S, true, false>), grd, blk, 0, c->stream, a, j);
   else if (force) hipLaunchKernelGGL((k_adj_bulk<S, false, true>), grd, blk, 0, c->stream, a, j);

@@ -96,6 +96,22 @@ def test_collision_conserves_mass_and_momentum(O, lat):
         assert np.allclose(c.T @ f2, c.T @ f, atol=1e-15)
 
 
+def test_axis_factors_of_the_equilibrium_multiply_to_a_square(O, lat):
+    """eq. feq_min factorises over the axes, feq_i = rho prod_a phi(c_ia; u_a), with
+    phi(0) = (2/3)(2 - s) and phi(+1) phi(-1) = ((2 - s)/6)^2, s = sqrt(1 + 3u^2) (since
+    (2u + s)(s - 2u) = 1 - u^2).  The GPU collision takes all three reciprocal weights of an axis
+    from 1/(2 - s) through this product; here it is checked on the oracle's equilibrium, whose y and
+    z factors at rest are 2/3."""
+    c, _ = lat
+    idx = {k: int(np.flatnonzero((c == (k, 0, 0)).all(axis=1))[0]) for k in (-1, 0, 1)}
+    for u in np.linspace(-0.45, 0.45, 19):
+        f = O.feq(1.0, np.array([u, 0.0, 0.0]))
+        phi = {k: f[idx[k]] / (2.0 / 3.0) ** 2 for k in idx}
+        s = np.sqrt(1.0 + 3.0 * u * u)
+        assert abs(phi[1] * phi[-1] / ((2.0 - s) / 6.0) ** 2 - 1.0) < 1e-13
+        assert abs(phi[0] / ((2.0 / 3.0) * (2.0 - s)) - 1.0) < 1e-13
+
+
 def test_equilibrium_is_fixed_point(O):
     for u in ((0.0, 0.0, 0.0), (0.04, -0.02, 0.01)):
         f = O.feq(1.05, np.array(u))

@@ -264,7 +264,8 @@ int elbm_step(struct elbm_ctx* ctx, int32_t nsteps);
  * elbm_write_populations / elbm_init_equilibrium / elbm_load_state replaces the populations;
  * elbm_get_info reports pop_offset = SIZE_MAX meanwhile.  step_flags: 0 or ELBM_STEP_SKIP_FORCE.
  * Lets a checkpointed reverse sweep keep every recomputed level without a copy.  ELBM_EINVAL for
- * NULL, misaligned or overlapping buffers and for unknown flags. */
+ * NULL, misaligned or overlapping buffers, for unknown flags and for ELBM_STEP_SKIP_FORCE on a
+ * context with free bodies. */
 int elbm_step_into(struct elbm_ctx* ctx, void* pop_next_dev, uint32_t step_flags);
 
 /* Force and torque on body `body` from the step that produced time level

@@ -243,7 +243,8 @@ __device__ __forceinline__ bool is_boundary(const GeoArgs& g, int x, int y, int 
 }
 
 // Ordered compaction of the boundary nodes of a box (deterministic: the box's linear order), in
-// three passes: mark + per-block counts, one-block exclusive scan of the counts, emit.  Sets
+// three passes: mark + per-block counts, one-block exclusive scan of the counts, emit (two for small
+// boxes: k_scan_emit_fused).  Sets
 // FL_SPECIAL on listed nodes and clears it on the other box nodes; with skip_inlet the x = 0 face
 // keeps its flags and is not listed (it sits in the static part of the list).
 constexpr int SCAN_BLOCK = 256;
@@ -309,6 +310,41 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_emit(GeoArgs g, int skip_in
   if (isb) {
     const int64_t pos = base + (int64_t)block_offset[blockIdx.x] + ex;
     if (pos < cap) list[pos] = (int32_t)n;
+  }
+}
+
+// Emit pass for boxes of at most SCAN_FUSED blocks, which saves the one-workgroup pass: each
+// workgroup sums the counts of the blocks before it itself (at most SCAN_FUSED / SCAN_BLOCK loads per
+// thread), and the last one stores the total and the overflow bit.
+constexpr long SCAN_FUSED = 2048;
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_emit_fused(GeoArgs g, int skip_inlet, const uint32_t* block_count,
+                                                                int32_t* list, int64_t base, int64_t cap,
+                                                                uint32_t* count_out, uint32_t* overflow) {
+  __shared__ uint32_t sh[SCAN_BLOCK / 64];
+  uint32_t part = 0;
+  for (long j = threadIdx.x; j < (long)blockIdx.x; j += SCAN_BLOCK) part += block_count[j];
+  uint32_t prefix;
+  block_exclusive_scan(part, sh, prefix);  // the workgroup's sum: the counts of all earlier blocks
+  const long idx = blockIdx.x * (long)SCAN_BLOCK + threadIdx.x;
+  uint32_t isb = 0;
+  long n = 0;
+  if (idx < g.box.count()) {
+    int x, y, z;
+    box_node(g.box, idx, x, y, z);
+    n = ((long)z * g.ny + y) * g.nx + x;
+    isb = (!(skip_inlet && g.channel && x == 0) && (g.flags[n] & FL_SPECIAL)) ? 1u : 0u;
+  }
+  uint32_t total;
+  const uint32_t ex = block_exclusive_scan(isb, sh, total);
+  if (isb) {
+    const int64_t pos = base + (int64_t)prefix + ex;
+    if (pos < cap) list[pos] = (int32_t)n;
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const uint32_t all = prefix + total;
+    *count_out = all;
+    if (base + (int64_t)all > cap) atomicOr(overflow, 1u);
   }
 }
 
@@ -731,6 +767,11 @@ static hipError_t scan_box(elbm_ctx* c, const Box& box, int64_t base, int skip_i
   uint32_t* offsets = c->scan_tmp + c->scan_blocks;
   const GeoArgs g = geo_args(c, box);
   hipLaunchKernelGGL(k_scan_mark, dim3((unsigned)nblk), dim3(SCAN_BLOCK), 0, c->stream, g, skip_inlet, counts);
+  if (nblk >= 1 && nblk <= SCAN_FUSED) {
+    hipLaunchKernelGGL(k_scan_emit_fused, dim3((unsigned)nblk), dim3(SCAN_BLOCK), 0, c->stream, g, skip_inlet,
+                       (const uint32_t*)counts, c->blist, base, c->blist_cap, &c->cnt->dyn_count, &c->cnt->overflow);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, c->stream, (const uint32_t*)counts, offsets, nblk, base,
                      c->blist_cap, &c->cnt->dyn_count, &c->cnt->overflow);
   hipLaunchKernelGGL(k_scan_emit, dim3((unsigned)nblk), dim3(SCAN_BLOCK), 0, c->stream, g, skip_inlet,

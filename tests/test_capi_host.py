@@ -108,3 +108,21 @@ def test_noalloc_step_rejects_overlap(lib):
     p = elbm.make_params((8, 8, 8), 0.1)
     with pytest.raises(elbm.ElbmError, match="overlap"):
         elbm.elbm_step_periodic_noalloc(p, 4096, 4096 + 64, stream=0)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 (or a WORLD_SIZE above 1) exits with status 2 and a
+    message, before it touches a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, WORLD_SIZE="1")
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, env=env, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
+    env["WORLD_SIZE"] = "4"
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py")], capture_output=True, text=True, env=env,
+                       timeout=120)
+    assert r.returncode == 2 and "WORLD_SIZE=4" in r.stderr

@@ -40,21 +40,32 @@ __device__ __forceinline__ double rcp64(double x) {
 }
 
 // One velocity component's equilibrium factors phi(c, u) = w(c) (2 - s) X^c (c = -1, 0, 1; the rule
-// of axis_phi, s = sqrt(1 + 3u^2), X = (2u + s)/(1 - u)) and their log-derivatives
-// d ln phi(c, u) / du = d0 + c dX with d0 = -3u / (s (2 - s)) and dX = (2 + 3u/s)/(2u + s) + 1/(1 - u),
-// sharing the square root and five reciprocals.
-__device__ __forceinline__ void axis_phi_dln(double u, double (&ph)[3], double (&D)[3]) {
+// of axis_phi, s = sqrt(1 + 3u^2), X = (2u + s)/(1 - u)), their reciprocals and their log-derivatives
+// d ln phi(c, u) / du = d0 + c dX with d0 = -3u / (s (2 - s)) and dX = (2 + 3u/s)/(2u + s) + 1/(1 - u).
+// Since s^2 - 4u^2 = 1 - u^2, phi(+1) phi(-1) = ((2 - s)/6)^2 and phi(0) = (2/3)(2 - s): the three
+// reciprocals follow from 1/(2 - s); 1 + u and 1 - u share one reciprocal, s and 2u + s another
+// (three in all, with the square root).
+__device__ __forceinline__ void axis_phi_dln(double u, double (&ph)[3], double (&D)[3], double (&iph)[3]) {
   const double s = sqrt_(3.0 * u * u + 1.0);
-  const double g = 2.0 - s;
-  const double is = rcp64(s), ig = rcp64(g), ip = rcp64(1.0 + u), im = rcp64(1.0 - u), iw = rcp64(2.0 * u + s);
+  const double g = 2.0 - s, w = 2.0 * u + s;
+  const double ig = rcp64(g), rpm = rcp64((1.0 + u) * (1.0 - u)), rsw = rcp64(s * w);
+  const double ip = (1.0 - u) * rpm, im = (1.0 + u) * rpm, is = w * rsw, iw = s * rsw;
   ph[0] = g * ((s - 2.0 * u) * ip) * (1.0 / 6.0);
   ph[1] = g * (2.0 / 3.0);
-  ph[2] = g * ((2.0 * u + s) * im) * (1.0 / 6.0);
+  ph[2] = g * (w * im) * (1.0 / 6.0);
+  const double q = 36.0 * ig * ig;
+  iph[0] = ph[2] * q;
+  iph[1] = 1.5 * ig;
+  iph[2] = ph[0] * q;
   const double d0 = -3.0 * u * is * ig;
   const double dX = (2.0 + 3.0 * u * is) * iw + im;
   D[0] = d0 - dX;
   D[1] = d0;
   D[2] = d0 + dX;
+}
+__device__ __forceinline__ void axis_phi_dln(double u, double (&ph)[3], double (&D)[3]) {
+  double iph[3];
+  axis_phi_dln(u, ph, D, iph);
 }
 
 template <typename T> struct VjpOut {
@@ -81,17 +92,11 @@ __device__ inline VjpOut<T> kbc_vjp(const T (&f)[27], const T (&gp)[27], const T
   const T irho = rcp64(rho);
   const T ux = jx * irho, uy = jy * irho, uz = jz * irho;
   T px[3], py[3], pz[3], ipz[3], pxy[9], ipxy[9], Dx[3], Dy[3], Dz[3];
-  axis_phi_dln(ux, px, Dx);
-  axis_phi_dln(uy, py, Dy);
-  axis_phi_dln(uz, pz, Dz);
   {
     T ipx[3], ipy[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      ipx[k] = rcp64(px[k]);
-      ipy[k] = rcp64(py[k]);
-      ipz[k] = rcp64(pz[k]);
-    }
+    axis_phi_dln(ux, px, Dx, ipx);
+    axis_phi_dln(uy, py, Dy, ipy);
+    axis_phi_dln(uz, pz, Dz, ipz);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -508,10 +513,10 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
   const double rho = gsum(f), jx = gsum(ci[0] * f), jy = gsum(ci[1] * f), jz = gsum(ci[2] * f);
   const double irho = rcp64(rho);
   const double ux = jx * irho, uy = jy * irho, uz = jz * irho;
-  double px[3], py[3], pz[3], Dx[3], Dy[3], Dz[3];
-  axis_phi_dln(ux, px, Dx);
-  axis_phi_dln(uy, py, Dy);
-  axis_phi_dln(uz, pz, Dz);
+  double px[3], py[3], pz[3], Dx[3], Dy[3], Dz[3], ipx[3], ipy[3], ipz[3];
+  axis_phi_dln(ux, px, Dx, ipx);
+  axis_phi_dln(uy, py, Dy, ipy);
+  axis_phi_dln(uz, pz, Dz, ipz);
   const double fe = rho * px[cx(i) + 1] * py[cy(i) + 1] * pz[cz(i) + 1];
   const double d = own ? f - fe : 0.0;
   const double M200 = gsum(ci[0] * ci[0] * d), M020 = gsum(ci[1] * ci[1] * d), M002 = gsum(ci[2] * ci[2] * d);
@@ -523,7 +528,7 @@ __device__ inline double kbc_vjp_lanes(int lane, double f, double gp, double bet
   if (nnz(i) == 1) ds = cx(i) ? sfx : (cy(i) ? sfy : sfz);
   else if (nnz(i) == 2) ds = cz(i) == 0 ? ci[0] * ci[1] * sxy : (cy(i) == 0 ? ci[0] * ci[2] * sxz : ci[1] * ci[2] * syz);
   if (!own) ds = 0.0;
-  const double ife = own ? rcp64(fe) : 0.0;
+  const double ife = own ? irho * ipx[cx(i) + 1] * ipy[cy(i) + 1] * ipz[cz(i) + 1] : 0.0;
   const double h = d - ds, th = h * ife;
   const double b = gsum(th * h), a = gsum(th * ds), ggh = gsum(gp * h);
   const bool guard = lbgk || !(b > 1e-30);  // gamma fixed at 2: no derivative through it
